@@ -1,0 +1,211 @@
+/*
+ * cellgraph.h -- C ABI of the MI355X (gfx950) cell-graph construction library.
+ *
+ * The library builds the cell graph of Kaczmarski, Rzazewski and Wolant,
+ * "Massively Parallel Construction of the Cell Graph" (arXiv:1503.06029):
+ * given a multiset X of binary vectors of length l (one constraint-sign
+ * vector per sampled point, Section 2.1), it deduplicates X into cells and
+ * emits every pair of cells at Hamming distance 1 (the graph G_X of
+ * Section 2.2).  The path is: pack (sign bytes -> words), dedup (radix sort
+ * + unique, Section 3.2), dictionary build (sorted keys + prefix directory
+ * + suffix-grouped order), distance-1 queries (Section 3.2, Algorithm 4's
+ * flip-and-look-up), and edge emission (prefix sum + compaction).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every d_* pointer is a DEVICE pointer owned by the caller.  The library
+ *   never allocates or frees device memory; scratch space is passed in as a
+ *   workspace whose size the matching *_workspace / *_size call reports.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Calls only
+ *   enqueue work on it and return; none synchronises with the host.  Values
+ *   that depend on the data (cell count, edge count, overflow) are written to
+ *   device scalars.
+ * - Synchronous return codes report argument validation and launch
+ *   failures only.  On any error nothing is enqueued after the failing
+ *   launch; cg_last_error() gives the text (per host thread).
+ * - No global mutable device state: concurrent calls on different streams
+ *   with disjoint buffers are safe.
+ *
+ * Packed-row layout (cg_layout)
+ * -----------------------------
+ * A vector x(0) .. x(l-1) (zero-based, Section 1.1) is stored as `words`
+ * unsigned machine words of `word_bits` bits (32 or 64), words = ceil(l /
+ * word_bits).  Bit i sits in word i / word_bits at bit position
+ * word_bits - 1 - (i mod word_bits): x(0) is the most significant bit of
+ * word 0.  Positions >= l must be 0 (cg_pack guarantees it; other producers
+ * must too).  Rows are contiguous, row r starting at word r * words.
+ * With this layout, comparing rows word by word as unsigned integers from
+ * word 0 is the lexicographic order with x(0) most significant, which is
+ * the order of the sorted cells and of the sets vectors(C, v) of Section 3.2.
+ *
+ * Output order
+ * ------------
+ * Cells are the distinct input rows in ascending lexicographic order; a
+ * cell's id is its rank.  Edges are the pairs (u, v), u < v, of cells at
+ * distance 1, in ascending (u, v) order; bit[e] is the one position where
+ * they differ (cell u has 0 there, cell v has 1).  The output is unique: the
+ * same input gives the same bytes whatever the parameters.
+ */
+#ifndef CELLGRAPH_H
+#define CELLGRAPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *cg_stream_t; /* same type as hipStream_t */
+
+typedef int32_t cg_status;
+#define CG_OK            0
+#define CG_EINVAL       -1  /* bad argument: null pointer, bad layout, size out of range */
+#define CG_EWORKSPACE   -2  /* workspace / dictionary memory smaller than reported size   */
+#define CG_ECAPACITY    -3  /* (device status only) more edges than the output capacity  */
+#define CG_EHIP         -4  /* HIP launch or runtime error; see cg_last_error()           */
+#define CG_EUNSUPPORTED -5  /* valid request this build does not implement               */
+
+typedef struct cg_layout {
+    int32_t ell;       /* vector length l, 1 <= l <= 65535                    */
+    int32_t word_bits; /* 32 or 64                                             */
+    int32_t words;     /* ceil(ell / word_bits)                                */
+} cg_layout;
+
+/* Library version, (major << 16) | minor. */
+int32_t cg_version(void);
+
+/* Static text for a status code. */
+const char *cg_status_string(cg_status st);
+
+/* Copies the calling thread's last error text (NUL-terminated, truncated to
+ * len) into buf; returns the status that produced it (CG_OK if none). */
+cg_status cg_last_error(char *buf, size_t len);
+
+/* Fills *lay for a vector length and word size; CG_EINVAL if out of range. */
+cg_status cg_make_layout(int32_t ell, int32_t word_bits, cg_layout *lay);
+
+/* ------------------------------------------------------------------ pack
+ * Section 2.1: bit i of a point's vector is 1 iff the point satisfies
+ * constraint c_i.  Packs an n x l byte matrix (row r at d_bits + r *
+ * row_stride, byte != 0 means 1) into n packed rows (layout above), writing
+ * n * lay.words words to d_packed and zeroing positions >= l.
+ * Errors: CG_EINVAL if n < 0, row_stride < l, or a required pointer is NULL
+ * while n > 0.  d_bits and d_packed must not overlap.                       */
+cg_status cg_pack(const uint8_t *d_bits, int64_t n, int64_t row_stride,
+                  cg_layout lay, void *d_packed, cg_stream_t stream);
+
+/* ----------------------------------------------------------------- dedup
+ * Section 2.2 (X may be a multiset; only unique pairs are wanted) and
+ * Section 3.2 (sort X by radix sort, removing duplicates).  Sorts the n
+ * packed rows lexicographically and removes duplicates:
+ *   d_cells      (capacity n rows) <- the distinct rows, ascending;
+ *   d_row_to_cell (nullable, n)    <- id of the cell equal to each row;
+ *   *d_ncells    (device int64)    <- number of cells.
+ * The input is not modified and must not overlap the outputs.  Requires
+ * n < 2^32.  Workspace: cg_dedup_workspace(n, lay) bytes, any alignment >= 256.
+ * Errors: CG_EINVAL (bad layout, n out of range, NULL pointers),
+ * CG_EWORKSPACE (ws_bytes too small).                                       */
+cg_status cg_dedup_workspace(int64_t n, cg_layout lay, size_t *bytes);
+cg_status cg_dedup(const void *d_packed, int64_t n, cg_layout lay, void *d_cells,
+                   uint32_t *d_row_to_cell, int64_t *d_ncells, void *d_ws,
+                   size_t ws_bytes, cg_stream_t stream);
+
+/* ------------------------------------------------------------ dictionary
+ * A device dictionary over the sorted distinct cells (Section 3.2: the
+ * sorted set makes every vectors(C, v) a contiguous index range; the paper's
+ * tree stores its values, the cell ids, in the leaves).  This build keeps:
+ *   - the sorted cells themselves (borrowed, not copied);
+ *   - a directory over the first p bits: dir[g] = first cell whose first p
+ *     bits are >= g, for g = 0 .. 2^p (the top levels of a 2^p-ary tree of
+ *     Section 3.2, held as ranges);
+ *   - a suffix-grouped order: the cell ids sorted by a 32-bit hash of bits
+ *     s .. l-1, so cells that agree on all bits past s sit together.
+ * A distance-1 pair that differs at bit k >= s shares its first s bits and
+ * is adjacent in the sorted order; one that differs at k < s shares bits
+ * s .. l-1 and is adjacent in the suffix-grouped order.                     */
+#define CG_DICT_SORTED 0        /* sorted keys + prefix directory + suffix order */
+#define CG_PATH_LOOKUP 0        /* edges by flip-and-look-up over the two orders */
+#define CG_PATH_ALLPAIRS 1      /* edges by the (*)-filtered all-pairs scan       */
+
+typedef struct cg_dict_params {
+    int32_t kind;       /* CG_DICT_SORTED                                         */
+    int32_t dir_bits;   /* p, 0..24; -1 = automatic (about log2 of the capacity)  */
+    int32_t split_bit;  /* s, 0..l; -1 = automatic                                */
+    int32_t path;       /* CG_PATH_LOOKUP or CG_PATH_ALLPAIRS (used by cg_edges)  */
+    int32_t n_refs;     /* h, 0..8: reference vectors of the all-pairs path       */
+    int32_t group_max;  /* groups larger than this are searched, not scanned;
+                           1..1024, -1 = automatic                                */
+    int32_t reserved[2];/* must be 0                                              */
+} cg_dict_params;
+
+/* The automatic parameters (all -1, kind/path 0, n_refs 4). */
+cg_status cg_dict_params_default(cg_dict_params *p);
+
+/* Host-side handle of device pointers.  It BORROWS d_cells, d_ncells and
+ * d_mem, which must outlive it; it needs no destroy call.  Fields are
+ * filled by cg_dict_build (parameters with their automatic values resolved)
+ * and are read-only for the caller. */
+typedef struct cg_dict {
+    uint32_t magic;
+    cg_layout lay;
+    cg_dict_params params;      /* resolved */
+    int64_t ncells_cap;
+    const void *cells;          /* ncells_cap rows, first *d_ncells valid   */
+    const int64_t *d_ncells;
+    uint32_t *dir;              /* 2^dir_bits + 1 entries                    */
+    uint64_t *sfx;              /* ncells_cap entries: (hash << 32) | id      */
+    void *mem;
+    size_t mem_bytes;
+} cg_dict;
+
+/* Bytes of dictionary memory for up to ncells_cap cells. */
+cg_status cg_dict_size(int64_t ncells_cap, cg_layout lay, const cg_dict_params *p,
+                       size_t *bytes);
+
+/* Builds the dictionary over d_cells[0 .. *d_ncells), which must be sorted
+ * and distinct (as written by cg_dedup; not checked).  p may be NULL for the
+ * defaults.  Errors: CG_EINVAL, CG_EWORKSPACE, CG_EUNSUPPORTED (kind). */
+cg_status cg_dict_build(const void *d_cells, const int64_t *d_ncells, int64_t ncells_cap,
+                        cg_layout lay, const cg_dict_params *p, void *d_mem,
+                        size_t mem_bytes, cg_dict *out, cg_stream_t stream);
+
+/* ----------------------------------------------------- distance-1 queries
+ * Section 3.2 (Algorithm 4): for every query vector q and every bit k, is
+ * q with bit k negated a cell?  For each of the nq rows at d_queries (same
+ * layout as the dictionary):
+ *   d_mask  (nullable, nq rows)  <- bit k set iff q xor e_k is a cell;
+ *   d_count (nullable, nq)       <- number of set mask bits;
+ *   d_self  (nullable, nq)       <- id of the cell equal to q, or 0xFFFFFFFF.
+ * Errors: CG_EINVAL (bad dictionary handle, nq < 0, NULL queries with nq > 0). */
+cg_status cg_neighbors_d1(const cg_dict *dict, const void *d_queries, int64_t nq,
+                          uint32_t *d_count, uint32_t *d_self, void *d_mask,
+                          cg_stream_t stream);
+
+/* ------------------------------------------------------------------ edges
+ * Section 2.2 (edges of G_X) over the dictionary's own cells, emitted in
+ * ascending (u, v) order by a prefix sum over the per-cell counts of upward
+ * neighbours (u < v):
+ *   d_uv      (cap x 2 uint32)    <- (u, v) pairs;
+ *   d_bit     (nullable, cap)     <- differing position of each pair;
+ *   *d_nedges (device int64)      <- |E|, always exact;
+ *   d_offsets (nullable, ncells_cap + 1 int64) <- offsets[u] = index of u's
+ *              first edge, offsets[*d_ncells] = |E|;
+ *   *d_status (device int32)      <- CG_OK, or CG_ECAPACITY if |E| > cap, in
+ *              which case nothing is written at or past index cap, the
+ *              contents below cap are unspecified, and the caller re-calls
+ *              with cap >= *d_nedges and the same dictionary.
+ * The dictionary's path parameter picks the method (flip-and-look-up or the
+ * (*)-filtered all-pairs scan of Section 3.1); the output bytes are the same.
+ * Workspace: cg_edges_workspace(dict, cap) bytes.
+ * Errors: CG_EINVAL, CG_EWORKSPACE.                                         */
+cg_status cg_edges_workspace(const cg_dict *dict, int64_t cap, size_t *bytes);
+cg_status cg_edges(const cg_dict *dict, uint32_t *d_uv, uint16_t *d_bit, int64_t cap,
+                   int64_t *d_nedges, int64_t *d_offsets, void *d_ws, size_t ws_bytes,
+                   int32_t *d_status, cg_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CELLGRAPH_H */

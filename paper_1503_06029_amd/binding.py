@@ -1,0 +1,178 @@
+"""Python binding of ``libcellgraph.so`` (ctypes).
+
+The functions below carry the C ABI's names and only marshal arguments:
+torch tensors supply device memory, ``torch.cuda.current_stream()`` supplies
+the stream, and every step of the path runs in the library's HIP kernels.
+There is no fallback: if the shared library is missing or fails to load,
+importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcellgraph.so")
+
+CG_OK, CG_EINVAL, CG_EWORKSPACE, CG_ECAPACITY, CG_EHIP, CG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+CG_DICT_SORTED = 0
+CG_PATH_LOOKUP, CG_PATH_ALLPAIRS = 0, 1
+
+c_i32, c_i64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("ell", c_i32), ("word_bits", c_i32), ("words", c_i32)]
+
+
+class DictParams(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("dir_bits", c_i32), ("split_bit", c_i32), ("path", c_i32),
+                ("n_refs", c_i32), ("group_max", c_i32), ("reserved", c_i32 * 2)]
+
+
+class Dict(ctypes.Structure):
+    _fields_ = [("magic", ctypes.c_uint32), ("lay", Layout), ("params", DictParams),
+                ("ncells_cap", c_i64), ("cells", c_vp), ("d_ncells", c_vp), ("dir", c_vp),
+                ("sfx", c_vp), ("mem", c_vp), ("mem_bytes", c_sz)]
+
+
+class CellGraphError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"cellgraph status {status}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(or python paper_1503_06029_amd/build.py) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+def _sig(name, args, res=c_i32):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_sig("cg_version", [])
+_sig("cg_status_string", [c_i32], ctypes.c_char_p)
+_sig("cg_last_error", [ctypes.c_char_p, c_sz])
+_sig("cg_make_layout", [c_i32, c_i32, ctypes.POINTER(Layout)])
+_sig("cg_pack", [c_vp, c_i64, c_i64, Layout, c_vp, c_vp])
+_sig("cg_dedup_workspace", [c_i64, Layout, ctypes.POINTER(c_sz)])
+_sig("cg_dedup", [c_vp, c_i64, Layout, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
+_sig("cg_dict_params_default", [ctypes.POINTER(DictParams)])
+_sig("cg_dict_size", [c_i64, Layout, ctypes.POINTER(DictParams), ctypes.POINTER(c_sz)])
+_sig("cg_dict_build", [c_vp, c_vp, c_i64, Layout, ctypes.POINTER(DictParams), c_vp, c_sz,
+                       ctypes.POINTER(Dict), c_vp])
+_sig("cg_neighbors_d1", [ctypes.POINTER(Dict), c_vp, c_i64, c_vp, c_vp, c_vp, c_vp])
+_sig("cg_edges_workspace", [ctypes.POINTER(Dict), c_i64, ctypes.POINTER(c_sz)])
+_sig("cg_edges", [ctypes.POINTER(Dict), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp])
+
+EXPORTS = ("cg_version", "cg_status_string", "cg_last_error", "cg_make_layout", "cg_pack",
+           "cg_dedup_workspace", "cg_dedup", "cg_dict_params_default", "cg_dict_size",
+           "cg_dict_build", "cg_neighbors_d1", "cg_edges_workspace", "cg_edges")
+
+
+def lib():
+    return _lib
+
+
+def _check(st: int):
+    if st != CG_OK:
+        buf = ctypes.create_string_buffer(512)
+        _lib.cg_last_error(buf, 512)
+        raise CellGraphError(st, buf.value.decode(errors="replace"))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def version() -> int:
+    return _lib.cg_version()
+
+
+def make_layout(ell: int, word_bits: int = 64) -> Layout:
+    lay = Layout()
+    _check(_lib.cg_make_layout(ell, word_bits, ctypes.byref(lay)))
+    return lay
+
+
+def word_dtype(word_bits: int):
+    return torch.int64 if word_bits == 64 else torch.int32
+
+
+# ------------------------------------------------------------ the C calls
+
+def cg_pack(d_bits, n: int, row_stride: int, lay: Layout, d_packed, stream=None):
+    _check(_lib.cg_pack(_ptr(d_bits), n, row_stride, lay, _ptr(d_packed), _stream(stream)))
+
+
+def cg_dedup_workspace(n: int, lay: Layout) -> int:
+    b = c_sz()
+    _check(_lib.cg_dedup_workspace(n, lay, ctypes.byref(b)))
+    return b.value
+
+
+def cg_dedup(d_packed, n: int, lay: Layout, d_cells, d_row_to_cell, d_ncells, d_ws, ws_bytes: int,
+             stream=None):
+    _check(_lib.cg_dedup(_ptr(d_packed), n, lay, _ptr(d_cells), _ptr(d_row_to_cell), _ptr(d_ncells),
+                         _ptr(d_ws), ws_bytes, _stream(stream)))
+
+
+def cg_dict_params_default(**overrides) -> DictParams:
+    p = DictParams()
+    _check(_lib.cg_dict_params_default(ctypes.byref(p)))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def cg_dict_size(ncells_cap: int, lay: Layout, params: DictParams | None = None) -> int:
+    b = c_sz()
+    _check(_lib.cg_dict_size(ncells_cap, lay, ctypes.byref(params) if params is not None else None,
+                             ctypes.byref(b)))
+    return b.value
+
+
+def cg_dict_build(d_cells, d_ncells, ncells_cap: int, lay: Layout, params: DictParams | None, d_mem,
+                  mem_bytes: int, stream=None) -> Dict:
+    out = Dict()
+    _check(_lib.cg_dict_build(_ptr(d_cells), _ptr(d_ncells), ncells_cap, lay,
+                              ctypes.byref(params) if params is not None else None, _ptr(d_mem), mem_bytes,
+                              ctypes.byref(out), _stream(stream)))
+    return out
+
+
+def cg_neighbors_d1(d: Dict, d_queries, nq: int, d_count=None, d_self=None, d_mask=None, stream=None):
+    _check(_lib.cg_neighbors_d1(ctypes.byref(d), _ptr(d_queries), nq, _ptr(d_count), _ptr(d_self),
+                                _ptr(d_mask), _stream(stream)))
+
+
+def cg_edges_workspace(d: Dict, cap: int) -> int:
+    b = c_sz()
+    _check(_lib.cg_edges_workspace(ctypes.byref(d), cap, ctypes.byref(b)))
+    return b.value
+
+
+def cg_edges(d: Dict, d_uv, d_bit, cap: int, d_nedges, d_offsets, d_ws, ws_bytes: int, d_status,
+             stream=None):
+    _check(_lib.cg_edges(ctypes.byref(d), _ptr(d_uv), _ptr(d_bit), cap, _ptr(d_nedges), _ptr(d_offsets),
+                         _ptr(d_ws), ws_bytes, _ptr(d_status), _stream(stream)))

@@ -1,0 +1,198 @@
+// Dictionary over the sorted distinct cells, and distance-1 queries against it.
+//
+// Section 3.2 builds a 2^r-ary search tree over the sorted vectors whose
+// nodes stand for the index ranges vectors(C, v) and whose leaves hold the
+// values.  Here the top of that tree is one flat level: a directory over the
+// first p bits (dir[g] = first cell whose top p bits are >= g), i.e. the
+// ranges of all 2^p nodes at depth p of a binary tree; below it a range is
+// finished by binary search over the sorted keys.  The suffix-grouped order
+// (cell ids sorted by a 32-bit hash of bits s .. l-1) is built here too;
+// cg_edges uses it for flips below bit s.
+//
+// Queries (Algorithm 4): for query q and bit k, the target q xor e_k never
+// exists as a row; each comparison XORs the flipped bit in on the fly
+// (Section 3.2 notes x' need not be materialised).
+#include "cg_internal.hpp"
+
+#include <algorithm>
+
+namespace cg {
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ uint32_t suffix_hash32(const T *row, int words, int s) {
+    constexpr int B = Bits<T>::B;
+    uint64_t h = 0x243f6a8885a308d3ull;
+    const int w0 = s / B;
+    for (int w = w0; w < words; ++w) {
+        T x = row[w];
+        if (w == w0 && (s % B)) x &= (T(~T(0)) >> (s % B));
+        h = fmix64(h ^ (static_cast<uint64_t>(x) + static_cast<uint64_t>(w + 1) * 0x9e3779b97f4a7c15ull));
+    }
+    return static_cast<uint32_t>(h >> 32);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_dict_scan(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
+                                                   int words, int p, int s, uint32_t *__restrict__ dir,
+                                                   uint64_t *__restrict__ sfx) {
+    const int64_t n = load_n(d_n, ncap);
+    const int64_t G = int64_t(1) << p;
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (n == 0) {
+        for (int64_t g = gid; g <= G; g += static_cast<int64_t>(gridDim.x) * blockDim.x) dir[g] = 0;
+        return;
+    }
+    for (int64_t i = gid; i < n; i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const T *row = cells + i * words;
+        const int64_t gi = p ? static_cast<int64_t>(head64<T>(row, words) >> (64 - p)) : 0;
+        const int64_t gp = i == 0 ? -1
+                                  : (p ? static_cast<int64_t>(head64<T>(row - words, words) >> (64 - p)) : 0);
+        for (int64_t g = gp + 1; g <= gi; ++g) dir[g] = static_cast<uint32_t>(i);
+        if (i == n - 1)
+            for (int64_t g = gi + 1; g <= G; ++g) dir[g] = static_cast<uint32_t>(n);
+        sfx[i] = (static_cast<uint64_t>(suffix_hash32<T>(row, words, s)) << 32) | static_cast<uint64_t>(i);
+    }
+}
+
+// One wave per query; lanes take bits k0 + lane for k0 = 0, 64, ...
+template <typename T>
+__global__ void __launch_bounds__(256) k_d1_query(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
+                                                  int words, int ell, const uint32_t *__restrict__ dir, int p,
+                                                  const T *__restrict__ queries, int64_t nq,
+                                                  uint32_t *__restrict__ count, uint32_t *__restrict__ self,
+                                                  T *__restrict__ mask) {
+    constexpr int B = Bits<T>::B;
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    const int64_t n = load_n(d_n, ncap);
+    (void)n;
+    for (int64_t qi = wid; qi < nq; qi += nw) {
+        const T *q = queries + qi * words;
+        const uint64_t qh = head64<T>(q, words);
+        uint32_t total = 0;
+        for (int k0 = 0; k0 < ell; k0 += 64) {
+            const int k = k0 + lane;
+            bool found = false;
+            if (k < ell) {
+                const uint64_t th = qh ^ (k < 64 ? (1ull << (63 - k)) : 0ull);
+                const int64_t g = p ? static_cast<int64_t>(th >> (64 - p)) : 0;
+                found = find_row<T>(cells, words, dir[g], dir[g + 1], q, k) >= 0;
+            }
+            const uint64_t m = ballot64(found);
+            total += static_cast<uint32_t>(__popcll(m));
+            if (mask) {
+                T *mrow = mask + qi * words;
+                if (B == 64) {
+                    if (lane == 0) mrow[k0 / 64] = static_cast<T>(__brevll(m));
+                } else {
+                    const int w = k0 / 32;
+                    if (lane == 0) mrow[w] = static_cast<T>(__brev(static_cast<uint32_t>(m)));
+                    if (lane == 1 && w + 1 < words) mrow[w + 1] = static_cast<T>(__brev(static_cast<uint32_t>(m >> 32)));
+                }
+            }
+        }
+        if (lane == 0) {
+            if (count) count[qi] = total;
+            if (self) {
+                const int64_t g = p ? static_cast<int64_t>(qh >> (64 - p)) : 0;
+                const int64_t id = find_row<T>(cells, words, dir[g], dir[g + 1], q, -1);
+                self[qi] = id >= 0 ? static_cast<uint32_t>(id) : 0xFFFFFFFFu;
+            }
+        }
+    }
+}
+
+struct DictMem {
+    uint32_t *dir;
+    uint64_t *sfx[2];
+    uint32_t *hist;
+    uint64_t *tile_sums;
+};
+
+DictMem carve_dict(void *base, int64_t ncap, const cg_dict_params &p, size_t *bytes) {
+    Carver c(base);
+    DictMem m{};
+    const int64_t n = ncap > 0 ? ncap : 1;
+    m.dir = c.take<uint32_t>((size_t(1) << p.dir_bits) + 1);
+    m.sfx[0] = c.take<uint64_t>(n);
+    m.sfx[1] = c.take<uint64_t>(n);
+    m.hist = c.take<uint32_t>(radix_hist_entries(n));
+    int64_t ts = scan_tiles(n), ts2 = scan_tiles(radix_hist_entries(n));
+    m.tile_sums = c.take<uint64_t>(std::max(ts, ts2));
+    *bytes = c.bytes();
+    return m;
+}
+
+int ceil_log2(int64_t x) {
+    int b = 0;
+    while ((int64_t(1) << b) < x) ++b;
+    return b;
+}
+
+}  // namespace
+
+cg_dict_params resolve_params(int64_t ncap, cg_layout lay, const cg_dict_params *in) {
+    cg_dict_params p;
+    cg_dict_params_default(&p);
+    if (in) p = *in;
+    const int lg = ceil_log2(ncap > 2 ? ncap : 2);
+    if (p.dir_bits < 0) p.dir_bits = std::max(1, std::min(lg, 22));
+    if (p.dir_bits > lay.ell) p.dir_bits = lay.ell;
+    if (p.split_bit < 0) {
+        int s = ((lg + 16 + 31) / 32) * 32;
+        p.split_bit = std::min(s, lay.ell);
+    }
+    if (p.group_max < 0) p.group_max = 64;
+    return p;
+}
+
+size_t dict_mem_bytes(int64_t ncap, cg_layout, const cg_dict_params &p) {
+    size_t b;
+    carve_dict(nullptr, ncap, p, &b);
+    return b;
+}
+
+template <typename T> static cg_status dict_build_impl(cg_dict &d, hipStream_t s) {
+    size_t b;
+    DictMem m = carve_dict(d.mem, d.ncells_cap, d.params, &b);
+    const int64_t ncap = d.ncells_cap;
+    const int64_t G = int64_t(1) << d.params.dir_bits;
+    const int64_t items = std::max<int64_t>(ncap, G + 1);
+    hipLaunchKernelGGL((k_dict_scan<T>), dim3(blocks_for(items, 256, 16384)), dim3(256), 0, s,
+                       static_cast<const T *>(d.cells), d.d_ncells, ncap, d.lay.words, d.params.dir_bits,
+                       d.params.split_bit, m.dir, m.sfx[0]);
+    CG_LAUNCHED("dict_scan");
+    int which = 0;
+    if (ncap > 0)
+        CG_TRY(radix_sort_u64(m.sfx, nullptr, ncap, d.d_ncells, 32, 64, m.hist, m.tile_sums, &which, s));
+    d.dir = m.dir;
+    d.sfx = m.sfx[which];
+    return CG_OK;
+}
+
+cg_status run_dict_build(cg_dict &d, hipStream_t s) {
+    if (d.lay.word_bits == 64) return dict_build_impl<uint64_t>(d, s);
+    return dict_build_impl<uint32_t>(d, s);
+}
+
+template <typename T>
+static cg_status d1_impl(const cg_dict &d, const void *q, int64_t nq, uint32_t *count, uint32_t *self, void *mask,
+                         hipStream_t s) {
+    if (nq == 0) return CG_OK;
+    hipLaunchKernelGGL((k_d1_query<T>), dim3(blocks_for(nq, 4, 65536)), dim3(256), 0, s,
+                       static_cast<const T *>(d.cells), d.d_ncells, d.ncells_cap, d.lay.words, d.lay.ell, d.dir,
+                       d.params.dir_bits, static_cast<const T *>(q), nq, count, self, static_cast<T *>(mask));
+    CG_LAUNCHED("d1_query");
+    return CG_OK;
+}
+
+cg_status run_neighbors_d1(const cg_dict &d, const void *q, int64_t nq, uint32_t *count, uint32_t *self,
+                           void *mask, hipStream_t s) {
+    if (d.lay.word_bits == 64) return d1_impl<uint64_t>(d, q, nq, count, self, mask, s);
+    return d1_impl<uint32_t>(d, q, nq, count, self, mask, s);
+}
+
+}  // namespace cg

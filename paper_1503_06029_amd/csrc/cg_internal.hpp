@@ -1,0 +1,276 @@
+// Internal declarations and device helpers of the cell-graph library.
+// Wave64 (CDNA) throughout: every wave-level helper assumes 64 lanes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/cellgraph.h"
+
+namespace cg {
+
+// ------------------------------------------------------------------ errors
+
+// Records an error for cg_last_error() and returns st.
+cg_status set_error(cg_status st, const char *fmt, ...);
+// Checks hipGetLastError() after a launch; returns CG_OK or CG_EHIP.
+cg_status check_launch(const char *what);
+
+#define CG_TRY(expr)                        \
+    do {                                    \
+        cg_status _st = (expr);             \
+        if (_st != CG_OK) return _st;       \
+    } while (0)
+
+#define CG_LAUNCHED(what) CG_TRY(::cg::check_launch(what))
+
+// --------------------------------------------------------- workspace carving
+
+// Bump allocator over a caller-provided buffer; with base == nullptr it only
+// measures.  Every carve is 256-byte aligned.
+struct Carver {
+    char *base;
+    size_t used;
+    explicit Carver(void *b) : base(static_cast<char *>(b)), used(0) {}
+    template <typename T> T *take(size_t count) {
+        size_t off = (used + 255) & ~size_t(255);
+        used = off + count * sizeof(T);
+        return base ? reinterpret_cast<T *>(base + off) : nullptr;
+    }
+    size_t bytes() const { return (used + 255) & ~size_t(255); }
+};
+
+// ------------------------------------------------------------- lane helpers
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint32_t shfl_up_u32(uint32_t x, int d) {
+    return static_cast<uint32_t>(__shfl_up(static_cast<int>(x), d, 64));
+}
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t x, int d) {
+    uint32_t lo = shfl_up_u32(static_cast<uint32_t>(x), d);
+    uint32_t hi = shfl_up_u32(static_cast<uint32_t>(x >> 32), d);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src) {
+    uint32_t lo = static_cast<uint32_t>(__shfl(static_cast<int>(static_cast<uint32_t>(x)), src, 64));
+    uint32_t hi = static_cast<uint32_t>(__shfl(static_cast<int>(static_cast<uint32_t>(x >> 32)), src, 64));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
+    int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t y = shfl_up_u64(x, d);
+        if (l >= d) x += y;
+    }
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+    int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t y = shfl_up_u32(x, d);
+        if (l >= d) x += y;
+    }
+    return x;
+}
+
+// Exclusive prefix sum over a 256-thread block (4 waves); returns the
+// exclusive value and writes the block total to *total.  `tmp` must hold 4
+// entries of LDS.  Contains __syncthreads().
+__device__ __forceinline__ uint64_t block256_excl_scan_u64(uint64_t x, uint64_t *tmp, uint64_t *total) {
+    int t = threadIdx.x, w = t >> 6, l = t & 63;
+    uint64_t inc = wave_incl_scan_u64(x);
+    if (l == 63) tmp[w] = inc;
+    __syncthreads();
+    uint64_t pre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        uint64_t v = tmp[i];
+        if (i < w) pre += v;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc - x;
+}
+
+// -------------------------------------------------------------- row helpers
+
+template <typename T> struct Bits;
+template <> struct Bits<uint32_t> { static constexpr int B = 32; };
+template <> struct Bits<uint64_t> { static constexpr int B = 64; };
+
+// Mask with only vector position k set inside its word (MSB-first layout).
+template <typename T> __device__ __forceinline__ T bitmask_of(int k) {
+    return T(1) << (Bits<T>::B - 1 - (k % Bits<T>::B));
+}
+
+template <typename T> __device__ __forceinline__ int get_bit(const T *row, int k) {
+    return static_cast<int>((row[k / Bits<T>::B] >> (Bits<T>::B - 1 - (k % Bits<T>::B))) & T(1));
+}
+
+// First 64 vector bits of a row as an unsigned integer, x(0) most significant.
+template <typename T> __device__ __forceinline__ uint64_t head64(const T *row, int words);
+template <> __device__ __forceinline__ uint64_t head64<uint64_t>(const uint64_t *row, int) { return row[0]; }
+template <> __device__ __forceinline__ uint64_t head64<uint32_t>(const uint32_t *row, int words) {
+    uint64_t hi = row[0];
+    uint64_t lo = words > 1 ? row[1] : 0u;
+    return (hi << 32) | lo;
+}
+
+template <typename T> __device__ __forceinline__ int popc(T x);
+template <> __device__ __forceinline__ int popc<uint32_t>(uint32_t x) { return __popc(x); }
+template <> __device__ __forceinline__ int popc<uint64_t>(uint64_t x) { return __popcll(x); }
+
+template <typename T> __device__ __forceinline__ int clz_t(T x);
+template <> __device__ __forceinline__ int clz_t<uint32_t>(uint32_t x) { return __clz(x); }
+template <> __device__ __forceinline__ int clz_t<uint64_t>(uint64_t x) { return __clzll(x); }
+
+// Three-way lexicographic compare of two rows from word `from` on.
+template <typename T>
+__device__ __forceinline__ int row_cmp(const T *a, const T *b, int words, int from = 0) {
+    for (int w = from; w < words; ++w) {
+        T x = a[w], y = b[w];
+        if (x != y) return x < y ? -1 : 1;
+    }
+    return 0;
+}
+
+// Compare cell row `c` with (q xor e_k), k < 0 meaning q itself.
+template <typename T>
+__device__ __forceinline__ int row_cmp_flip(const T *c, const T *q, int words, int kw, T km) {
+    for (int w = 0; w < words; ++w) {
+        T y = q[w] ^ (w == kw ? km : T(0));
+        T x = c[w];
+        if (x != y) return x < y ? -1 : 1;
+    }
+    return 0;
+}
+
+// Hamming distance of two rows, stopping once it reaches 2.  On distance 1,
+// *pos receives the differing position.
+template <typename T>
+__device__ __forceinline__ int dist_upto2(const T *a, const T *b, int words, int *pos) {
+    int d = 0;
+    for (int w = 0; w < words; ++w) {
+        T x = a[w] ^ b[w];
+        if (x) {
+            d += popc<T>(x);
+            if (d >= 2) return 2;
+            *pos = w * Bits<T>::B + clz_t<T>(x);
+        }
+    }
+    return d;
+}
+
+// Index of the cell equal to (q xor e_k) within the sorted rows [lo, hi), or
+// -1.  k < 0 looks up q itself.
+template <typename T>
+__device__ __forceinline__ int64_t find_row(const T *cells, int words, int64_t lo, int64_t hi,
+                                            const T *q, int k) {
+    int kw = k >= 0 ? k / Bits<T>::B : -1;
+    T km = k >= 0 ? bitmask_of<T>(k) : T(0);
+    const int64_t end = hi;
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (row_cmp_flip<T>(cells + mid * words, q, words, kw, km) < 0) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < end && row_cmp_flip<T>(cells + lo * words, q, words, kw, km) == 0) return lo;
+    return -1;
+}
+
+// 64-bit finaliser (the MurmurHash3 fmix64 mixing function).
+__device__ __forceinline__ uint64_t fmix64(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return x;
+}
+
+__device__ __forceinline__ int64_t load_n(const int64_t *d_n, int64_t cap) {
+    if (!d_n) return cap;
+    int64_t n = *d_n;
+    return n < cap ? (n < 0 ? 0 : n) : cap;
+}
+
+// -------------------------------------------------------- host-side helpers
+
+inline unsigned blocks_for(int64_t items, int64_t per_block, int64_t max_blocks = 1 << 30) {
+    int64_t b = (items + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return static_cast<unsigned>(b);
+}
+
+// ------------------------------------------------- primitives (cg_prims.hip)
+
+// Device-wide exclusive scan.  Each primitive reads a per-item 32-bit value,
+// writes the exclusive prefix to out[i] (i < n) and the total to *total (if
+// non-null).  n = min(*d_n, n_cap) (d_n may be null).  tile_sums must hold
+// scan_tiles(n_cap) entries.
+int64_t scan_tiles(int64_t n_cap);
+cg_status scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n_cap, const int64_t *d_n,
+                          uint64_t *tile_sums, uint32_t *total, hipStream_t s);
+cg_status scan_u8_to_u32(const uint8_t *in, uint32_t *out, int64_t n_cap, const int64_t *d_n,
+                         uint64_t *tile_sums, int64_t *total, hipStream_t s);
+// out[i] = sum_{j<i} (a[j] + b[j]) as int64; out[n] and *total = the sum.
+cg_status scan_pair_to_i64(const uint32_t *a, const uint32_t *b, int64_t *out, int64_t n_cap,
+                           const int64_t *d_n, uint64_t *tile_sums, int64_t *total, hipStream_t s);
+// Same for popcounts of `words` words per row (T-sized words).
+cg_status scan_rowpop_to_i64(const void *rows, int word_bits, int words, int64_t *out, int64_t n_cap,
+                             const int64_t *d_n, uint64_t *tile_sums, int64_t *total, hipStream_t s);
+
+// LSD radix sort of 64-bit keys (with optional 32-bit values) by key bits
+// [bit_lo, bit_hi), 8 bits per pass, stable.  The sorted data ends in
+// keys[res] / vals[res], res returned in *which (0 or 1).  keys[1]/vals[1]
+// are scratch of the same size.  hist needs radix_hist_entries(n_cap).
+int64_t radix_hist_entries(int64_t n_cap);
+cg_status radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], int64_t n_cap, const int64_t *d_n,
+                         int bit_lo, int bit_hi, uint32_t *hist, uint64_t *tile_sums, int *which,
+                         hipStream_t s);
+
+// Fill kernel (graph-capture safe replacement for hipMemsetAsync).
+cg_status fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+cg_status fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
+
+// ------------------------------------------------------------ path pieces
+
+cg_status launch_pack(const uint8_t *bits, int64_t n, int64_t row_stride, cg_layout lay, void *out,
+                      hipStream_t s);
+
+size_t dedup_workspace_bytes(int64_t n, cg_layout lay);
+cg_status run_dedup(const void *rows, int64_t n, cg_layout lay, void *cells, uint32_t *row_to_cell,
+                    int64_t *d_ncells, void *ws, size_t ws_bytes, hipStream_t s);
+
+size_t dict_mem_bytes(int64_t ncap, cg_layout lay, const cg_dict_params &p);
+cg_dict_params resolve_params(int64_t ncap, cg_layout lay, const cg_dict_params *p);
+cg_status run_dict_build(cg_dict &d, hipStream_t s);
+
+cg_status run_neighbors_d1(const cg_dict &d, const void *q, int64_t nq, uint32_t *count, uint32_t *self,
+                           void *mask, hipStream_t s);
+
+size_t edges_workspace_bytes(const cg_dict &d, int64_t cap);
+cg_status run_edges(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap, int64_t *d_nedges,
+                    int64_t *d_offsets, void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s);
+
+size_t allpairs_workspace_bytes(const cg_dict &d, int64_t cap);
+cg_status run_edges_allpairs(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap,
+                             int64_t *d_nedges, int64_t *d_offsets, void *ws, size_t ws_bytes,
+                             int32_t *d_status, hipStream_t s);
+
+}  // namespace cg

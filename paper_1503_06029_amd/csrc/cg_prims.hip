@@ -1,0 +1,329 @@
+// Device-wide primitives: exclusive scans, LSD radix sort, fills.
+//
+// Scans are three-phase (tile reduce -> one-block scan of tile sums -> tile
+// rescan), deterministic and free of inter-block waiting.  The radix sort is
+// the classic per-pass histogram / scan / stable scatter; each scatter stages
+// its tile in LDS, sorted by digit, so global writes go out in contiguous runs.
+#include "cg_internal.hpp"
+
+namespace cg {
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;  // 4096
+
+struct U32Arr {
+    const uint32_t *p;
+    __device__ uint32_t operator()(int64_t i) const { return p[i]; }
+};
+struct U8Arr {
+    const uint8_t *p;
+    __device__ uint32_t operator()(int64_t i) const { return p[i]; }
+};
+struct PairSum {
+    const uint32_t *a, *b;
+    __device__ uint32_t operator()(int64_t i) const { return a[i] + b[i]; }
+};
+template <typename T> struct RowPop {
+    const T *rows;
+    int words;
+    __device__ uint32_t operator()(int64_t i) const {
+        uint32_t c = 0;
+        const T *r = rows + i * words;
+        for (int w = 0; w < words; ++w) c += popc<T>(r[w]);
+        return c;
+    }
+};
+
+template <class F>
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(F f, int64_t n_cap, const int64_t *d_n,
+                                                              uint64_t *tile_sums) {
+    __shared__ uint64_t tmp[4];
+    const int64_t n = load_n(d_n, n_cap);
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE;
+    uint64_t acc = 0;
+    if (base < n) {
+#pragma unroll 4
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            int64_t i = base + j * SCAN_THREADS + threadIdx.x;
+            if (i < n) acc += f(i);
+        }
+    }
+    uint64_t total;
+    block256_excl_scan_u64(acc, tmp, &total);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// One block: exclusive scan of the tile sums in place; total to the outputs.
+template <typename TO>
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_tiles(uint64_t *tile_sums, int64_t n_cap,
+                                                             const int64_t *d_n, TO *out_end,
+                                                             int64_t *total_i64, uint32_t *total_u32) {
+    __shared__ uint64_t tmp[4];
+    const int64_t n = load_n(d_n, n_cap);
+    const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    uint64_t carry = 0;
+    for (int64_t c = 0; c < tiles; c += SCAN_THREADS) {
+        int64_t i = c + threadIdx.x;
+        uint64_t v = i < tiles ? tile_sums[i] : 0;
+        uint64_t tot;
+        uint64_t ex = block256_excl_scan_u64(v, tmp, &tot);
+        if (i < tiles) tile_sums[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        if (out_end) out_end[n] = static_cast<TO>(carry);
+        if (total_i64) *total_i64 = static_cast<int64_t>(carry);
+        if (total_u32) *total_u32 = static_cast<uint32_t>(carry);
+    }
+}
+
+template <class F, typename TO>
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(F f, TO *out, int64_t n_cap, const int64_t *d_n,
+                                                            const uint64_t *tile_sums) {
+    __shared__ uint64_t vals[SCAN_TILE];
+    __shared__ uint64_t tmp[4];
+    const int64_t n = load_n(d_n, n_cap);
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE;
+    if (base >= n) return;
+    const int t = threadIdx.x;
+#pragma unroll 4
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j * SCAN_THREADS + t;
+        vals[j * SCAN_THREADS + t] = i < n ? f(i) : 0;
+    }
+    __syncthreads();
+    uint64_t local[SCAN_ITEMS];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        local[j] = vals[t * SCAN_ITEMS + j];
+        sum += local[j];
+    }
+    uint64_t tot;
+    uint64_t ex = block256_excl_scan_u64(sum, tmp, &tot) + tile_sums[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        vals[t * SCAN_ITEMS + j] = ex;
+        ex += local[j];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j * SCAN_THREADS + t;
+        if (i < n) out[i] = static_cast<TO>(vals[j * SCAN_THREADS + t]);
+    }
+}
+
+template <class F, typename TO>
+cg_status scan_generic(F f, TO *out, int64_t n_cap, const int64_t *d_n, uint64_t *tile_sums, TO *out_end,
+                       int64_t *total_i64, uint32_t *total_u32, hipStream_t s) {
+    unsigned tiles = blocks_for(n_cap, SCAN_TILE);
+    hipLaunchKernelGGL((k_scan_reduce<F>), dim3(tiles), dim3(SCAN_THREADS), 0, s, f, n_cap, d_n, tile_sums);
+    CG_LAUNCHED("scan_reduce");
+    hipLaunchKernelGGL((k_scan_tiles<TO>), dim3(1), dim3(SCAN_THREADS), 0, s, tile_sums, n_cap, d_n, out_end,
+                       total_i64, total_u32);
+    CG_LAUNCHED("scan_tiles");
+    hipLaunchKernelGGL((k_scan_down<F, TO>), dim3(tiles), dim3(SCAN_THREADS), 0, s, f, out, n_cap, d_n,
+                       tile_sums);
+    CG_LAUNCHED("scan_down");
+    return CG_OK;
+}
+
+// ------------------------------------------------------------------ radix
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_ITEMS = 8;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // 2048
+constexpr int RADIX = 256;
+
+__global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint64_t *keys, int64_t n_cap, const int64_t *d_n,
+                                                           int shift, uint32_t *hist, int num_tiles) {
+    __shared__ uint32_t h[RADIX];
+    const int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const int64_t n = load_n(d_n, n_cap);
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * RS_TILE;
+    if (base < n) {
+        for (int j = 0; j < RS_ITEMS; ++j) {
+            int64_t i = base + j * RS_THREADS + t;
+            if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
+        }
+    }
+    __syncthreads();
+    hist[static_cast<int64_t>(t) * num_tiles + blockIdx.x] = h[t];
+}
+
+template <bool HAS_VALS>
+__global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *kin, const uint32_t *vin,
+                                                              uint64_t *kout, uint32_t *vout, int64_t n_cap,
+                                                              const int64_t *d_n, int shift,
+                                                              const uint32_t *hist_off, int num_tiles) {
+    __shared__ uint32_t wcnt[RS_WAVES][RADIX];
+    __shared__ uint32_t tile_start[RADIX];
+    __shared__ uint32_t gbase[RADIX];
+    __shared__ uint64_t sk[RS_TILE];
+    __shared__ uint32_t sv[HAS_VALS ? RS_TILE : 1];
+    __shared__ uint64_t tmp[4];
+
+    const int64_t n = load_n(d_n, n_cap);
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * RS_TILE;
+    if (base >= n) return;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int tile_n = static_cast<int>(n - base < RS_TILE ? n - base : RS_TILE);
+
+    for (int i = t; i < RS_WAVES * RADIX; i += RS_THREADS) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+
+    uint64_t key[RS_ITEMS];
+    uint32_t val[RS_ITEMS];
+    uint32_t rank[RS_ITEMS];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        // wave w owns the contiguous sub-tile [w * 64 * ITEMS, (w + 1) * 64 * ITEMS)
+        int li = (w * RS_ITEMS + j) * 64 + lane;
+        bool valid = li < tile_n;
+        key[j] = valid ? kin[base + li] : 0;
+        if (HAS_VALS) val[j] = valid ? vin[base + li] : 0;
+        int d = static_cast<int>((key[j] >> shift) & (RADIX - 1));
+        uint64_t m = ballot64(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t bb = ballot64((d >> b) & 1);
+            m &= ((d >> b) & 1) ? bb : ~bb;
+        }
+        uint32_t before = 0;
+        if (valid) before = wcnt[w][d];
+        __builtin_amdgcn_wave_barrier();
+        if (valid) {
+            rank[j] = before + static_cast<uint32_t>(__popcll(m & lt));
+            if ((m & lt) == 0) wcnt[w][d] = before + static_cast<uint32_t>(__popcll(m));
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // thread t owns digit t: wave prefix, tile count, tile-local start
+    {
+        uint32_t c[RS_WAVES], run = 0;
+#pragma unroll
+        for (int i = 0; i < RS_WAVES; ++i) {
+            c[i] = wcnt[i][t];
+            wcnt[i][t] = run;
+            run += c[i];
+        }
+        uint64_t tot;
+        uint64_t ex = block256_excl_scan_u64(run, tmp, &tot);
+        tile_start[t] = static_cast<uint32_t>(ex);
+        gbase[t] = hist_off[static_cast<int64_t>(t) * num_tiles + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        int li = (w * RS_ITEMS + j) * 64 + lane;
+        if (li < tile_n) {
+            int d = static_cast<int>((key[j] >> shift) & (RADIX - 1));
+            uint32_t p = tile_start[d] + wcnt[w][d] + rank[j];
+            sk[p] = key[j];
+            if (HAS_VALS) sv[p] = val[j];
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < tile_n; i += RS_THREADS) {
+        uint64_t k = sk[i];
+        int d = static_cast<int>((k >> shift) & (RADIX - 1));
+        int64_t g = static_cast<int64_t>(gbase[d]) + (i - static_cast<int>(tile_start[d]));
+        kout[g] = k;
+        if (HAS_VALS) vout[g] = sv[i];
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_i64(int64_t *p, int64_t v, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace
+
+int64_t scan_tiles(int64_t n_cap) { return (n_cap + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+cg_status scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n_cap, const int64_t *d_n,
+                          uint64_t *tile_sums, uint32_t *total, hipStream_t s) {
+    return scan_generic(U32Arr{in}, out, n_cap, d_n, tile_sums, static_cast<uint32_t *>(nullptr), nullptr,
+                        total, s);
+}
+
+cg_status scan_u8_to_u32(const uint8_t *in, uint32_t *out, int64_t n_cap, const int64_t *d_n,
+                         uint64_t *tile_sums, int64_t *total, hipStream_t s) {
+    return scan_generic(U8Arr{in}, out, n_cap, d_n, tile_sums, static_cast<uint32_t *>(nullptr), total,
+                        nullptr, s);
+}
+
+cg_status scan_pair_to_i64(const uint32_t *a, const uint32_t *b, int64_t *out, int64_t n_cap,
+                           const int64_t *d_n, uint64_t *tile_sums, int64_t *total, hipStream_t s) {
+    return scan_generic(PairSum{a, b}, out, n_cap, d_n, tile_sums, out, total, nullptr, s);
+}
+
+cg_status scan_rowpop_to_i64(const void *rows, int word_bits, int words, int64_t *out, int64_t n_cap,
+                             const int64_t *d_n, uint64_t *tile_sums, int64_t *total, hipStream_t s) {
+    if (word_bits == 64)
+        return scan_generic(RowPop<uint64_t>{static_cast<const uint64_t *>(rows), words}, out, n_cap, d_n,
+                            tile_sums, out, total, nullptr, s);
+    return scan_generic(RowPop<uint32_t>{static_cast<const uint32_t *>(rows), words}, out, n_cap, d_n,
+                        tile_sums, out, total, nullptr, s);
+}
+
+int64_t radix_hist_entries(int64_t n_cap) {
+    return static_cast<int64_t>(RADIX) * blocks_for(n_cap, RS_TILE);
+}
+
+cg_status radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], int64_t n_cap, const int64_t *d_n, int bit_lo,
+                         int bit_hi, uint32_t *hist, uint64_t *tile_sums, int *which, hipStream_t s) {
+    const int num_tiles = static_cast<int>(blocks_for(n_cap, RS_TILE));
+    const int64_t hist_n = static_cast<int64_t>(RADIX) * num_tiles;
+    int cur = 0;
+    for (int shift = bit_lo; shift < bit_hi; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(num_tiles), dim3(RS_THREADS), 0, s, keys[cur], n_cap, d_n, shift,
+                           hist, num_tiles);
+        CG_LAUNCHED("radix_hist");
+        CG_TRY(scan_u32_to_u32(hist, hist, hist_n, nullptr, tile_sums, nullptr, s));
+        if (vals) {
+            hipLaunchKernelGGL((k_radix_scatter<true>), dim3(num_tiles), dim3(RS_THREADS), 0, s, keys[cur],
+                               vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_cap, d_n, shift, hist, num_tiles);
+        } else {
+            hipLaunchKernelGGL((k_radix_scatter<false>), dim3(num_tiles), dim3(RS_THREADS), 0, s, keys[cur],
+                               static_cast<const uint32_t *>(nullptr), keys[cur ^ 1], static_cast<uint32_t *>(nullptr),
+                               n_cap, d_n, shift, hist, num_tiles);
+        }
+        CG_LAUNCHED("radix_scatter");
+        cur ^= 1;
+    }
+    *which = cur;
+    return CG_OK;
+}
+
+cg_status fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return CG_OK;
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, p, v, n);
+    CG_LAUNCHED("fill_u32");
+    return CG_OK;
+}
+
+cg_status fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return CG_OK;
+    hipLaunchKernelGGL(k_fill_i64, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, p, v, n);
+    CG_LAUNCHED("fill_i64");
+    return CG_OK;
+}
+
+}  // namespace cg

@@ -1,0 +1,355 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer work throughout, so every comparison is bit-exact: packed words,
+sorted cells, row_to_cell, cell and edge counts, edge arrays, differing
+positions, offsets and distance-1 query masks.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_06029_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_1503_06029_amd import binding, pipeline
+    return torch, binding, pipeline
+
+
+def oracle_graph(R, ell, wb, packed=False):
+    rows = R if packed else oracle.pack(R, wb)
+    cells, r2c = oracle.dedup(rows, ell, wb)
+    uv, bit, off = oracle.edges(cells, wb)
+    return rows, cells, r2c, uv, bit, off
+
+
+def assert_same(res, ref, check_r2c=True):
+    rows, cells, r2c, uv, bit, off = ref
+    assert res["ncells"] == cells.shape[0]
+    assert np.array_equal(res["cells"], cells)
+    if check_r2c:
+        assert np.array_equal(res["row_to_cell"], r2c)
+    assert res["nedges"] == len(uv)
+    assert res["status"] == 0
+    assert np.array_equal(res["uv"], uv)
+    assert np.array_equal(res["bit"], bit)
+    assert np.array_equal(res["offsets"], off)
+
+
+# ------------------------------------------------------------------- pack
+
+@pytest.mark.parametrize("ell", [1, 5, 16, 31, 32, 33, 63, 64, 65, 100, 128, 257, 1024])
+@pytest.mark.parametrize("wb", [32, 64])
+def test_pack_parity(gpu, ell, wb):
+    torch, B, P = gpu
+    say("pack", ell, wb)
+    rng = np.random.default_rng(ell * 3 + wb)
+    n = 1000
+    for stride in (ell, ell + 7, ((ell + 15) // 16) * 16 + 16):
+        host = rng.integers(0, 3, (n, stride)).astype(np.uint8)   # values 0/1/2: nonzero is 1
+        R = host[:, :ell]
+        want = oracle.pack(R, wb)
+        bits = torch.from_numpy(host).cuda()
+        lay = B.make_layout(ell, wb)
+        out = torch.full((n, lay.words), -1, dtype=B.word_dtype(wb), device="cuda")
+        B.cg_pack(bits, n, stride, lay, out)
+        got = out.cpu().numpy().view(want.dtype)
+        assert np.array_equal(got, want), (ell, wb, stride)
+
+
+# ---------------------------------------------------------- dedup + edges
+
+CASES = [
+    # (name, ell, n_bases, fam, dups)
+    ("tiny", 3, 4, 2, 5),
+    ("l16", 16, 200, 4, 100),
+    ("l32", 32, 300, 3, 200),
+    ("l63", 63, 300, 6, 100),
+    ("l64", 64, 300, 6, 100),
+    ("l65", 65, 300, 6, 100),
+    ("l100", 100, 500, 8, 400),
+    ("l128", 128, 700, 10, 700),
+    ("l300", 300, 400, 12, 300),
+    ("l1024", 1024, 300, 15, 500),
+]
+
+
+@pytest.mark.parametrize("name,ell,nb,fam,dups", CASES)
+@pytest.mark.parametrize("wb", [32, 64])
+def test_path_parity_clustered(gpu, name, ell, nb, fam, dups, wb):
+    torch, B, P = gpu
+    rng = np.random.default_rng(abs(hash((name, wb))) % (2 ** 32))
+    R = inputs.clustered_multiset(rng, nb, ell, fam, dups)
+    say("clustered", name, wb, R.shape)
+    ref = oracle_graph(R, ell, wb)
+    res = P.cell_graph(R, ell, wb)
+    assert_same(res, ref)
+
+
+@pytest.mark.parametrize("ell", [7, 20, 40, 70, 200])
+def test_dedup_heavy_duplicates(gpu, ell):
+    # few distinct rows, many copies: long equal-key segments (the block path)
+    torch, B, P = gpu
+    rng = np.random.default_rng(ell)
+    R = inputs.random_multiset(rng, 20000, ell, n_distinct=12)
+    say("heavy-dups", ell)
+    for wb in (32, 64):
+        ref = oracle_graph(R, ell, wb)
+        assert_same(P.cell_graph(R, ell, wb), ref)
+
+
+def test_dedup_long_shared_prefix(gpu):
+    # all rows share their first 64+ bits: one big segment sorted by the tail
+    torch, B, P = gpu
+    rng = np.random.default_rng(7)
+    ell = 200
+    R = inputs.clustered_multiset(rng, 300, ell, 4, 300)
+    R[:, :120] = 1
+    say("shared-prefix", R.shape)
+    for wb in (32, 64):
+        assert_same(P.cell_graph(R, ell, wb), oracle_graph(R, ell, wb))
+
+
+@pytest.mark.parametrize("wb", [32, 64])
+def test_edge_cases(gpu, wb):
+    torch, B, P = gpu
+    say("edge cases", wb)
+    # empty input
+    R = np.zeros((0, 10), dtype=np.uint8)
+    res = P.cell_graph(R, 10, wb)
+    assert res["ncells"] == 0 and res["nedges"] == 0 and res["offsets"].tolist() == [0]
+    # one row; l = 1
+    for R, ell in ((np.ones((1, 1), np.uint8), 1), (np.array([[0], [1], [1], [0]], np.uint8), 1),
+                   (np.ones((50, 33), np.uint8), 33)):
+        assert_same(P.cell_graph(R, ell, wb), oracle_graph(R, ell, wb))
+    # full hypercube l = 9 and Figure 1
+    n = 2 ** 9
+    R = ((np.arange(n)[:, None] >> np.arange(8, -1, -1)[None, :]) & 1).astype(np.uint8)
+    R = R[np.random.default_rng(1).permutation(n)]
+    res = P.cell_graph(R, 9, wb)
+    assert res["nedges"] == 9 * 2 ** 8
+    assert_same(res, oracle_graph(R, 9, wb))
+    R = np.array([[1, 1, 1], [1, 1, 0], [1, 0, 0], [1, 0, 1]], np.uint8)
+    res = P.cell_graph(R, 3, wb)
+    assert res["uv"].tolist() == [[0, 1], [0, 2], [1, 3], [2, 3]] and res["bit"].tolist() == [2, 1, 1, 2]
+
+
+PARAMS = [
+    dict(),
+    dict(split_bit=0),
+    dict(split_bit=1, group_max=1),
+    dict(split_bit=7, dir_bits=3, group_max=2),
+    dict(split_bit=-1, dir_bits=0, group_max=1024),
+    dict(path=1, n_refs=0),
+    dict(path=1, n_refs=1),
+    dict(path=1, n_refs=4),
+    dict(path=1, n_refs=8),
+]
+
+
+@pytest.mark.parametrize("pi", range(len(PARAMS)))
+@pytest.mark.parametrize("ell,wb", [(40, 32), (90, 64), (129, 32), (200, 64)])
+def test_parameters_do_not_change_bytes(gpu, pi, ell, wb):
+    torch, B, P = gpu
+    kw = dict(PARAMS[pi])
+    if kw.get("split_bit", -1) > ell:
+        kw["split_bit"] = ell
+    say("params", ell, wb, kw)
+    rng = np.random.default_rng(ell + pi)
+    R = inputs.clustered_multiset(rng, 250, ell, 6, 100)
+    ref = oracle_graph(R, ell, wb)
+    params = B.cg_dict_params_default(**kw)
+    assert_same(P.cell_graph(R, ell, wb, params=params), ref)
+
+
+def test_split_at_full_length(gpu):
+    torch, B, P = gpu
+    rng = np.random.default_rng(3)
+    for ell in (20, 64, 100):
+        R = inputs.clustered_multiset(rng, 100, ell, 5, 10)
+        say("split=l", ell)
+        params = B.cg_dict_params_default(split_bit=ell, group_max=3)
+        assert_same(P.cell_graph(R, ell, 64, params=params), oracle_graph(R, ell, 64))
+
+
+# ------------------------------------------------------- capacity overflow
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_capacity_overflow(gpu, path):
+    torch, B, P = gpu
+    say("capacity", path)
+    rng = np.random.default_rng(11)
+    ell, wb = 70, 64
+    R = inputs.clustered_multiset(rng, 100, ell, 5, 50)
+    ref = oracle_graph(R, ell, wb)
+    E = len(ref[3])
+    for cap in (0, 1, E - 1, E):
+        g = P.CellGraph(R.shape[0], ell, wb, B.cg_dict_params_default(path=path), edge_cap=cap)
+        sentinel = -7
+        g.uv.fill_(sentinel)
+        g.pack(torch.from_numpy(R).cuda())
+        g.run()
+        torch.cuda.synchronize()
+        assert int(g.nedges.item()) == E
+        assert int(g.status.item()) == (B.CG_ECAPACITY if cap < E else B.CG_OK)
+        uv = g.uv.cpu().numpy()
+        if cap < E:
+            assert (uv[cap:] == sentinel).all()  # nothing written at or past cap
+        else:
+            assert np.array_equal(uv[:E].view(np.uint32), ref[3])
+        # regrow and re-run edges only: exact
+        g.grow_edges(E)
+        g.edges()
+        torch.cuda.synchronize()
+        assert int(g.status.item()) == B.CG_OK
+        assert np.array_equal(g.uv[:E].cpu().numpy().view(np.uint32), ref[3])
+
+
+# ----------------------------------------------------- distance-1 queries
+
+@pytest.mark.parametrize("ell,wb", [(3, 32), (33, 32), (64, 64), (150, 64), (150, 32), (1024, 64)])
+def test_neighbors_d1_parity(gpu, ell, wb):
+    torch, B, P = gpu
+    say("d1 queries", ell, wb)
+    rng = np.random.default_rng(ell * wb)
+    R = inputs.clustered_multiset(rng, 200, ell, 6, 50)
+    res = P.cell_graph(R, ell, wb)
+    g = res["graph"]
+    cells = res["cells"]
+    # queries: the cells themselves, random vectors, and one-bit flips of cells
+    Qr = oracle.pack((rng.random((300, ell)) < 0.5).astype(np.uint8), wb)
+    Qf = oracle.pack(np.unpackbits(cells.astype(">u8" if wb == 64 else ">u4").view(np.uint8), axis=1)[:300, :ell]
+                     ^ np.eye(ell, dtype=np.uint8)[rng.integers(0, ell, min(300, len(cells)))], wb)
+    for Q in (cells, Qr, Qf):
+        want = oracle.d1_queries(cells, Q, wb)
+        got = g.neighbors_d1(P.to_device_words(Q))
+        for a, b in zip(got, want):
+            assert np.array_equal(a, b)
+    # and with a different directory width
+    for p in (0, 1, 5):
+        params = B.cg_dict_params_default(dir_bits=min(p, ell))
+        g2 = P.cell_graph(R, ell, wb, params=params)["graph"]
+        want = oracle.d1_queries(cells, Qr, wb)
+        for a, b in zip(g2.neighbors_d1(P.to_device_words(Qr)), want):
+            assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------ determinism
+
+def test_repeatable_bytes(gpu):
+    torch, B, P = gpu
+    say("repeat")
+    rng = np.random.default_rng(5)
+    R = inputs.clustered_multiset(rng, 3000, 256, 10, 3000)
+    g = P.CellGraph(R.shape[0], 256, 64)
+    bits = torch.from_numpy(R).cuda()
+    outs = []
+    for _ in range(3):
+        g.pack(bits)
+        g.run()
+        r = g.fetch()
+        outs.append((r["cells"].copy(), r["uv"].copy(), r["bit"].copy(), r["row_to_cell"].copy()))
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
+# -------------------------------------------------------- the workloads
+
+def test_config0(gpu):
+    torch, B, P = gpu
+    say("config0")
+    R = inputs.c0()
+    ref = oracle_graph(R, 32, 32)
+    assert_same(P.cell_graph(R, 32, 32), ref)
+    assert_same(P.cell_graph(R, 32, 64), oracle_graph(R, 32, 64))
+
+
+@pytest.mark.timeout(600)
+def test_config1(gpu):
+    torch, B, P = gpu
+    say("config1: generate")
+    R = inputs.c1()
+    say("config1: oracle")
+    ref = oracle_graph(R, 128, 32)
+    say("config1: gpu")
+    res = P.cell_graph(R, 128, 32)
+    assert_same(res, ref)
+    assert res["nedges"] <= 1_040_512
+
+
+@pytest.mark.timeout(600)
+def test_config2_full_size(gpu):
+    """Config 2 at its real size: dedup checked against the oracle in full,
+    edges by properties plus sampled oracle neighbour lists."""
+    torch, B, P = gpu
+    say("config2: generate")
+    rows = inputs.c2()
+    n = rows.shape[0]
+    want_cells, want_E = inputs.c2_expected()
+    say("config2: gpu")
+    res = P.cell_graph(rows, 1024, 64, packed=True)
+    cells, r2c, uv, bit, off = res["cells"], res["row_to_cell"], res["uv"], res["bit"], res["offsets"]
+    assert res["ncells"] == want_cells and res["nedges"] == want_E and res["status"] == 0
+    say("config2: properties")
+    # cells strictly increasing (lexicographic = unsigned word order), every row maps to an equal cell,
+    # and every cell is hit: so the cells are exactly the distinct rows, sorted
+    diff = cells[1:] != cells[:-1]
+    first = diff.argmax(axis=1)
+    idx = np.arange(len(first))
+    assert diff.any(axis=1).all()
+    assert (cells[1:][idx, first] > cells[:-1][idx, first]).all()
+    assert np.array_equal(cells[r2c], rows)
+    assert (np.bincount(r2c, minlength=want_cells) > 0).all()
+    # every edge is a distance-1 pair with u < v, differing exactly at bit
+    u = uv[:, 0].astype(np.int64)
+    v = uv[:, 1].astype(np.int64)
+    assert (u < v).all()
+    x = cells[u] ^ cells[v]
+    pc = np.unpackbits(x.view(np.uint8), axis=1).sum(axis=1)
+    assert (pc == 1).all()
+    w = bit.astype(np.int64) // 64
+    assert (x[np.arange(len(u)), w] == (np.uint64(1) << (63 - (bit.astype(np.uint64) % np.uint64(64))))).all()
+    # strictly ascending (u, v): no duplicates, canonical order
+    key = u * (1 << 32) + v
+    assert (np.diff(key) > 0).all()
+    assert off[-1] == want_E and np.array_equal(np.diff(off), np.bincount(u, minlength=want_cells))
+    say("config2: oracle dedup")
+    ocells, or2c = oracle.dedup(rows, 1024, 64)
+    assert np.array_equal(ocells, cells) and np.array_equal(or2c, r2c)
+    say("config2: sampled neighbour lists")
+    rng = np.random.default_rng(2)
+    sample = np.sort(rng.choice(want_cells, 300, replace=False))
+    nbrs, cnt = oracle.neighbors_of(cells, sample, 64)
+    allv = np.concatenate([uv, uv[:, ::-1]])
+    order = np.lexsort((allv[:, 1], allv[:, 0]))
+    allv = allv[order]
+    starts = np.searchsorted(allv[:, 0], sample)
+    ends = np.searchsorted(allv[:, 0], sample, side="right")
+    for s, a, b, nb in zip(sample, starts, ends, nbrs):
+        assert np.array_equal(np.sort(allv[a:b, 1]), nb)
+    assert n == rows.shape[0]
+
+
+@pytest.mark.parametrize("i", [0, 1, 2, 3, 5, 8, 13])
+def test_config3_scenes(gpu, i):
+    torch, B, P = gpu
+    ell, n = inputs.c3_scene_params(i)
+    if n > 60000:
+        pytest.skip("large scene: covered by the batched tests")
+    say("config3 scene", i, ell, n)
+    R = inputs.c3_scene(i)
+    wb = 32 if i % 2 else 64
+    assert_same(P.cell_graph(R, ell, wb), oracle_graph(R, ell, wb))
