@@ -6,9 +6,10 @@
 //    value = row index;
 // 2. LSD radix sort of (key, index) over the key bits that can be nonzero;
 // 3. rows with equal keys form segments; when l > 64 each segment of two or
-//    more rows is ordered by the full row: segments of up to `smax` rows by
-//    one wave each (rank sort in LDS), longer ones by one block each (bitonic
-//    network over an index array in global memory);
+//    more rows is ordered by the full row: segments of up to `smax` rows in
+//    the LDS of the block whose tile holds their first position (rank sort),
+//    longer ones by one block each (bitonic network over an index array in
+//    global memory);
 // 4. a row is a new cell iff it differs from its predecessor; a scan of those
 //    flags gives cell ids, and a gather writes the cells and row_to_cell.
 #include "cg_internal.hpp"
@@ -18,8 +19,7 @@ namespace cg {
 namespace {
 
 constexpr uint32_t SENT = 0xFFFFFFFFu;
-constexpr int SMALL_WAVES = 4;
-constexpr int SMALL_LDS_PER_WAVE = 16384;
+constexpr int64_t TILE_LDS = 53248;  // three blocks per CU
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_extract(const T *__restrict__ rows, int64_t n, int words,
@@ -50,70 +50,265 @@ __device__ __forceinline__ int64_t run_end(const uint64_t *keys, int64_t j, int6
     return bad;
 }
 
-__global__ void __launch_bounds__(256) k_heads(const uint64_t *__restrict__ keys, int64_t n, bool tiefix,
-                                               int smax, uint8_t *__restrict__ uniq, uint2 *small_list,
-                                               uint2 *large_list, uint32_t *counters) {
-    for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
-         j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const bool head = (j == 0) || keys[j] != keys[j - 1];
-        uniq[j] = head ? 1 : 0;
-        if (tiefix && head) {
-            const int64_t e = run_end(keys, j, n);
-            const int64_t len = e - j;
-            if (len >= 2) {
-                uint2 seg = make_uint2(static_cast<uint32_t>(j), static_cast<uint32_t>(len));
-                if (len <= smax) small_list[atomicAdd(&counters[0], 1u)] = seg;
-                else large_list[atomicAdd(&counters[1], 1u)] = seg;
+// l <= 64: the key is the whole row, so a row is a new cell iff its key
+// differs from its predecessor's.
+__global__ void __launch_bounds__(256) k_heads(const uint64_t *__restrict__ keys, int64_t n,
+                                               uint8_t *__restrict__ uniq) {
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j < n) uniq[j] = ((j == 0) || keys[j] != keys[j - 1]) ? 1 : 0;
+}
+
+// One block per tile of PT sorted positions (l > 64).  The tile owns the
+// segments (runs of equal keys) whose first position lies in it; a segment of
+// 2..smax rows may reach up to smax positions past the tile.  The rows of the
+// owned multi-row segments are gathered into LDS (slot = position - tile
+// start), every row computes its rank within its segment by comparing the
+// remaining words with all others (ties broken by position), and the sorted
+// row indices and first-of-equal-run flags are written back.  Singletons are
+// flagged unique; longer segments go to the large-segment list (rare, so one
+// atomic each is fine).
+constexpr int TT = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, const uint64_t *__restrict__ keys,
+                                                    int64_t n, int words, int from, int smax,
+                                                    uint32_t *__restrict__ vals, uint8_t *__restrict__ uniq,
+                                                    uint2 *__restrict__ large_list,
+                                                    unsigned long long *__restrict__ counters) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int LW = words + ((words & 1) ? 0 : 1);
+    const int slots = TT + smax;
+    // keys of positions b0 - 1 .. b0 + slots - 1 (index = position - b0 + 1)
+    uint64_t *skeys = reinterpret_cast<uint64_t *>(smem);
+    T *lrows = reinterpret_cast<T *>(skeys + slots + 1);
+    // with smax == 1 no segment is small and the row area is not allocated
+    int32_t *segof = reinterpret_cast<int32_t *>(lrows + (smax > 1 ? static_cast<size_t>(slots) * LW : 0));
+    int32_t *seglen = segof + slots;
+    uint32_t *sval = reinterpret_cast<uint32_t *>(seglen + slots);
+    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * TT;
+    const int t = threadIdx.x;
+    const int64_t wend = (b0 + slots < n) ? b0 + slots : n;  // window end (exclusive)
+    for (int e0 = t; e0 <= slots; e0 += TT * 4) {
+        uint64_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t pos = b0 - 1 + e0 + u * TT;
+            v[u] = (e0 + u * TT <= slots && pos >= 0 && pos < wend) ? keys[pos] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e0 + u * TT <= slots) skeys[e0 + u * TT] = v[u];
+    }
+    for (int r = t; r < slots; r += TT) segof[r] = -1;
+    __syncthreads();
+    const int64_t p = b0 + t;
+    if (p < n) {
+        const uint64_t k = skeys[t + 1];
+        const bool head = (p == 0) || k != skeys[t];
+        if (head) {
+            int64_t e = p + 1;
+            while (e < wend && skeys[e - b0 + 1] == k) ++e;
+            if (e == wend && e < n) e = run_end(keys, p, n);  // reaches past the window: long segment
+            const int64_t len = e - p;
+            if (len == 1) {
+                uniq[p] = 1;
+            } else if (len <= smax) {
+                for (int r = 0; r < len; ++r) {
+                    segof[t + r] = t;
+                    seglen[t + r] = static_cast<int32_t>(len);
+                }
+            } else {
+                const unsigned long long slot = atomicAdd(&counters[1], 1ull);
+                large_list[slot] = make_uint2(static_cast<uint32_t>(p), static_cast<uint32_t>(len));
             }
         }
+    }
+    __syncthreads();
+    for (int r0 = t; r0 < slots; r0 += TT * 4) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u * TT;
+            v[u] = (r < slots && segof[r] >= 0) ? vals[b0 + r] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u * TT;
+            if (r < slots && segof[r] >= 0) sval[r] = v[u];
+        }
+    }
+    __syncthreads();
+    constexpr int U = 16;
+    for (int e0 = t; e0 < slots * words; e0 += TT * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * TT;
+            const int r = e / words;
+            v[u] = (e < slots * words && segof[r] >= 0) ? rows[static_cast<int64_t>(sval[r]) * words + (e - r * words)]
+                                                        : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * TT;
+            const int r = e / words;
+            if (e < slots * words && segof[r] >= 0) lrows[r * LW + (e - r * words)] = v[u];
+        }
+    }
+    __syncthreads();
+    for (int r = t; r < slots; r += TT) {
+        const int a = segof[r];
+        if (a < 0) continue;
+        const int len = seglen[r];
+        const T *me = lrows + r * LW;
+        int rank = 0;
+        bool dup = false;
+        for (int j = a; j < a + len; ++j) {
+            if (j == r) continue;
+            const int c = row_cmp<T>(lrows + j * LW, me, words, from);
+            if (c < 0 || (c == 0 && j < r)) ++rank;
+            if (c == 0 && j < r) dup = true;
+        }
+        vals[b0 + a + rank] = sval[r];
+        uniq[b0 + a + rank] = dup ? 0 : 1;
     }
 }
 
-// One wave per segment of 2..smax rows: rank sort by the full row in LDS.
-template <typename T>
-__global__ void __launch_bounds__(256) k_tiefix_small(const T *__restrict__ rows, int words, int from,
-                                                      int lds_stride, int smax, const uint2 *__restrict__ list,
-                                                      const uint32_t *__restrict__ counters,
-                                                      uint32_t *__restrict__ vals, uint8_t *__restrict__ uniq) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    T *lds = reinterpret_cast<T *>(smem) + static_cast<size_t>(wave) * smax * lds_stride;
-    const uint32_t count = counters[0];
-    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
-    for (uint32_t s = blockIdx.x * (blockDim.x >> 6) + wave; s < count; s += nwaves) {
-        const uint2 seg = list[s];
-        const int64_t a = seg.x;
-        const int len = static_cast<int>(seg.y);
-        uint32_t myval = lane < len ? vals[a + lane] : 0u;
-        // cooperative copy of the segment's rows into LDS (all lanes take part
-        // in every shuffle; only in-range slots are stored)
-        const int total = len * words;
-        for (int i0 = 0; i0 < total; i0 += 64) {
-            const int i = i0 + lane;
-            const int r = i < total ? i / words : 0;
-            const uint32_t src = static_cast<uint32_t>(__shfl(static_cast<int>(myval), r, 64));
-            if (i < total) lds[r * lds_stride + (i - r * words)] = rows[static_cast<int64_t>(src) * words + (i - r * words)];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane < len) {
-            const T *me = lds + lane * lds_stride;
-            int rank = 0;
-            bool dup = false;
-            for (int j = 0; j < len; ++j) {
-                if (j == lane) continue;
-                const int c = row_cmp<T>(lds + j * lds_stride, me, words, from);
-                if (c < 0 || (c == 0 && j < lane)) ++rank;
-                if (c == 0 && j < lane) dup = true;
-            }
-            vals[a + rank] = myval;
-            uniq[a + rank] = dup ? 0 : 1;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Same, with rows zero-padded to WT words in LDS (WT a power of two fixed at
+// compile time): the copy and every comparison are straight-line code.
+template <typename T, int WT>
+__device__ __forceinline__ int lex_cmp_t(const T *a, const T *b) {
+    constexpr int FROM = 64 / Bits<T>::B;  // words covered by the sort key
+    int res = 0;
+#pragma unroll
+    for (int w = WT - 1; w >= FROM; --w) {
+        const T x = a[w], y = b[w];
+        res = (x != y) ? (x < y ? -1 : 1) : res;
     }
+    return res;
+}
+
+template <typename T, int WT>
+__global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, const uint64_t *__restrict__ keys,
+                                                 int64_t n, int words, int smax, uint32_t *__restrict__ vals,
+                                                 uint8_t *__restrict__ uniq, uint2 *__restrict__ large_list,
+                                                 unsigned long long *__restrict__ counters) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int LW = WT + 1;
+    const int slots = TT + smax;
+    uint64_t *skeys = reinterpret_cast<uint64_t *>(smem);  // positions b0 - 1 .. b0 + slots - 1
+    T *lrows = reinterpret_cast<T *>(skeys + slots + 1);
+    int32_t *segof = reinterpret_cast<int32_t *>(lrows + static_cast<size_t>(slots) * LW);
+    int32_t *seglen = segof + slots;
+    uint32_t *sval = reinterpret_cast<uint32_t *>(seglen + slots);
+    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * TT;
+    const int t = threadIdx.x;
+    const int64_t wend = (b0 + slots < n) ? b0 + slots : n;
+    for (int e0 = t; e0 <= slots; e0 += TT * 4) {
+        uint64_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t pos = b0 - 1 + e0 + u * TT;
+            v[u] = (e0 + u * TT <= slots && pos >= 0 && pos < wend) ? keys[pos] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e0 + u * TT <= slots) skeys[e0 + u * TT] = v[u];
+    }
+    for (int r = t; r < slots; r += TT) segof[r] = -1;
+    __syncthreads();
+    const int64_t p = b0 + t;
+    if (p < n) {
+        const uint64_t k = skeys[t + 1];
+        if (p == 0 || k != skeys[t]) {
+            int64_t e = p + 1;
+            while (e < wend && skeys[e - b0 + 1] == k) ++e;
+            if (e == wend && e < n) e = run_end(keys, p, n);
+            const int64_t len = e - p;
+            if (len == 1) {
+                uniq[p] = 1;
+            } else if (len <= smax) {
+                for (int r = 0; r < len; ++r) {
+                    segof[t + r] = t;
+                    seglen[t + r] = static_cast<int32_t>(len);
+                }
+            } else {
+                const unsigned long long slot = atomicAdd(&counters[1], 1ull);
+                large_list[slot] = make_uint2(static_cast<uint32_t>(p), static_cast<uint32_t>(len));
+            }
+        }
+    }
+    __syncthreads();
+    for (int r0 = t; r0 < slots; r0 += TT * 4) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u * TT;
+            v[u] = (r < slots && segof[r] >= 0) ? vals[b0 + r] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u * TT;
+            if (r < slots && segof[r] >= 0) sval[r] = v[u];
+        }
+    }
+    __syncthreads();
+    constexpr int U = 16;
+    const int tot = slots * WT;
+    for (int e0 = t; e0 < tot; e0 += TT * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * TT;
+            const int r = e / WT, w = e % WT;
+            v[u] = (e < tot && w < words && segof[r] >= 0) ? rows[static_cast<int64_t>(sval[r]) * words + w] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * TT;
+            if (e < tot) lrows[(e / WT) * LW + (e % WT)] = v[u];
+        }
+    }
+    __syncthreads();
+    for (int r = t; r < slots; r += TT) {
+        const int a = segof[r];
+        if (a < 0) continue;
+        const int len = seglen[r];
+        const T *me = lrows + r * LW;
+        int rank = 0;
+        bool dup = false;
+        for (int j = a; j < a + len; ++j) {
+            const int c = lex_cmp_t<T, WT>(lrows + j * LW, me);
+            rank += (c < 0 || (c == 0 && j < r)) ? 1 : 0;
+            dup = dup || (c == 0 && j < r);
+        }
+        vals[b0 + a + rank] = sval[r];
+        uniq[b0 + a + rank] = dup ? 0 : 1;
+    }
+}
+
+template <typename T, int WT>
+size_t tiefix_t_lds(int smax) {
+    return static_cast<size_t>(TT + smax + 1) * 8 + static_cast<size_t>(TT + smax) * ((WT + 1) * sizeof(T) + 12);
+}
+
+template <typename T, int WT>
+int tiefix_t_smax() {
+    const int64_t per = (WT + 1) * static_cast<int64_t>(sizeof(T)) + 20;
+    int64_t smax = (TILE_LDS - 8) / per - TT - 1;
+    if (smax > 512) smax = 512;
+    return static_cast<int>(smax);
+}
+
+template <typename T, int WT>
+cg_status tiefix_t_launch(const T *rows, const uint64_t *keys, int64_t n, int words, uint32_t *vals, uint8_t *uniq,
+                          uint2 *large_list, unsigned long long *counters, hipStream_t s) {
+    const int smax = tiefix_t_smax<T, WT>();
+    const size_t lds = tiefix_t_lds<T, WT>(smax);
+    hipLaunchKernelGGL((k_tiefix_t<T, WT>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, keys, n, words, smax,
+                       vals, uniq, large_list, counters);
+    CG_LAUNCHED("dedup_tiefix_t");
+    return CG_OK;
 }
 
 template <typename T>
@@ -130,9 +325,9 @@ __device__ __forceinline__ bool idx_less(const T *rows, int words, int from, uin
 template <typename T>
 __global__ void __launch_bounds__(256) k_tiefix_large(const T *__restrict__ rows, int words, int from,
                                                       const uint2 *__restrict__ list,
-                                                      const uint32_t *__restrict__ counters, uint32_t *vals,
+                                                      const unsigned long long *__restrict__ counters, uint32_t *vals,
                                                       uint8_t *uniq, uint32_t *scratch) {
-    const uint32_t count = counters[1];
+    const uint32_t count = static_cast<uint32_t>(counters[1]);
     for (uint32_t s = blockIdx.x; s < count; s += gridDim.x) {
         const uint2 seg = list[s];
         const int64_t a = seg.x;
@@ -172,20 +367,22 @@ __global__ void __launch_bounds__(256) k_tiefix_large(const T *__restrict__ rows
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_gather(const T *__restrict__ rows, int64_t n, int words,
+// One thread per (sorted position, 16-byte piece of the row) when rows are a
+// whole number of 16-byte pieces, else per (position, word).
+template <typename V>
+__global__ void __launch_bounds__(256) k_gather(const V *__restrict__ rows, int64_t n, int pieces,
                                                 const uint32_t *__restrict__ vals, const uint8_t *__restrict__ uniq,
-                                                const uint32_t *__restrict__ cidx, T *__restrict__ cells,
+                                                const uint32_t *__restrict__ cidx, V *__restrict__ cells,
                                                 uint32_t *__restrict__ row_to_cell) {
-    const int64_t total = n * words;
+    const int64_t total = n * pieces;
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
          g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int64_t j = g / words;
-        const int w = static_cast<int>(g - j * words);
+        const int64_t j = g / pieces;
+        const int w = static_cast<int>(g - j * pieces);
         const uint32_t u = uniq[j];
         const uint32_t cid = cidx[j] + u - 1;
         const uint32_t src = vals[j];
-        if (u) cells[static_cast<int64_t>(cid) * words + w] = rows[static_cast<int64_t>(src) * words + w];
+        if (u) cells[static_cast<int64_t>(cid) * pieces + w] = rows[static_cast<int64_t>(src) * pieces + w];
         if (w == 0 && row_to_cell) row_to_cell[src] = cid;
     }
 }
@@ -197,8 +394,8 @@ struct DedupWs {
     uint64_t *tile_sums;
     uint8_t *uniq;
     uint32_t *cidx;
-    uint2 *small_list, *large_list;
-    uint32_t *counters;
+    uint2 *large_list;
+    unsigned long long *counters;
     uint32_t *scratch;
 };
 
@@ -216,9 +413,8 @@ DedupWs carve_dedup(void *base, int64_t n, cg_layout lay, size_t *bytes) {
     w.tile_sums = c.take<uint64_t>(ts > ts2 ? ts : ts2);
     w.uniq = c.take<uint8_t>(m);
     w.cidx = c.take<uint32_t>(m);
-    w.counters = c.take<uint32_t>(4);
+    w.counters = c.take<unsigned long long>(4);
     if (lay.ell > 64) {
-        w.small_list = c.take<uint2>(m / 2 + 1);
         w.large_list = c.take<uint2>(m / 2 + 1);
         w.scratch = c.take<uint32_t>(2 * m);
     }
@@ -248,32 +444,51 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
     const bool tiefix = lay.ell > 64;
     const int B = static_cast<int>(sizeof(T) * 8);
     const int from = 64 / B;  // words covered by the sort key
-    int lds_stride = words + ((words % 2 == 0) ? 1 : 0);
-    int smax = 0;
-    if (tiefix) {
-        const int64_t per_row = static_cast<int64_t>(lds_stride) * sizeof(T);
-        smax = static_cast<int>(SMALL_LDS_PER_WAVE / per_row);
-        if (smax > 64) smax = 64;
-        CG_TRY(fill_u32(w.counters, 0, 4, s));
-    }
-    hipLaunchKernelGGL(k_heads, dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, keys, n, tiefix,
-                       smax < 2 ? 1 : smax, w.uniq, w.small_list, w.large_list, w.counters);
-    CG_LAUNCHED("dedup_heads");
-    if (tiefix) {
-        if (smax >= 2) {
-            const size_t lds = static_cast<size_t>(SMALL_WAVES) * smax * lds_stride * sizeof(T);
-            hipLaunchKernelGGL((k_tiefix_small<T>), dim3(blocks_for(n / 2 + 1, SMALL_WAVES, 2048)),
-                               dim3(64 * SMALL_WAVES), lds, s, rows, words, from, lds_stride, smax, w.small_list,
-                               w.counters, vals, w.uniq);
-            CG_LAUNCHED("dedup_tiefix_small");
+    if (!tiefix) {
+        hipLaunchKernelGGL(k_heads, dim3(blocks_for(n, 256)), dim3(256), 0, s, keys, n, w.uniq);
+        CG_LAUNCHED("dedup_heads");
+    } else {
+        const int LW = words + ((words % 2 == 0) ? 1 : 0);
+        const int64_t per_slot = static_cast<int64_t>(LW) * sizeof(T) + 20;
+        int64_t smax = TILE_LDS / per_slot - TT - 1;
+        if (smax > 512) smax = 512;
+        size_t lds = static_cast<size_t>(TT + smax) * per_slot + 8;
+        if (smax < 2) {  // rows too wide for LDS: every multi-row segment takes the large path
+            smax = 1;
+            lds = static_cast<size_t>(TT + 1) * 20 + 8;
+        }
+        CG_TRY(fill_i64(reinterpret_cast<int64_t *>(w.counters), 0, 4, s));
+        int wt = 1;
+        while (wt < words) wt <<= 1;
+        const int wcap = sizeof(T) == 8 ? 16 : 32;
+        if (wt <= wcap) {  // every such width leaves room for segments of 80+ rows
+            switch (wt) {
+            case 2: CG_TRY((tiefix_t_launch<T, 2>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, s))); break;
+            case 4: CG_TRY((tiefix_t_launch<T, 4>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, s))); break;
+            case 8: CG_TRY((tiefix_t_launch<T, 8>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, s))); break;
+            case 16: CG_TRY((tiefix_t_launch<T, 16>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, s))); break;
+            default: CG_TRY((tiefix_t_launch<T, 32>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, s))); break;
+            }
+        } else {
+            hipLaunchKernelGGL((k_tiefix_tile<T>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, keys, n, words,
+                               from, static_cast<int>(smax), vals, w.uniq, w.large_list, w.counters);
+            CG_LAUNCHED("dedup_tiefix_tile");
         }
         hipLaunchKernelGGL((k_tiefix_large<T>), dim3(256), dim3(256), 0, s, rows, words, from, w.large_list,
                            w.counters, vals, w.uniq, w.scratch);
         CG_LAUNCHED("dedup_tiefix_large");
     }
     CG_TRY(scan_u8_to_u32(w.uniq, w.cidx, n, nullptr, w.tile_sums, d_ncells, s));
-    hipLaunchKernelGGL((k_gather<T>), dim3(blocks_for(n * words, 256, 65536)), dim3(256), 0, s, rows, n, words,
-                       vals, w.uniq, w.cidx, cells, row_to_cell);
+    const size_t rowbytes = static_cast<size_t>(words) * sizeof(T);
+    if (rowbytes % 16 == 0) {
+        const int pieces = static_cast<int>(rowbytes / 16);
+        hipLaunchKernelGGL((k_gather<uint4>), dim3(blocks_for(n * pieces, 256, 65536)), dim3(256), 0, s,
+                           reinterpret_cast<const uint4 *>(rows), n, pieces, vals, w.uniq, w.cidx,
+                           reinterpret_cast<uint4 *>(cells), row_to_cell);
+    } else {
+        hipLaunchKernelGGL((k_gather<T>), dim3(blocks_for(n * words, 256, 65536)), dim3(256), 0, s, rows, n, words,
+                           vals, w.uniq, w.cidx, cells, row_to_cell);
+    }
     CG_LAUNCHED("dedup_gather");
     return CG_OK;
 }

@@ -33,27 +33,42 @@ __device__ __forceinline__ uint32_t suffix_hash32(const T *row, int words, int s
     return static_cast<uint32_t>(h >> 32);
 }
 
+// One block per 256-cell tile.  The tile's rows are read once, coalesced,
+// into LDS (when they fit; wide rows are read in place), then each thread
+// hashes its cell's suffix and writes the directory entries that point at it.
+constexpr int DT = 256;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_dict_scan(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
-                                                   int words, int p, int s, uint32_t *__restrict__ dir,
-                                                   uint64_t *__restrict__ sfx) {
+__global__ void __launch_bounds__(DT) k_dict_scan(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
+                                                  int words, int p, int s, uint32_t *__restrict__ dir,
+                                                  uint64_t *__restrict__ sfx, bool stage) {
+    extern __shared__ __align__(16) unsigned char smem[];
     const int64_t n = load_n(d_n, ncap);
     const int64_t G = int64_t(1) << p;
-    const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * DT;
     if (n == 0) {
-        for (int64_t g = gid; g <= G; g += static_cast<int64_t>(gridDim.x) * blockDim.x) dir[g] = 0;
+        for (int64_t g = base + threadIdx.x; g <= G; g += static_cast<int64_t>(gridDim.x) * DT) dir[g] = 0;
         return;
     }
-    for (int64_t i = gid; i < n; i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const T *row = cells + i * words;
-        const int64_t gi = p ? static_cast<int64_t>(head64<T>(row, words) >> (64 - p)) : 0;
-        const int64_t gp = i == 0 ? -1
-                                  : (p ? static_cast<int64_t>(head64<T>(row - words, words) >> (64 - p)) : 0);
-        for (int64_t g = gp + 1; g <= gi; ++g) dir[g] = static_cast<uint32_t>(i);
-        if (i == n - 1)
-            for (int64_t g = gi + 1; g <= G; ++g) dir[g] = static_cast<uint32_t>(n);
-        sfx[i] = (static_cast<uint64_t>(suffix_hash32<T>(row, words, s)) << 32) | static_cast<uint64_t>(i);
+    if (base >= n) return;
+    const int tr = static_cast<int>(n - base < DT ? n - base : DT);
+    const int LW = words | 1;
+    T *lrows = reinterpret_cast<T *>(smem);
+    if (stage) {
+        copy_rows_to_lds<T, DT>(lrows, LW, cells + base * words, tr, words);
+        __syncthreads();
     }
+    const int t = threadIdx.x;
+    if (t >= tr) return;
+    const int64_t i = base + t;
+    const T *row = stage ? lrows + t * LW : cells + i * words;
+    const int64_t gi = p ? static_cast<int64_t>(head64<T>(row, words) >> (64 - p)) : 0;
+    const T *prev = (stage && t > 0) ? lrows + (t - 1) * LW : cells + (i - 1) * words;
+    const int64_t gp = i == 0 ? -1 : (p ? static_cast<int64_t>(head64<T>(prev, words) >> (64 - p)) : 0);
+    for (int64_t g = gp + 1; g <= gi; ++g) dir[g] = static_cast<uint32_t>(i);
+    if (i == n - 1)
+        for (int64_t g = gi + 1; g <= G; ++g) dir[g] = static_cast<uint32_t>(n);
+    sfx[i] = (static_cast<uint64_t>(suffix_hash32<T>(row, words, s)) << 32) | static_cast<uint64_t>(i);
 }
 
 // One wave per query; lanes take bits k0 + lane for k0 = 0, 64, ...
@@ -161,9 +176,11 @@ template <typename T> static cg_status dict_build_impl(cg_dict &d, hipStream_t s
     const int64_t ncap = d.ncells_cap;
     const int64_t G = int64_t(1) << d.params.dir_bits;
     const int64_t items = std::max<int64_t>(ncap, G + 1);
-    hipLaunchKernelGGL((k_dict_scan<T>), dim3(blocks_for(items, 256, 16384)), dim3(256), 0, s,
+    const size_t lds = static_cast<size_t>(DT) * (d.lay.words | 1) * sizeof(T);
+    const bool stage = lds <= 65536;
+    hipLaunchKernelGGL((k_dict_scan<T>), dim3(blocks_for(items, DT)), dim3(DT), stage ? lds : 0, s,
                        static_cast<const T *>(d.cells), d.d_ncells, ncap, d.lay.words, d.params.dir_bits,
-                       d.params.split_bit, m.dir, m.sfx[0]);
+                       d.params.split_bit, m.dir, m.sfx[0], stage);
     CG_LAUNCHED("dict_scan");
     int which = 0;
     if (ncap > 0)

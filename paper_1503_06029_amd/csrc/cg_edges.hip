@@ -17,8 +17,17 @@
 // flips in descending k: first its P-neighbours (k >= s) in group order,
 // then its S-neighbours (k < s) in run order (ids ascend within a run).
 // So edge slots are offsets[u] + rank for P, offsets[u] + cntP[u] + rank for
-// S, with offsets = exclusive scan of cntP + cntS.  Each pass runs twice:
-// once to count, once to write.
+// S, with offsets = exclusive scan of cntP + cntS.
+//
+// Fast path (rows of at most 252 bytes): the S pass runs first, writing
+// cntS and a list of its edges (with their ranks); then one P kernel reads
+// every cell exactly once into LDS (a 256-cell tile per block), counts each
+// cell's P-neighbours, takes its edge offset from a decoupled look-back scan
+// over tiles, and writes offsets and P edges in the same pass; a last small
+// kernel drops the listed S edges into their slots.  Pairs inside a group
+// are pre-filtered with the bound (*) of Section 1.1 against the zero
+// vector: a distance-1 pair has popcounts differing by exactly one.
+// Generic path (longer rows): count and write passes over global memory.
 #include "cg_internal.hpp"
 
 namespace cg {
@@ -131,29 +140,612 @@ __global__ void k_status(const int64_t *total, int64_t cap, int32_t *status) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *status = (*total > cap) ? CG_ECAPACITY : CG_OK;
 }
 
+// ------------------------------------------------------------- fast path
+//
+// No global atomics and no inter-block waiting (same-address device atomics
+// serialise at roughly 10 ns each, so tickets and shared cursors do not
+// scale).  Each pass works on a 256-item tile and keeps what it found in a
+// per-tile stash; a one-block scan over tile totals gives every tile its
+// output offset; placement passes then copy stashes to their final slots.
+//
+//   E0 init      zero cntS
+//   E1 S-find    per suffix-order tile: cntS[u], S edges (u, v, k, rank) to
+//                the tile's S stash
+//   E2 P-find    per cell tile, rows in LDS: cntP[u] (bit 31: found by
+//                look-up, recomputed at placement), P edges (v - u, k) to the
+//                tile's P stash; tile total of cntP + cntS
+//   E3 scan      exclusive scan of tile totals; |E|, offsets[n], status
+//   E4 P-place   per cell tile: offsets (or the sparse next-offsets needed by
+//                E5), P edges from the stash (or recomputed on overflow)
+//   E5 S-place   per suffix-order tile: S edges to next(u) - cntS[u] + rank
+
+constexpr int PT = 256;              // items per tile = threads per block
+constexpr int P_STASH = 4 * PT;      // P edges kept per cell tile
+constexpr int S_STASH = PT;          // S edges kept per suffix-order tile
+constexpr uint32_t BIG = 0x80000000u;
+constexpr int FAST_LDS_MAX = 65536;
+
+__device__ __forceinline__ int padded_words(int W) { return W + ((W & 1) ? 0 : 1); }
+
+__global__ void k_edges_init(uint32_t *cntS, int64_t ncap, int64_t *d_nedges, int64_t *offsets, int32_t *status) {
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = gid; i < ncap; i += stride) cntS[i] = 0;
+    if (gid == 0) {
+        *d_nedges = 0;
+        if (offsets) offsets[0] = 0;
+        *status = CG_OK;
+    }
+}
+
+// S-neighbours of the cell at suffix-order position q: run [lo, hi] of equal
+// hashes around q (or a look-up for every k < s when the run is long).  The
+// suffix-order entries of the tile and rmax + 1 positions on either side sit
+// in LDS (hs = hash, ids = cell id, index = position - win0).
+struct SRun {
+    uint32_t id;
+    int64_t lo, hi;
+    bool big;
+};
+
+__device__ __forceinline__ SRun s_run(const uint32_t *hs, const uint32_t *ids, int64_t win0, int64_t q, int64_t n,
+                                      int rmax) {
+    SRun r{0, 0, -1, false};
+    const int64_t e = q - win0;
+    const uint32_t h = hs[e];
+    r.id = ids[e];
+    int64_t left = 0, right = 0;
+    while (left <= rmax && q - left - 1 >= 0 && hs[e - left - 1] == h) ++left;
+    while (right <= rmax && q + right + 1 < n && hs[e + right + 1] == h) ++right;
+    r.lo = q - left;
+    r.hi = q + right;
+    r.big = left + right + 1 > rmax;
+    return r;
+}
+
+// Calls f(v, k, rank) for each S-neighbour v > id in ascending v; returns the
+// count.
+template <typename T, class F>
+__device__ __forceinline__ uint32_t s_neighbours(const SRun &r, const uint32_t *ids, int64_t win0,
+                                                 const T *__restrict__ cells, int64_t n, int words, int s, F f) {
+    uint32_t c = 0;
+    if (r.hi <= r.lo) return 0;
+    const T *me = cells + static_cast<int64_t>(r.id) * words;
+    if (r.big) {
+        for (int k = s - 1; k >= 0; --k) {
+            if (get_bit<T>(me, k)) continue;
+            const int64_t v = find_row<T>(cells, words, static_cast<int64_t>(r.id) + 1, n, me, k);
+            if (v >= 0) { f(static_cast<uint32_t>(v), k, c); ++c; }
+        }
+    } else {
+        for (int64_t rr = r.lo; rr <= r.hi; ++rr) {
+            const uint32_t v = ids[rr - win0];
+            int pos;
+            if (v > r.id && dist_full<T>(me, cells + static_cast<int64_t>(v) * words, words, &pos) == 1 && pos < s) {
+                f(v, pos, c);
+                ++c;
+            }
+        }
+    }
+    return c;
+}
+
+// Loads the suffix-order window [tile * PT - rmax - 1, tile * PT + PT + rmax + 1)
+// into LDS; returns win0.  Block-wide.
+__device__ __forceinline__ int64_t load_s_window(uint32_t *hs, uint32_t *ids, const uint64_t *__restrict__ sfx,
+                                                 int64_t tile, int64_t n, int rmax) {
+    const int64_t win0 = tile * PT - (rmax + 1);
+    const int wl = PT + 2 * (rmax + 1);
+    for (int e0 = threadIdx.x; e0 < wl; e0 += PT * 4) {
+        uint64_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t pos = win0 + e0 + u * PT;
+            v[u] = (e0 + u * PT < wl && pos >= 0 && pos < n) ? sfx[pos] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * PT;
+            if (e < wl) {
+                hs[e] = static_cast<uint32_t>(v[u] >> 32);
+                ids[e] = static_cast<uint32_t>(v[u]);
+            }
+        }
+    }
+    __syncthreads();
+    return win0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(PT) k_s_find(const T *__restrict__ cells, const uint64_t *__restrict__ sfx,
+                                               const int64_t *d_n, int64_t ncap, int words, int s, int rmax,
+                                               uint32_t *__restrict__ cntS, uint4 *__restrict__ stash,
+                                               uint32_t *__restrict__ stash_n) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint64_t tmp[4];
+    uint32_t *hs = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *ids = hs + PT + 2 * (rmax + 1);
+    const int64_t n = load_n(d_n, ncap);
+    const int64_t tile = blockIdx.x;
+    const int64_t q = tile * PT + threadIdx.x;
+    if (tile * PT >= n) return;
+    const int64_t win0 = load_s_window(hs, ids, sfx, tile, n, rmax);
+    SRun r{0, 0, -1, false};
+    uint32_t c = 0;
+    if (q < n) {
+        r = s_run(hs, ids, win0, q, n, rmax);
+        c = s_neighbours<T>(r, ids, win0, cells, n, words, s, [](uint32_t, int, uint32_t) {});
+    }
+    uint64_t tot;
+    const uint64_t ex = block256_excl_scan_u64(c, tmp, &tot);
+    if (threadIdx.x == 0) stash_n[tile] = static_cast<uint32_t>(tot > 0xffffffffull ? 0xffffffffull : tot);
+    if (c == 0) return;
+    cntS[r.id] = c;
+    if (tot > static_cast<uint64_t>(S_STASH)) return;  // placement recomputes this tile
+    uint4 *out = stash + tile * S_STASH + ex;
+    const uint32_t id = r.id;
+    s_neighbours<T>(r, ids, win0, cells, n, words, s, [&](uint32_t v, int k, uint32_t rank) {
+        out[rank] = make_uint4(id, v, static_cast<uint32_t>(k) | (rank << 16), c);
+    });
+}
+
+__device__ __forceinline__ void emit(uint32_t *uv, uint16_t *bit, int64_t cap, int64_t pos, uint32_t u,
+                                     uint32_t v, int k);
+
+template <typename T>
+__global__ void __launch_bounds__(PT) k_s_place(const T *__restrict__ cells, const uint64_t *__restrict__ sfx,
+                                                const int64_t *d_n, int64_t ncap, int words, int s, int rmax,
+                                                const uint32_t *__restrict__ cntS, const uint4 *__restrict__ stash,
+                                                const uint32_t *__restrict__ stash_n,
+                                                const int64_t *__restrict__ offsets,
+                                                const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
+                                                uint16_t *__restrict__ bit, int64_t cap) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t n = load_n(d_n, ncap);
+    const int64_t tile = blockIdx.x;
+    if (tile * PT >= n) return;
+    const uint32_t m = stash_n[tile];
+    if (m <= static_cast<uint32_t>(S_STASH)) {
+        for (uint32_t e = threadIdx.x; e < m; e += PT) {
+            const uint4 r = stash[tile * S_STASH + e];
+            const int64_t next = offsets ? offsets[static_cast<int64_t>(r.x) + 1] : offnext[r.x];
+            emit(uv, bit, cap, next - r.w + (r.z >> 16), r.x, r.y, static_cast<int>(r.z & 0xffffu));
+        }
+        return;
+    }
+    // overflowed stash: recompute
+    uint32_t *hs = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *ids = hs + PT + 2 * (rmax + 1);
+    const int64_t win0 = load_s_window(hs, ids, sfx, tile, n, rmax);
+    const int64_t q = tile * PT + threadIdx.x;
+    if (q >= n) return;
+    const SRun r = s_run(hs, ids, win0, q, n, rmax);
+    const uint32_t c = cntS[r.id];
+    if (r.hi <= r.lo || c == 0) return;
+    const int64_t next = offsets ? offsets[static_cast<int64_t>(r.id) + 1] : offnext[r.id];
+    const uint32_t id = r.id;
+    s_neighbours<T>(r, ids, win0, cells, n, words, s, [&](uint32_t v, int k, uint32_t rank) {
+        emit(uv, bit, cap, next - c + rank, id, v, k);
+    });
+}
+
+// ---------------------------------------------------------------- P tiles
+//
+// A P tile holds PT cells plus up to HALO following rows (for the prefix
+// group that crosses the tile's end) in LDS, each row zero-padded to WT
+// words (WT a power of two, fixed at compile time, so every row operation
+// is straight-line code; the zero words change neither distances nor order).
+
+constexpr int HALO = 32;       // rows past the tile kept in LDS
+constexpr int NB = 12;         // P-neighbours remembered per cell between count and write
+constexpr int PROWS = PT + HALO;
+
+template <typename T, int WT> struct PTile {
+    static constexpr int LW = WT + 1;  // odd stride: lanes reading different rows spread over banks
+    static constexpr size_t rows_bytes = static_cast<size_t>(PROWS) * LW * sizeof(T);
+    static constexpr size_t bytes = rows_bytes + PROWS * 4 /* pcs */ + PT * NB * 4 /* nbl */ + PROWS + 4 /* heads */;
+};
+
+// Block-wide copy of nrows contiguous global rows into LDS rows padded with
+// zero words to WT (stride LW), U loads in flight per thread.
+template <typename T, int WT, int NT, int U>
+__device__ __forceinline__ void copy_rows_padded(T *lds, const T *__restrict__ src, int nrows, int words) {
+    constexpr int LW = WT + 1;
+    const int tot = nrows * WT;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += NT * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * NT;
+            const int r = e / WT, w = e % WT;
+            v[u] = (e < tot && w < words) ? src[r * words + w] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * NT;
+            if (e < tot) lds[(e / WT) * LW + (e % WT)] = v[u];
+        }
+    }
+}
+
+template <typename T, int WT>
+__device__ __forceinline__ bool same_prefix_t(const T *a, const T *b, int s) {
+    constexpr int B = Bits<T>::B;
+    const int full = s / B, rem = s % B;
+    T acc = 0;
+#pragma unroll
+    for (int w = 0; w < WT; ++w) {
+        const T m = w < full ? static_cast<T>(~T(0)) : (w == full && rem ? static_cast<T>(~T(0)) << (B - rem) : T(0));
+        acc |= (a[w] ^ b[w]) & m;
+    }
+    return acc == 0;
+}
+
+template <typename T, int WT>
+__device__ __forceinline__ int dist_t(const T *a, const T *b, int *pos) {
+    int d = 0, first = -1;
+#pragma unroll
+    for (int w = 0; w < WT; ++w) {
+        const T x = a[w] ^ b[w];
+        d += popc<T>(x);
+        first = (x && first < 0) ? w * Bits<T>::B + clz_t<T>(x) : first;
+    }
+    *pos = first;
+    return d;
+}
+
+// Loads the tile (tr rows) and its halo (rows after it sharing the last
+// row's first s bits, at most HALO) into LDS with popcounts and group heads
+// (heads[r] = 1 iff row r starts a prefix group; heads[tr + th] = 1).
+template <typename T, int WT>
+__device__ __forceinline__ int load_ptile(T *rows, uint32_t *pcs, uint8_t *heads, int *s_th,
+                                          const T *__restrict__ cells, int words, int s, int64_t base, int64_t n,
+                                          int *th) {
+    constexpr int LW = WT + 1;
+    const int tr = static_cast<int>(n - base < PT ? n - base : PT);
+    copy_rows_padded<T, WT, PT, 16>(rows, cells + base * words, tr, words);
+    if (threadIdx.x == 0) *s_th = HALO;
+    __syncthreads();
+    const int64_t avail = n - base - tr;
+    const int hmax = static_cast<int>(avail < HALO ? avail : HALO);
+    if (static_cast<int>(threadIdx.x) < hmax) {
+        const T *o = cells + (base + tr + threadIdx.x) * words;
+        if (!same_prefix<T>(rows + (tr - 1) * LW, o, s)) atomicMin(s_th, static_cast<int>(threadIdx.x));
+    }
+    __syncthreads();
+    const int h = *s_th < hmax ? *s_th : hmax;
+    copy_rows_padded<T, WT, PT, 4>(rows + tr * LW, cells + (base + tr) * words, h, words);
+    __syncthreads();
+    for (int r = threadIdx.x; r < tr + h; r += PT) {
+        uint32_t pc = 0;
+        const T *me = rows + r * LW;
+#pragma unroll
+        for (int w = 0; w < WT; ++w) pc += popc<T>(me[w]);
+        pcs[r] = pc;
+        heads[r] = (r == 0 || !same_prefix_t<T, WT>(rows + (r - 1) * LW, me, s)) ? 1 : 0;
+    }
+    if (threadIdx.x == 0) heads[tr + h] = 1;
+    __syncthreads();
+    *th = h;
+    return tr;
+}
+
+// P-neighbours of tile cell t (global index i), in ascending v: the rest of
+// its prefix group, from LDS, then past the loaded rows in global memory.
+// f(delta = v - i, k, rank) per neighbour.  Returns the count, or BIG when
+// the group holds more than gmax cells after i (f is then not called).
+template <typename T, int WT, class F>
+__device__ __forceinline__ uint32_t p_scan_t(const T *rows, const uint32_t *pcs, const uint8_t *heads, int tl,
+                                             int t, int64_t i, int64_t base, int64_t n,
+                                             const T *__restrict__ cells, int words, int s, int gmax, F f) {
+    constexpr int LW = WT + 1;
+    const T *me = rows + t * LW;
+    const uint32_t pc = pcs[t];
+    uint32_t c = 0;
+    int jj = t + 1;
+    for (; jj < tl; ++jj) {
+        if (heads[jj]) return c;
+        if (jj - t > gmax) return BIG;
+        const uint32_t po = pcs[jj];
+        if (po == pc + 1 || po + 1 == pc) {
+            int pos;
+            if (dist_t<T, WT>(me, rows + jj * LW, &pos) == 1) { f(static_cast<uint32_t>(jj - t), pos, c); ++c; }
+        }
+    }
+    if (heads[tl]) {
+        // loaded rows ended inside the group: it may go on in global memory
+        for (int64_t j = base + tl; j < n; ++j) {
+            const T *o = cells + j * words;
+            if (!same_prefix<T>(me, o, s)) break;
+            if (j - i > gmax) return BIG;
+            int pos;
+            if (dist_full<T>(me, o, words, &pos) == 1) { f(static_cast<uint32_t>(j - i), pos, c); ++c; }
+        }
+    }
+    return c;
+}
+
+// Look-up form of the P-neighbours of cell i (all k >= s, descending k).
+template <typename T, class F>
+__device__ __forceinline__ uint32_t p_lookup(const T *__restrict__ cells, int64_t i, int64_t n, int words, int ell,
+                                             int s, F f) {
+    const T *me = cells + i * words;
+    uint32_t c = 0;
+    for (int k = ell - 1; k >= s; --k) {
+        if (get_bit<T>(me, k)) continue;
+        const int64_t v = find_row<T>(cells, words, i + 1, n, me, k);
+        if (v >= 0) { f(static_cast<uint32_t>(v), k, c); ++c; }
+    }
+    return c;
+}
+
+template <typename T, int WT>
+__global__ void __launch_bounds__(PT) k_p_find(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
+                                               int words, int ell, int s, int gmax,
+                                               const uint32_t *__restrict__ cntS, uint32_t *__restrict__ cntP,
+                                               uint32_t *__restrict__ stash, uint32_t *__restrict__ stash_n,
+                                               uint64_t *__restrict__ tile_tot) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint64_t tmp[4];
+    __shared__ int s_th;
+    using L = PTile<T, WT>;
+    T *rows = reinterpret_cast<T *>(smem);
+    uint32_t *pcs = reinterpret_cast<uint32_t *>(smem + L::rows_bytes);
+    uint32_t *nbl = pcs + PROWS;
+    uint8_t *heads = reinterpret_cast<uint8_t *>(nbl + PT * NB);
+    const int64_t n = load_n(d_n, ncap);
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * PT;
+    if (base >= n) return;
+    int th;
+    const int tr = load_ptile<T, WT>(rows, pcs, heads, &s_th, cells, words, s, base, n, &th);
+    const int t = threadIdx.x;
+    const int64_t i = base + t;
+    uint32_t *mine = nbl + t * NB;
+    uint32_t cp = 0, cs = 0;
+    if (t < tr) {
+        cp = p_scan_t<T, WT>(rows, pcs, heads, tr + th, t, i, base, n, cells, words, s, gmax,
+                             [&](uint32_t d, int k, uint32_t r) {
+                                 if (r < NB) mine[r] = (d << 16) | static_cast<uint32_t>(k);
+                             });
+        if (cp & BIG) cp = BIG | p_lookup<T>(cells, i, n, words, ell, s, [](uint32_t, int, uint32_t) {});
+        cs = cntS[i];
+        cntP[i] = cp;
+    }
+    const uint32_t stashed = (cp & BIG) ? 0u : cp;
+    uint64_t tot_stash, tot_all;
+    const uint64_t ex = block256_excl_scan_u64(stashed, tmp, &tot_stash);
+    block256_excl_scan_u64(static_cast<uint64_t>(cp & ~BIG) + cs, tmp, &tot_all);
+    if (t == 0) {
+        tile_tot[tile] = tot_all;
+        stash_n[tile] = static_cast<uint32_t>(tot_stash > 0xffffffffull ? 0xffffffffull : tot_stash);
+    }
+    if (tot_stash > static_cast<uint64_t>(P_STASH) || stashed == 0) return;
+    uint32_t *out = stash + tile * P_STASH + ex;
+    if (stashed <= static_cast<uint32_t>(NB)) {
+        for (uint32_t r = 0; r < stashed; ++r) out[r] = mine[r];
+    } else {
+        p_scan_t<T, WT>(rows, pcs, heads, tr + th, t, i, base, n, cells, words, s, gmax,
+                        [&](uint32_t d, int k, uint32_t r) { out[r] = (d << 16) | static_cast<uint32_t>(k); });
+    }
+}
+
+// One block: exclusive scan of tile totals in place; |E|, offsets[n], status.
+// Thread t owns a contiguous chunk of the totals (one load round).
+__global__ void __launch_bounds__(256) k_tile_scan(uint64_t *tile_tot, const int64_t *d_n, int64_t ncap,
+                                                   int64_t cap, int64_t *d_nedges, int64_t *offsets,
+                                                   int32_t *status) {
+    __shared__ uint64_t tmp[4];
+    const int64_t n = load_n(d_n, ncap);
+    const int64_t tiles = (n + PT - 1) / PT;
+    const int64_t per = (tiles + 255) / 256;
+    const int64_t a = threadIdx.x * per;
+    const int64_t b = a + per < tiles ? a + per : tiles;
+    uint64_t sum = 0;
+    for (int64_t k = a; k < b; ++k) sum += tile_tot[k];
+    uint64_t total;
+    uint64_t run = block256_excl_scan_u64(sum, tmp, &total);
+    for (int64_t k = a; k < b; ++k) {
+        const uint64_t v = tile_tot[k];
+        tile_tot[k] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) {
+        const int64_t tot = static_cast<int64_t>(total);
+        *d_nedges = tot;
+        if (offsets) offsets[n] = tot;
+        *status = tot > cap ? CG_ECAPACITY : CG_OK;
+    }
+}
+
+// Placement of P edges for tiles whose stash held them; offsets for all.
+template <typename T>
+__global__ void __launch_bounds__(PT) k_p_place(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
+                                                int words, int ell, int s,
+                                                const uint32_t *__restrict__ cntS, const uint32_t *__restrict__ cntP,
+                                                const uint32_t *__restrict__ stash,
+                                                const uint32_t *__restrict__ stash_n,
+                                                const uint64_t *__restrict__ tile_off, int64_t *__restrict__ offsets,
+                                                int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
+                                                uint16_t *__restrict__ bit, int64_t cap) {
+    __shared__ uint64_t tmp[4];
+    const int64_t n = load_n(d_n, ncap);
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * PT;
+    if (base >= n) return;
+    const int t = threadIdx.x;
+    const int64_t i = base + t;
+    const int tr = static_cast<int>(n - base < PT ? n - base : PT);
+    uint32_t cp = 0, cs = 0;
+    if (t < tr) {
+        cp = cntP[i];
+        cs = cntS[i];
+    }
+    const uint32_t c = cp & ~BIG;
+    const uint32_t stashed = (cp & BIG) ? 0u : cp;
+    uint64_t tot_all, tot_stash;
+    const uint64_t exa = block256_excl_scan_u64(static_cast<uint64_t>(c) + cs, tmp, &tot_all);
+    const uint64_t exs = block256_excl_scan_u64(stashed, tmp, &tot_stash);
+    const int64_t out0 = static_cast<int64_t>(tile_off[tile] + exa);
+    if (t < tr) {
+        if (offsets) offsets[i] = out0;
+        else if (cs) offnext[i] = out0 + c + cs;
+    }
+    if (t >= tr) return;
+    if (cp & BIG) {
+        p_lookup<T>(cells, i, n, words, ell, s, [&](uint32_t v, int k, uint32_t r) {
+            emit(uv, bit, cap, out0 + r, static_cast<uint32_t>(i), v, k);
+        });
+        return;
+    }
+    if (stash_n[tile] > static_cast<uint32_t>(P_STASH)) return;  // k_p_fix writes this tile
+    const uint32_t *src = stash + tile * P_STASH + exs;
+    for (uint32_t r = 0; r < c; ++r) {
+        const uint32_t e = src[r];
+        emit(uv, bit, cap, out0 + r, static_cast<uint32_t>(i), static_cast<uint32_t>(i + (e >> 16)),
+             static_cast<int>(e & 0xffffu));
+    }
+}
+
+// Tiles whose P stash overflowed: reload and write their scanned P edges.
+template <typename T, int WT>
+__global__ void __launch_bounds__(PT) k_p_fix(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
+                                              int words, int s, int gmax, const uint32_t *__restrict__ cntS,
+                                              const uint32_t *__restrict__ cntP,
+                                              const uint32_t *__restrict__ stash_n,
+                                              const uint64_t *__restrict__ tile_off, uint32_t *__restrict__ uv,
+                                              uint16_t *__restrict__ bit, int64_t cap) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint64_t tmp[4];
+    __shared__ int s_th;
+    const int64_t n = load_n(d_n, ncap);
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * PT;
+    if (base >= n || stash_n[tile] <= static_cast<uint32_t>(P_STASH)) return;
+    using L = PTile<T, WT>;
+    T *rows = reinterpret_cast<T *>(smem);
+    uint32_t *pcs = reinterpret_cast<uint32_t *>(smem + L::rows_bytes);
+    uint32_t *nbl = pcs + PROWS;
+    uint8_t *heads = reinterpret_cast<uint8_t *>(nbl + PT * NB);
+    int th;
+    const int tr = load_ptile<T, WT>(rows, pcs, heads, &s_th, cells, words, s, base, n, &th);
+    const int t = threadIdx.x;
+    const int64_t i = base + t;
+    uint32_t cp = 0, cs = 0;
+    if (t < tr) {
+        cp = cntP[i];
+        cs = cntS[i];
+    }
+    uint64_t tot;
+    const uint64_t exa = block256_excl_scan_u64(static_cast<uint64_t>(cp & ~BIG) + cs, tmp, &tot);
+    if (t >= tr || (cp & BIG) || cp == 0) return;
+    const int64_t out0 = static_cast<int64_t>(tile_off[tile] + exa);
+    p_scan_t<T, WT>(rows, pcs, heads, tr + th, t, i, base, n, cells, words, s, gmax,
+                    [&](uint32_t d, int k, uint32_t r) {
+                        emit(uv, bit, cap, out0 + r, static_cast<uint32_t>(i), static_cast<uint32_t>(i + d), k);
+                    });
+}
+
 struct EdgesWs {
     uint32_t *cntP, *cntS;
     int64_t *offsets;
     uint64_t *tile_sums;
+    uint64_t *tile_tot;
+    uint32_t *p_stash, *p_stash_n;
+    uint4 *s_stash;
+    uint32_t *s_stash_n;
 };
 
-EdgesWs carve_edges(void *base, int64_t ncap, bool need_offsets, size_t *bytes) {
+// Padded row width (power of two) for the P tiles, or 0 when rows are too
+// wide for them (u64: up to 16 words, u32: up to 32 words, i.e. l <= 1024).
+int tile_width(const cg_dict &d) {
+    const int cap = d.lay.word_bits == 64 ? 16 : 32;
+    int wt = 1;
+    while (wt < d.lay.words) wt <<= 1;
+    return wt <= cap ? wt : 0;
+}
+
+bool fast_path_ok(const cg_dict &d) { return tile_width(d) > 0 && d.params.group_max < 65536; }
+
+EdgesWs carve_edges(void *base, int64_t ncap, size_t *bytes) {
     Carver c(base);
     EdgesWs w{};
     const int64_t n = ncap > 0 ? ncap : 1;
+    const int64_t tiles = (n + PT - 1) / PT;
     w.cntP = c.take<uint32_t>(n);
     w.cntS = c.take<uint32_t>(n);
-    w.offsets = need_offsets ? c.take<int64_t>(n + 1) : nullptr;
+    w.offsets = c.take<int64_t>(n + 1);
     w.tile_sums = c.take<uint64_t>(scan_tiles(n));
+    w.tile_tot = c.take<uint64_t>(tiles);
+    w.p_stash = c.take<uint32_t>(tiles * P_STASH);
+    w.p_stash_n = c.take<uint32_t>(tiles);
+    w.s_stash = c.take<uint4>(tiles * S_STASH);
+    w.s_stash_n = c.take<uint32_t>(tiles);
     *bytes = c.bytes();
     return w;
 }
 
+template <typename T, int WT>
+cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t *d_nedges, int64_t *d_offsets,
+                        int64_t *offnext, uint32_t *uv, uint16_t *bit, int32_t *d_status, hipStream_t s) {
+    const int64_t ncap = d.ncells_cap;
+    const T *cells = static_cast<const T *>(d.cells);
+    const int words = d.lay.words, ell = d.lay.ell, sp = d.params.split_bit, gmax = d.params.group_max;
+    const dim3 grid(static_cast<unsigned>((ncap + PT - 1) / PT));
+    const size_t lds = PTile<T, WT>::bytes;
+    hipLaunchKernelGGL((k_p_find<T, WT>), grid, dim3(PT), lds, s, cells, d.d_ncells, ncap, words, ell, sp, gmax,
+                       w.cntS, w.cntP, w.p_stash, w.p_stash_n, w.tile_tot);
+    CG_LAUNCHED("edges_p_find");
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, s, w.tile_tot, d.d_ncells, ncap, cap, d_nedges, d_offsets,
+                       d_status);
+    CG_LAUNCHED("edges_tile_scan");
+    hipLaunchKernelGGL((k_p_place<T>), grid, dim3(PT), 0, s, cells, d.d_ncells, ncap, words, ell, sp, w.cntS,
+                       w.cntP, w.p_stash, w.p_stash_n, w.tile_tot, d_offsets, offnext, uv, bit, cap);
+    CG_LAUNCHED("edges_p_place");
+    hipLaunchKernelGGL((k_p_fix<T, WT>), grid, dim3(PT), lds, s, cells, d.d_ncells, ncap, words, sp, gmax, w.cntS,
+                       w.cntP, w.p_stash_n, w.tile_tot, uv, bit, cap);
+    CG_LAUNCHED("edges_p_fix");
+    return CG_OK;
+}
+
 template <typename T>
-cg_status edges_impl(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap, int64_t *d_nedges,
-                     int64_t *d_offsets, void *ws, int32_t *d_status, hipStream_t s) {
-    size_t b;
-    EdgesWs w = carve_edges(ws, d.ncells_cap, true, &b);
+cg_status edges_fast(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap, int64_t *d_nedges,
+                     int64_t *d_offsets, const EdgesWs &w, int32_t *d_status, hipStream_t s) {
+    const int64_t ncap = d.ncells_cap;
+    const T *cells = static_cast<const T *>(d.cells);
+    const int words = d.lay.words, sp = d.params.split_bit, gmax = d.params.group_max;
+    const int64_t ntiles = (ncap + PT - 1) / PT;
+    int64_t *offnext = w.offsets;  // sparse next-offsets when the caller wants no offsets
+    hipLaunchKernelGGL(k_edges_init, dim3(blocks_for(ncap, 256, 4096)), dim3(256), 0, s, w.cntS, ncap, d_nedges,
+                       d_offsets, d_status);
+    CG_LAUNCHED("edges_init");
+    if (ncap == 0) return CG_OK;
+    const dim3 grid(static_cast<unsigned>(ntiles));
+    const size_t s_lds = static_cast<size_t>(PT + 2 * (gmax + 1)) * 2 * sizeof(uint32_t);
+    if (sp > 0) {
+        hipLaunchKernelGGL((k_s_find<T>), grid, dim3(PT), s_lds, s, cells, d.sfx, d.d_ncells, ncap, words, sp, gmax,
+                           w.cntS, w.s_stash, w.s_stash_n);
+        CG_LAUNCHED("edges_s_find");
+    }
+    switch (tile_width(d)) {
+    case 1: CG_TRY((p_pass_launch<T, 1>(d, w, cap, d_nedges, d_offsets, offnext, uv, bit, d_status, s))); break;
+    case 2: CG_TRY((p_pass_launch<T, 2>(d, w, cap, d_nedges, d_offsets, offnext, uv, bit, d_status, s))); break;
+    case 4: CG_TRY((p_pass_launch<T, 4>(d, w, cap, d_nedges, d_offsets, offnext, uv, bit, d_status, s))); break;
+    case 8: CG_TRY((p_pass_launch<T, 8>(d, w, cap, d_nedges, d_offsets, offnext, uv, bit, d_status, s))); break;
+    case 16: CG_TRY((p_pass_launch<T, 16>(d, w, cap, d_nedges, d_offsets, offnext, uv, bit, d_status, s))); break;
+    default: CG_TRY((p_pass_launch<T, 32>(d, w, cap, d_nedges, d_offsets, offnext, uv, bit, d_status, s))); break;
+    }
+    if (sp > 0) {
+        hipLaunchKernelGGL((k_s_place<T>), grid, dim3(PT), s_lds, s, cells, d.sfx, d.d_ncells, ncap, words, sp, gmax,
+                           w.cntS, w.s_stash, w.s_stash_n, d_offsets, offnext, uv, bit, cap);
+        CG_LAUNCHED("edges_s_place");
+    }
+    return CG_OK;
+}
+
+template <typename T>
+cg_status edges_generic(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap, int64_t *d_nedges,
+                        int64_t *d_offsets, const EdgesWs &w, int32_t *d_status, hipStream_t s) {
     int64_t *offsets = d_offsets ? d_offsets : w.offsets;
     const int64_t ncap = d.ncells_cap;
     const T *cells = static_cast<const T *>(d.cells);
@@ -192,12 +784,21 @@ cg_status edges_impl(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap,
     return CG_OK;
 }
 
+template <typename T>
+cg_status edges_impl(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap, int64_t *d_nedges,
+                     int64_t *d_offsets, void *ws, int32_t *d_status, hipStream_t s) {
+    size_t b;
+    EdgesWs w = carve_edges(ws, d.ncells_cap, &b);
+    if (fast_path_ok(d)) return edges_fast<T>(d, uv, bit, cap, d_nedges, d_offsets, w, d_status, s);
+    return edges_generic<T>(d, uv, bit, cap, d_nedges, d_offsets, w, d_status, s);
+}
+
 }  // namespace
 
 size_t edges_workspace_bytes(const cg_dict &d, int64_t cap) {
     (void)cap;
     size_t b;
-    carve_edges(nullptr, d.ncells_cap, true, &b);
+    carve_edges(nullptr, d.ncells_cap, &b);
     return b;
 }
 

@@ -66,6 +66,12 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src) {
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
+__device__ __forceinline__ uint64_t shfl_u64_xor(uint64_t x, int m) {
+    uint32_t lo = static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint32_t>(x)), m, 64));
+    uint32_t hi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint32_t>(x >> 32)), m, 64));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 // Inclusive prefix sum across the 64 lanes of a wave.
 __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
     int l = lane_id();
@@ -175,6 +181,54 @@ __device__ __forceinline__ int dist_upto2(const T *a, const T *b, int words, int
     return d;
 }
 
+// Hamming distance without early exit, loading 8 words per batch so their
+// loads are in flight together (what global-memory rows want).  *pos gets
+// the first differing position (meaningful when the distance is 1).
+template <typename T>
+__device__ __forceinline__ int dist_full(const T *a, const T *b, int words, int *pos) {
+    int d = 0;
+    int first = -1;
+    for (int w0 = 0; w0 < words; w0 += 8) {
+        T x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int w = w0 + u;
+            x[u] = w < words ? (a[w] ^ b[w]) : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            d += popc<T>(x[u]);
+            if (x[u] && first < 0) first = (w0 + u) * Bits<T>::B + clz_t<T>(x[u]);
+        }
+    }
+    *pos = first;
+    return d;
+}
+
+// Block-wide copy of nrows contiguous global rows (`words` words each) into
+// LDS rows of stride LW, with U loads in flight per thread (a plain loop with
+// a run-time trip count would wait for each load before the next).
+template <typename T, int NT, int U = 16>
+__device__ __forceinline__ void copy_rows_to_lds(T *lds, int LW, const T *__restrict__ src, int nrows, int words) {
+    const int tot = nrows * words;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += NT * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * NT;
+            v[u] = e < tot ? src[e] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * NT;
+            if (e < tot) {
+                const int r = e / words;
+                lds[r * LW + (e - r * words)] = v[u];
+            }
+        }
+    }
+}
+
 // Index of the cell equal to (q xor e_k) within the sorted rows [lo, hi), or
 // -1.  k < 0 looks up q itself.
 template <typename T>
@@ -206,6 +260,69 @@ __device__ __forceinline__ int64_t load_n(const int64_t *d_n, int64_t cap) {
     if (!d_n) return cap;
     int64_t n = *d_n;
     return n < cap ? (n < 0 ? 0 : n) : cap;
+}
+
+// ------------------------------------------------ decoupled look-back scan
+
+// Tile status words: value in the low 62 bits, flag in the top two.
+constexpr uint64_t LB_AGG = 1ull << 62;   // tile aggregate published
+constexpr uint64_t LB_INC = 2ull << 62;   // inclusive prefix published
+constexpr uint64_t LB_VAL = (1ull << 62) - 1;
+constexpr int LB_SPIN_LIMIT = 1 << 22;
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block-wide: given this tile's aggregate (same value in every thread) and
+// its ticket t (tiles are taken in ticket order, so every tile below t is
+// already running), returns the sum of the aggregates of tiles 0 .. t-1.
+// status[] must be zero before the launch.  A wait that exceeds the spin
+// limit sets *err and gives up (the result is then invalid, never a hang).
+// Contains __syncthreads().
+__device__ __forceinline__ uint64_t lookback_exclusive(uint64_t *status, int64_t t, uint64_t agg, uint32_t *err,
+                                                       uint64_t *slot) {
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        uint64_t excl = 0;
+        if (t == 0) {
+            if (lane == 0) lb_store(&status[0], LB_INC | agg);
+        } else {
+            if (lane == 0) lb_store(&status[t], LB_AGG | agg);
+            int64_t look = t - 1;
+            int spins = 0;
+            while (true) {
+                const int64_t idx = look - lane;
+                const uint64_t v = idx >= 0 ? lb_load(&status[idx]) : LB_INC;
+                const uint64_t fl = v >> 62;
+                const uint64_t pmask = ballot64(fl == 2);
+                const uint64_t xmask = ballot64(fl == 0);
+                const int firstP = pmask ? __builtin_ctzll(pmask) : 64;
+                const uint64_t need = firstP >= 63 ? ~0ull : ((2ull << firstP) - 1);
+                if (xmask & need) {
+                    if (++spins > LB_SPIN_LIMIT) {
+                        if (lane == 0) atomicOr(err, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                uint64_t val = lane <= firstP ? (v & LB_VAL) : 0;
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) val += shfl_u64_xor(val, d);
+                excl += val;
+                if (firstP < 64) break;
+                look -= 64;
+            }
+            if (lane == 0) lb_store(&status[t], LB_INC | ((excl + agg) & LB_VAL));
+        }
+        if (lane == 0) *slot = excl;
+    }
+    __syncthreads();
+    return *slot;
 }
 
 // -------------------------------------------------------- host-side helpers

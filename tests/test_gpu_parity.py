@@ -353,3 +353,30 @@ def test_config3_scenes(gpu, i):
     R = inputs.c3_scene(i)
     wb = 32 if i % 2 else 64
     assert_same(P.cell_graph(R, ell, wb), oracle_graph(R, ell, wb))
+
+
+@pytest.mark.parametrize("ell,kw", [(10, dict(split_bit=0, group_max=1024)), (12, dict(split_bit=0, group_max=1024)),
+                                    (12, dict(split_bit=3)), (12, dict()), (11, dict(split_bit=11, group_max=8))])
+def test_dense_hypercube_stash_overflow(gpu, ell, kw):
+    """Full hypercubes: many edges per tile, so the per-tile edge stashes
+    overflow and placement recomputes; long prefix groups take look-ups."""
+    torch, B, P = gpu
+    say("dense cube", ell, kw)
+    n = 2 ** ell
+    R = ((np.arange(n)[:, None] >> np.arange(ell - 1, -1, -1)[None, :]) & 1).astype(np.uint8)
+    R = R[np.random.default_rng(ell).permutation(n)]
+    for wb in (32, 64):
+        res = P.cell_graph(R, ell, wb, params=B.cg_dict_params_default(**kw))
+        assert res["nedges"] == ell * 2 ** (ell - 1)
+        assert_same(res, oracle_graph(R, ell, wb))
+
+
+def test_wide_rows_generic_paths(gpu):
+    """Rows too wide for the LDS tiles (l = 4000): the generic edge passes and
+    the large-segment dedup path."""
+    torch, B, P = gpu
+    rng = np.random.default_rng(21)
+    R = inputs.clustered_multiset(rng, 60, 4000, 3, 40)
+    say("wide rows", R.shape)
+    for wb in (32, 64):
+        assert_same(P.cell_graph(R, 4000, wb), oracle_graph(R, 4000, wb))
