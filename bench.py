@@ -65,10 +65,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-dedup-rows", type=int, default=400_000)
     ap.add_argument("--cpu-pair-samples", type=int, default=96)
+    ap.add_argument("--workload", choices=("long", "batched", "served"), default="long",
+                    help="long: 1024-bit vectors (the headline); batched: 512 plane scenes in one graph; "
+                         "served: Poisson stream of those scenes")
+    ap.add_argument("--scenes", type=int, default=512)
+    ap.add_argument("--seconds", type=float, default=5.0, help="served: trace length")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "served":
+        return bench_served(args)
 
     import torch
     from paper_1503_06029_amd import binding as B, inputs, pipeline
@@ -162,6 +171,103 @@ def main():
     if not ok:
         log(f"WRONG RESULT: cells {nc} (want {want_cells}), edges {E} (want {want_E}), status {status}")
         sys.exit(1)
+
+
+def scene_pool(k):
+    from paper_1503_06029_amd import inputs
+    return [inputs.c3_scene(i) for i in range(k)]
+
+
+def bench_batched(args):
+    """512 scenes (l uniform in 16..512 planes, log-uniform sample counts) as
+    one captured graph, against plain per-scene launch chains."""
+    import torch
+    from paper_1503_06029_amd import batch, pipeline
+    log("generating scenes")
+    scenes = scene_pool(args.scenes)
+    shapes = [(R.shape[0], R.shape[1]) for R in scenes]
+    rows = sum(n for n, _ in shapes)
+    runner = batch.BatchRunner(shapes)
+    runner.upload(scenes)
+    runner.run_checked()
+    runner.capture()
+    for _ in range(args.warmup):
+        runner.replay()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for k in range(args.steps):
+        runner.replay()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+    cells, edges = runner.totals()
+    log("per-scene baseline")
+    graphs = []
+    for R in scenes:
+        g = pipeline.CellGraph(R.shape[0], R.shape[1], 32, edge_cap=max(4096, 4 * R.shape[0]))
+        bits = torch.from_numpy(np.ascontiguousarray(R)).cuda()
+        graphs.append((g, bits))
+    for g, bits in graphs:  # warm up, size buffers
+        if bits.shape[0]:
+            g.pack(bits)
+        g.run_checked()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g, bits in graphs:
+        if bits.shape[0]:
+            g.pack(bits)
+        g.run()
+    torch.cuda.synchronize()
+    base_ms = (time.perf_counter() - t0) * 1e3
+    base_edges = sum(int(g.nedges.item()) for g, _ in graphs)
+    ms = float(step_ms.mean())
+    out = {
+        "metric": "batched scenes: cell-graph edges/s, one captured graph vs per-scene launches",
+        "value": edges / (ms / 1e3), "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(scenes)} scenes, l uniform 16..512 planes in R^3, log-uniform 1e3..2e5 "
+                               f"points ({rows} rows)", "cells": cells, "edges": edges},
+        "rows_per_s": rows / (ms / 1e3),
+        "p50_ms": float(np.percentile(step_ms, 50)), "p99_ms": float(np.percentile(step_ms, 99)),
+        "per_scene_ms": base_ms, "speedup_vs_per_scene": base_ms / ms,
+        "correct": base_edges == edges,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(args):
+    """Poisson arrivals at 2,000 scenes/s over the scene pool: continuous
+    batching against serial per-scene launches; p50/p99 latency."""
+    import torch
+    from paper_1503_06029_amd import inputs, serve
+    log("generating scene pool")
+    pool = scene_pool(args.scenes)
+    t, sc = inputs.c4_trace(seconds=args.seconds)
+    t = np.asarray(t)
+    log(f"{len(t)} requests over {args.seconds} s")
+    srv = serve.Server(pool)
+    # warm-up: a short burst
+    srv.serve(np.zeros(8), sc[:8])
+    lat, _, wall = srv.serve(t, sc)
+    log("per-scene baseline")
+    base = serve.PerSceneBaseline(pool)
+    base.serve(np.zeros(4), sc[:4])
+    blat, _, bwall = base.serve(t, sc)
+    rows = sum(pool[int(i)].shape[0] for i in sc)
+    out = {
+        "metric": "served scenes: requests/s and p50/p99 latency, continuous batching vs per-scene launches",
+        "value": len(t) / wall, "unit": "requests/s", "n_gpus": 1, "steps": len(t), "warmup": 8,
+        "ms_per_step": wall * 1e3 / len(t), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"Poisson 2000/s for {args.seconds} s over {len(pool)} scenes "
+                               "(l 16..512, 1e3..2e5 points)", "requests": int(len(t)), "rows": int(rows)},
+        "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "baseline": {"requests_per_s": len(t) / bwall, "p50_ms": float(np.percentile(blat, 50) * 1e3),
+                     "p99_ms": float(np.percentile(blat, 99) * 1e3)},
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

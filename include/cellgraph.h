@@ -204,6 +204,47 @@ cg_status cg_edges(const cg_dict *dict, uint32_t *d_uv, uint16_t *d_bit, int64_t
                    int64_t *d_nedges, int64_t *d_offsets, void *d_ws, size_t ws_bytes,
                    int32_t *d_status, cg_stream_t stream);
 
+/* --------------------------------------------------------- batched scenes
+ * Many independent scenes (each its own multiset of sign vectors, with its
+ * own l, Section 2.2) in one pass.  The scenes of a batch are packed into one
+ * virtual scene whose rows are 32-bit words: word 0 holds the scene number
+ * twice ((j << 16) | j), so rows of different scenes differ in at least two
+ * bits and are never neighbours; words 1.. hold the scene's vector (MSB
+ * first, zero beyond its l).  cg_dedup / cg_dict_build / cg_edges then run
+ * unchanged on the virtual scene: cells come out grouped by scene (word 0 is
+ * most significant), each scene's cells in lexicographic order, and its
+ * edges form a contiguous slice of the edge list.  cg_batch_split finds
+ * those slices and rewrites ids and bit positions to scene-local values.
+ * At most 65536 scenes per batch. */
+
+/* Layout of the virtual scene for scenes of length at most ell_max: 32-bit
+ * words, 1 + ceil(ell_max / 32) of them (l = 32 + 32 * that). */
+cg_status cg_batch_layout(int32_t ell_max, cg_layout *lay);
+
+/* Packs the scenes into virtual rows.  Scene j (0 <= j < n_scenes) has
+ * scene_rows[j+1] - scene_rows[j] rows of scene_ell[j] sign bytes each,
+ * row r at d_bits + bits_off[j] + r * scene_ell[j]; it becomes virtual rows
+ * scene_rows[j] .. scene_rows[j+1]-1.  d_scene_rows (n_scenes + 1 entries,
+ * exclusive prefix sums, first 0), d_bits_off and d_scene_ell are device
+ * arrays.  Writes scene_rows[n_scenes] * lay.words words to d_packed.
+ * Errors: CG_EINVAL (lay not from cg_batch_layout, scene l > the layout's,
+ * n_scenes out of 0..65536, NULL pointers). */
+cg_status cg_batch_pack(const uint8_t *d_bits, const int64_t *d_bits_off, const int32_t *d_scene_ell,
+                        const int64_t *d_scene_rows, int32_t n_scenes, int64_t n_rows, cg_layout lay,
+                        void *d_packed, cg_stream_t stream);
+
+/* After cg_edges on the virtual scene's dictionary (with d_offsets):
+ *   d_cell_off (n_scenes + 1 int64) <- first virtual cell of each scene;
+ *   d_edge_off (n_scenes + 1 int64) <- first edge of each scene;
+ * and, if localize != 0, rewrites d_uv[0 .. min(|E|, cap)) to scene-local
+ * cell ids and d_bit (nullable) to scene-local positions (minus 32), and
+ * d_row_to_cell (nullable, n_rows) to scene-local cell ids.
+ * Errors: CG_EINVAL. */
+cg_status cg_batch_split(const cg_dict *dict, int32_t n_scenes, const int64_t *d_offsets,
+                         const int64_t *d_nedges, int64_t cap, int64_t *d_cell_off, int64_t *d_edge_off,
+                         int32_t localize, uint32_t *d_uv, uint16_t *d_bit, uint32_t *d_row_to_cell,
+                         const int64_t *d_scene_rows, int64_t n_rows, cg_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

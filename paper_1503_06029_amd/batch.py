@@ -1,0 +1,233 @@
+"""Batched scenes: many independent scenes through one set of launches.
+
+Scenes are grouped by width into classes (virtual rows of 2, 4, 8, 16 or 32
+32-bit words: one tag word holding the scene number twice, then the
+scene's vector).  Each class is one virtual scene for the ordinary
+``cg_dedup`` / ``cg_dict_build`` / ``cg_edges`` calls; ``cg_batch_split``
+finds every scene's slice and makes ids and positions scene-local.  Classes
+run on their own streams and the whole batch can be captured into one HIP
+graph (``BatchRunner.capture``), so a replay is a single graph launch.
+
+Only buffer management and argument marshalling live here.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+CLASS_WORDS = (2, 4, 8, 16, 32)  # tag word + data words, a power of two
+
+
+def class_words(ell: int) -> int:
+    need = 1 + -(-ell // 32)
+    for w in CLASS_WORDS:
+        if need <= w:
+            return w
+    raise ValueError(f"l = {ell} is too long for a batch class (max {32 * (CLASS_WORDS[-1] - 1)})")
+
+
+class SceneBatch:
+    """One width class: scenes of lengths ``ells`` and row counts ``ns``.
+
+    Buffers are sized for capacities (rows, scenes, sign bytes, edges), so the
+    same object can take another set of scenes with ``set_scenes`` (the
+    serving loop reuses it batch after batch)."""
+
+    def __init__(self, ells, ns, words: int, params: B.DictParams | None = None, edge_cap: int | None = None,
+                 device="cuda", max_rows: int | None = None, max_scenes: int | None = None,
+                 max_bytes: int | None = None):
+        ells = np.asarray(ells, dtype=np.int32)
+        ns = np.asarray(ns, dtype=np.int64)
+        self.words = words
+        self.lay = B.cg_batch_layout(32 * (words - 1))
+        assert self.lay.words == words
+        self.device = torch.device(device)
+        dev = self.device
+        self.cap_rows = int(max_rows if max_rows is not None else ns.sum())
+        self.cap_scenes = int(max_scenes if max_scenes is not None else len(ells))
+        self.cap_bytes = int(max_bytes if max_bytes is not None else (ns * ells).sum())
+        m = max(self.cap_rows, 1)
+        self.scene_rows = torch.zeros(self.cap_scenes + 1, dtype=torch.int64, device=dev)
+        self.bits_off = torch.zeros(max(self.cap_scenes, 1), dtype=torch.int64, device=dev)
+        self.scene_ell = torch.zeros(max(self.cap_scenes, 1), dtype=torch.int32, device=dev)
+        self.bits = torch.empty(max(self.cap_bytes, 16), dtype=torch.uint8, device=dev)
+        self.packed = torch.empty((m, words), dtype=torch.int32, device=dev)
+        self.cells = torch.empty((m, words), dtype=torch.int32, device=dev)
+        self.r2c = torch.empty(m, dtype=torch.int32, device=dev)
+        self.ncells = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.ws_dedup_bytes = B.cg_dedup_workspace(self.cap_rows, self.lay)
+        self.ws_dedup = torch.empty(self.ws_dedup_bytes, dtype=torch.uint8, device=dev)
+        self.params = params if params is not None else B.cg_dict_params_default()
+        self.dict_bytes = B.cg_dict_size(self.cap_rows, self.lay, self.params)
+        self.dict_mem = torch.empty(self.dict_bytes, dtype=torch.uint8, device=dev)
+        self.edge_cap = int(edge_cap if edge_cap is not None else max(4096, 4 * self.cap_rows))
+        self.uv = torch.empty((self.edge_cap, 2), dtype=torch.int32, device=dev)
+        self.bit = torch.empty(self.edge_cap, dtype=torch.int16, device=dev)
+        self.offsets = torch.empty(m + 1, dtype=torch.int64, device=dev)
+        self.nedges = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.cell_off = torch.zeros(self.cap_scenes + 1, dtype=torch.int64, device=dev)
+        self.edge_off = torch.zeros(self.cap_scenes + 1, dtype=torch.int64, device=dev)
+        self.dict = None
+        self.ws_edges = None
+        self.ws_edges_bytes = 0
+        self.set_scenes(ells, ns)
+
+    def set_scenes(self, ells, ns):
+        """Point the batch at a new set of scenes (within capacity)."""
+        self.ells = np.asarray(ells, dtype=np.int32)
+        self.ns = np.asarray(ns, dtype=np.int64)
+        self.n_scenes = len(self.ells)
+        assert 1 <= self.n_scenes <= self.cap_scenes
+        rows = np.zeros(self.n_scenes + 1, dtype=np.int64)
+        rows[1:] = np.cumsum(self.ns)
+        bytes_per = self.ns * self.ells
+        boff = np.zeros(self.n_scenes, dtype=np.int64)
+        boff[1:] = np.cumsum(bytes_per)[:-1]
+        self.n_rows = int(rows[-1])
+        self.total_bytes = int(bytes_per.sum())
+        assert self.n_rows <= self.cap_rows and self.total_bytes <= self.cap_bytes
+        assert int(self.ells.max()) <= 32 * (self.words - 1)
+        self.scene_rows_h = rows
+        self.bits_off_h = boff
+        self.scene_rows[:self.n_scenes + 1].copy_(torch.from_numpy(rows))
+        self.bits_off[:self.n_scenes].copy_(torch.from_numpy(boff))
+        self.scene_ell[:self.n_scenes].copy_(torch.from_numpy(self.ells))
+
+    def upload(self, scenes, stream=None):
+        """Copy the scenes' uint8 sign matrices into the batch's byte buffer."""
+        host = np.empty(self.total_bytes, dtype=np.uint8)
+        for j, R in enumerate(scenes):
+            assert R.shape == (self.ns[j], self.ells[j])
+            o = self.bits_off_h[j]
+            host[o:o + R.size] = np.ascontiguousarray(R, dtype=np.uint8).reshape(-1)
+        if self.total_bytes:
+            self.bits[:self.total_bytes].copy_(torch.from_numpy(host), non_blocking=False)
+
+    def _edges_ws(self):
+        need = B.cg_edges_workspace(self.dict, self.edge_cap)
+        if self.ws_edges is None or need > self.ws_edges_bytes:
+            self.ws_edges = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self.ws_edges_bytes = need
+
+    def run(self, stream=None):
+        B.cg_batch_pack(self.bits, self.bits_off, self.scene_ell, self.scene_rows, self.n_scenes, self.n_rows,
+                        self.lay, self.packed, stream)
+        B.cg_dedup(self.packed, self.n_rows, self.lay, self.cells, self.r2c, self.ncells, self.ws_dedup,
+                   self.ws_dedup_bytes, stream)
+        self.dict = B.cg_dict_build(self.cells, self.ncells, self.n_rows, self.lay, self.params, self.dict_mem,
+                                    self.dict_bytes, stream)
+        self._edges_ws()  # allocates only when a larger batch needs more
+        B.cg_edges(self.dict, self.uv, self.bit, self.edge_cap, self.nedges, self.offsets, self.ws_edges,
+                   self.ws_edges_bytes, self.status, stream)
+        B.cg_batch_split(self.dict, self.n_scenes, self.offsets, self.nedges, self.edge_cap, self.cell_off,
+                         self.edge_off, True, self.uv, self.bit, self.r2c, self.scene_rows, self.n_rows, stream)
+
+    def ensure_capacity(self):
+        """After a run: grow the edge buffers if they overflowed (needs a re-run)."""
+        torch.cuda.synchronize()
+        if int(self.status.item()) == B.CG_ECAPACITY:
+            self.edge_cap = int(self.nedges.item())
+            self.uv = torch.empty((self.edge_cap, 2), dtype=torch.int32, device=self.device)
+            self.bit = torch.empty(self.edge_cap, dtype=torch.int16, device=self.device)
+            self._edges_ws()
+            return False
+        return True
+
+    def fetch(self, sync: bool = True):
+        """Per-scene host results: list of dicts (cells in the scene's own u32 layout).
+        With sync=False the copies are ordered on the current stream only."""
+        if sync:
+            torch.cuda.synchronize()
+        E = int(self.nedges.item())
+        nc = int(self.ncells.item())
+        cells = self.cells[:nc].cpu().numpy().view(np.uint32)
+        uv = self.uv[:E].cpu().numpy().view(np.uint32)
+        bit = self.bit[:E].cpu().numpy().view(np.uint16)
+        off = self.offsets[:nc + 1].cpu().numpy()
+        r2c = self.r2c[:self.n_rows].cpu().numpy().view(np.uint32)
+        co = self.cell_off.cpu().numpy()
+        eo = self.edge_off.cpu().numpy()
+        out = []
+        for j in range(self.n_scenes):
+            wj = -(-int(self.ells[j]) // 32)
+            a, b = co[j], co[j + 1]
+            out.append({
+                "ncells": int(b - a),
+                "nedges": int(eo[j + 1] - eo[j]),
+                "cells": cells[a:b, 1:1 + wj].copy(),
+                "uv": uv[eo[j]:eo[j + 1]].copy(),
+                "bit": bit[eo[j]:eo[j + 1]].copy(),
+                "offsets": off[a:b + 1] - eo[j],
+                "row_to_cell": r2c[self.scene_rows_h[j]:self.scene_rows_h[j + 1]].copy(),
+            })
+        return out
+
+
+class BatchRunner:
+    """All classes of a batch; ``run`` launches them on per-class streams,
+    ``capture`` records one HIP graph of the whole batch."""
+
+    def __init__(self, shapes, params_for=None, device="cuda"):
+        self.shapes = list(shapes)  # (n_j, ell_j)
+        groups = {}
+        for idx, (n, ell) in enumerate(self.shapes):
+            groups.setdefault(class_words(ell), []).append(idx)
+        self.classes = []
+        for w in sorted(groups):
+            ids = groups[w]
+            params = params_for(w, sum(self.shapes[i][0] for i in ids)) if params_for else None
+            sb = SceneBatch([self.shapes[i][1] for i in ids], [self.shapes[i][0] for i in ids], w, params,
+                            device=device)
+            self.classes.append((ids, sb))
+        self.streams = [torch.cuda.Stream() for _ in self.classes]
+        self.graph = None
+
+    def upload(self, scenes):
+        for ids, sb in self.classes:
+            sb.upload([scenes[i] for i in ids])
+
+    def run(self):
+        main = torch.cuda.current_stream()
+        for st, (ids, sb) in zip(self.streams, self.classes):
+            st.wait_stream(main)
+            with torch.cuda.stream(st):
+                sb.run(st)
+        for st in self.streams:
+            main.wait_stream(st)
+
+    def run_checked(self):
+        """run(); re-run any class whose edge buffer overflowed, with room."""
+        self.run()
+        torch.cuda.synchronize()
+        again = [sb for _, sb in self.classes if not sb.ensure_capacity()]
+        for sb in again:
+            sb.run()
+        torch.cuda.synchronize()
+
+    def capture(self):
+        """Record the whole batch (all classes, their streams) into one graph."""
+        self.graph = torch.cuda.CUDAGraph()
+        cap_stream = torch.cuda.Stream()
+        cap_stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(self.graph, stream=cap_stream):
+            self.run()
+        torch.cuda.synchronize()
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()
+
+    def fetch(self):
+        res = [None] * len(self.shapes)
+        for ids, sb in self.classes:
+            for i, r in zip(ids, sb.fetch()):
+                res[i] = r
+        return res
+
+    def totals(self):
+        torch.cuda.synchronize()
+        return (sum(int(sb.ncells.item()) for _, sb in self.classes),
+                sum(int(sb.nedges.item()) for _, sb in self.classes))

@@ -72,10 +72,15 @@ _sig("cg_dict_build", [c_vp, c_vp, c_i64, Layout, ctypes.POINTER(DictParams), c_
 _sig("cg_neighbors_d1", [ctypes.POINTER(Dict), c_vp, c_i64, c_vp, c_vp, c_vp, c_vp])
 _sig("cg_edges_workspace", [ctypes.POINTER(Dict), c_i64, ctypes.POINTER(c_sz)])
 _sig("cg_edges", [ctypes.POINTER(Dict), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp])
+_sig("cg_batch_layout", [c_i32, ctypes.POINTER(Layout)])
+_sig("cg_batch_pack", [c_vp, c_vp, c_vp, c_vp, c_i32, c_i64, Layout, c_vp, c_vp])
+_sig("cg_batch_split", [ctypes.POINTER(Dict), c_i32, c_vp, c_vp, c_i64, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
+                        c_i64, c_vp])
 
 EXPORTS = ("cg_version", "cg_status_string", "cg_last_error", "cg_make_layout", "cg_pack",
            "cg_dedup_workspace", "cg_dedup", "cg_dict_params_default", "cg_dict_size",
-           "cg_dict_build", "cg_neighbors_d1", "cg_edges_workspace", "cg_edges")
+           "cg_dict_build", "cg_neighbors_d1", "cg_edges_workspace", "cg_edges",
+           "cg_batch_layout", "cg_batch_pack", "cg_batch_split")
 
 
 def lib():
@@ -176,3 +181,23 @@ def cg_edges(d: Dict, d_uv, d_bit, cap: int, d_nedges, d_offsets, d_ws, ws_bytes
              stream=None):
     _check(_lib.cg_edges(ctypes.byref(d), _ptr(d_uv), _ptr(d_bit), cap, _ptr(d_nedges), _ptr(d_offsets),
                          _ptr(d_ws), ws_bytes, _ptr(d_status), _stream(stream)))
+
+
+def cg_batch_layout(ell_max: int) -> Layout:
+    lay = Layout()
+    _check(_lib.cg_batch_layout(ell_max, ctypes.byref(lay)))
+    return lay
+
+
+def cg_batch_pack(d_bits, d_bits_off, d_scene_ell, d_scene_rows, n_scenes: int, n_rows: int, lay: Layout,
+                  d_packed, stream=None):
+    _check(_lib.cg_batch_pack(_ptr(d_bits), _ptr(d_bits_off), _ptr(d_scene_ell), _ptr(d_scene_rows), n_scenes,
+                              n_rows, lay, _ptr(d_packed), _stream(stream)))
+
+
+def cg_batch_split(d: Dict, n_scenes: int, d_offsets, d_nedges, cap: int, d_cell_off, d_edge_off,
+                   localize: bool, d_uv=None, d_bit=None, d_row_to_cell=None, d_scene_rows=None, n_rows: int = 0,
+                   stream=None):
+    _check(_lib.cg_batch_split(ctypes.byref(d), n_scenes, _ptr(d_offsets), _ptr(d_nedges), cap, _ptr(d_cell_off),
+                               _ptr(d_edge_off), 1 if localize else 0, _ptr(d_uv), _ptr(d_bit),
+                               _ptr(d_row_to_cell), _ptr(d_scene_rows), n_rows, _stream(stream)))

@@ -202,4 +202,37 @@ cg_status cg_edges(const cg_dict *dict, uint32_t *d_uv, uint16_t *d_bit, int64_t
     return run_edges(*dict, d_uv, d_bit, cap, d_nedges, d_offsets, d_ws, ws_bytes, d_status, s);
 }
 
+cg_status cg_batch_layout(int32_t ell_max, cg_layout *lay) {
+    if (!lay) return set_error(CG_EINVAL, "cg_batch_layout: lay is NULL");
+    return batch_layout(ell_max, lay);
+}
+
+cg_status cg_batch_pack(const uint8_t *d_bits, const int64_t *d_bits_off, const int32_t *d_scene_ell,
+                        const int64_t *d_scene_rows, int32_t n_scenes, int64_t n_rows, cg_layout lay,
+                        void *d_packed, cg_stream_t stream) {
+    CG_TRY(check_layout(lay));
+    if (lay.word_bits != 32 || lay.ell != 32 * lay.words || lay.words < 2)
+        return set_error(CG_EINVAL, "cg_batch_pack: layout not made by cg_batch_layout");
+    if (n_rows < 0 || n_rows >= (int64_t(1) << 32)) return set_error(CG_EINVAL, "cg_batch_pack: n_rows out of range");
+    if (n_rows > 0 && (!d_bits || !d_bits_off || !d_scene_ell || !d_scene_rows || !d_packed))
+        return set_error(CG_EINVAL, "cg_batch_pack: NULL buffer");
+    return run_batch_pack(d_bits, d_bits_off, d_scene_ell, d_scene_rows, n_scenes, n_rows, lay, d_packed,
+                          reinterpret_cast<hipStream_t>(stream));
+}
+
+cg_status cg_batch_split(const cg_dict *dict, int32_t n_scenes, const int64_t *d_offsets, const int64_t *d_nedges,
+                         int64_t cap, int64_t *d_cell_off, int64_t *d_edge_off, int32_t localize, uint32_t *d_uv,
+                         uint16_t *d_bit, uint32_t *d_row_to_cell, const int64_t *d_scene_rows, int64_t n_rows,
+                         cg_stream_t stream) {
+    CG_TRY(check_dict(dict));
+    if (dict->lay.word_bits != 32 || dict->lay.words < 2)
+        return set_error(CG_EINVAL, "cg_batch_split: dictionary is not over a batched layout");
+    if (!d_offsets || !d_nedges || !d_cell_off || !d_edge_off) return set_error(CG_EINVAL, "cg_batch_split: NULL buffer");
+    if (localize && d_row_to_cell && n_rows > 0 && !d_scene_rows)
+        return set_error(CG_EINVAL, "cg_batch_split: d_scene_rows is NULL");
+    if (cap < 0) return set_error(CG_EINVAL, "cg_batch_split: cap < 0");
+    return run_batch_split(*dict, n_scenes, d_offsets, d_nedges, cap, d_cell_off, d_edge_off, localize, d_uv, d_bit,
+                           d_row_to_cell, d_scene_rows, n_rows, reinterpret_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

@@ -270,15 +270,48 @@ __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, con
         }
     }
     __syncthreads();
+    // Summary of each row against its segment's first row a: the first word
+    // f (past the sort key) where they differ (WT if equal) and the row's
+    // word there.  Two rows then compare by their summaries alone unless
+    // they differ from row a first in the same word with the same value.
+    uint8_t *sf = reinterpret_cast<uint8_t *>(sval + slots);
+    T *sv = reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(sf + slots + 7) & ~uintptr_t(7));
+    constexpr int FROM = 64 / Bits<T>::B;
+    for (int r = t; r < slots; r += TT) {
+        const int a = segof[r];
+        if (a < 0) continue;
+        const T *me = lrows + r * LW, *hd = lrows + a * LW;
+        int f = WT;
+        T v = 0;
+#pragma unroll
+        for (int w = WT - 1; w >= FROM; --w) {
+            const bool ne = me[w] != hd[w];
+            f = ne ? w : f;
+            v = ne ? me[w] : v;
+        }
+        sf[r] = static_cast<uint8_t>(f);
+        sv[r] = v;
+    }
+    __syncthreads();
     for (int r = t; r < slots; r += TT) {
         const int a = segof[r];
         if (a < 0) continue;
         const int len = seglen[r];
-        const T *me = lrows + r * LW;
+        const T *me = lrows + r * LW, *hd = lrows + a * LW;
+        const int fm = sf[r];
+        const T vm = sv[r];
+        const T hm = fm < WT ? hd[fm] : T(0);
         int rank = 0;
         bool dup = false;
         for (int j = a; j < a + len; ++j) {
-            const int c = lex_cmp_t<T, WT>(lrows + j * LW, me);
+            const int fj = sf[j];
+            const T vj = sv[j];
+            int c;  // compare row j with row r
+            if (fj < fm) c = vj < hd[fj] ? -1 : 1;
+            else if (fj > fm) c = hm < vm ? -1 : 1;
+            else if (fj == WT) c = 0;
+            else if (vj != vm) c = vj < vm ? -1 : 1;
+            else c = lex_cmp_t<T, WT>(lrows + j * LW, me);
             rank += (c < 0 || (c == 0 && j < r)) ? 1 : 0;
             dup = dup || (c == 0 && j < r);
         }
@@ -289,13 +322,14 @@ __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, con
 
 template <typename T, int WT>
 size_t tiefix_t_lds(int smax) {
-    return static_cast<size_t>(TT + smax + 1) * 8 + static_cast<size_t>(TT + smax) * ((WT + 1) * sizeof(T) + 12);
+    const size_t slots = static_cast<size_t>(TT + smax);
+    return (slots + 1) * 8 + slots * ((WT + 1) * sizeof(T) + 12) + slots + 8 + slots * sizeof(T);
 }
 
 template <typename T, int WT>
 int tiefix_t_smax() {
-    const int64_t per = (WT + 1) * static_cast<int64_t>(sizeof(T)) + 20;
-    int64_t smax = (TILE_LDS - 8) / per - TT - 1;
+    const int64_t per = (WT + 2) * static_cast<int64_t>(sizeof(T)) + 21;
+    int64_t smax = (TILE_LDS - 16) / per - TT - 1;
     if (smax > 512) smax = 512;
     return static_cast<int>(smax);
 }

@@ -203,33 +203,6 @@ __device__ __forceinline__ SRun s_run(const uint32_t *hs, const uint32_t *ids, i
     return r;
 }
 
-// Calls f(v, k, rank) for each S-neighbour v > id in ascending v; returns the
-// count.
-template <typename T, class F>
-__device__ __forceinline__ uint32_t s_neighbours(const SRun &r, const uint32_t *ids, int64_t win0,
-                                                 const T *__restrict__ cells, int64_t n, int words, int s, F f) {
-    uint32_t c = 0;
-    if (r.hi <= r.lo) return 0;
-    const T *me = cells + static_cast<int64_t>(r.id) * words;
-    if (r.big) {
-        for (int k = s - 1; k >= 0; --k) {
-            if (get_bit<T>(me, k)) continue;
-            const int64_t v = find_row<T>(cells, words, static_cast<int64_t>(r.id) + 1, n, me, k);
-            if (v >= 0) { f(static_cast<uint32_t>(v), k, c); ++c; }
-        }
-    } else {
-        for (int64_t rr = r.lo; rr <= r.hi; ++rr) {
-            const uint32_t v = ids[rr - win0];
-            int pos;
-            if (v > r.id && dist_full<T>(me, cells + static_cast<int64_t>(v) * words, words, &pos) == 1 && pos < s) {
-                f(v, pos, c);
-                ++c;
-            }
-        }
-    }
-    return c;
-}
-
 // Loads the suffix-order window [tile * PT - rmax - 1, tile * PT + PT + rmax + 1)
 // into LDS; returns win0.  Block-wide.
 __device__ __forceinline__ int64_t load_s_window(uint32_t *hs, uint32_t *ids, const uint64_t *__restrict__ sfx,
@@ -256,77 +229,149 @@ __device__ __forceinline__ int64_t load_s_window(uint32_t *hs, uint32_t *ids, co
     return win0;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(PT) k_s_find(const T *__restrict__ cells, const uint64_t *__restrict__ sfx,
+// S pass over one tile of the suffix order.  Runs are found in the LDS
+// window; the rows of every window position that belongs to a scanned run
+// (2..rmax members) are gathered into LDS once (up to SCAP rows; the rest are
+// compared in global memory), then each cell compares its row with the later
+// members of its run.
+constexpr int SRMAX = 64;   // longest scanned run; longer runs use look-ups
+constexpr int SWIN = PT + 2 * (SRMAX + 1);
+constexpr int SCAP = 160;   // rows staged per tile
+
+template <typename T, int WT> struct SFind {
+    static constexpr int LW = WT + 1;
+    // rows[SCAP] | hs[SWIN] | ids[SWIN] | slot[SWIN]
+    static constexpr size_t bytes = static_cast<size_t>(SCAP) * LW * sizeof(T) + 3 * SWIN * 4;
+};
+
+template <typename T, int WT, bool PLACE>
+__global__ void __launch_bounds__(PT) k_s_tile(const T *__restrict__ cells, const uint64_t *__restrict__ sfx,
                                                const int64_t *d_n, int64_t ncap, int words, int s, int rmax,
                                                uint32_t *__restrict__ cntS, uint4 *__restrict__ stash,
-                                               uint32_t *__restrict__ stash_n) {
+                                               uint32_t *__restrict__ stash_n, const int64_t *__restrict__ offsets,
+                                               const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
+                                               uint16_t *__restrict__ bit, int64_t cap) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint64_t tmp[4];
-    uint32_t *hs = reinterpret_cast<uint32_t *>(smem);
-    uint32_t *ids = hs + PT + 2 * (rmax + 1);
+    using L = SFind<T, WT>;
+    constexpr int LW = L::LW;
+    T *srows = reinterpret_cast<T *>(smem);
+    uint32_t *hs = reinterpret_cast<uint32_t *>(srows + SCAP * LW);
+    uint32_t *ids = hs + SWIN;
+    int32_t *slot = reinterpret_cast<int32_t *>(ids + SWIN);
     const int64_t n = load_n(d_n, ncap);
     const int64_t tile = blockIdx.x;
-    const int64_t q = tile * PT + threadIdx.x;
     if (tile * PT >= n) return;
-    const int64_t win0 = load_s_window(hs, ids, sfx, tile, n, rmax);
+    if (PLACE && stash_n[tile] <= static_cast<uint32_t>(S_STASH)) return;  // the stash already holds this tile
+    const int64_t q = tile * PT + threadIdx.x;
+    for (int e = threadIdx.x; e < SWIN; e += PT) slot[e] = -1;
+    const int64_t win0 = load_s_window(hs, ids, sfx, tile, n, SRMAX);  // contains a barrier
     SRun r{0, 0, -1, false};
-    uint32_t c = 0;
-    if (q < n) {
-        r = s_run(hs, ids, win0, q, n, rmax);
-        c = s_neighbours<T>(r, ids, win0, cells, n, words, s, [](uint32_t, int, uint32_t) {});
-    }
+    if (q < n) r = s_run(hs, ids, win0, q, n, rmax);
+    const bool scan = q < n && r.hi > r.lo && !r.big;
+    if (scan)
+        for (int64_t p = r.lo; p <= r.hi; ++p) slot[p - win0] = 0;  // needed
+    __syncthreads();
+    // number the needed window positions (two per thread at most)
+    int need0 = 0;
+    for (int e = threadIdx.x * 2; e < threadIdx.x * 2 + 2; ++e) need0 += (e < SWIN && slot[e] == 0) ? 1 : 0;
     uint64_t tot;
-    const uint64_t ex = block256_excl_scan_u64(c, tmp, &tot);
-    if (threadIdx.x == 0) stash_n[tile] = static_cast<uint32_t>(tot > 0xffffffffull ? 0xffffffffull : tot);
-    if (c == 0) return;
-    cntS[r.id] = c;
-    if (tot > static_cast<uint64_t>(S_STASH)) return;  // placement recomputes this tile
-    uint4 *out = stash + tile * S_STASH + ex;
-    const uint32_t id = r.id;
-    s_neighbours<T>(r, ids, win0, cells, n, words, s, [&](uint32_t v, int k, uint32_t rank) {
-        out[rank] = make_uint4(id, v, static_cast<uint32_t>(k) | (rank << 16), c);
-    });
+    int k = static_cast<int>(block256_excl_scan_u64(static_cast<uint64_t>(need0), tmp, &tot));
+    for (int e = threadIdx.x * 2; e < threadIdx.x * 2 + 2; ++e)
+        if (e < SWIN && slot[e] == 0) slot[e] = k < SCAP ? k++ : (++k, -2);  // -2: not staged
+    __syncthreads();
+    // gather the staged rows (each staged slot's row; U loads in flight)
+    const int nst = static_cast<int>(tot < SCAP ? tot : SCAP);
+    {
+        constexpr int U = 8;
+        const int totw = SWIN * WT;
+        for (int e0 = threadIdx.x; e0 < totw; e0 += PT * U) {
+            T v[U];
+            int dst[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * PT;
+                const int ps = e / WT, w = e % WT;
+                const int sl = e < totw ? slot[ps] : -1;
+                dst[u] = sl >= 0 ? sl * LW + w : -1;
+                v[u] = (sl >= 0 && w < words) ? cells[static_cast<int64_t>(ids[ps]) * words + w] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (dst[u] >= 0) srows[dst[u]] = v[u];
+        }
+    }
+    (void)nst;
+    __syncthreads();
+    // compare my row with the later members of my run
+    auto for_each = [&](auto f) -> uint32_t {
+        uint32_t c = 0;
+        if (!(q < n) || r.hi <= r.lo) return 0;
+        const T *gme = cells + static_cast<int64_t>(r.id) * words;
+        if (r.big) {
+            for (int kk = s - 1; kk >= 0; --kk) {
+                if (get_bit<T>(gme, kk)) continue;
+                const int64_t v = find_row<T>(cells, words, static_cast<int64_t>(r.id) + 1, n, gme, kk);
+                if (v >= 0) { f(static_cast<uint32_t>(v), kk, c); ++c; }
+            }
+            return c;
+        }
+        const int ms = slot[q - win0];
+        for (int64_t p = r.lo; p <= r.hi; ++p) {
+            const uint32_t v = ids[p - win0];
+            if (v <= r.id) continue;
+            const int os = slot[p - win0];
+            int pos, dd;
+            if (ms >= 0 && os >= 0) dd = dist_t<T, WT>(srows + ms * LW, srows + os * LW, &pos);
+            else dd = dist_full<T>(gme, cells + static_cast<int64_t>(v) * words, words, &pos);
+            if (dd == 1 && pos < s) { f(v, pos, c); ++c; }
+        }
+        return c;
+    };
+    if (!PLACE) {
+        const uint32_t c = for_each([](uint32_t, int, uint32_t) {});
+        uint64_t tc;
+        const uint64_t ex = block256_excl_scan_u64(c, tmp, &tc);
+        if (threadIdx.x == 0) stash_n[tile] = static_cast<uint32_t>(tc > 0xffffffffull ? 0xffffffffull : tc);
+        if (c == 0) return;
+        cntS[r.id] = c;
+        if (tc > static_cast<uint64_t>(S_STASH)) return;  // placement recomputes this tile
+        uint4 *out = stash + tile * S_STASH + ex;
+        const uint32_t id = r.id;
+        for_each([&](uint32_t v, int kk, uint32_t rank) {
+            out[rank] = make_uint4(id, v, static_cast<uint32_t>(kk) | (rank << 16), c);
+        });
+    } else {
+        if (!(q < n)) return;
+        const uint32_t c = cntS[r.id];
+        if (c == 0) return;
+        const int64_t next = offsets ? offsets[static_cast<int64_t>(r.id) + 1] : offnext[r.id];
+        const uint32_t id = r.id;
+        for_each([&](uint32_t v, int kk, uint32_t rank) { emit(uv, bit, cap, next - c + rank, id, v, kk); });
+    }
 }
 
 __device__ __forceinline__ void emit(uint32_t *uv, uint16_t *bit, int64_t cap, int64_t pos, uint32_t u,
                                      uint32_t v, int k);
 
-template <typename T>
-__global__ void __launch_bounds__(PT) k_s_place(const T *__restrict__ cells, const uint64_t *__restrict__ sfx,
-                                                const int64_t *d_n, int64_t ncap, int words, int s, int rmax,
-                                                const uint32_t *__restrict__ cntS, const uint4 *__restrict__ stash,
+// Drop the stashed S edges of each tile into their slots:
+// next(u) - cntS[u] + rank.  Tiles whose stash overflowed are redone by
+// k_s_tile<.., true>.
+__global__ void __launch_bounds__(PT) k_s_place(const int64_t *d_n, int64_t ncap, const uint4 *__restrict__ stash,
                                                 const uint32_t *__restrict__ stash_n,
                                                 const int64_t *__restrict__ offsets,
                                                 const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
                                                 uint16_t *__restrict__ bit, int64_t cap) {
-    extern __shared__ __align__(16) unsigned char smem[];
     const int64_t n = load_n(d_n, ncap);
     const int64_t tile = blockIdx.x;
     if (tile * PT >= n) return;
     const uint32_t m = stash_n[tile];
-    if (m <= static_cast<uint32_t>(S_STASH)) {
-        for (uint32_t e = threadIdx.x; e < m; e += PT) {
-            const uint4 r = stash[tile * S_STASH + e];
-            const int64_t next = offsets ? offsets[static_cast<int64_t>(r.x) + 1] : offnext[r.x];
-            emit(uv, bit, cap, next - r.w + (r.z >> 16), r.x, r.y, static_cast<int>(r.z & 0xffffu));
-        }
-        return;
+    if (m > static_cast<uint32_t>(S_STASH)) return;
+    for (uint32_t e = threadIdx.x; e < m; e += PT) {
+        const uint4 r = stash[tile * S_STASH + e];
+        const int64_t next = offsets ? offsets[static_cast<int64_t>(r.x) + 1] : offnext[r.x];
+        emit(uv, bit, cap, next - r.w + (r.z >> 16), r.x, r.y, static_cast<int>(r.z & 0xffffu));
     }
-    // overflowed stash: recompute
-    uint32_t *hs = reinterpret_cast<uint32_t *>(smem);
-    uint32_t *ids = hs + PT + 2 * (rmax + 1);
-    const int64_t win0 = load_s_window(hs, ids, sfx, tile, n, rmax);
-    const int64_t q = tile * PT + threadIdx.x;
-    if (q >= n) return;
-    const SRun r = s_run(hs, ids, win0, q, n, rmax);
-    const uint32_t c = cntS[r.id];
-    if (r.hi <= r.lo || c == 0) return;
-    const int64_t next = offsets ? offsets[static_cast<int64_t>(r.id) + 1] : offnext[r.id];
-    const uint32_t id = r.id;
-    s_neighbours<T>(r, ids, win0, cells, n, words, s, [&](uint32_t v, int k, uint32_t rank) {
-        emit(uv, bit, cap, next - c + rank, id, v, k);
-    });
 }
 
 // ---------------------------------------------------------------- P tiles
@@ -381,22 +426,10 @@ __device__ __forceinline__ bool same_prefix_t(const T *a, const T *b, int s) {
     return acc == 0;
 }
 
-template <typename T, int WT>
-__device__ __forceinline__ int dist_t(const T *a, const T *b, int *pos) {
-    int d = 0, first = -1;
-#pragma unroll
-    for (int w = 0; w < WT; ++w) {
-        const T x = a[w] ^ b[w];
-        d += popc<T>(x);
-        first = (x && first < 0) ? w * Bits<T>::B + clz_t<T>(x) : first;
-    }
-    *pos = first;
-    return d;
-}
-
 // Loads the tile (tr rows) and its halo (rows after it sharing the last
 // row's first s bits, at most HALO) into LDS with popcounts and group heads
-// (heads[r] = 1 iff row r starts a prefix group; heads[tr + th] = 1).
+// (heads[r] = 1 iff row r starts a prefix group; heads[tr + th] = 0 iff the
+// last group may continue past the loaded rows).
 template <typename T, int WT>
 __device__ __forceinline__ int load_ptile(T *rows, uint32_t *pcs, uint8_t *heads, int *s_th,
                                           const T *__restrict__ cells, int words, int s, int64_t base, int64_t n,
@@ -424,7 +457,8 @@ __device__ __forceinline__ int load_ptile(T *rows, uint32_t *pcs, uint8_t *heads
         pcs[r] = pc;
         heads[r] = (r == 0 || !same_prefix_t<T, WT>(rows + (r - 1) * LW, me, s)) ? 1 : 0;
     }
-    if (threadIdx.x == 0) heads[tr + h] = 1;
+    // past the loaded rows: 0 if the last group may go on (full halo, more cells), else 1
+    if (threadIdx.x == 0) heads[tr + h] = (h == HALO && base + tr + h < n) ? 0 : 1;
     __syncthreads();
     *th = h;
     return tr;
@@ -452,8 +486,8 @@ __device__ __forceinline__ uint32_t p_scan_t(const T *rows, const uint32_t *pcs,
             if (dist_t<T, WT>(me, rows + jj * LW, &pos) == 1) { f(static_cast<uint32_t>(jj - t), pos, c); ++c; }
         }
     }
-    if (heads[tl]) {
-        // loaded rows ended inside the group: it may go on in global memory
+    if (!heads[tl]) {
+        // loaded rows ended inside the group: it goes on in global memory
         for (int64_t j = base + tl; j < n; ++j) {
             const T *o = cells + j * words;
             if (!same_prefix<T>(me, o, s)) break;
@@ -479,6 +513,24 @@ __device__ __forceinline__ uint32_t p_lookup(const T *__restrict__ cells, int64_
     return c;
 }
 
+// Count and record the P-neighbours of one tile.  Lanes walk their groups in
+// lock-step over the offset d = j - i (branch-free: one step costs a few
+// vector instructions), keeping only pairs whose popcounts differ by one (the
+// bound (*) against the zero vector).  Those candidates are queued per wave
+// and checked 64 at a time, so the full-row test runs on dense lanes.  A
+// found pair sets bit d - 1 of the cell's offset mask and is listed with its
+// position; since in-tile scans stop at d = PSCAN, a cell's rank of an edge
+// is the popcount of its mask below d.
+constexpr int CQ = 128;    // per-wave candidate ring
+constexpr int PSCAN = 64;  // longest in-tile scan; longer groups use look-ups
+
+template <typename T, int WT> struct PFind {
+    static constexpr int LW = WT + 1;
+    static constexpr size_t rows_bytes = static_cast<size_t>(PROWS) * LW * sizeof(T);
+    // rows | mask[PT] (u64) | pcs[PROWS + 1] | res[P_STASH] | cq[4][CQ] | heads[PROWS + 4]
+    static constexpr size_t bytes = rows_bytes + PT * 8 + (PROWS + 1) * 4 + P_STASH * 4 + 4 * CQ * 4 + PROWS + 4;
+};
+
 template <typename T, int WT>
 __global__ void __launch_bounds__(PT) k_p_find(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
                                                int words, int ell, int s, int gmax,
@@ -488,27 +540,91 @@ __global__ void __launch_bounds__(PT) k_p_find(const T *__restrict__ cells, cons
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint64_t tmp[4];
     __shared__ int s_th;
-    using L = PTile<T, WT>;
+    __shared__ uint32_t s_nres;
+    __shared__ uint32_t sbase[PT];
+    using L = PFind<T, WT>;
+    constexpr int LW = L::LW;
     T *rows = reinterpret_cast<T *>(smem);
-    uint32_t *pcs = reinterpret_cast<uint32_t *>(smem + L::rows_bytes);
-    uint32_t *nbl = pcs + PROWS;
-    uint8_t *heads = reinterpret_cast<uint8_t *>(nbl + PT * NB);
+    unsigned long long *mask = reinterpret_cast<unsigned long long *>(smem + L::rows_bytes);
+    uint32_t *pcs = reinterpret_cast<uint32_t *>(mask + PT);
+    uint32_t *res = pcs + PROWS + 1;
+    uint32_t *cq = res + P_STASH;
+    uint8_t *heads = reinterpret_cast<uint8_t *>(cq + 4 * CQ);
     const int64_t n = load_n(d_n, ncap);
     const int64_t tile = blockIdx.x;
     const int64_t base = tile * PT;
     if (base >= n) return;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    mask[t] = 0;
+    if (t == 0) s_nres = 0;
     int th;
     const int tr = load_ptile<T, WT>(rows, pcs, heads, &s_th, cells, words, s, base, n, &th);
-    const int t = threadIdx.x;
+    const int tl = tr + th;
+    if (t == 0) pcs[tl] = 0xffffffffu;  // clamp target past the loaded rows
+    __syncthreads();
     const int64_t i = base + t;
-    uint32_t *mine = nbl + t * NB;
+    uint32_t *q = cq + wv * CQ;
+    const uint64_t lt = lanemask_lt();
+    const int gm = gmax < PSCAN ? gmax : PSCAN;
+
+    // entry: cell (8 bits) | offset (8 bits, 1..64) | position (16 bits)
+    auto found = [&](int t0, int d0, int k) {
+        atomicOr(&mask[t0], 1ull << (d0 - 1));
+        const uint32_t r = atomicAdd(&s_nres, 1u);
+        if (r < static_cast<uint32_t>(P_STASH))
+            res[r] = (static_cast<uint32_t>(t0) << 24) | (static_cast<uint32_t>(d0) << 16) | static_cast<uint32_t>(k);
+    };
+    auto check = [&](uint32_t e) {
+        const int t0 = static_cast<int>(e >> 16), j0 = static_cast<int>(e & 0xffffu);
+        int pos;
+        if (dist_t<T, WT>(rows + t0 * LW, rows + j0 * LW, &pos) == 1) found(t0, j0 - t0, pos);
+    };
+
+    bool scanning = t < tr;
+    bool big = false, spill = false;  // spill: the group runs past the loaded rows
+    const uint32_t pc = t < tl ? pcs[t] : 0u;
+    uint32_t qn = 0, qh = 0;
+    for (int d = 1; ballot64(scanning) != 0; ++d) {
+        const int jj = t + d;
+        const int jc = jj < tl ? jj : tl;
+        const uint32_t h = heads[jc];  // at tl: 0 iff the group may go on
+        const uint32_t po = pcs[jc];
+        const bool past = jj >= tl;
+        const bool tiny = d > gm;
+        // past the loaded rows with the group possibly going on: finish in global
+        // memory (which also settles d > gm there)
+        spill = spill || (scanning && past && h == 0);
+        big = big || (scanning && !past && h == 0 && tiny);
+        const bool stop = past || h != 0 || tiny;
+        const bool cand = scanning && !stop && (po == pc + 1 || po + 1 == pc);
+        scanning = scanning && !stop;
+        const uint64_t m = ballot64(cand);
+        if (cand) q[(qn + static_cast<uint32_t>(__popcll(m & lt))) % CQ] = (static_cast<uint32_t>(t) << 16) | static_cast<uint32_t>(jj);
+        qn += static_cast<uint32_t>(__popcll(m));
+        while (qn - qh >= 64) {  // a full batch: lane e checks queued pair qh + e
+            __builtin_amdgcn_wave_barrier();
+            check(q[(qh + lane) % CQ]);
+            qh += 64;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (static_cast<uint32_t>(lane) < qn - qh) check(q[(qh + lane) % CQ]);
+    if (spill) {
+        // the group goes on past the loaded rows: finish it in global memory
+        const T *me = rows + t * LW;
+        for (int64_t j = base + tl; j < n; ++j) {
+            const T *o = cells + j * words;
+            if (!same_prefix<T>(me, o, s)) break;
+            if (j - i > gm) { big = true; break; }
+            int pos;
+            if (dist_full<T>(me, o, words, &pos) == 1) found(t, static_cast<int>(j - i), pos);
+        }
+    }
+    __syncthreads();
     uint32_t cp = 0, cs = 0;
     if (t < tr) {
-        cp = p_scan_t<T, WT>(rows, pcs, heads, tr + th, t, i, base, n, cells, words, s, gmax,
-                             [&](uint32_t d, int k, uint32_t r) {
-                                 if (r < NB) mine[r] = (d << 16) | static_cast<uint32_t>(k);
-                             });
-        if (cp & BIG) cp = BIG | p_lookup<T>(cells, i, n, words, ell, s, [](uint32_t, int, uint32_t) {});
+        cp = big ? (BIG | p_lookup<T>(cells, i, n, words, ell, s, [](uint32_t, int, uint32_t) {}))
+                 : static_cast<uint32_t>(__popcll(mask[t]));
         cs = cntS[i];
         cntP[i] = cp;
     }
@@ -516,39 +632,57 @@ __global__ void __launch_bounds__(PT) k_p_find(const T *__restrict__ cells, cons
     uint64_t tot_stash, tot_all;
     const uint64_t ex = block256_excl_scan_u64(stashed, tmp, &tot_stash);
     block256_excl_scan_u64(static_cast<uint64_t>(cp & ~BIG) + cs, tmp, &tot_all);
+    sbase[t] = (cp & BIG) ? 0xffffffffu : static_cast<uint32_t>(ex);
+    const uint32_t nres = s_nres;
     if (t == 0) {
         tile_tot[tile] = tot_all;
-        stash_n[tile] = static_cast<uint32_t>(tot_stash > 0xffffffffull ? 0xffffffffull : tot_stash);
+        const uint64_t m = nres > tot_stash ? nres : tot_stash;
+        stash_n[tile] = static_cast<uint32_t>(m > 0xffffffffull ? 0xffffffffull : m);
     }
-    if (tot_stash > static_cast<uint64_t>(P_STASH) || stashed == 0) return;
-    uint32_t *out = stash + tile * P_STASH + ex;
-    if (stashed <= static_cast<uint32_t>(NB)) {
-        for (uint32_t r = 0; r < stashed; ++r) out[r] = mine[r];
-    } else {
-        p_scan_t<T, WT>(rows, pcs, heads, tr + th, t, i, base, n, cells, words, s, gmax,
-                        [&](uint32_t d, int k, uint32_t r) { out[r] = (d << 16) | static_cast<uint32_t>(k); });
+    __syncthreads();
+    if (nres > static_cast<uint32_t>(P_STASH)) return;  // k_p_fix recomputes this tile
+    uint32_t *out = stash + tile * P_STASH;
+    for (uint32_t r = t; r < nres; r += PT) {
+        const uint32_t e = res[r];
+        const int t0 = static_cast<int>(e >> 24);
+        const int d0 = static_cast<int>((e >> 16) & 0xffu);
+        if (sbase[t0] == 0xffffffffu) continue;  // found by look-up at placement instead
+        const uint32_t rank = static_cast<uint32_t>(__popcll(mask[t0] & ((1ull << (d0 - 1)) - 1ull)));
+        out[sbase[t0] + rank] = (static_cast<uint32_t>(d0) << 16) | (e & 0xffffu);
     }
 }
 
 // One block: exclusive scan of tile totals in place; |E|, offsets[n], status.
-// Thread t owns a contiguous chunk of the totals (one load round).
+// Thread t owns a contiguous chunk of the totals, read and written in
+// batches of 16 so the loads overlap.
 __global__ void __launch_bounds__(256) k_tile_scan(uint64_t *tile_tot, const int64_t *d_n, int64_t ncap,
                                                    int64_t cap, int64_t *d_nedges, int64_t *offsets,
                                                    int32_t *status) {
     __shared__ uint64_t tmp[4];
+    constexpr int U = 16;
     const int64_t n = load_n(d_n, ncap);
     const int64_t tiles = (n + PT - 1) / PT;
-    const int64_t per = (tiles + 255) / 256;
+    const int64_t per = ((tiles + 255) / 256 + U - 1) / U * U;
     const int64_t a = threadIdx.x * per;
-    const int64_t b = a + per < tiles ? a + per : tiles;
     uint64_t sum = 0;
-    for (int64_t k = a; k < b; ++k) sum += tile_tot[k];
+    for (int64_t k0 = a; k0 < a + per; k0 += U) {
+        uint64_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = (k0 + u < tiles) ? tile_tot[k0 + u] : 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) sum += v[u];
+    }
     uint64_t total;
     uint64_t run = block256_excl_scan_u64(sum, tmp, &total);
-    for (int64_t k = a; k < b; ++k) {
-        const uint64_t v = tile_tot[k];
-        tile_tot[k] = run;
-        run += v;
+    for (int64_t k0 = a; k0 < a + per; k0 += U) {
+        uint64_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = (k0 + u < tiles) ? tile_tot[k0 + u] : 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k0 + u < tiles) tile_tot[k0 + u] = run;
+            run += v[u];
+        }
     }
     if (threadIdx.x == 0) {
         const int64_t tot = static_cast<int64_t>(total);
@@ -693,7 +827,16 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
     const int words = d.lay.words, ell = d.lay.ell, sp = d.params.split_bit, gmax = d.params.group_max;
     const dim3 grid(static_cast<unsigned>((ncap + PT - 1) / PT));
     const size_t lds = PTile<T, WT>::bytes;
-    hipLaunchKernelGGL((k_p_find<T, WT>), grid, dim3(PT), lds, s, cells, d.d_ncells, ncap, words, ell, sp, gmax,
+    const size_t lds_find = PFind<T, WT>::bytes;
+    const size_t lds_s = SFind<T, WT>::bytes;
+    const int rmax = gmax < SRMAX ? gmax : SRMAX;
+    if (sp > 0) {
+        hipLaunchKernelGGL((k_s_tile<T, WT, false>), grid, dim3(PT), lds_s, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
+                           rmax, w.cntS, w.s_stash, w.s_stash_n, static_cast<const int64_t *>(nullptr),
+                           static_cast<const int64_t *>(nullptr), uv, bit, cap);
+        CG_LAUNCHED("edges_s_find");
+    }
+    hipLaunchKernelGGL((k_p_find<T, WT>), grid, dim3(PT), lds_find, s, cells, d.d_ncells, ncap, words, ell, sp, gmax,
                        w.cntS, w.cntP, w.p_stash, w.p_stash_n, w.tile_tot);
     CG_LAUNCHED("edges_p_find");
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, s, w.tile_tot, d.d_ncells, ncap, cap, d_nedges, d_offsets,
@@ -702,9 +845,18 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
     hipLaunchKernelGGL((k_p_place<T>), grid, dim3(PT), 0, s, cells, d.d_ncells, ncap, words, ell, sp, w.cntS,
                        w.cntP, w.p_stash, w.p_stash_n, w.tile_tot, d_offsets, offnext, uv, bit, cap);
     CG_LAUNCHED("edges_p_place");
-    hipLaunchKernelGGL((k_p_fix<T, WT>), grid, dim3(PT), lds, s, cells, d.d_ncells, ncap, words, sp, gmax, w.cntS,
+    const int gm = gmax < PSCAN ? gmax : PSCAN;  // same scan limit as k_p_find
+    hipLaunchKernelGGL((k_p_fix<T, WT>), grid, dim3(PT), lds, s, cells, d.d_ncells, ncap, words, sp, gm, w.cntS,
                        w.cntP, w.p_stash_n, w.tile_tot, uv, bit, cap);
     CG_LAUNCHED("edges_p_fix");
+    if (sp > 0) {
+        hipLaunchKernelGGL(k_s_place, grid, dim3(PT), 0, s, d.d_ncells, ncap, w.s_stash, w.s_stash_n, d_offsets,
+                           offnext, uv, bit, cap);
+        CG_LAUNCHED("edges_s_place");
+        hipLaunchKernelGGL((k_s_tile<T, WT, true>), grid, dim3(PT), lds_s, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
+                           rmax, w.cntS, w.s_stash, w.s_stash_n, d_offsets, offnext, uv, bit, cap);
+        CG_LAUNCHED("edges_s_redo");
+    }
     return CG_OK;
 }
 
@@ -712,8 +864,6 @@ template <typename T>
 cg_status edges_fast(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap, int64_t *d_nedges,
                      int64_t *d_offsets, const EdgesWs &w, int32_t *d_status, hipStream_t s) {
     const int64_t ncap = d.ncells_cap;
-    const T *cells = static_cast<const T *>(d.cells);
-    const int words = d.lay.words, sp = d.params.split_bit, gmax = d.params.group_max;
     const int64_t ntiles = (ncap + PT - 1) / PT;
     int64_t *offnext = w.offsets;  // sparse next-offsets when the caller wants no offsets
     hipLaunchKernelGGL(k_edges_init, dim3(blocks_for(ncap, 256, 4096)), dim3(256), 0, s, w.cntS, ncap, d_nedges,
@@ -721,12 +871,6 @@ cg_status edges_fast(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap,
     CG_LAUNCHED("edges_init");
     if (ncap == 0) return CG_OK;
     const dim3 grid(static_cast<unsigned>(ntiles));
-    const size_t s_lds = static_cast<size_t>(PT + 2 * (gmax + 1)) * 2 * sizeof(uint32_t);
-    if (sp > 0) {
-        hipLaunchKernelGGL((k_s_find<T>), grid, dim3(PT), s_lds, s, cells, d.sfx, d.d_ncells, ncap, words, sp, gmax,
-                           w.cntS, w.s_stash, w.s_stash_n);
-        CG_LAUNCHED("edges_s_find");
-    }
     switch (tile_width(d)) {
     case 1: CG_TRY((p_pass_launch<T, 1>(d, w, cap, d_nedges, d_offsets, offnext, uv, bit, d_status, s))); break;
     case 2: CG_TRY((p_pass_launch<T, 2>(d, w, cap, d_nedges, d_offsets, offnext, uv, bit, d_status, s))); break;
@@ -734,11 +878,6 @@ cg_status edges_fast(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap,
     case 8: CG_TRY((p_pass_launch<T, 8>(d, w, cap, d_nedges, d_offsets, offnext, uv, bit, d_status, s))); break;
     case 16: CG_TRY((p_pass_launch<T, 16>(d, w, cap, d_nedges, d_offsets, offnext, uv, bit, d_status, s))); break;
     default: CG_TRY((p_pass_launch<T, 32>(d, w, cap, d_nedges, d_offsets, offnext, uv, bit, d_status, s))); break;
-    }
-    if (sp > 0) {
-        hipLaunchKernelGGL((k_s_place<T>), grid, dim3(PT), s_lds, s, cells, d.sfx, d.d_ncells, ncap, words, sp, gmax,
-                           w.cntS, w.s_stash, w.s_stash_n, d_offsets, offnext, uv, bit, cap);
-        CG_LAUNCHED("edges_s_place");
     }
     return CG_OK;
 }

@@ -205,6 +205,21 @@ __device__ __forceinline__ int dist_full(const T *a, const T *b, int words, int 
     return d;
 }
 
+// Hamming distance of two rows of exactly WT words (compile time), without
+// branches; *pos gets the first differing position (meaningful at distance 1).
+template <typename T, int WT>
+__device__ __forceinline__ int dist_t(const T *a, const T *b, int *pos) {
+    int d = 0, first = -1;
+#pragma unroll
+    for (int w = 0; w < WT; ++w) {
+        const T x = a[w] ^ b[w];
+        d += popc<T>(x);
+        first = (x && first < 0) ? w * Bits<T>::B + clz_t<T>(x) : first;
+    }
+    *pos = first;
+    return d;
+}
+
 // Block-wide copy of nrows contiguous global rows (`words` words each) into
 // LDS rows of stride LW, with U loads in flight per thread (a plain loop with
 // a run-time trip count would wait for each load before the next).
@@ -389,5 +404,13 @@ size_t allpairs_workspace_bytes(const cg_dict &d, int64_t cap);
 cg_status run_edges_allpairs(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap,
                              int64_t *d_nedges, int64_t *d_offsets, void *ws, size_t ws_bytes,
                              int32_t *d_status, hipStream_t s);
+
+cg_status batch_layout(int32_t ell_max, cg_layout *lay);
+cg_status run_batch_pack(const uint8_t *bits, const int64_t *bits_off, const int32_t *scene_ell,
+                         const int64_t *scene_rows, int32_t n_scenes, int64_t n_rows, cg_layout lay, void *out,
+                         hipStream_t s);
+cg_status run_batch_split(const cg_dict &d, int32_t n_scenes, const int64_t *offsets, const int64_t *d_nedges,
+                          int64_t cap, int64_t *cell_off, int64_t *edge_off, int32_t localize, uint32_t *uv,
+                          uint16_t *bit, uint32_t *r2c, const int64_t *scene_rows, int64_t n_rows, hipStream_t s);
 
 }  // namespace cg

@@ -1,0 +1,202 @@
+"""Serving loop: continuous batching of cell-graph requests.
+
+Requests (arrival time, scene) are admitted into the next batch as soon as
+they have arrived and the batch has room: each width class has a fixed
+device footprint (rows, scenes, sign bytes, edges), and a request that does
+not fit waits for the next batch.  Two batch slots alternate: while one
+batch computes on its stream, the host admits the next arrivals, stages
+their sign bytes in pinned memory and launches them on the other slot, then
+collects the finished batch.  So requests that arrive while others are on
+the GPU are picked up as soon as a slot frees, and copies of one batch
+overlap the compute of the other.  Latency is measured from a request's
+arrival to the moment its results are on the host.
+
+The per-scene baseline serves the same trace one request at a time with
+plain per-scene launches (preallocated per pool scene).
+
+Only scheduling, staging and marshalling live here; all compute is in the
+library's kernels.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+
+import numpy as np
+import torch
+
+from . import batch as BT
+from . import pipeline
+
+
+class Slot:
+    """Device buffers for one in-flight batch: one SceneBatch per class."""
+
+    def __init__(self, class_caps, device="cuda"):
+        self.stream = torch.cuda.Stream()
+        self.batches = {}
+        self.pinned = {}
+        for w, (rows, scenes, nbytes) in class_caps.items():
+            ell = 32 * (w - 1)
+            sb = BT.SceneBatch([ell], [1], w, max_rows=rows, max_scenes=scenes, max_bytes=nbytes,
+                               edge_cap=max(4096, 4 * rows), device=device)
+            self.batches[w] = sb
+            self.pinned[w] = torch.empty(max(nbytes, 16), dtype=torch.uint8).pin_memory()
+        self.requests = None
+        self.done = None
+
+    def launch(self, reqs, scenes):
+        """Stage and launch one batch: reqs = [(req_id, scene_idx)]."""
+        by_class = {}
+        for rid, si in reqs:
+            R = scenes[si]
+            by_class.setdefault(BT.class_words(R.shape[1]), []).append((rid, si))
+        self.requests = by_class
+        with torch.cuda.stream(self.stream):
+            for w, items in by_class.items():
+                sb = self.batches[w]
+                sb.set_scenes([scenes[si].shape[1] for _, si in items], [scenes[si].shape[0] for _, si in items])
+                host = self.pinned[w].numpy()
+                o = 0
+                for _, si in items:
+                    R = scenes[si]
+                    host[o:o + R.size] = R.reshape(-1)
+                    o += R.size
+                if o:
+                    sb.bits[:o].copy_(self.pinned[w][:o], non_blocking=True)
+                sb.run(self.stream)
+            self.done = torch.cuda.Event()
+            self.done.record(self.stream)
+
+    def collect(self):
+        """Wait for the batch; return {req_id: result dict}.  Copies go on the
+        slot's own stream, so the other slot's batch keeps running."""
+        self.done.synchronize()
+        out = {}
+        with torch.cuda.stream(self.stream):
+            for w, items in self.requests.items():
+                sb = self.batches[w]
+                if int(sb.status.item()) != 0:
+                    raise RuntimeError("edge capacity of a serving slot exceeded; raise its footprint")
+                for (rid, _), r in zip(items, sb.fetch(sync=False)):
+                    out[rid] = r
+        self.requests = None
+        return out
+
+
+def admit_requests(queue: deque, now: float, caps, shapes):
+    """Take the requests that have arrived by `now`, in arrival order, while
+    their width class has room (rows, scenes, sign bytes); the others stay
+    queued, still in arrival order.  queue holds (req_id, arrival, scene);
+    shapes[scene] = (rows, l).  Returns [(req_id, scene)]."""
+    used = {w: [0, 0, 0] for w in caps}
+    taken = []
+    keep = deque()
+    while queue and queue[0][1] <= now:
+        rid, t, si = queue.popleft()
+        n, ell = shapes[si]
+        w = BT.class_words(ell)
+        rows, nsc, nb = caps[w]
+        u = used[w]
+        if u[0] + n <= rows and u[1] + 1 <= nsc and u[2] + n * ell <= nb:
+            u[0] += n
+            u[1] += 1
+            u[2] += n * ell
+            taken.append((rid, si))
+        else:
+            keep.append((rid, t, si))  # no room in this batch: the next one
+    keep.extend(queue)  # skipped requests arrived first: order is kept
+    queue.clear()
+    queue.extend(keep)
+    return taken
+
+
+class Server:
+    def __init__(self, scenes, rows_per_class: int = 1 << 21, scenes_per_class: int = 4096,
+                 device="cuda"):
+        self.scenes = scenes
+        ells = {BT.class_words(R.shape[1]) for R in scenes}
+        caps = {}
+        for w in ells:
+            caps[w] = (rows_per_class, scenes_per_class, rows_per_class * 32 * (w - 1))
+        self.caps = caps
+        self.slots = [Slot(caps, device), Slot(caps, device)]
+
+    def _admit(self, queue: deque, now: float):
+        return admit_requests(queue, now, self.caps, [R.shape for R in self.scenes])
+
+    def serve(self, arrivals, scene_idx, keep_results: bool = False):
+        """Serve a trace in real time.  Returns (latencies in s, results or None, wall seconds)."""
+        n = len(arrivals)
+        queue = deque((i, float(arrivals[i]), int(scene_idx[i])) for i in range(n))
+        lat = np.zeros(n)
+        results = {} if keep_results else None
+        inflight = []  # slots with a launched batch, oldest first
+        free = list(self.slots)
+        t0 = time.perf_counter()
+        served = 0
+        while served < n:
+            now = time.perf_counter() - t0
+            progressed = False
+            if free and queue and queue[0][1] <= now:
+                reqs = self._admit(queue, now)
+                if reqs:
+                    slot = free.pop(0)
+                    slot.launch(reqs, self.scenes)
+                    inflight.append(slot)
+                    progressed = True
+            if inflight and (not free or inflight[0].done.query()):
+                slot = inflight.pop(0)
+                out = slot.collect()
+                tdone = time.perf_counter() - t0
+                for rid, r in out.items():
+                    lat[rid] = tdone - arrivals[rid]
+                    if keep_results:
+                        results[rid] = r
+                served += len(out)
+                free.append(slot)
+                progressed = True
+            if not progressed:
+                wait = (queue[0][1] - (time.perf_counter() - t0)) if queue else 0.0002
+                time.sleep(min(max(wait, 0.0), 0.0002))
+        wall = time.perf_counter() - t0
+        return lat, results, wall
+
+
+class PerSceneBaseline:
+    """The same trace with plain per-scene launches, one request at a time."""
+
+    def __init__(self, scenes, device="cuda"):
+        self.scenes = scenes
+        self.graphs = {}
+        self.bits = {}
+        for si, R in enumerate(scenes):
+            g = pipeline.CellGraph(R.shape[0], R.shape[1], 32, edge_cap=max(4096, 4 * R.shape[0]),
+                                   device=device)
+            self.graphs[si] = g
+            self.bits[si] = torch.from_numpy(np.ascontiguousarray(R)).pin_memory()
+        self.dev_bits = {}
+
+    def serve(self, arrivals, scene_idx, keep_results: bool = False):
+        n = len(arrivals)
+        lat = np.zeros(n)
+        results = {} if keep_results else None
+        t0 = time.perf_counter()
+        for i in range(n):
+            now = time.perf_counter() - t0
+            if arrivals[i] > now:
+                time.sleep(arrivals[i] - now)
+            si = int(scene_idx[i])
+            g = self.graphs[si]
+            R = self.scenes[si]
+            dev = torch.empty(R.shape, dtype=torch.uint8, device="cuda")
+            dev.copy_(self.bits[si], non_blocking=True)
+            if R.shape[0]:
+                g.pack(dev)
+            g.run()
+            r = g.fetch()
+            lat[i] = time.perf_counter() - t0 - arrivals[i]
+            if keep_results:
+                results[i] = r
+        wall = time.perf_counter() - t0
+        return lat, results, wall

@@ -1,0 +1,102 @@
+"""Batched scenes (one set of launches for many scenes): every scene's slice
+must equal the oracle run on that scene alone, bit for bit, and a captured
+HIP graph must give the same bytes on every replay."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_06029_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_1503_06029_amd import batch, binding
+    return torch, binding, batch
+
+
+def make_scenes(seed, specs):
+    rng = np.random.default_rng(seed)
+    scenes = []
+    for kind, n, ell in specs:
+        if kind == "planes":
+            scenes.append(inputs.planes_in_cube(rng, ell, n))
+        elif kind == "clustered":
+            R = inputs.clustered_multiset(rng, max(1, n // 8), ell, 4, n // 4)
+            scenes.append(R)
+        else:
+            scenes.append((rng.random((n, ell)) < 0.5).astype(np.uint8))
+    return scenes
+
+
+SPECS = [("planes", 2000, 16), ("clustered", 800, 5), ("random", 0, 40), ("random", 1, 33),
+         ("planes", 3000, 31), ("clustered", 900, 32), ("planes", 1500, 33), ("clustered", 700, 64),
+         ("planes", 2500, 65), ("clustered", 1000, 96), ("planes", 2000, 97), ("clustered", 600, 200),
+         ("planes", 1200, 224), ("clustered", 800, 300), ("planes", 1000, 480), ("clustered", 500, 481),
+         ("planes", 900, 512), ("random", 300, 7), ("clustered", 400, 128), ("planes", 1800, 150)]
+
+
+def check_scene(res, R, ell):
+    rows = oracle.pack(R, 32)
+    cells, r2c = oracle.dedup(rows, ell, 32)
+    uv, bit, off = oracle.edges(cells, 32)
+    assert res["ncells"] == cells.shape[0]
+    assert np.array_equal(res["cells"], cells)
+    assert np.array_equal(res["row_to_cell"], r2c)
+    assert res["nedges"] == len(uv)
+    assert np.array_equal(res["uv"], uv)
+    assert np.array_equal(res["bit"], bit)
+    assert np.array_equal(res["offsets"], off)
+
+
+def test_batched_scenes_match_oracle(gpu):
+    torch, B, batch = gpu
+    scenes = make_scenes(1, SPECS)
+    shapes = [(R.shape[0], R.shape[1]) for R in scenes]
+    say("batch", len(scenes), "scenes")
+    runner = batch.BatchRunner(shapes)
+    runner.upload(scenes)
+    runner.run_checked()
+    res = runner.fetch()
+    for j, (R, r) in enumerate(zip(scenes, res)):
+        say("scene", j, R.shape)
+        check_scene(r, R, R.shape[1])
+
+
+def test_batched_graph_replays(gpu):
+    torch, B, batch = gpu
+    scenes = make_scenes(2, SPECS[:12])
+    shapes = [(R.shape[0], R.shape[1]) for R in scenes]
+    say("graph batch", len(scenes))
+    runner = batch.BatchRunner(shapes)
+    runner.upload(scenes)
+    runner.run_checked()  # sizes buffers, warms up
+    eager = runner.fetch()
+    runner.capture()
+    for rep in range(3):
+        # clobber the outputs between replays with unrelated eager work
+        for _, sb in runner.classes:
+            sb.uv.fill_(-1)
+            sb.cells.fill_(-1)
+            sb.r2c.fill_(-1)
+        x = torch.randn(1024, device="cuda").sum()
+        torch.cuda.synchronize()
+        runner.replay()
+        torch.cuda.synchronize()
+        got = runner.fetch()
+        say("replay", rep, float(x))
+        for a, b in zip(got, eager):
+            for key in ("cells", "uv", "bit", "offsets", "row_to_cell"):
+                assert np.array_equal(a[key], b[key]), (rep, key)
+    for j, (R, r) in enumerate(zip(scenes, got)):
+        check_scene(r, R, R.shape[1])

@@ -356,7 +356,9 @@ def test_config3_scenes(gpu, i):
 
 
 @pytest.mark.parametrize("ell,kw", [(10, dict(split_bit=0, group_max=1024)), (12, dict(split_bit=0, group_max=1024)),
-                                    (12, dict(split_bit=3)), (12, dict()), (11, dict(split_bit=11, group_max=8))])
+                                    (12, dict(split_bit=3)), (12, dict()), (11, dict(split_bit=11, group_max=8)),
+                                    (10, dict(split_bit=5)), (10, dict(split_bit=6, group_max=64)),
+                                    (9, dict(split_bit=4, group_max=40))])
 def test_dense_hypercube_stash_overflow(gpu, ell, kw):
     """Full hypercubes: many edges per tile, so the per-tile edge stashes
     overflow and placement recomputes; long prefix groups take look-ups."""
