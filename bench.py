@@ -69,6 +69,7 @@ def main():
                     help="long: 1024-bit vectors (the headline); batched: 512 plane scenes in one graph; "
                          "served: Poisson stream of those scenes")
     ap.add_argument("--scenes", type=int, default=512)
+    ap.add_argument("--no-tune", action="store_true", help="batched: skip the autotuner")
     ap.add_argument("--seconds", type=float, default=5.0, help="served: trace length")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -189,6 +190,17 @@ def bench_batched(args):
     rows = sum(n for n, _ in shapes)
     runner = batch.BatchRunner(shapes)
     runner.upload(scenes)
+    tuned = {}
+    t_tune = 0.0
+    if not args.no_tune:
+        from paper_1503_06029_amd import tuner
+        tn = tuner.Tuner(path=None)
+        t0 = time.perf_counter()
+        for ids, sb in runner.classes:
+            best, ms = tn.tune_class(sb)
+            tuned[f"w{sb.words}"] = dict(best, ms=round(ms, 3))
+            log(f"class w{sb.words}: {best} {ms:.2f} ms")
+        t_tune = time.perf_counter() - t0
     runner.run_checked()
     runner.capture()
     for _ in range(args.warmup):
@@ -228,7 +240,8 @@ def bench_batched(args):
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": f"{len(scenes)} scenes, l uniform 16..512 planes in R^3, log-uniform 1e3..2e5 "
-                               f"points ({rows} rows)", "cells": cells, "edges": edges},
+                               f"points ({rows} rows)", "cells": cells, "edges": edges,
+                   "tuned": tuned, "tune_s": round(t_tune, 2)},
         "rows_per_s": rows / (ms / 1e3),
         "p50_ms": float(np.percentile(step_ms, 50)), "p99_ms": float(np.percentile(step_ms, 99)),
         "per_scene_ms": base_ms, "speedup_vs_per_scene": base_ms / ms,

@@ -18,6 +18,18 @@ import torch
 from . import binding as B
 
 CLASS_WORDS = (2, 4, 8, 16, 32)  # tag word + data words, a power of two
+TAG_BITS = 32
+
+# Data bits of the default split per class: the P pass (flips at or after
+# the split) sees groups of cells that agree on the tag and the first
+# SPLIT_DATA planes, the S pass runs of cells that agree on the rest.  For
+# arrangements of planes both stay small when each side holds a good share
+# of a scene's planes; a class holds scenes of l in (32 (w/2 - 1), 32 (w - 1)].
+SPLIT_DATA = {2: 16, 4: 32, 8: 64, 16: 128, 32: 256}
+
+
+def default_params(words: int) -> B.DictParams:
+    return B.cg_dict_params_default(split_bit=TAG_BITS + SPLIT_DATA[words])
 
 
 def class_words(ell: int) -> int:
@@ -59,7 +71,7 @@ class SceneBatch:
         self.ncells = torch.zeros(1, dtype=torch.int64, device=dev)
         self.ws_dedup_bytes = B.cg_dedup_workspace(self.cap_rows, self.lay)
         self.ws_dedup = torch.empty(self.ws_dedup_bytes, dtype=torch.uint8, device=dev)
-        self.params = params if params is not None else B.cg_dict_params_default()
+        self.params = params if params is not None else default_params(words)
         self.dict_bytes = B.cg_dict_size(self.cap_rows, self.lay, self.params)
         self.dict_mem = torch.empty(self.dict_bytes, dtype=torch.uint8, device=dev)
         self.edge_cap = int(edge_cap if edge_cap is not None else max(4096, 4 * self.cap_rows))

@@ -20,14 +20,28 @@ __device__ __forceinline__ int scene_of(const int64_t *rows, int n_scenes, int64
     return lo;
 }
 
+// Sign bytes -> 32 column bits, MSB first: x holds 4 bytes (lowest address in
+// the low byte); the result's top nibble has one bit per byte (set iff the
+// byte is nonzero), the lowest-addressed byte most significant.
+__device__ __forceinline__ uint32_t nibble_of(uint32_t x) {
+    uint32_t y = x | (x >> 4);
+    y |= y >> 2;
+    y |= y >> 1;
+    y &= 0x01010101u;
+    return (y * 0x80402010u) >> 28;  // byte b's flag lands on bit 31 - b, nothing carries into 28..31
+}
+
 // One thread per (virtual row, 32-bit word): word 0 is the scene tag, word w
 // >= 1 packs columns 32 (w - 1) .. 32 w - 1 of the scene's row, MSB first.
+// The 32 bytes are read as aligned 4-byte words (those lying wholly inside
+// the scene's bytes; the others byte by byte) and aligned with alignbyte.
 __global__ void __launch_bounds__(256) k_batch_pack(const uint8_t *__restrict__ bits,
                                                     const int64_t *__restrict__ bits_off,
                                                     const int32_t *__restrict__ scene_ell,
                                                     const int64_t *__restrict__ scene_rows, int n_scenes,
                                                     int64_t n_rows, int words, uint32_t *__restrict__ out) {
     const int64_t total = n_rows * words;
+    const bool aligned = (reinterpret_cast<uintptr_t>(bits) & 3) == 0;
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
          g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t r = g / words;
@@ -41,9 +55,38 @@ __global__ void __launch_bounds__(256) k_batch_pack(const uint8_t *__restrict__ 
             const int col0 = (w - 1) * 32;
             v = 0;
             if (col0 < ell) {
-                const uint8_t *src = bits + bits_off[j] + (r - scene_rows[j]) * ell + col0;
+                const int64_t s0 = bits_off[j];
+                const int64_t s1 = s0 + (scene_rows[j + 1] - scene_rows[j]) * ell;  // end of the scene's bytes
+                const int64_t A = s0 + (r - scene_rows[j]) * ell + col0;
                 const int lim = ell - col0 < 32 ? ell - col0 : 32;
-                for (int c = 0; c < lim; ++c) v |= static_cast<uint32_t>(src[c] != 0) << (31 - c);
+                if (aligned) {
+                    const int64_t A4 = A & ~int64_t(3);
+                    const int off = static_cast<int>(A - A4);
+                    uint32_t wd[9];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) {
+                        const int64_t p = A4 + 4 * k;
+                        if (p >= A + lim) {
+                            wd[k] = 0;
+                        } else if (p >= s0 && p + 4 <= s1) {
+                            wd[k] = *reinterpret_cast<const uint32_t *>(bits + p);
+                        } else {
+                            uint32_t x = 0;
+                            for (int b = 0; b < 4; ++b)
+                                if (p + b >= s0 && p + b < s1) x |= static_cast<uint32_t>(bits[p + b]) << (8 * b);
+                            wd[k] = x;
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const uint32_t x = __builtin_amdgcn_alignbyte(wd[k + 1], wd[k], static_cast<uint32_t>(off));
+                        v |= nibble_of(x) << (28 - 4 * k);
+                    }
+                    if (lim < 32) v &= ~0u << (32 - lim);
+                } else {
+                    const uint8_t *src = bits + A;
+                    for (int c = 0; c < lim; ++c) v |= static_cast<uint32_t>(src[c] != 0) << (31 - c);
+                }
             }
         }
         out[g] = v;

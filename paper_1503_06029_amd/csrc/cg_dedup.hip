@@ -8,8 +8,9 @@
 // 3. rows with equal keys form segments; when l > 64 each segment of two or
 //    more rows is ordered by the full row: segments of up to `smax` rows in
 //    the LDS of the block whose tile holds their first position (rank sort),
-//    longer ones by one block each (bitonic network over an index array in
-//    global memory);
+//    up to LMAX rows by one block each (bitonic network over (next 64 bits,
+//    index) pairs in LDS), longer ones by one block each (bitonic network over
+//    an index array in global memory);
 // 4. a row is a new cell iff it differs from its predecessor; a scan of those
 //    flags gives cell ids, and a gather writes the cells and row_to_cell.
 #include "cg_internal.hpp"
@@ -20,6 +21,7 @@ namespace {
 
 constexpr uint32_t SENT = 0xFFFFFFFFu;
 constexpr int64_t TILE_LDS = 53248;  // three blocks per CU
+constexpr int LMAX = 4096;          // longest segment sorted in one block's LDS
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_extract(const T *__restrict__ rows, int64_t n, int words,
@@ -366,6 +368,7 @@ __global__ void __launch_bounds__(256) k_tiefix_large(const T *__restrict__ rows
         const uint2 seg = list[s];
         const int64_t a = seg.x;
         const int64_t len = seg.y;
+        if (len <= LMAX) continue;  // k_tiefix_mid took it
         int64_t P = 1;
         while (P < len) P <<= 1;
         uint32_t *scr = scratch + 2 * a;
@@ -401,8 +404,91 @@ __global__ void __launch_bounds__(256) k_tiefix_large(const T *__restrict__ rows
     }
 }
 
-// One thread per (sorted position, 16-byte piece of the row) when rows are a
-// whole number of 16-byte pieces, else per (position, word).
+// Segments longer than the tile kernel takes, up to LMAX rows: one block per
+// segment sorts (next 64 bits of the row, row index) pairs by a bitonic
+// network in LDS; pairs whose 64-bit values tie compare the rest of the rows
+// in global memory.  Then a row is flagged new iff it differs from its
+// predecessor in the segment.
+template <typename T>
+__device__ __forceinline__ uint64_t key2_of(const T *row, int words, int from);
+template <>
+__device__ __forceinline__ uint64_t key2_of<uint64_t>(const uint64_t *row, int words, int from) {
+    return from < words ? row[from] : 0ull;
+}
+template <>
+__device__ __forceinline__ uint64_t key2_of<uint32_t>(const uint32_t *row, int words, int from) {
+    const uint64_t hi = from < words ? row[from] : 0u;
+    const uint64_t lo = from + 1 < words ? row[from + 1] : 0u;
+    return (hi << 32) | lo;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_tiefix_mid(const T *__restrict__ rows, int words, int from,
+                                                     const uint2 *__restrict__ list,
+                                                     const unsigned long long *__restrict__ counters,
+                                                     uint32_t *__restrict__ vals, uint8_t *__restrict__ uniq) {
+    __shared__ uint64_t sk[LMAX];
+    __shared__ uint32_t si[LMAX];
+    constexpr int K2 = 64 / Bits<T>::B;  // words covered by the second key
+    const int from2 = from + K2;
+    const uint32_t count = static_cast<uint32_t>(counters[1]);
+    for (uint32_t sgi = blockIdx.x; sgi < count; sgi += gridDim.x) {
+        const uint2 seg = list[sgi];
+        const int64_t a = seg.x;
+        const int len = static_cast<int>(seg.y);
+        if (len > LMAX) continue;  // k_tiefix_large takes it
+        int P = 1;
+        while (P < len) P <<= 1;
+        for (int i = threadIdx.x; i < P; i += blockDim.x) {
+            if (i < len) {
+                const uint32_t v = vals[a + i];
+                si[i] = v;
+                sk[i] = key2_of<T>(rows + static_cast<int64_t>(v) * words, words, from);
+            } else {
+                si[i] = SENT;
+                sk[i] = ~0ull;
+            }
+        }
+        __syncthreads();
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                    const int p = i ^ j;
+                    if (p > i) {
+                        const uint64_t ka = sk[i], kb = sk[p];
+                        const uint32_t ia = si[i], ib = si[p];
+                        bool a_gt;
+                        if (ka != kb) {
+                            a_gt = ka > kb;
+                        } else if (ia == SENT || ib == SENT) {
+                            a_gt = ia == SENT;
+                        } else {
+                            const int c = row_cmp<T>(rows + static_cast<int64_t>(ia) * words,
+                                                     rows + static_cast<int64_t>(ib) * words, words, from2);
+                            a_gt = c > 0 || (c == 0 && ia > ib);
+                        }
+                        if (((i & k) == 0) == a_gt) {
+                            sk[i] = kb; sk[p] = ka;
+                            si[i] = ib; si[p] = ia;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = threadIdx.x; i < len; i += blockDim.x) {
+            const uint32_t x = si[i];
+            vals[a + i] = x;
+            bool u = true;
+            if (i > 0 && sk[i - 1] == sk[i])
+                u = row_cmp<T>(rows + static_cast<int64_t>(x) * words, rows + static_cast<int64_t>(si[i - 1]) * words,
+                               words, from2) != 0;
+            uniq[a + i] = u ? 1 : 0;
+        }
+        __syncthreads();
+    }
+}
+
 template <typename V>
 __global__ void __launch_bounds__(256) k_gather(const V *__restrict__ rows, int64_t n, int pieces,
                                                 const uint32_t *__restrict__ vals, const uint8_t *__restrict__ uniq,
@@ -508,6 +594,9 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
                                from, static_cast<int>(smax), vals, w.uniq, w.large_list, w.counters);
             CG_LAUNCHED("dedup_tiefix_tile");
         }
+        hipLaunchKernelGGL((k_tiefix_mid<T>), dim3(1024), dim3(1024), 0, s, rows, words, from, w.large_list,
+                           w.counters, vals, w.uniq);
+        CG_LAUNCHED("dedup_tiefix_mid");
         hipLaunchKernelGGL((k_tiefix_large<T>), dim3(256), dim3(256), 0, s, rows, words, from, w.large_list,
                            w.counters, vals, w.uniq, w.scratch);
         CG_LAUNCHED("dedup_tiefix_large");

@@ -35,13 +35,35 @@ __device__ __forceinline__ uint32_t suffix_hash32(const T *row, int words, int s
 
 // One block per 256-cell tile.  The tile's rows are read once, coalesced,
 // into LDS (when they fit; wide rows are read in place), then each thread
-// hashes its cell's suffix and writes the directory entries that point at it.
+// hashes its cell's suffix and writes the directory entries that point at it:
+// those of the empty groups between its predecessor's top p bits and its
+// own.  Short gaps are filled in place; a gap longer than GAPMIN entries
+// (clustered keys, e.g. batched scenes whose top bits are a scene tag) is
+// listed, and k_dir_gaps fills it with a whole block.  Gaps are disjoint, so
+// at most (2^p + 1) / (GAPMIN + 1) + 1 are listed.
 constexpr int DT = 256;
+constexpr int GAPMIN = 64;
+
+__device__ __forceinline__ void push_gap(uint4 *gaps, unsigned long long *gap_n, int64_t cap, bool want,
+                                         int64_t lo, int64_t hi, uint32_t v) {
+    const uint64_t m = ballot64(want);
+    if (m == 0) return;
+    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    unsigned long long b = 0;
+    if (lane_id() == leader) b = atomicAdd(gap_n, static_cast<unsigned long long>(__popcll(m)));
+    b = shfl_u64(b, leader);
+    if (want) {
+        const unsigned long long k = b + static_cast<unsigned long long>(__popcll(m & lanemask_lt()));
+        if (static_cast<int64_t>(k) < cap)
+            gaps[k] = make_uint4(static_cast<uint32_t>(lo), static_cast<uint32_t>(hi), v, 0u);
+    }
+}
 
 template <typename T>
 __global__ void __launch_bounds__(DT) k_dict_scan(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
                                                   int words, int p, int s, uint32_t *__restrict__ dir,
-                                                  uint64_t *__restrict__ sfx, bool stage) {
+                                                  uint64_t *__restrict__ sfx, bool stage, uint4 *__restrict__ gaps,
+                                                  unsigned long long *gap_n, int64_t gap_cap) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t n = load_n(d_n, ncap);
     const int64_t G = int64_t(1) << p;
@@ -65,10 +87,38 @@ __global__ void __launch_bounds__(DT) k_dict_scan(const T *__restrict__ cells, c
     const int64_t gi = p ? static_cast<int64_t>(head64<T>(row, words) >> (64 - p)) : 0;
     const T *prev = (stage && t > 0) ? lrows + (t - 1) * LW : cells + (i - 1) * words;
     const int64_t gp = i == 0 ? -1 : (p ? static_cast<int64_t>(head64<T>(prev, words) >> (64 - p)) : 0);
-    for (int64_t g = gp + 1; g <= gi; ++g) dir[g] = static_cast<uint32_t>(i);
-    if (i == n - 1)
-        for (int64_t g = gi + 1; g <= G; ++g) dir[g] = static_cast<uint32_t>(n);
+    // entries gp + 1 .. gi point at cell i
+    const bool long_gap = gi - gp > GAPMIN;
+    if (long_gap) {
+        dir[gi] = static_cast<uint32_t>(i);
+    } else {
+        for (int64_t g = gp + 1; g <= gi; ++g) dir[g] = static_cast<uint32_t>(i);
+    }
+    push_gap(gaps, gap_n, gap_cap, long_gap, gp + 1, gi - 1, static_cast<uint32_t>(i));
+    if (i == n - 1) {  // entries gi + 1 .. G point past the end
+        if (G - gi > GAPMIN) {
+            const unsigned long long k = atomicAdd(gap_n, 1ull);
+            if (static_cast<int64_t>(k) < gap_cap)
+                gaps[k] = make_uint4(static_cast<uint32_t>(gi + 1), static_cast<uint32_t>(G),
+                                     static_cast<uint32_t>(n), 0u);
+        } else {
+            for (int64_t g = gi + 1; g <= G; ++g) dir[g] = static_cast<uint32_t>(n);
+        }
+    }
     sfx[i] = (static_cast<uint64_t>(suffix_hash32<T>(row, words, s)) << 32) | static_cast<uint64_t>(i);
+}
+
+// Fills the listed long gaps: gap (lo, hi, v) sets dir[lo .. hi] = v; one
+// block per gap at a time, threads strided over it.
+__global__ void __launch_bounds__(256) k_dir_gaps(uint32_t *__restrict__ dir, const uint4 *__restrict__ gaps,
+                                                  const unsigned long long *gap_n, int64_t gap_cap) {
+    int64_t cnt = static_cast<int64_t>(*gap_n);
+    if (cnt > gap_cap) cnt = gap_cap;
+    for (int64_t k = blockIdx.x; k < cnt; k += gridDim.x) {
+        const uint4 g = gaps[k];
+        for (int64_t e = static_cast<int64_t>(g.x) + threadIdx.x; e <= static_cast<int64_t>(g.y); e += blockDim.x)
+            dir[e] = g.z;
+    }
 }
 
 // One wave per query; lanes take bits k0 + lane for k0 = 0, 64, ...
@@ -122,6 +172,9 @@ __global__ void __launch_bounds__(256) k_d1_query(const T *__restrict__ cells, c
 
 struct DictMem {
     uint32_t *dir;
+    uint4 *gaps;
+    unsigned long long *gap_n;
+    int64_t gap_cap;
     uint64_t *sfx[2];
     uint32_t *hist;
     uint64_t *tile_sums;
@@ -132,6 +185,9 @@ DictMem carve_dict(void *base, int64_t ncap, const cg_dict_params &p, size_t *by
     DictMem m{};
     const int64_t n = ncap > 0 ? ncap : 1;
     m.dir = c.take<uint32_t>((size_t(1) << p.dir_bits) + 1);
+    m.gap_cap = (int64_t(1) << p.dir_bits) / (GAPMIN + 1) + 2;
+    m.gaps = c.take<uint4>(m.gap_cap);
+    m.gap_n = c.take<unsigned long long>(1);
     m.sfx[0] = c.take<uint64_t>(n);
     m.sfx[1] = c.take<uint64_t>(n);
     m.hist = c.take<uint32_t>(radix_hist_entries(n));
@@ -178,10 +234,13 @@ template <typename T> static cg_status dict_build_impl(cg_dict &d, hipStream_t s
     const int64_t items = std::max<int64_t>(ncap, G + 1);
     const size_t lds = static_cast<size_t>(DT) * (d.lay.words | 1) * sizeof(T);
     const bool stage = lds <= 65536;
+    CG_TRY(fill_i64(reinterpret_cast<int64_t *>(m.gap_n), 0, 1, s));
     hipLaunchKernelGGL((k_dict_scan<T>), dim3(blocks_for(items, DT)), dim3(DT), stage ? lds : 0, s,
                        static_cast<const T *>(d.cells), d.d_ncells, ncap, d.lay.words, d.params.dir_bits,
-                       d.params.split_bit, m.dir, m.sfx[0], stage);
+                       d.params.split_bit, m.dir, m.sfx[0], stage, m.gaps, m.gap_n, m.gap_cap);
     CG_LAUNCHED("dict_scan");
+    hipLaunchKernelGGL(k_dir_gaps, dim3(256), dim3(256), 0, s, m.dir, m.gaps, m.gap_n, m.gap_cap);
+    CG_LAUNCHED("dict_gaps");
     int which = 0;
     if (ncap > 0)
         CG_TRY(radix_sort_u64(m.sfx, nullptr, ncap, d.d_ncells, 32, 64, m.hist, m.tile_sums, &which, s));

@@ -19,14 +19,14 @@
 // So edge slots are offsets[u] + rank for P, offsets[u] + cntP[u] + rank for
 // S, with offsets = exclusive scan of cntP + cntS.
 //
-// Fast path (rows of at most 252 bytes): the S pass runs first, writing
-// cntS and a list of its edges (with their ranks); then one P kernel reads
-// every cell exactly once into LDS (a 256-cell tile per block), counts each
-// cell's P-neighbours, takes its edge offset from a decoupled look-back scan
-// over tiles, and writes offsets and P edges in the same pass; a last small
-// kernel drops the listed S edges into their slots.  Pairs inside a group
-// are pre-filtered with the bound (*) of Section 1.1 against the zero
-// vector: a distance-1 pair has popcounts differing by exactly one.
+// Fast path (rows of at most 1024 bits): the S pass counts each cell's
+// S-neighbours from the cells that share a suffix hash; one persistent P
+// kernel streams every cell once through LDS (256-cell tiles), counts each
+// cell's P-neighbours and stashes them per tile; a scan over tile totals
+// gives offsets; placement writes P edges slot by slot, and a second S pass
+// writes the S edges.  Pairs inside a group are pre-filtered with the bound
+// (*) of Section 1.1 against the zero vector: a distance-1 pair has
+// popcounts differing by exactly one.
 // Generic path (longer rows): count and write passes over global memory.
 #include "cg_internal.hpp"
 
@@ -144,28 +144,26 @@ __global__ void k_status(const int64_t *total, int64_t cap, int32_t *status) {
 //
 // No global atomics and no inter-block waiting (same-address device atomics
 // serialise at roughly 10 ns each, so tickets and shared cursors do not
-// scale).  Each pass works on a 256-item tile and keeps what it found in a
-// per-tile stash; a one-block scan over tile totals gives every tile its
-// output offset; placement passes then copy stashes to their final slots.
+// scale).  The P pass keeps what it found in a per-tile stash; a one-block
+// scan over tile totals gives every tile its output offset; placement then
+// copies stashes to their final slots.
 //
 //   E0 init      zero cntS
-//   E1 S-find    per suffix-order tile: cntS[u], S edges (u, v, k, rank) to
-//                the tile's S stash
-//   E2 P-find    per cell tile, rows in LDS: cntP[u] (bit 31: found by
-//                look-up, recomputed at placement), P edges (v - u, k) to the
-//                tile's P stash; tile total of cntP + cntS
+//   E1 S-count   per block of the suffix order: cntS[u] for cells followed by
+//                an equal suffix hash
+//   E2 P-find    persistent, per cell tile, rows in LDS: cntP[u] (bit 31:
+//                found by look-up, recomputed at placement), P edges (v - u,
+//                k) to the tile's P stash; tile total of cntP + cntS
 //   E3 scan      exclusive scan of tile totals; |E|, offsets[n], status
 //   E4 P-place   per cell tile: offsets (or the sparse next-offsets needed by
-//                E5), P edges from the stash (or recomputed on overflow)
-//   E5 S-place   per suffix-order tile: S edges to next(u) - cntS[u] + rank
+//                E6), P edges from the stash, slot by slot
+//   E5 P-fix     tiles whose stash overflowed: rescan and write
+//   E6 S-write   the S pass again, writing at next(u) - cntS[u] + rank
 
 constexpr int PT = 256;              // items per tile = threads per block
 constexpr int P_STASH = 4 * PT;      // P edges kept per cell tile
-constexpr int S_STASH = PT;          // S edges kept per suffix-order tile
 constexpr uint32_t BIG = 0x80000000u;
-constexpr int FAST_LDS_MAX = 65536;
 
-__device__ __forceinline__ int padded_words(int W) { return W + ((W & 1) ? 0 : 1); }
 
 __global__ void k_edges_init(uint32_t *cntS, int64_t ncap, int64_t *d_nedges, int64_t *offsets, int32_t *status) {
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -178,199 +176,113 @@ __global__ void k_edges_init(uint32_t *cntS, int64_t ncap, int64_t *d_nedges, in
     }
 }
 
-// S-neighbours of the cell at suffix-order position q: run [lo, hi] of equal
-// hashes around q (or a look-up for every k < s when the run is long).  The
-// suffix-order entries of the tile and rmax + 1 positions on either side sit
-// in LDS (hs = hash, ids = cell id, index = position - win0).
-struct SRun {
-    uint32_t id;
-    int64_t lo, hi;
-    bool big;
-};
+// S pass over the suffix order (cells sorted by (32-bit suffix hash, id)).
+// Only positions followed by an equal hash can have a later S-neighbour, so a
+// block streams SC positions of the order, lists those "starters" in LDS and
+// gives them to its threads: each compares its row with the rows of the later
+// members of its run (ids ascend along a run, so partners come in ascending
+// v), or, when more than rmax members follow, looks up u xor e_k for every
+// k < s.  The count pass writes cntS[u]; the write pass redoes the same work
+// and emits at next(u) - cntS[u] + rank.
+constexpr int SC = 8 * PT;  // suffix-order positions per block
+constexpr int SRMAX = 64;   // most later run members scanned; more use look-ups
 
-__device__ __forceinline__ SRun s_run(const uint32_t *hs, const uint32_t *ids, int64_t win0, int64_t q, int64_t n,
-                                      int rmax) {
-    SRun r{0, 0, -1, false};
-    const int64_t e = q - win0;
-    const uint32_t h = hs[e];
-    r.id = ids[e];
-    int64_t left = 0, right = 0;
-    while (left <= rmax && q - left - 1 >= 0 && hs[e - left - 1] == h) ++left;
-    while (right <= rmax && q + right + 1 < n && hs[e + right + 1] == h) ++right;
-    r.lo = q - left;
-    r.hi = q + right;
-    r.big = left + right + 1 > rmax;
-    return r;
-}
-
-// Loads the suffix-order window [tile * PT - rmax - 1, tile * PT + PT + rmax + 1)
-// into LDS; returns win0.  Block-wide.
-__device__ __forceinline__ int64_t load_s_window(uint32_t *hs, uint32_t *ids, const uint64_t *__restrict__ sfx,
-                                                 int64_t tile, int64_t n, int rmax) {
-    const int64_t win0 = tile * PT - (rmax + 1);
-    const int wl = PT + 2 * (rmax + 1);
-    for (int e0 = threadIdx.x; e0 < wl; e0 += PT * 4) {
-        uint64_t v[4];
+template <typename T, bool WRITE>
+__global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, const uint64_t *__restrict__ sfx,
+                                               const int64_t *d_n, int64_t ncap, int words, int s, int rmax,
+                                               uint32_t *__restrict__ cntS, const int64_t *__restrict__ offsets,
+                                               const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
+                                               uint16_t *__restrict__ bit, int64_t cap) {
+    __shared__ uint32_t hs[SC + 1];
+    __shared__ uint32_t ids[SC];
+    __shared__ uint16_t lst[SC];
+    __shared__ uint64_t tmp[4];
+    const int64_t n = load_n(d_n, ncap);
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * SC;
+    if (c0 >= n) return;
+    const int cl = static_cast<int>(n - c0 < SC ? n - c0 : SC);
+    const bool hasnx = c0 + cl < n;  // hs[cl] holds the next position's hash
+    const int t = threadIdx.x;
+    {
+        uint64_t v[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t pos = win0 + e0 + u * PT;
-            v[u] = (e0 + u * PT < wl && pos >= 0 && pos < n) ? sfx[pos] : 0;
+        for (int u = 0; u < 8; ++u) {
+            const int e = t + u * PT;
+            v[u] = e < cl ? sfx[c0 + e] : 0;
         }
+        const uint64_t nx = (t == 0 && hasnx) ? sfx[c0 + cl] : 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = e0 + u * PT;
-            if (e < wl) {
+        for (int u = 0; u < 8; ++u) {
+            const int e = t + u * PT;
+            if (e < cl) {
                 hs[e] = static_cast<uint32_t>(v[u] >> 32);
                 ids[e] = static_cast<uint32_t>(v[u]);
             }
         }
+        if (t == 0 && hasnx) hs[cl] = static_cast<uint32_t>(nx >> 32);
     }
     __syncthreads();
-    return win0;
-}
-
-// S pass over one tile of the suffix order.  Runs are found in the LDS
-// window; the rows of every window position that belongs to a scanned run
-// (2..rmax members) are gathered into LDS once (up to SCAP rows; the rest are
-// compared in global memory), then each cell compares its row with the later
-// members of its run.
-constexpr int SRMAX = 64;   // longest scanned run; longer runs use look-ups
-constexpr int SWIN = PT + 2 * (SRMAX + 1);
-constexpr int SCAP = 160;   // rows staged per tile
-
-template <typename T, int WT> struct SFind {
-    static constexpr int LW = WT + 1;
-    // rows[SCAP] | hs[SWIN] | ids[SWIN] | slot[SWIN]
-    static constexpr size_t bytes = static_cast<size_t>(SCAP) * LW * sizeof(T) + 3 * SWIN * 4;
-};
-
-template <typename T, int WT, bool PLACE>
-__global__ void __launch_bounds__(PT) k_s_tile(const T *__restrict__ cells, const uint64_t *__restrict__ sfx,
-                                               const int64_t *d_n, int64_t ncap, int words, int s, int rmax,
-                                               uint32_t *__restrict__ cntS, uint4 *__restrict__ stash,
-                                               uint32_t *__restrict__ stash_n, const int64_t *__restrict__ offsets,
-                                               const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
-                                               uint16_t *__restrict__ bit, int64_t cap) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint64_t tmp[4];
-    using L = SFind<T, WT>;
-    constexpr int LW = L::LW;
-    T *srows = reinterpret_cast<T *>(smem);
-    uint32_t *hs = reinterpret_cast<uint32_t *>(srows + SCAP * LW);
-    uint32_t *ids = hs + SWIN;
-    int32_t *slot = reinterpret_cast<int32_t *>(ids + SWIN);
-    const int64_t n = load_n(d_n, ncap);
-    const int64_t tile = blockIdx.x;
-    if (tile * PT >= n) return;
-    if (PLACE && stash_n[tile] <= static_cast<uint32_t>(S_STASH)) return;  // the stash already holds this tile
-    const int64_t q = tile * PT + threadIdx.x;
-    for (int e = threadIdx.x; e < SWIN; e += PT) slot[e] = -1;
-    const int64_t win0 = load_s_window(hs, ids, sfx, tile, n, SRMAX);  // contains a barrier
-    SRun r{0, 0, -1, false};
-    if (q < n) r = s_run(hs, ids, win0, q, n, rmax);
-    const bool scan = q < n && r.hi > r.lo && !r.big;
-    if (scan)
-        for (int64_t p = r.lo; p <= r.hi; ++p) slot[p - win0] = 0;  // needed
-    __syncthreads();
-    // number the needed window positions (two per thread at most)
-    int need0 = 0;
-    for (int e = threadIdx.x * 2; e < threadIdx.x * 2 + 2; ++e) need0 += (e < SWIN && slot[e] == 0) ? 1 : 0;
-    uint64_t tot;
-    int k = static_cast<int>(block256_excl_scan_u64(static_cast<uint64_t>(need0), tmp, &tot));
-    for (int e = threadIdx.x * 2; e < threadIdx.x * 2 + 2; ++e)
-        if (e < SWIN && slot[e] == 0) slot[e] = k < SCAP ? k++ : (++k, -2);  // -2: not staged
-    __syncthreads();
-    // gather the staged rows (each staged slot's row; U loads in flight)
-    const int nst = static_cast<int>(tot < SCAP ? tot : SCAP);
-    {
-        constexpr int U = 8;
-        const int totw = SWIN * WT;
-        for (int e0 = threadIdx.x; e0 < totw; e0 += PT * U) {
-            T v[U];
-            int dst[U];
+    uint32_t flags = 0;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = e0 + u * PT;
-                const int ps = e / WT, w = e % WT;
-                const int sl = e < totw ? slot[ps] : -1;
-                dst[u] = sl >= 0 ? sl * LW + w : -1;
-                v[u] = (sl >= 0 && w < words) ? cells[static_cast<int64_t>(ids[ps]) * words + w] : T(0);
-            }
+    for (int u = 0; u < 8; ++u) {
+        const int e = t * 8 + u;
+        const bool st = e < cl && (e + 1 < cl || hasnx) && hs[e + 1] == hs[e];
+        flags |= st ? (1u << u) : 0u;
+    }
+    uint64_t nst;
+    uint32_t k = static_cast<uint32_t>(block256_excl_scan_u64(static_cast<uint64_t>(__popc(flags)), tmp, &nst));
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (dst[u] >= 0) srows[dst[u]] = v[u];
+    for (int u = 0; u < 8; ++u)
+        if (flags & (1u << u)) lst[k++] = static_cast<uint16_t>(t * 8 + u);
+    __syncthreads();
+    for (int li = t; li < static_cast<int>(nst); li += PT) {
+        const int e = lst[li];
+        const int64_t q = c0 + e;
+        const uint32_t u = ids[e];
+        const uint32_t h = hs[e];
+        auto hash_at = [&](int64_t p) -> uint32_t {
+            const int64_t ep = p - c0;
+            return (ep < cl || (ep == cl && hasnx)) ? hs[ep] : static_cast<uint32_t>(sfx[p] >> 32);
+        };
+        auto id_at = [&](int64_t p) -> uint32_t {
+            const int64_t ep = p - c0;
+            return ep < cl ? ids[ep] : static_cast<uint32_t>(sfx[p]);
+        };
+        int L = 1;  // later members (a starter has at least one)
+        bool big = false;
+        while (q + L + 1 < n && hash_at(q + L + 1) == h) {
+            if (L == rmax) { big = true; break; }
+            ++L;
         }
-    }
-    (void)nst;
-    __syncthreads();
-    // compare my row with the later members of my run
-    auto for_each = [&](auto f) -> uint32_t {
+        const T *me = cells + static_cast<int64_t>(u) * words;
+        int64_t base = 0;
+        if (WRITE) {
+            const uint32_t ct = cntS[u];
+            if (ct == 0) continue;
+            const int64_t next = offsets ? offsets[static_cast<int64_t>(u) + 1] : offnext[u];
+            base = next - ct;
+        }
         uint32_t c = 0;
-        if (!(q < n) || r.hi <= r.lo) return 0;
-        const T *gme = cells + static_cast<int64_t>(r.id) * words;
-        if (r.big) {
+        if (big) {
             for (int kk = s - 1; kk >= 0; --kk) {
-                if (get_bit<T>(gme, kk)) continue;
-                const int64_t v = find_row<T>(cells, words, static_cast<int64_t>(r.id) + 1, n, gme, kk);
-                if (v >= 0) { f(static_cast<uint32_t>(v), kk, c); ++c; }
+                if (get_bit<T>(me, kk)) continue;
+                const int64_t v = find_row<T>(cells, words, static_cast<int64_t>(u) + 1, n, me, kk);
+                if (v >= 0) {
+                    if (WRITE) emit(uv, bit, cap, base + c, u, static_cast<uint32_t>(v), kk);
+                    ++c;
+                }
             }
-            return c;
+        } else {
+            for (int j = 1; j <= L; ++j) {
+                const uint32_t v = id_at(q + j);
+                int pos;
+                if (dist_full<T>(me, cells + static_cast<int64_t>(v) * words, words, &pos) == 1 && pos < s) {
+                    if (WRITE) emit(uv, bit, cap, base + c, u, v, pos);
+                    ++c;
+                }
+            }
         }
-        const int ms = slot[q - win0];
-        for (int64_t p = r.lo; p <= r.hi; ++p) {
-            const uint32_t v = ids[p - win0];
-            if (v <= r.id) continue;
-            const int os = slot[p - win0];
-            int pos, dd;
-            if (ms >= 0 && os >= 0) dd = dist_t<T, WT>(srows + ms * LW, srows + os * LW, &pos);
-            else dd = dist_full<T>(gme, cells + static_cast<int64_t>(v) * words, words, &pos);
-            if (dd == 1 && pos < s) { f(v, pos, c); ++c; }
-        }
-        return c;
-    };
-    if (!PLACE) {
-        const uint32_t c = for_each([](uint32_t, int, uint32_t) {});
-        uint64_t tc;
-        const uint64_t ex = block256_excl_scan_u64(c, tmp, &tc);
-        if (threadIdx.x == 0) stash_n[tile] = static_cast<uint32_t>(tc > 0xffffffffull ? 0xffffffffull : tc);
-        if (c == 0) return;
-        cntS[r.id] = c;
-        if (tc > static_cast<uint64_t>(S_STASH)) return;  // placement recomputes this tile
-        uint4 *out = stash + tile * S_STASH + ex;
-        const uint32_t id = r.id;
-        for_each([&](uint32_t v, int kk, uint32_t rank) {
-            out[rank] = make_uint4(id, v, static_cast<uint32_t>(kk) | (rank << 16), c);
-        });
-    } else {
-        if (!(q < n)) return;
-        const uint32_t c = cntS[r.id];
-        if (c == 0) return;
-        const int64_t next = offsets ? offsets[static_cast<int64_t>(r.id) + 1] : offnext[r.id];
-        const uint32_t id = r.id;
-        for_each([&](uint32_t v, int kk, uint32_t rank) { emit(uv, bit, cap, next - c + rank, id, v, kk); });
-    }
-}
-
-__device__ __forceinline__ void emit(uint32_t *uv, uint16_t *bit, int64_t cap, int64_t pos, uint32_t u,
-                                     uint32_t v, int k);
-
-// Drop the stashed S edges of each tile into their slots:
-// next(u) - cntS[u] + rank.  Tiles whose stash overflowed are redone by
-// k_s_tile<.., true>.
-__global__ void __launch_bounds__(PT) k_s_place(const int64_t *d_n, int64_t ncap, const uint4 *__restrict__ stash,
-                                                const uint32_t *__restrict__ stash_n,
-                                                const int64_t *__restrict__ offsets,
-                                                const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
-                                                uint16_t *__restrict__ bit, int64_t cap) {
-    const int64_t n = load_n(d_n, ncap);
-    const int64_t tile = blockIdx.x;
-    if (tile * PT >= n) return;
-    const uint32_t m = stash_n[tile];
-    if (m > static_cast<uint32_t>(S_STASH)) return;
-    for (uint32_t e = threadIdx.x; e < m; e += PT) {
-        const uint4 r = stash[tile * S_STASH + e];
-        const int64_t next = offsets ? offsets[static_cast<int64_t>(r.x) + 1] : offnext[r.x];
-        emit(uv, bit, cap, next - r.w + (r.z >> 16), r.x, r.y, static_cast<int>(r.z & 0xffffu));
+        if (!WRITE && c) cntS[u] = c;
     }
 }
 
@@ -413,16 +325,17 @@ __device__ __forceinline__ void copy_rows_padded(T *lds, const T *__restrict__ s
     }
 }
 
+// s is uniform across the block, so the word loop's bound is a scalar branch:
+// only the ceil(s / B) words that hold the prefix are read.
 template <typename T, int WT>
 __device__ __forceinline__ bool same_prefix_t(const T *a, const T *b, int s) {
     constexpr int B = Bits<T>::B;
     const int full = s / B, rem = s % B;
     T acc = 0;
 #pragma unroll
-    for (int w = 0; w < WT; ++w) {
-        const T m = w < full ? static_cast<T>(~T(0)) : (w == full && rem ? static_cast<T>(~T(0)) << (B - rem) : T(0));
-        acc |= (a[w] ^ b[w]) & m;
-    }
+    for (int w = 0; w < WT; ++w)
+        if (w < full) acc |= a[w] ^ b[w];
+    if (rem && full < WT) acc |= (a[full] ^ b[full]) & (static_cast<T>(~T(0)) << (B - rem));
     return acc == 0;
 }
 
@@ -531,6 +444,14 @@ template <typename T, int WT> struct PFind {
     static constexpr size_t bytes = rows_bytes + PT * 8 + (PROWS + 1) * 4 + P_STASH * 4 + 4 * CQ * 4 + PROWS + 4;
 };
 
+// Persistent: each block walks a strided sequence of tiles and, while it
+// works on one tile in LDS, already has the next tile's rows (tile plus
+// HALO rows, padded to WT words) and cntS values in flight in registers, so
+// the stream of rows never waits for the comparisons.  Tiles are dealt out
+// per XCD (workgroups go round-robin over the 8 XCDs): XCD x takes the x-th
+// eighth of the tiles, so a tile and the one after it (whose first rows are
+// the tile's halo) are read on the same XCD at about the same time and the
+// halo comes from that XCD's L2.
 template <typename T, int WT>
 __global__ void __launch_bounds__(PT) k_p_find(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
                                                int words, int ell, int s, int gmax,
@@ -539,11 +460,11 @@ __global__ void __launch_bounds__(PT) k_p_find(const T *__restrict__ cells, cons
                                                uint64_t *__restrict__ tile_tot) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint64_t tmp[4];
-    __shared__ int s_th;
     __shared__ uint32_t s_nres;
     __shared__ uint32_t sbase[PT];
     using L = PFind<T, WT>;
     constexpr int LW = L::LW;
+    constexpr int NE = (PROWS * WT + PT - 1) / PT;  // prefetched words per thread
     T *rows = reinterpret_cast<T *>(smem);
     unsigned long long *mask = reinterpret_cast<unsigned long long *>(smem + L::rows_bytes);
     uint32_t *pcs = reinterpret_cast<uint32_t *>(mask + PT);
@@ -551,137 +472,211 @@ __global__ void __launch_bounds__(PT) k_p_find(const T *__restrict__ cells, cons
     uint32_t *cq = res + P_STASH;
     uint8_t *heads = reinterpret_cast<uint8_t *>(cq + 4 * CQ);
     const int64_t n = load_n(d_n, ncap);
-    const int64_t tile = blockIdx.x;
-    const int64_t base = tile * PT;
-    if (base >= n) return;
+    const int64_t ntiles = (n + PT - 1) / PT;
+    const int G8 = static_cast<int>(gridDim.x >> 3);
+    const int xcd = static_cast<int>(blockIdx.x & 7), lb = static_cast<int>(blockIdx.x >> 3);
+    const int64_t T8 = (ntiles + 7) / 8;
+    const int64_t r0 = xcd * T8;
+    const int64_t r1 = r0 + T8 < ntiles ? r0 + T8 : ntiles;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    mask[t] = 0;
-    if (t == 0) s_nres = 0;
-    int th;
-    const int tr = load_ptile<T, WT>(rows, pcs, heads, &s_th, cells, words, s, base, n, &th);
-    const int tl = tr + th;
-    if (t == 0) pcs[tl] = 0xffffffffu;  // clamp target past the loaded rows
-    __syncthreads();
-    const int64_t i = base + t;
     uint32_t *q = cq + wv * CQ;
     const uint64_t lt = lanemask_lt();
     const int gm = gmax < PSCAN ? gmax : PSCAN;
 
-    // entry: cell (8 bits) | offset (8 bits, 1..64) | position (16 bits)
-    auto found = [&](int t0, int d0, int k) {
-        atomicOr(&mask[t0], 1ull << (d0 - 1));
-        const uint32_t r = atomicAdd(&s_nres, 1u);
-        if (r < static_cast<uint32_t>(P_STASH))
-            res[r] = (static_cast<uint32_t>(t0) << 24) | (static_cast<uint32_t>(d0) << 16) | static_cast<uint32_t>(k);
-    };
-    auto check = [&](uint32_t e) {
-        const int t0 = static_cast<int>(e >> 16), j0 = static_cast<int>(e & 0xffffu);
-        int pos;
-        if (dist_t<T, WT>(rows + t0 * LW, rows + j0 * LW, &pos) == 1) found(t0, j0 - t0, pos);
+    T pre[NE];
+    uint32_t pre_cs = 0;
+    auto prefetch = [&](int64_t tile) {
+        const int64_t base = tile * PT;
+        const int64_t av = n - base;
+        const int avail = static_cast<int>(av < PROWS ? av : PROWS);
+        const int tot = avail * WT;
+        const T *src = cells + base * words;
+#pragma unroll
+        for (int u = 0; u < NE; ++u) {
+            const int e = t + u * PT;
+            const int r = e / WT, w = e % WT;
+            pre[u] = (e < tot && w < words) ? src[static_cast<int64_t>(r) * words + w] : T(0);
+        }
+        pre_cs = base + t < n ? cntS[base + t] : 0u;
     };
 
-    bool scanning = t < tr;
-    bool big = false, spill = false;  // spill: the group runs past the loaded rows
-    const uint32_t pc = t < tl ? pcs[t] : 0u;
-    uint32_t qn = 0, qh = 0;
-    for (int d = 1; ballot64(scanning) != 0; ++d) {
-        const int jj = t + d;
-        const int jc = jj < tl ? jj : tl;
-        const uint32_t h = heads[jc];  // at tl: 0 iff the group may go on
-        const uint32_t po = pcs[jc];
-        const bool past = jj >= tl;
-        const bool tiny = d > gm;
-        // past the loaded rows with the group possibly going on: finish in global
-        // memory (which also settles d > gm there)
-        spill = spill || (scanning && past && h == 0);
-        big = big || (scanning && !past && h == 0 && tiny);
-        const bool stop = past || h != 0 || tiny;
-        const bool cand = scanning && !stop && (po == pc + 1 || po + 1 == pc);
-        scanning = scanning && !stop;
-        const uint64_t m = ballot64(cand);
-        if (cand) q[(qn + static_cast<uint32_t>(__popcll(m & lt))) % CQ] = (static_cast<uint32_t>(t) << 16) | static_cast<uint32_t>(jj);
-        qn += static_cast<uint32_t>(__popcll(m));
-        while (qn - qh >= 64) {  // a full batch: lane e checks queued pair qh + e
-            __builtin_amdgcn_wave_barrier();
-            check(q[(qh + lane) % CQ]);
-            qh += 64;
+    int64_t tile = r0 + lb;
+    if (tile < r1) prefetch(tile);
+    for (; tile < r1; tile += G8) {
+        const int64_t base = tile * PT;
+        const int tr = static_cast<int>(n - base < PT ? n - base : PT);
+        const int tl = static_cast<int>(n - base < PROWS ? n - base : PROWS);  // loaded rows
+#pragma unroll
+        for (int u = 0; u < NE; ++u) {
+            const int e = t + u * PT;
+            if (e < PROWS * WT) rows[(e / WT) * LW + (e % WT)] = pre[u];
         }
-    }
-    __builtin_amdgcn_wave_barrier();
-    if (static_cast<uint32_t>(lane) < qn - qh) check(q[(qh + lane) % CQ]);
-    if (spill) {
-        // the group goes on past the loaded rows: finish it in global memory
-        const T *me = rows + t * LW;
-        for (int64_t j = base + tl; j < n; ++j) {
-            const T *o = cells + j * words;
-            if (!same_prefix<T>(me, o, s)) break;
-            if (j - i > gm) { big = true; break; }
+        const uint32_t cs = pre_cs;
+        mask[t] = 0;
+        if (t == 0) s_nres = 0;
+        __syncthreads();
+        if (tile + G8 < r1) prefetch(tile + G8);
+        for (int r = t; r < tl; r += PT) {
+            const T *me = rows + r * LW;
+            uint32_t pc = 0;
+#pragma unroll
+            for (int w = 0; w < WT; ++w) pc += popc<T>(me[w]);
+            pcs[r] = pc;
+            heads[r] = (r == 0 || !same_prefix_t<T, WT>(me - LW, me, s)) ? 1 : 0;
+        }
+        if (t == 0) {
+            heads[tl] = base + tl < n ? 0 : 1;  // 0: the last group may go on past the loaded rows
+            pcs[tl] = 0xffffffffu;
+        }
+        __syncthreads();
+        const int64_t i = base + t;
+
+        // entry: cell (8 bits) | offset (8 bits, 1..64) | position (16 bits)
+        auto found = [&](int t0, int d0, int k) {
+            atomicOr(&mask[t0], 1ull << (d0 - 1));
+            const uint32_t r = atomicAdd(&s_nres, 1u);
+            if (r < static_cast<uint32_t>(P_STASH))
+                res[r] = (static_cast<uint32_t>(t0) << 24) | (static_cast<uint32_t>(d0) << 16) |
+                         static_cast<uint32_t>(k);
+        };
+        auto check = [&](uint32_t e) {
+            const int t0 = static_cast<int>(e >> 16), j0 = static_cast<int>(e & 0xffffu);
             int pos;
-            if (dist_full<T>(me, o, words, &pos) == 1) found(t, static_cast<int>(j - i), pos);
+            if (dist_t4<T, WT>(rows + t0 * LW, rows + j0 * LW, &pos) == 1) found(t0, j0 - t0, pos);
+        };
+
+        bool scanning = t < tr;
+        bool big = false, spill = false;  // spill: the group runs past the loaded rows
+        const uint32_t pc = t < tl ? pcs[t] : 0u;
+        uint32_t qn = 0, qh = 0;
+        for (int d = 1; ballot64(scanning) != 0; ++d) {
+            const int jj = t + d;
+            const int jc = jj < tl ? jj : tl;
+            const uint32_t h = heads[jc];  // at tl: 0 iff the group may go on
+            const uint32_t po = pcs[jc];
+            const bool past = jj >= tl;
+            const bool tiny = d > gm;
+            // past the loaded rows with the group possibly going on: finish in global
+            // memory (which also settles d > gm there)
+            spill = spill || (scanning && past && h == 0);
+            big = big || (scanning && !past && h == 0 && tiny);
+            const bool stop = past || h != 0 || tiny;
+            const bool cand = scanning && !stop && (po == pc + 1 || po + 1 == pc);
+            scanning = scanning && !stop;
+            const uint64_t m = ballot64(cand);
+            if (cand)
+                q[(qn + static_cast<uint32_t>(__popcll(m & lt))) % CQ] =
+                    (static_cast<uint32_t>(t) << 16) | static_cast<uint32_t>(jj);
+            qn += static_cast<uint32_t>(__popcll(m));
+            while (qn - qh >= 64) {  // a full batch: lane e checks queued pair qh + e
+                __builtin_amdgcn_wave_barrier();
+                check(q[(qh + lane) % CQ]);
+                qh += 64;
+            }
         }
-    }
-    __syncthreads();
-    uint32_t cp = 0, cs = 0;
-    if (t < tr) {
-        cp = big ? (BIG | p_lookup<T>(cells, i, n, words, ell, s, [](uint32_t, int, uint32_t) {}))
-                 : static_cast<uint32_t>(__popcll(mask[t]));
-        cs = cntS[i];
-        cntP[i] = cp;
-    }
-    const uint32_t stashed = (cp & BIG) ? 0u : cp;
-    uint64_t tot_stash, tot_all;
-    const uint64_t ex = block256_excl_scan_u64(stashed, tmp, &tot_stash);
-    block256_excl_scan_u64(static_cast<uint64_t>(cp & ~BIG) + cs, tmp, &tot_all);
-    sbase[t] = (cp & BIG) ? 0xffffffffu : static_cast<uint32_t>(ex);
-    const uint32_t nres = s_nres;
-    if (t == 0) {
-        tile_tot[tile] = tot_all;
-        const uint64_t m = nres > tot_stash ? nres : tot_stash;
-        stash_n[tile] = static_cast<uint32_t>(m > 0xffffffffull ? 0xffffffffull : m);
-    }
-    __syncthreads();
-    if (nres > static_cast<uint32_t>(P_STASH)) return;  // k_p_fix recomputes this tile
-    uint32_t *out = stash + tile * P_STASH;
-    for (uint32_t r = t; r < nres; r += PT) {
-        const uint32_t e = res[r];
-        const int t0 = static_cast<int>(e >> 24);
-        const int d0 = static_cast<int>((e >> 16) & 0xffu);
-        if (sbase[t0] == 0xffffffffu) continue;  // found by look-up at placement instead
-        const uint32_t rank = static_cast<uint32_t>(__popcll(mask[t0] & ((1ull << (d0 - 1)) - 1ull)));
-        out[sbase[t0] + rank] = (static_cast<uint32_t>(d0) << 16) | (e & 0xffffu);
+        __builtin_amdgcn_wave_barrier();
+        if (static_cast<uint32_t>(lane) < qn - qh) check(q[(qh + lane) % CQ]);
+        if (spill) {
+            // the group goes on past the loaded rows: finish it in global memory
+            const T *me = rows + t * LW;
+            for (int64_t j = base + tl; j < n; ++j) {
+                const T *o = cells + j * words;
+                if (!same_prefix<T>(me, o, s)) break;
+                if (j - i > gm) { big = true; break; }
+                int pos;
+                if (dist_full<T>(me, o, words, &pos) == 1) found(t, static_cast<int>(j - i), pos);
+            }
+        }
+        __syncthreads();
+        uint32_t cp = 0;
+        if (t < tr) {
+            cp = big ? (BIG | p_lookup<T>(cells, i, n, words, ell, s, [](uint32_t, int, uint32_t) {}))
+                     : static_cast<uint32_t>(__popcll(mask[t]));
+            cntP[i] = cp;
+        }
+        const uint32_t csv = t < tr ? cs : 0u;
+        const uint32_t stashed = (cp & BIG) ? 0u : cp;
+        uint64_t tot_stash, tot_all;
+        const uint64_t ex = block256_excl_scan_u64(stashed, tmp, &tot_stash);
+        block256_excl_scan_u64(static_cast<uint64_t>(cp & ~BIG) + csv, tmp, &tot_all);
+        sbase[t] = (cp & BIG) ? 0xffffffffu : static_cast<uint32_t>(ex);
+        const uint32_t nres = s_nres;
+        if (t == 0) {
+            tile_tot[tile] = tot_all;
+            const uint64_t m = nres > tot_stash ? nres : tot_stash;
+            stash_n[tile] = static_cast<uint32_t>(m > 0xffffffffull ? 0xffffffffull : m);
+        }
+        __syncthreads();
+        if (nres <= static_cast<uint32_t>(P_STASH)) {  // else k_p_fix recomputes this tile
+            uint32_t *out = stash + tile * P_STASH;
+            for (uint32_t r = t; r < nres; r += PT) {
+                const uint32_t e = res[r];
+                const int t0 = static_cast<int>(e >> 24);
+                const int d0 = static_cast<int>((e >> 16) & 0xffu);
+                if (sbase[t0] == 0xffffffffu) continue;  // found by look-up at placement instead
+                const uint32_t rank = static_cast<uint32_t>(__popcll(mask[t0] & ((1ull << (d0 - 1)) - 1ull)));
+                out[sbase[t0] + rank] = (static_cast<uint32_t>(d0) << 16) | (e & 0xffffu);
+            }
+        }
+        __syncthreads();  // LDS is refilled for the next tile
     }
 }
 
-// One block: exclusive scan of tile totals in place; |E|, offsets[n], status.
-// Thread t owns a contiguous chunk of the totals, read and written in
-// batches of 16 so the loads overlap.
-__global__ void __launch_bounds__(256) k_tile_scan(uint64_t *tile_tot, const int64_t *d_n, int64_t ncap,
-                                                   int64_t cap, int64_t *d_nedges, int64_t *offsets,
-                                                   int32_t *status) {
-    __shared__ uint64_t tmp[4];
+// One block of 1024 threads: exclusive scan of the tile totals in place;
+// |E|, offsets[n], status.  Thread t owns a contiguous chunk; up to 16 per
+// thread (16,384 tiles) the chunk is read once and kept in registers.
+constexpr int TS_T = 1024;
+__global__ void __launch_bounds__(TS_T) k_tile_scan(uint64_t *tile_tot, const int64_t *d_n, int64_t ncap,
+                                                    int64_t cap, int64_t *d_nedges, int64_t *offsets,
+                                                    int32_t *status) {
+    __shared__ uint64_t wsum[TS_T / 64];
     constexpr int U = 16;
     const int64_t n = load_n(d_n, ncap);
     const int64_t tiles = (n + PT - 1) / PT;
-    const int64_t per = ((tiles + 255) / 256 + U - 1) / U * U;
+    const int64_t per = (tiles + TS_T - 1) / TS_T;
     const int64_t a = threadIdx.x * per;
+    uint64_t v[U];
     uint64_t sum = 0;
-    for (int64_t k0 = a; k0 < a + per; k0 += U) {
-        uint64_t v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = (k0 + u < tiles) ? tile_tot[k0 + u] : 0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) sum += v[u];
-    }
-    uint64_t total;
-    uint64_t run = block256_excl_scan_u64(sum, tmp, &total);
-    for (int64_t k0 = a; k0 < a + per; k0 += U) {
-        uint64_t v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = (k0 + u < tiles) ? tile_tot[k0 + u] : 0;
+    if (per <= U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (k0 + u < tiles) tile_tot[k0 + u] = run;
+            v[u] = (u < per && a + u < tiles) ? tile_tot[a + u] : 0;
+            sum += v[u];
+        }
+    } else {
+        for (int64_t k0 = a; k0 < a + per; k0 += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = (k0 + u < a + per && k0 + u < tiles) ? tile_tot[k0 + u] : 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) sum += v[u];
+        }
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const uint64_t inc = wave_incl_scan_u64(sum);
+    if (l == 63) wsum[w] = inc;
+    __syncthreads();
+    uint64_t run = inc - sum, total = 0;
+#pragma unroll
+    for (int k = 0; k < TS_T / 64; ++k) {
+        const uint64_t x = wsum[k];
+        if (k < w) run += x;
+        total += x;
+    }
+    if (per <= U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (u < per && a + u < tiles) tile_tot[a + u] = run;
             run += v[u];
+        }
+    } else {
+        for (int64_t k0 = a; k0 < a + per; k0 += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = (k0 + u < a + per && k0 + u < tiles) ? tile_tot[k0 + u] : 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (k0 + u < a + per && k0 + u < tiles) tile_tot[k0 + u] = run;
+                run += v[u];
+            }
         }
     }
     if (threadIdx.x == 0) {
@@ -693,6 +688,10 @@ __global__ void __launch_bounds__(256) k_tile_scan(uint64_t *tile_tot, const int
 }
 
 // Placement of P edges for tiles whose stash held them; offsets for all.
+// The tile's edges fill one contiguous range of slots: thread r takes slots
+// r, r + PT, ..., finds the owning cell by binary search over the tile's
+// exclusive scan, and copies the P edge from the stash (the cell's S slots
+// are left to the S write pass), so the output is written coalesced.
 template <typename T>
 __global__ void __launch_bounds__(PT) k_p_place(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
                                                 int words, int ell, int s,
@@ -703,6 +702,9 @@ __global__ void __launch_bounds__(PT) k_p_place(const T *__restrict__ cells, con
                                                 int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
                                                 uint16_t *__restrict__ bit, int64_t cap) {
     __shared__ uint64_t tmp[4];
+    __shared__ uint32_t sx[PT];   // tile-relative first slot of each cell
+    __shared__ uint32_t ssb[PT];  // first stash entry of each cell
+    __shared__ uint32_t scp[PT];  // P count (BIG flag kept)
     const int64_t n = load_n(d_n, ncap);
     const int64_t tile = blockIdx.x;
     const int64_t base = tile * PT;
@@ -715,29 +717,42 @@ __global__ void __launch_bounds__(PT) k_p_place(const T *__restrict__ cells, con
         cp = cntP[i];
         cs = cntS[i];
     }
+    const uint64_t t_off = tile_off[tile];
+    const uint32_t sn = stash_n[tile];
     const uint32_t c = cp & ~BIG;
     const uint32_t stashed = (cp & BIG) ? 0u : cp;
     uint64_t tot_all, tot_stash;
     const uint64_t exa = block256_excl_scan_u64(static_cast<uint64_t>(c) + cs, tmp, &tot_all);
     const uint64_t exs = block256_excl_scan_u64(stashed, tmp, &tot_stash);
-    const int64_t out0 = static_cast<int64_t>(tile_off[tile] + exa);
+    const int64_t out0 = static_cast<int64_t>(t_off + exa);
     if (t < tr) {
         if (offsets) offsets[i] = out0;
         else if (cs) offnext[i] = out0 + c + cs;
     }
-    if (t >= tr) return;
-    if (cp & BIG) {
+    sx[t] = static_cast<uint32_t>(exa);
+    ssb[t] = static_cast<uint32_t>(exs);
+    scp[t] = t < tr ? cp : 0u;
+    __syncthreads();
+    if (t < tr && (cp & BIG)) {
         p_lookup<T>(cells, i, n, words, ell, s, [&](uint32_t v, int k, uint32_t r) {
             emit(uv, bit, cap, out0 + r, static_cast<uint32_t>(i), v, k);
         });
-        return;
     }
-    if (stash_n[tile] > static_cast<uint32_t>(P_STASH)) return;  // k_p_fix writes this tile
-    const uint32_t *src = stash + tile * P_STASH + exs;
-    for (uint32_t r = 0; r < c; ++r) {
-        const uint32_t e = src[r];
-        emit(uv, bit, cap, out0 + r, static_cast<uint32_t>(i), static_cast<uint32_t>(i + (e >> 16)),
-             static_cast<int>(e & 0xffffu));
+    if (sn > static_cast<uint32_t>(P_STASH)) return;  // k_p_fix writes this tile's scanned P edges
+    const uint32_t *src = stash + tile * P_STASH;
+    for (uint32_t r = t; r < static_cast<uint32_t>(tot_all); r += PT) {
+        int lo = 0, hi = tr;  // last cell with sx <= r
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (sx[mid] <= r) lo = mid; else hi = mid;
+        }
+        const uint32_t k = r - sx[lo];
+        const uint32_t cpl = scp[lo];
+        if ((cpl & BIG) || k >= cpl) continue;  // looked-up cell, or an S slot
+        const uint32_t e = src[ssb[lo] + k];
+        const int64_t u = base + lo;
+        emit(uv, bit, cap, static_cast<int64_t>(t_off) + r, static_cast<uint32_t>(u),
+             static_cast<uint32_t>(u + (e >> 16)), static_cast<int>(e & 0xffffu));
     }
 }
 
@@ -786,8 +801,6 @@ struct EdgesWs {
     uint64_t *tile_sums;
     uint64_t *tile_tot;
     uint32_t *p_stash, *p_stash_n;
-    uint4 *s_stash;
-    uint32_t *s_stash_n;
 };
 
 // Padded row width (power of two) for the P tiles, or 0 when rows are too
@@ -813,10 +826,24 @@ EdgesWs carve_edges(void *base, int64_t ncap, size_t *bytes) {
     w.tile_tot = c.take<uint64_t>(tiles);
     w.p_stash = c.take<uint32_t>(tiles * P_STASH);
     w.p_stash_n = c.take<uint32_t>(tiles);
-    w.s_stash = c.take<uint4>(tiles * S_STASH);
-    w.s_stash_n = c.take<uint32_t>(tiles);
     *bytes = c.bytes();
     return w;
+}
+
+// Blocks of a persistent kernel: as many as fit on the device at once
+// (a multiple of 8, one share per XCD), but no more than there are tiles.
+unsigned persistent_blocks(const void *kernel, size_t lds, int64_t ntiles) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, PT, lds) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
+    int64_t g = static_cast<int64_t>(cus) * per_cu;
+    const int64_t need = (ntiles + 7) / 8 * 8;
+    if (g > need) g = need;
+    g = g / 8 * 8;
+    return static_cast<unsigned>(g < 8 ? 8 : g);
 }
 
 template <typename T, int WT>
@@ -825,21 +852,23 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
     const int64_t ncap = d.ncells_cap;
     const T *cells = static_cast<const T *>(d.cells);
     const int words = d.lay.words, ell = d.lay.ell, sp = d.params.split_bit, gmax = d.params.group_max;
-    const dim3 grid(static_cast<unsigned>((ncap + PT - 1) / PT));
+    const int64_t ntiles = (ncap + PT - 1) / PT;
+    const dim3 grid(static_cast<unsigned>(ntiles));
+    const dim3 sgrid(static_cast<unsigned>((ncap + SC - 1) / SC));
     const size_t lds = PTile<T, WT>::bytes;
     const size_t lds_find = PFind<T, WT>::bytes;
-    const size_t lds_s = SFind<T, WT>::bytes;
     const int rmax = gmax < SRMAX ? gmax : SRMAX;
     if (sp > 0) {
-        hipLaunchKernelGGL((k_s_tile<T, WT, false>), grid, dim3(PT), lds_s, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
-                           rmax, w.cntS, w.s_stash, w.s_stash_n, static_cast<const int64_t *>(nullptr),
-                           static_cast<const int64_t *>(nullptr), uv, bit, cap);
-        CG_LAUNCHED("edges_s_find");
+        hipLaunchKernelGGL((k_s_scan<T, false>), sgrid, dim3(PT), 0, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
+                           rmax, w.cntS, static_cast<const int64_t *>(nullptr), static_cast<const int64_t *>(nullptr),
+                           uv, bit, cap);
+        CG_LAUNCHED("edges_s_count");
     }
-    hipLaunchKernelGGL((k_p_find<T, WT>), grid, dim3(PT), lds_find, s, cells, d.d_ncells, ncap, words, ell, sp, gmax,
-                       w.cntS, w.cntP, w.p_stash, w.p_stash_n, w.tile_tot);
+    const unsigned pblocks = persistent_blocks(reinterpret_cast<const void *>(&k_p_find<T, WT>), lds_find, ntiles);
+    hipLaunchKernelGGL((k_p_find<T, WT>), dim3(pblocks), dim3(PT), lds_find, s, cells, d.d_ncells, ncap, words, ell,
+                       sp, gmax, w.cntS, w.cntP, w.p_stash, w.p_stash_n, w.tile_tot);
     CG_LAUNCHED("edges_p_find");
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, s, w.tile_tot, d.d_ncells, ncap, cap, d_nedges, d_offsets,
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(TS_T), 0, s, w.tile_tot, d.d_ncells, ncap, cap, d_nedges, d_offsets,
                        d_status);
     CG_LAUNCHED("edges_tile_scan");
     hipLaunchKernelGGL((k_p_place<T>), grid, dim3(PT), 0, s, cells, d.d_ncells, ncap, words, ell, sp, w.cntS,
@@ -850,12 +879,9 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
                        w.cntP, w.p_stash_n, w.tile_tot, uv, bit, cap);
     CG_LAUNCHED("edges_p_fix");
     if (sp > 0) {
-        hipLaunchKernelGGL(k_s_place, grid, dim3(PT), 0, s, d.d_ncells, ncap, w.s_stash, w.s_stash_n, d_offsets,
-                           offnext, uv, bit, cap);
-        CG_LAUNCHED("edges_s_place");
-        hipLaunchKernelGGL((k_s_tile<T, WT, true>), grid, dim3(PT), lds_s, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
-                           rmax, w.cntS, w.s_stash, w.s_stash_n, d_offsets, offnext, uv, bit, cap);
-        CG_LAUNCHED("edges_s_redo");
+        hipLaunchKernelGGL((k_s_scan<T, true>), sgrid, dim3(PT), 0, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
+                           rmax, w.cntS, d_offsets, offnext, uv, bit, cap);
+        CG_LAUNCHED("edges_s_write");
     }
     return CG_OK;
 }

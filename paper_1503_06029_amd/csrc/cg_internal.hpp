@@ -220,6 +220,28 @@ __device__ __forceinline__ int dist_t(const T *a, const T *b, int *pos) {
     return d;
 }
 
+// dist_t in chunks of 4 words with a rolled outer loop: fewer registers
+// live at once (for kernels that keep other state in registers).
+template <typename T, int WT>
+__device__ __forceinline__ int dist_t4(const T *a, const T *b, int *pos) {
+    if constexpr (WT <= 4) {
+        return dist_t<T, WT>(a, b, pos);
+    } else {
+        int d = 0, first = -1;
+#pragma unroll 1
+        for (int w0 = 0; w0 < WT; w0 += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const T x = a[w0 + u] ^ b[w0 + u];
+                d += popc<T>(x);
+                first = (x && first < 0) ? (w0 + u) * Bits<T>::B + clz_t<T>(x) : first;
+            }
+        }
+        *pos = first;
+        return d;
+    }
+}
+
 // Block-wide copy of nrows contiguous global rows (`words` words each) into
 // LDS rows of stride LW, with U loads in flight per thread (a plain loop with
 // a run-time trip count would wait for each load before the next).

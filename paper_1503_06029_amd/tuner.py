@@ -20,11 +20,14 @@ from . import binding as B
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_params.json")
 
 
-def candidates(ell: int, n_rows: int):
-    """A small grid over s (split bit), p (directory bits) and group limit."""
+def candidates(ell: int, n_rows: int, tag_bits: int = 0):
+    """A small grid over s (split bit) and the group limit; tag_bits leading
+    bits that never differ inside a scene (a batch's scene tag) are skipped."""
     lg = max(1, math.ceil(math.log2(max(n_rows, 2))))
+    splits = {tag_bits + d for d in (16, 32, 48, 64, 96, 128, 192, 256, 384)}
+    splits.add(((lg + 16 + 31) // 32) * 32)
     out = []
-    for s in sorted({min(ell, v) for v in (32, 64, 96, ((lg + 16 + 31) // 32) * 32)}):
+    for s in sorted(v for v in splits if tag_bits < v < ell):
         for gmax in (32, 64):
             out.append(dict(split_bit=s, dir_bits=min(lg, 22, ell), group_max=gmax))
     return out
@@ -35,14 +38,17 @@ def key_of(words: int, n_rows: int) -> str:
 
 
 class Tuner:
-    def __init__(self, path: str = DEFAULT_TABLE):
+    def __init__(self, path: str | None = DEFAULT_TABLE):
+        """path=None: an in-memory table (nothing read or written)."""
         self.path = path
         self.table = {}
-        if os.path.exists(path):
+        if path is not None and os.path.exists(path):
             with open(path) as f:
                 self.table = json.load(f)
 
     def save(self):
+        if self.path is None:
+            return
         tmp = self.path + ".tmp"
         with open(tmp, "w") as f:
             json.dump(self.table, f, indent=1, sort_keys=True)
@@ -52,34 +58,43 @@ class Tuner:
         e = self.table.get(key_of(words, n_rows))
         return B.cg_dict_params_default(**e) if e else None
 
-    def tune_class(self, sb, reps: int = 3):
-        """Time candidate parameters on SceneBatch `sb` (already uploaded)."""
+    def tune_class(self, sb, reps: int = 2, tag_bits: int = 32):
+        """Time candidate parameters on SceneBatch `sb` (already uploaded).
+        A candidate whose first run is more than 3x slower than the best so
+        far is dropped without further timing."""
         ell = sb.lay.ell
         best, best_ms, ref_E = None, float("inf"), None
-        for cand in candidates(ell, sb.n_rows):
+
+        def timed_run():
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record()
+            sb.run()
+            t1.record()
+            torch.cuda.synchronize()
+            return t0.elapsed_time(t1)
+
+        for cand in candidates(ell, sb.n_rows, tag_bits):
             sb.params = B.cg_dict_params_default(**cand)
             sb.dict_bytes = B.cg_dict_size(sb.n_rows, sb.lay, sb.params)
             if sb.dict_mem.numel() < sb.dict_bytes:
                 sb.dict_mem = torch.empty(sb.dict_bytes, dtype=torch.uint8, device=sb.device)
             sb.ws_edges = None
-            sb.run()
-            sb.ensure_capacity() or sb.run()
-            torch.cuda.synchronize()
+            first = timed_run()
+            if not sb.ensure_capacity():
+                first = timed_run()
             E = int(sb.nedges.item())
             if ref_E is None:
                 ref_E = E
             assert E == ref_E, "parameters changed the edge count"
-            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            t0.record()
-            for _ in range(reps):
-                sb.run()
-            t1.record()
-            torch.cuda.synchronize()
-            ms = t0.elapsed_time(t1) / reps
+            if first > 3 * best_ms:
+                continue
+            ms = min(timed_run() for _ in range(reps))
             if ms < best_ms:
                 best, best_ms = cand, ms
         self.table[key_of(sb.words, sb.n_rows)] = best
         sb.params = B.cg_dict_params_default(**best)
         sb.dict_bytes = B.cg_dict_size(sb.n_rows, sb.lay, sb.params)
+        if sb.dict_mem.numel() < sb.dict_bytes:
+            sb.dict_mem = torch.empty(sb.dict_bytes, dtype=torch.uint8, device=sb.device)
         sb.ws_edges = None
         return best, best_ms

@@ -100,3 +100,39 @@ def test_batched_graph_replays(gpu):
                 assert np.array_equal(a[key], b[key]), (rep, key)
     for j, (R, r) in enumerate(zip(scenes, got)):
         check_scene(r, R, R.shape[1])
+
+
+def test_tuned_params_keep_bytes(gpu):
+    """The autotuner may pick any split / group limit: a tuned class must
+    still give the oracle's bytes for every scene."""
+    torch, B, batch = gpu
+    from paper_1503_06029_amd import tuner
+    scenes = make_scenes(3, [s for s in SPECS if 97 <= s[2] <= 224])
+    shapes = [(R.shape[0], R.shape[1]) for R in scenes]
+    runner = batch.BatchRunner(shapes)
+    runner.upload(scenes)
+    tn = tuner.Tuner(path=None)
+    for _, sb in runner.classes:
+        best, ms = tn.tune_class(sb, reps=1)
+        say("tuned", sb.words, best, ms)
+    runner.run_checked()
+    for j, (R, r) in enumerate(zip(scenes, runner.fetch())):
+        check_scene(r, R, R.shape[1])
+
+
+def test_directory_over_sparse_tags(gpu):
+    """Scenes far apart in the tag space leave long empty stretches of the
+    prefix directory; d1 queries through it must still find every cell."""
+    torch, B, batch = gpu
+    scenes = make_scenes(4, [("planes", 1500, 40), ("planes", 900, 60)])
+    shapes = [(R.shape[0], R.shape[1]) for R in scenes]
+    runner = batch.BatchRunner(shapes)
+    runner.upload(scenes)
+    runner.run_checked()
+    (_, sb), = runner.classes
+    nc = int(sb.ncells.item())
+    q = sb.cells[:nc].contiguous()
+    self_id = torch.empty(nc, dtype=torch.int32, device="cuda")
+    B.cg_neighbors_d1(sb.dict, q, nc, None, self_id, None)
+    torch.cuda.synchronize()
+    assert np.array_equal(self_id.cpu().numpy(), np.arange(nc, dtype=np.int32))
