@@ -22,13 +22,20 @@ namespace {
 constexpr uint32_t SENT = 0xFFFFFFFFu;
 constexpr int64_t TILE_LDS = 53248;  // three blocks per CU
 constexpr int LMAX = 4096;          // longest segment sorted in one block's LDS
+#ifndef CG_DEDUP_KEY_BITS
+#define CG_DEDUP_KEY_BITS 64
+#endif
+// Leading bits sorted by the radix passes when rows are longer than 64 bits
+// (32 or 64); equal-key segments are then finished by full-row comparison.
+constexpr int KEY_BITS = CG_DEDUP_KEY_BITS;
+static_assert(KEY_BITS == 32 || KEY_BITS == 64, "sort key is 32 or 64 bits");
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_extract(const T *__restrict__ rows, int64_t n, int words,
+__global__ void __launch_bounds__(256) k_extract(const T *__restrict__ rows, int64_t n, int words, uint64_t kmask,
                                                  uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
     for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
          j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        keys[j] = head64<T>(rows + j * words, words);
+        keys[j] = head64<T>(rows + j * words, words) & kmask;
         vals[j] = static_cast<uint32_t>(j);
     }
 }
@@ -104,6 +111,8 @@ __global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, 
     for (int r = t; r < slots; r += TT) segof[r] = -1;
     __syncthreads();
     const int64_t p = b0 + t;
+    bool large = false;
+    uint2 seg = make_uint2(0u, 0u);
     if (p < n) {
         const uint64_t k = skeys[t + 1];
         const bool head = (p == 0) || k != skeys[t];
@@ -120,11 +129,12 @@ __global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, 
                     seglen[t + r] = static_cast<int32_t>(len);
                 }
             } else {
-                const unsigned long long slot = atomicAdd(&counters[1], 1ull);
-                large_list[slot] = make_uint2(static_cast<uint32_t>(p), static_cast<uint32_t>(len));
+                large = true;
+                seg = make_uint2(static_cast<uint32_t>(p), static_cast<uint32_t>(len));
             }
         }
     }
+    wave_append<uint2>(large_list, &counters[1], n, large, seg);
     __syncthreads();
     for (int r0 = t; r0 < slots; r0 += TT * 4) {
         uint32_t v[4];
@@ -178,9 +188,9 @@ __global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, 
 
 // Same, with rows zero-padded to WT words in LDS (WT a power of two fixed at
 // compile time): the copy and every comparison are straight-line code.
-template <typename T, int WT>
+template <typename T, int WT, int FROM>
 __device__ __forceinline__ int lex_cmp_t(const T *a, const T *b) {
-    constexpr int FROM = 64 / Bits<T>::B;  // words covered by the sort key
+    // words before FROM are covered by the sort key
     int res = 0;
 #pragma unroll
     for (int w = WT - 1; w >= FROM; --w) {
@@ -190,7 +200,7 @@ __device__ __forceinline__ int lex_cmp_t(const T *a, const T *b) {
     return res;
 }
 
-template <typename T, int WT>
+template <typename T, int WT, int FROM>
 __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, const uint64_t *__restrict__ keys,
                                                  int64_t n, int words, int smax, uint32_t *__restrict__ vals,
                                                  uint8_t *__restrict__ uniq, uint2 *__restrict__ large_list,
@@ -220,6 +230,8 @@ __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, con
     for (int r = t; r < slots; r += TT) segof[r] = -1;
     __syncthreads();
     const int64_t p = b0 + t;
+    bool large = false;
+    uint2 seg = make_uint2(0u, 0u);
     if (p < n) {
         const uint64_t k = skeys[t + 1];
         if (p == 0 || k != skeys[t]) {
@@ -235,11 +247,12 @@ __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, con
                     seglen[t + r] = static_cast<int32_t>(len);
                 }
             } else {
-                const unsigned long long slot = atomicAdd(&counters[1], 1ull);
-                large_list[slot] = make_uint2(static_cast<uint32_t>(p), static_cast<uint32_t>(len));
+                large = true;
+                seg = make_uint2(static_cast<uint32_t>(p), static_cast<uint32_t>(len));
             }
         }
     }
+    wave_append<uint2>(large_list, &counters[1], n, large, seg);
     __syncthreads();
     for (int r0 = t; r0 < slots; r0 += TT * 4) {
         uint32_t v[4];
@@ -278,7 +291,6 @@ __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, con
     // they differ from row a first in the same word with the same value.
     uint8_t *sf = reinterpret_cast<uint8_t *>(sval + slots);
     T *sv = reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(sf + slots + 7) & ~uintptr_t(7));
-    constexpr int FROM = 64 / Bits<T>::B;
     for (int r = t; r < slots; r += TT) {
         const int a = segof[r];
         if (a < 0) continue;
@@ -313,7 +325,7 @@ __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, con
             else if (fj > fm) c = hm < vm ? -1 : 1;
             else if (fj == WT) c = 0;
             else if (vj != vm) c = vj < vm ? -1 : 1;
-            else c = lex_cmp_t<T, WT>(lrows + j * LW, me);
+            else c = lex_cmp_t<T, WT, FROM>(lrows + j * LW, me);
             rank += (c < 0 || (c == 0 && j < r)) ? 1 : 0;
             dup = dup || (c == 0 && j < r);
         }
@@ -341,7 +353,8 @@ cg_status tiefix_t_launch(const T *rows, const uint64_t *keys, int64_t n, int wo
                           uint2 *large_list, unsigned long long *counters, hipStream_t s) {
     const int smax = tiefix_t_smax<T, WT>();
     const size_t lds = tiefix_t_lds<T, WT>(smax);
-    hipLaunchKernelGGL((k_tiefix_t<T, WT>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, keys, n, words, smax,
+    constexpr int FROM = KEY_BITS / Bits<T>::B;
+    hipLaunchKernelGGL((k_tiefix_t<T, WT, FROM>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, keys, n, words, smax,
                        vals, uniq, large_list, counters);
     CG_LAUNCHED("dedup_tiefix_t");
     return CG_OK;
@@ -550,20 +563,22 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
     const int words = lay.words;
     if (n == 0) return fill_i64(d_ncells, 0, 1, s);
 
-    hipLaunchKernelGGL((k_extract<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words,
+    const bool tiefix = lay.ell > 64;
+    const uint64_t kmask = (tiefix && KEY_BITS < 64) ? ~((uint64_t(1) << (64 - KEY_BITS)) - 1) : ~uint64_t(0);
+    hipLaunchKernelGGL((k_extract<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words, kmask,
                        w.keys[0], w.vals[0]);
     CG_LAUNCHED("dedup_extract");
 
-    const int sig = lay.ell < 64 ? lay.ell : 64;  // key bits that can be nonzero: [64 - sig, 64)
+    // key bits that can be nonzero: [64 - sig, 64)
+    const int sig = tiefix ? KEY_BITS : lay.ell;
     const int lo = ((64 - sig) / 8) * 8;
     int which = 0;
     CG_TRY(radix_sort_u64(w.keys, w.vals, n, nullptr, lo, 64, w.hist, w.tile_sums, &which, s));
     uint64_t *keys = w.keys[which];
     uint32_t *vals = w.vals[which];
 
-    const bool tiefix = lay.ell > 64;
     const int B = static_cast<int>(sizeof(T) * 8);
-    const int from = 64 / B;  // words covered by the sort key
+    const int from = KEY_BITS / B;  // words covered by the sort key
     if (!tiefix) {
         hipLaunchKernelGGL(k_heads, dim3(blocks_for(n, 256)), dim3(256), 0, s, keys, n, w.uniq);
         CG_LAUNCHED("dedup_heads");

@@ -165,11 +165,14 @@ constexpr int P_STASH = 4 * PT;      // P edges kept per cell tile
 constexpr uint32_t BIG = 0x80000000u;
 
 
-__global__ void k_edges_init(uint32_t *cntS, int64_t ncap, int64_t *d_nedges, int64_t *offsets, int32_t *status) {
+__global__ void k_edges_init(uint32_t *cntS, int64_t ncap, int64_t *d_nedges, int64_t *offsets, int32_t *status,
+                             unsigned long long *big_n) {
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t i = gid; i < ncap; i += stride) cntS[i] = 0;
     if (gid == 0) {
+        big_n[0] = 0;
+        big_n[1] = 0;
         *d_nedges = 0;
         if (offsets) offsets[0] = 0;
         *status = CG_OK;
@@ -178,24 +181,35 @@ __global__ void k_edges_init(uint32_t *cntS, int64_t ncap, int64_t *d_nedges, in
 
 // S pass over the suffix order (cells sorted by (32-bit suffix hash, id)).
 // Only positions followed by an equal hash can have a later S-neighbour, so a
-// block streams SC positions of the order, lists those "starters" in LDS and
-// gives them to its threads: each compares its row with the rows of the later
-// members of its run (ids ascend along a run, so partners come in ascending
-// v), or, when more than rmax members follow, looks up u xor e_k for every
-// k < s.  The count pass writes cntS[u]; the write pass redoes the same work
+// block streams SC positions of the order and lists those "starters" in LDS.
+// Each starter pairs with the later members of its run (at most rmax; ids
+// ascend along a run, so partners come in ascending v); the (starter,
+// partner) pairs of the block are numbered by a scan and checked by groups
+// of 16 lanes, each lane taking every 16th word of both rows, so a row is
+// read as whole 128-byte lines rather than one word per lane.  A found edge
+// sets bit j - 1 of its starter's mask (j = partner's offset in the run), so
+// a starter's rank of an edge is the popcount of its mask below j.  A starter
+// followed by more than rmax members looks up u xor e_k for every k < s
+// instead.  The count pass writes cntS[u]; the write pass redoes the checks
 // and emits at next(u) - cntS[u] + rank.
-constexpr int SC = 8 * PT;  // suffix-order positions per block
+constexpr int SC = 4 * PT;  // suffix-order positions per block
 constexpr int SRMAX = 64;   // most later run members scanned; more use look-ups
+constexpr int SG = 16;      // lanes per pair check
 
 template <typename T, bool WRITE>
 __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, const uint64_t *__restrict__ sfx,
                                                const int64_t *d_n, int64_t ncap, int words, int s, int rmax,
                                                uint32_t *__restrict__ cntS, const int64_t *__restrict__ offsets,
                                                const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
-                                               uint16_t *__restrict__ bit, int64_t cap) {
+                                               uint16_t *__restrict__ bit, int64_t cap, uint32_t *__restrict__ big_list,
+                                               unsigned long long *__restrict__ big_n) {
+    constexpr int B = Bits<T>::B;
+    constexpr int PER = SC / PT;
     __shared__ uint32_t hs[SC + 1];
     __shared__ uint32_t ids[SC];
     __shared__ uint16_t lst[SC];
+    __shared__ uint32_t pofs[SC + 1];  // first pair of each starter; big starters own none
+    __shared__ unsigned long long smask[SC];
     __shared__ uint64_t tmp[4];
     const int64_t n = load_n(d_n, ncap);
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * SC;
@@ -204,15 +218,15 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
     const bool hasnx = c0 + cl < n;  // hs[cl] holds the next position's hash
     const int t = threadIdx.x;
     {
-        uint64_t v[8];
+        uint64_t v[PER];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < PER; ++u) {
             const int e = t + u * PT;
             v[u] = e < cl ? sfx[c0 + e] : 0;
         }
         const uint64_t nx = (t == 0 && hasnx) ? sfx[c0 + cl] : 0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < PER; ++u) {
             const int e = t + u * PT;
             if (e < cl) {
                 hs[e] = static_cast<uint32_t>(v[u] >> 32);
@@ -222,67 +236,193 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
         if (t == 0 && hasnx) hs[cl] = static_cast<uint32_t>(nx >> 32);
     }
     __syncthreads();
+    auto hash_at = [&](int64_t p) -> uint32_t {
+        const int64_t ep = p - c0;
+        return (ep < cl || (ep == cl && hasnx)) ? hs[ep] : static_cast<uint32_t>(sfx[p] >> 32);
+    };
+    auto id_at = [&](int64_t p) -> uint32_t {
+        const int64_t ep = p - c0;
+        return ep < cl ? ids[ep] : static_cast<uint32_t>(sfx[p]);
+    };
+    // starters, in position order: thread t looks at positions PER t .. PER t + PER - 1
     uint32_t flags = 0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int e = t * 8 + u;
+    for (int u = 0; u < PER; ++u) {
+        const int e = t * PER + u;
         const bool st = e < cl && (e + 1 < cl || hasnx) && hs[e + 1] == hs[e];
         flags |= st ? (1u << u) : 0u;
     }
-    uint64_t nst;
-    uint32_t k = static_cast<uint32_t>(block256_excl_scan_u64(static_cast<uint64_t>(__popc(flags)), tmp, &nst));
+    uint64_t nst64;
+    uint32_t k = static_cast<uint32_t>(block256_excl_scan_u64(static_cast<uint64_t>(__popc(flags)), tmp, &nst64));
+    const int nst = static_cast<int>(nst64);
+    // partners per starter (big: none, looked up below); starters k .. of this thread
+    uint32_t np[PER];
+    bool bigs[PER];
+    uint32_t mine = 0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-        if (flags & (1u << u)) lst[k++] = static_cast<uint16_t>(t * 8 + u);
+    for (int u = 0; u < PER; ++u) {
+        np[u] = 0;
+        bigs[u] = false;
+        if (flags & (1u << u)) {
+            const int e = t * PER + u;
+            const int64_t q = c0 + e;
+            const uint32_t h = hs[e];
+            int L = 1;
+            bool big = false;
+            while (q + L + 1 < n && hash_at(q + L + 1) == h) {
+                if (L == rmax) { big = true; break; }
+                ++L;
+            }
+            bigs[u] = big;
+            np[u] = big ? 0u : static_cast<uint32_t>(L);
+            mine += np[u];
+        }
+    }
+    uint64_t npairs64;
+    uint32_t pf = static_cast<uint32_t>(block256_excl_scan_u64(mine, tmp, &npairs64));
+    const uint32_t npairs = static_cast<uint32_t>(npairs64);
+    uint32_t kk = k;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        if (flags & (1u << u)) {
+            lst[kk] = static_cast<uint16_t>(t * PER + u);
+            pofs[kk] = pf;
+            smask[kk] = 0;
+            pf += np[u];
+            ++kk;
+        }
+    }
+    if (t == 0) pofs[nst] = npairs;
     __syncthreads();
-    for (int li = t; li < static_cast<int>(nst); li += PT) {
-        const int e = lst[li];
-        const int64_t q = c0 + e;
+
+    // pair checks: group g of SG lanes takes pairs g, g + PT / SG, ...
+    const int lg = t % SG, g = t / SG;
+    auto check_pair = [&](uint32_t pidx, int *li_out, int *j_out, uint32_t *u_out, uint32_t *v_out, int *pos_out) {
+        int lo = 0, hi = nst;  // last starter with pofs <= pidx
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pofs[mid] <= pidx) lo = mid; else hi = mid;
+        }
+        const int j = static_cast<int>(pidx - pofs[lo]) + 1;
+        const int e = lst[lo];
         const uint32_t u = ids[e];
-        const uint32_t h = hs[e];
-        auto hash_at = [&](int64_t p) -> uint32_t {
-            const int64_t ep = p - c0;
-            return (ep < cl || (ep == cl && hasnx)) ? hs[ep] : static_cast<uint32_t>(sfx[p] >> 32);
-        };
-        auto id_at = [&](int64_t p) -> uint32_t {
-            const int64_t ep = p - c0;
-            return ep < cl ? ids[ep] : static_cast<uint32_t>(sfx[p]);
-        };
-        int L = 1;  // later members (a starter has at least one)
-        bool big = false;
-        while (q + L + 1 < n && hash_at(q + L + 1) == h) {
-            if (L == rmax) { big = true; break; }
-            ++L;
+        const uint32_t v = id_at(c0 + e + j);
+        const T *a = cells + static_cast<int64_t>(u) * words;
+        const T *b = cells + static_cast<int64_t>(v) * words;
+        int d = 0, first = 0x7fffffff;
+        for (int w = lg; w < words; w += SG) {
+            const T x = a[w] ^ b[w];
+            d += popc<T>(x);
+            first = (x && first == 0x7fffffff) ? w * B + clz_t<T>(x) : first;
         }
-        const T *me = cells + static_cast<int64_t>(u) * words;
-        int64_t base = 0;
-        if (WRITE) {
-            const uint32_t ct = cntS[u];
-            if (ct == 0) continue;
-            const int64_t next = offsets ? offsets[static_cast<int64_t>(u) + 1] : offnext[u];
-            base = next - ct;
+#pragma unroll
+        for (int m = SG / 2; m > 0; m >>= 1) {
+            d += __shfl_xor(d, m, 64);
+            const int o = __shfl_xor(first, m, 64);
+            first = o < first ? o : first;
         }
-        uint32_t c = 0;
-        if (big) {
-            for (int kk = s - 1; kk >= 0; --kk) {
-                if (get_bit<T>(me, kk)) continue;
-                const int64_t v = find_row<T>(cells, words, static_cast<int64_t>(u) + 1, n, me, kk);
-                if (v >= 0) {
-                    if (WRITE) emit(uv, bit, cap, base + c, u, static_cast<uint32_t>(v), kk);
-                    ++c;
+        *li_out = lo;
+        *j_out = j;
+        *u_out = u;
+        *v_out = v;
+        *pos_out = first;
+        return d;
+    };
+    for (uint32_t p0 = 0; p0 < npairs; p0 += PT / SG) {
+        const uint32_t pidx = p0 + g;
+        if (pidx < npairs) {  // uniform across the SG lanes of a group
+            int li, j, pos;
+            uint32_t u, v;
+            const int d = check_pair(pidx, &li, &j, &u, &v, &pos);
+            if (lg == 0 && d == 1 && pos < s) atomicOr(&smask[li], 1ull << (j - 1));
+        }
+    }
+    __syncthreads();
+
+    if (!WRITE) {
+        kk = k;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            if (flags & (1u << u)) {
+                const uint32_t c = static_cast<uint32_t>(__popcll(smask[kk]));
+                if (c) cntS[ids[t * PER + u]] = c;
+                ++kk;
+            }
+        }
+        // starters of long runs go to k_big_lookup
+#pragma unroll
+        for (int u = 0; u < PER; ++u)
+            wave_append<uint32_t>(big_list, big_n, n, (flags & (1u << u)) && bigs[u], ids[t * PER + u < cl ? t * PER + u : 0]);
+        return;
+    }
+    // write: found pairs again, at next(u) - cntS[u] + rank
+    for (uint32_t p0 = 0; p0 < npairs; p0 += PT / SG) {
+        const uint32_t pidx = p0 + g;
+        if (pidx < npairs) {
+            int li, j, pos;
+            uint32_t u, v;
+            const int d = check_pair(pidx, &li, &j, &u, &v, &pos);
+            if (lg == 0 && d == 1 && pos < s) {
+                const int64_t next = offsets ? offsets[static_cast<int64_t>(u) + 1] : offnext[u];
+                const unsigned long long m = smask[li];
+                const int64_t slot = next - cntS[u] + __popcll(m & ((1ull << (j - 1)) - 1ull));
+                emit(uv, bit, cap, slot, u, v, pos);
+            }
+        }
+    }
+}
+
+// Cells whose group (P) or run (S) is too long to scan are listed by the
+// scanning kernels and handled here, one wave per cell, lanes over the bits
+// (wave_flip_lookups): MODE 0 counts S-neighbours (k < s) into cntS, MODE 1
+// counts P-neighbours (k >= s) into cntP (flagged BIG) and the cell's tile
+// total, MODE 2 and 3 write the S and P edges at their slots.
+enum { BIG_S_COUNT = 0, BIG_P_COUNT = 1, BIG_S_WRITE = 2, BIG_P_WRITE = 3 };
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_big_lookup(const T *__restrict__ cells, const uint32_t *__restrict__ dir,
+                                                    int p, int words, int ell, int s,
+                                                    const uint32_t *__restrict__ list,
+                                                    const unsigned long long *__restrict__ list_n, int64_t list_cap,
+                                                    uint32_t *__restrict__ cntS, uint32_t *__restrict__ cntP,
+                                                    uint64_t *__restrict__ tile_tot,
+                                                    const int64_t *__restrict__ offsets,
+                                                    const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
+                                                    uint16_t *__restrict__ bit, int64_t cap) {
+    int64_t cnt = static_cast<int64_t>(*list_n);
+    if (cnt > list_cap) cnt = list_cap;
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
+    constexpr bool S_SIDE = MODE == BIG_S_COUNT || MODE == BIG_S_WRITE;
+    const int khi = S_SIDE ? s - 1 : ell - 1, klo = S_SIDE ? 0 : s;
+    for (int64_t it = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); it < cnt;
+         it += nw) {
+        const uint32_t u = list[it];
+        const T *q = cells + static_cast<int64_t>(u) * words;
+        if (MODE == BIG_S_COUNT || MODE == BIG_P_COUNT) {
+            const uint32_t c = wave_flip_lookups<T>(cells, words, dir, p, q, khi, klo, [](uint32_t, int, uint32_t) {});
+            if (lane == 0) {
+                if (MODE == BIG_S_COUNT) {
+                    cntS[u] = c;
+                } else {
+                    cntP[u] = BIG | c;
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&tile_tot[u / PT]),
+                              static_cast<unsigned long long>(c));
                 }
             }
         } else {
-            for (int j = 1; j <= L; ++j) {
-                const uint32_t v = id_at(q + j);
-                int pos;
-                if (dist_full<T>(me, cells + static_cast<int64_t>(v) * words, words, &pos) == 1 && pos < s) {
-                    if (WRITE) emit(uv, bit, cap, base + c, u, v, pos);
-                    ++c;
-                }
+            int64_t base;
+            if (MODE == BIG_S_WRITE) {
+                const uint32_t ct = cntS[u];
+                base = (offsets ? offsets[static_cast<int64_t>(u) + 1] : offnext[u]) - ct;
+            } else {
+                base = offsets ? offsets[u]
+                               : offnext[u] - static_cast<int64_t>(cntP[u] & ~BIG) - static_cast<int64_t>(cntS[u]);
             }
+            wave_flip_lookups<T>(cells, words, dir, p, q, khi, klo, [&](uint32_t v, int k, uint32_t r) {
+                emit(uv, bit, cap, base + r, u, v, k);
+            });
         }
-        if (!WRITE && c) cntS[u] = c;
     }
 }
 
@@ -452,12 +592,17 @@ template <typename T, int WT> struct PFind {
 // eighth of the tiles, so a tile and the one after it (whose first rows are
 // the tile's halo) are read on the same XCD at about the same time and the
 // halo comes from that XCD's L2.
+// Blocks per CU the register budget is sized for: three (the LDS allows
+// three), except 32-word u32 rows, whose unrolled row work needs two.
+template <typename T, int WT> constexpr int p_find_blocks() { return (sizeof(T) == 4 && WT == 32) ? 2 : 3; }
+
 template <typename T, int WT>
-__global__ void __launch_bounds__(PT) k_p_find(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
-                                               int words, int ell, int s, int gmax,
+__global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T *__restrict__ cells,
+                                               const int64_t *d_n, int64_t ncap, int words, int ell, int s, int gmax,
                                                const uint32_t *__restrict__ cntS, uint32_t *__restrict__ cntP,
                                                uint32_t *__restrict__ stash, uint32_t *__restrict__ stash_n,
-                                               uint64_t *__restrict__ tile_tot) {
+                                               uint64_t *__restrict__ tile_tot, uint32_t *__restrict__ big_list,
+                                               unsigned long long *__restrict__ big_n) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint64_t tmp[4];
     __shared__ uint32_t s_nres;
@@ -470,7 +615,6 @@ __global__ void __launch_bounds__(PT) k_p_find(const T *__restrict__ cells, cons
     uint32_t *pcs = reinterpret_cast<uint32_t *>(mask + PT);
     uint32_t *res = pcs + PROWS + 1;
     uint32_t *cq = res + P_STASH;
-    uint8_t *heads = reinterpret_cast<uint8_t *>(cq + 4 * CQ);
     const int64_t n = load_n(d_n, ncap);
     const int64_t ntiles = (n + PT - 1) / PT;
     const int G8 = static_cast<int>(gridDim.x >> 3);
@@ -480,7 +624,6 @@ __global__ void __launch_bounds__(PT) k_p_find(const T *__restrict__ cells, cons
     const int64_t r1 = r0 + T8 < ntiles ? r0 + T8 : ntiles;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     uint32_t *q = cq + wv * CQ;
-    const uint64_t lt = lanemask_lt();
     const int gm = gmax < PSCAN ? gmax : PSCAN;
 
     T pre[NE];
@@ -515,20 +658,18 @@ __global__ void __launch_bounds__(PT) k_p_find(const T *__restrict__ cells, cons
         mask[t] = 0;
         if (t == 0) s_nres = 0;
         __syncthreads();
-        if (tile + G8 < r1) prefetch(tile + G8);
         for (int r = t; r < tl; r += PT) {
             const T *me = rows + r * LW;
             uint32_t pc = 0;
 #pragma unroll
             for (int w = 0; w < WT; ++w) pc += popc<T>(me[w]);
-            pcs[r] = pc;
-            heads[r] = (r == 0 || !same_prefix_t<T, WT>(me - LW, me, s)) ? 1 : 0;
+            // popcount, bit 31: row r starts a prefix group
+            const bool hd = r == 0 || !same_prefix_t<T, WT>(me - LW, me, s);
+            pcs[r] = pc | (hd ? 0x80000000u : 0u);
         }
-        if (t == 0) {
-            heads[tl] = base + tl < n ? 0 : 1;  // 0: the last group may go on past the loaded rows
-            pcs[tl] = 0xffffffffu;
-        }
+        if (t == 0) pcs[tl] = 0x80000000u;  // read only as "past the loaded rows"
         __syncthreads();
+        if (tile + G8 < r1) prefetch(tile + G8);
         const int64_t i = base + t;
 
         // entry: cell (8 bits) | offset (8 bits, 1..64) | position (16 bits)
@@ -545,37 +686,52 @@ __global__ void __launch_bounds__(PT) k_p_find(const T *__restrict__ cells, cons
             if (dist_t4<T, WT>(rows + t0 * LW, rows + j0 * LW, &pos) == 1) found(t0, j0 - t0, pos);
         };
 
-        bool scanning = t < tr;
+        // Lock-step over the offset d = j - i: a lane stays alive while row
+        // t + d is in its group; pairs whose popcounts differ by one set bit
+        // d - 1 of the lane's candidate mask.
+        const bool more = base + tl < n;  // cells exist past the loaded rows
+        bool alive = t < tr;
         bool big = false, spill = false;  // spill: the group runs past the loaded rows
-        const uint32_t pc = t < tl ? pcs[t] : 0u;
-        uint32_t qn = 0, qh = 0;
-        for (int d = 1; ballot64(scanning) != 0; ++d) {
+        const uint32_t pc = pcs[t < tl ? t : tl] & 0x7fffffffu;
+        unsigned long long cm = 0;
+        for (int d = 1; d <= gm && ballot64(alive) != 0; ++d) {
             const int jj = t + d;
-            const int jc = jj < tl ? jj : tl;
-            const uint32_t h = heads[jc];  // at tl: 0 iff the group may go on
-            const uint32_t po = pcs[jc];
             const bool past = jj >= tl;
-            const bool tiny = d > gm;
-            // past the loaded rows with the group possibly going on: finish in global
-            // memory (which also settles d > gm there)
-            spill = spill || (scanning && past && h == 0);
-            big = big || (scanning && !past && h == 0 && tiny);
-            const bool stop = past || h != 0 || tiny;
-            const bool cand = scanning && !stop && (po == pc + 1 || po + 1 == pc);
-            scanning = scanning && !stop;
-            const uint64_t m = ballot64(cand);
-            if (cand)
-                q[(qn + static_cast<uint32_t>(__popcll(m & lt))) % CQ] =
-                    (static_cast<uint32_t>(t) << 16) | static_cast<uint32_t>(jj);
-            qn += static_cast<uint32_t>(__popcll(m));
-            while (qn - qh >= 64) {  // a full batch: lane e checks queued pair qh + e
+            const uint32_t x = pcs[past ? tl : jj];
+            spill = spill || (alive && past && more);
+            alive = alive && !past && (x >> 31) == 0;
+            const uint32_t po = x & 0x7fffffffu;
+            const bool cand = alive && (po == pc + 1 || po + 1 == pc);
+            cm |= cand ? (1ull << (d - 1)) : 0ull;
+        }
+        if (alive) {  // still inside the group after gm rows: one more member means look-ups
+            const int jj = t + gm + 1;
+            if (jj < tl) big = (pcs[jj] >> 31) == 0;
+            else spill = spill || more;
+        }
+        // candidates to the wave's queue, checked 64 at a time on dense lanes
+        {
+            const uint32_t nc = static_cast<uint32_t>(__popcll(cm));
+            const uint32_t inc = wave_incl_scan_u32(nc);
+            const uint32_t tot = __shfl(inc, 63, 64);
+            const uint32_t off = inc - nc;
+            for (uint32_t done = 0; done < tot; done += CQ) {
+                unsigned long long m = cm;
+                uint32_t gi = off;
+                while (m) {
+                    const int d0 = __ffsll(m);  // offset d0 (bit d0 - 1)
+                    m &= m - 1;
+                    if (gi >= done && gi < done + CQ)
+                        q[gi - done] = (static_cast<uint32_t>(t) << 16) | static_cast<uint32_t>(t + d0);
+                    ++gi;
+                }
                 __builtin_amdgcn_wave_barrier();
-                check(q[(qh + lane) % CQ]);
-                qh += 64;
+                const uint32_t cnt = tot - done < static_cast<uint32_t>(CQ) ? tot - done : static_cast<uint32_t>(CQ);
+                for (uint32_t e0 = 0; e0 < cnt; e0 += 64)
+                    if (e0 + lane < cnt) check(q[e0 + lane]);
+                __builtin_amdgcn_wave_barrier();
             }
         }
-        __builtin_amdgcn_wave_barrier();
-        if (static_cast<uint32_t>(lane) < qn - qh) check(q[(qh + lane) % CQ]);
         if (spill) {
             // the group goes on past the loaded rows: finish it in global memory
             const T *me = rows + t * LW;
@@ -587,11 +743,12 @@ __global__ void __launch_bounds__(PT) k_p_find(const T *__restrict__ cells, cons
                 if (dist_full<T>(me, o, words, &pos) == 1) found(t, static_cast<int>(j - i), pos);
             }
         }
+        // cells of long groups: counted by k_big_lookup, which also adds them to the tile total
+        wave_append<uint32_t>(big_list, big_n, n, big && t < tr, static_cast<uint32_t>(i));
         __syncthreads();
         uint32_t cp = 0;
         if (t < tr) {
-            cp = big ? (BIG | p_lookup<T>(cells, i, n, words, ell, s, [](uint32_t, int, uint32_t) {}))
-                     : static_cast<uint32_t>(__popcll(mask[t]));
+            cp = big ? BIG : static_cast<uint32_t>(__popcll(mask[t]));
             cntP[i] = cp;
         }
         const uint32_t csv = t < tr ? cs : 0u;
@@ -693,8 +850,7 @@ __global__ void __launch_bounds__(TS_T) k_tile_scan(uint64_t *tile_tot, const in
 // exclusive scan, and copies the P edge from the stash (the cell's S slots
 // are left to the S write pass), so the output is written coalesced.
 template <typename T>
-__global__ void __launch_bounds__(PT) k_p_place(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
-                                                int words, int ell, int s,
+__global__ void __launch_bounds__(PT) k_p_place(const int64_t *d_n, int64_t ncap,
                                                 const uint32_t *__restrict__ cntS, const uint32_t *__restrict__ cntP,
                                                 const uint32_t *__restrict__ stash,
                                                 const uint32_t *__restrict__ stash_n,
@@ -727,17 +883,12 @@ __global__ void __launch_bounds__(PT) k_p_place(const T *__restrict__ cells, con
     const int64_t out0 = static_cast<int64_t>(t_off + exa);
     if (t < tr) {
         if (offsets) offsets[i] = out0;
-        else if (cs) offnext[i] = out0 + c + cs;
+        else if (cs || (cp & BIG)) offnext[i] = out0 + c + cs;
     }
     sx[t] = static_cast<uint32_t>(exa);
     ssb[t] = static_cast<uint32_t>(exs);
     scp[t] = t < tr ? cp : 0u;
     __syncthreads();
-    if (t < tr && (cp & BIG)) {
-        p_lookup<T>(cells, i, n, words, ell, s, [&](uint32_t v, int k, uint32_t r) {
-            emit(uv, bit, cap, out0 + r, static_cast<uint32_t>(i), v, k);
-        });
-    }
     if (sn > static_cast<uint32_t>(P_STASH)) return;  // k_p_fix writes this tile's scanned P edges
     const uint32_t *src = stash + tile * P_STASH;
     for (uint32_t r = t; r < static_cast<uint32_t>(tot_all); r += PT) {
@@ -801,6 +952,8 @@ struct EdgesWs {
     uint64_t *tile_sums;
     uint64_t *tile_tot;
     uint32_t *p_stash, *p_stash_n;
+    uint32_t *s_big, *p_big;     // cells left to k_big_lookup
+    unsigned long long *big_n;   // [0]: S list length, [1]: P list length
 };
 
 // Padded row width (power of two) for the P tiles, or 0 when rows are too
@@ -826,6 +979,9 @@ EdgesWs carve_edges(void *base, int64_t ncap, size_t *bytes) {
     w.tile_tot = c.take<uint64_t>(tiles);
     w.p_stash = c.take<uint32_t>(tiles * P_STASH);
     w.p_stash_n = c.take<uint32_t>(tiles);
+    w.s_big = c.take<uint32_t>(n);
+    w.p_big = c.take<uint32_t>(n);
+    w.big_n = c.take<unsigned long long>(2);
     *bytes = c.bytes();
     return w;
 }
@@ -852,36 +1008,50 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
     const int64_t ncap = d.ncells_cap;
     const T *cells = static_cast<const T *>(d.cells);
     const int words = d.lay.words, ell = d.lay.ell, sp = d.params.split_bit, gmax = d.params.group_max;
+    const int pb = d.params.dir_bits;
     const int64_t ntiles = (ncap + PT - 1) / PT;
     const dim3 grid(static_cast<unsigned>(ntiles));
     const dim3 sgrid(static_cast<unsigned>((ncap + SC - 1) / SC));
+    const dim3 bgrid(blocks_for(ncap, 4, 2048));  // one wave per listed cell
     const size_t lds = PTile<T, WT>::bytes;
     const size_t lds_find = PFind<T, WT>::bytes;
     const int rmax = gmax < SRMAX ? gmax : SRMAX;
+    const int64_t *no_off = nullptr;
     if (sp > 0) {
         hipLaunchKernelGGL((k_s_scan<T, false>), sgrid, dim3(PT), 0, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
-                           rmax, w.cntS, static_cast<const int64_t *>(nullptr), static_cast<const int64_t *>(nullptr),
-                           uv, bit, cap);
+                           rmax, w.cntS, no_off, no_off, uv, bit, cap, w.s_big, w.big_n);
         CG_LAUNCHED("edges_s_count");
+        hipLaunchKernelGGL((k_big_lookup<T, BIG_S_COUNT>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
+                           w.s_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, no_off, no_off, uv, bit, cap);
+        CG_LAUNCHED("edges_s_big_count");
     }
     const unsigned pblocks = persistent_blocks(reinterpret_cast<const void *>(&k_p_find<T, WT>), lds_find, ntiles);
     hipLaunchKernelGGL((k_p_find<T, WT>), dim3(pblocks), dim3(PT), lds_find, s, cells, d.d_ncells, ncap, words, ell,
-                       sp, gmax, w.cntS, w.cntP, w.p_stash, w.p_stash_n, w.tile_tot);
+                       sp, gmax, w.cntS, w.cntP, w.p_stash, w.p_stash_n, w.tile_tot, w.p_big, w.big_n + 1);
     CG_LAUNCHED("edges_p_find");
+    hipLaunchKernelGGL((k_big_lookup<T, BIG_P_COUNT>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
+                       w.p_big, w.big_n + 1, ncap, w.cntS, w.cntP, w.tile_tot, no_off, no_off, uv, bit, cap);
+    CG_LAUNCHED("edges_p_big_count");
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(TS_T), 0, s, w.tile_tot, d.d_ncells, ncap, cap, d_nedges, d_offsets,
                        d_status);
     CG_LAUNCHED("edges_tile_scan");
-    hipLaunchKernelGGL((k_p_place<T>), grid, dim3(PT), 0, s, cells, d.d_ncells, ncap, words, ell, sp, w.cntS,
-                       w.cntP, w.p_stash, w.p_stash_n, w.tile_tot, d_offsets, offnext, uv, bit, cap);
+    hipLaunchKernelGGL((k_p_place<T>), grid, dim3(PT), 0, s, d.d_ncells, ncap, w.cntS, w.cntP, w.p_stash,
+                       w.p_stash_n, w.tile_tot, d_offsets, offnext, uv, bit, cap);
     CG_LAUNCHED("edges_p_place");
+    hipLaunchKernelGGL((k_big_lookup<T, BIG_P_WRITE>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
+                       w.p_big, w.big_n + 1, ncap, w.cntS, w.cntP, w.tile_tot, d_offsets, offnext, uv, bit, cap);
+    CG_LAUNCHED("edges_p_big_write");
     const int gm = gmax < PSCAN ? gmax : PSCAN;  // same scan limit as k_p_find
     hipLaunchKernelGGL((k_p_fix<T, WT>), grid, dim3(PT), lds, s, cells, d.d_ncells, ncap, words, sp, gm, w.cntS,
                        w.cntP, w.p_stash_n, w.tile_tot, uv, bit, cap);
     CG_LAUNCHED("edges_p_fix");
     if (sp > 0) {
         hipLaunchKernelGGL((k_s_scan<T, true>), sgrid, dim3(PT), 0, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
-                           rmax, w.cntS, d_offsets, offnext, uv, bit, cap);
+                           rmax, w.cntS, d_offsets, offnext, uv, bit, cap, w.s_big, w.big_n);
         CG_LAUNCHED("edges_s_write");
+        hipLaunchKernelGGL((k_big_lookup<T, BIG_S_WRITE>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
+                           w.s_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, d_offsets, offnext, uv, bit, cap);
+        CG_LAUNCHED("edges_s_big_write");
     }
     return CG_OK;
 }
@@ -893,7 +1063,7 @@ cg_status edges_fast(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap,
     const int64_t ntiles = (ncap + PT - 1) / PT;
     int64_t *offnext = w.offsets;  // sparse next-offsets when the caller wants no offsets
     hipLaunchKernelGGL(k_edges_init, dim3(blocks_for(ncap, 256, 4096)), dim3(256), 0, s, w.cntS, ncap, d_nedges,
-                       d_offsets, d_status);
+                       d_offsets, d_status, w.big_n);
     CG_LAUNCHED("edges_init");
     if (ncap == 0) return CG_OK;
     const dim3 grid(static_cast<unsigned>(ntiles));

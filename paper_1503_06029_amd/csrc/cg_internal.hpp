@@ -112,6 +112,24 @@ __device__ __forceinline__ uint64_t block256_excl_scan_u64(uint64_t x, uint64_t 
     return pre + inc - x;
 }
 
+// Appends `item` to list[] at a slot taken from *counter with one atomic per
+// wave (same-address atomics serialise, so per-lane atomics do not scale).
+// Every active lane of the wave must call it; lanes with want == false only
+// vote.  Slots at or past cap are counted but not written.
+template <typename V>
+__device__ __forceinline__ void wave_append(V *list, unsigned long long *counter, int64_t cap, bool want, V item) {
+    const uint64_t m = ballot64(want);
+    if (m == 0) return;
+    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    unsigned long long b = 0;
+    if (lane_id() == leader) b = atomicAdd(counter, static_cast<unsigned long long>(__popcll(m)));
+    b = shfl_u64(b, leader);
+    if (want) {
+        const unsigned long long k = b + static_cast<unsigned long long>(__popcll(m & lanemask_lt()));
+        if (static_cast<int64_t>(k) < cap) list[k] = item;
+    }
+}
+
 // -------------------------------------------------------------- row helpers
 
 template <typename T> struct Bits;
@@ -281,6 +299,42 @@ __device__ __forceinline__ int64_t find_row(const T *cells, int words, int64_t l
     }
     if (lo < end && row_cmp_flip<T>(cells + lo * words, q, words, kw, km) == 0) return lo;
     return -1;
+}
+
+// find_row for q xor e_k, searching only the directory bucket of the flipped
+// vector's top p bits (dir[g] = first cell whose top p bits are >= g).
+template <typename T>
+__device__ __forceinline__ int64_t find_flip_dir(const T *cells, int words, const uint32_t *dir, int p, const T *q,
+                                                 int k) {
+    uint64_t h = head64<T>(q, words);
+    if (k < 64) h ^= 1ull << (63 - k);
+    const int64_t g = p ? static_cast<int64_t>(h >> (64 - p)) : 0;
+    return find_row<T>(cells, words, dir[g], dir[g + 1], q, k);
+}
+
+// Wave-cooperative look-ups of q xor e_k for k = khi, khi - 1, ..., klo
+// where q has a 0 at k (so the target is larger than q): each round the
+// lanes take 64 consecutive k, descending.  f(v, k, rank) runs on the lane
+// that found cell v; rank counts the targets found at larger k (that is,
+// smaller v).  Every lane of the wave calls it with the same q; returns the
+// number found.
+template <typename T, class F>
+__device__ __forceinline__ uint32_t wave_flip_lookups(const T *cells, int words, const uint32_t *dir, int p,
+                                                      const T *q, int khi, int klo, F f) {
+    const int lane = __lane_id();
+    uint32_t c = 0;
+    for (int k0 = khi; k0 >= klo; k0 -= 64) {
+        const int k = k0 - lane;
+        int64_t v = -1;
+        if (k >= klo && !get_bit<T>(q, k)) v = find_flip_dir<T>(cells, words, dir, p, q, k);
+        const uint64_t m = __ballot(v >= 0);
+        if (v >= 0) {
+            const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+            f(static_cast<uint32_t>(v), k, c + static_cast<uint32_t>(__popcll(m & below)));
+        }
+        c += static_cast<uint32_t>(__popcll(m));
+    }
+    return c;
 }
 
 // 64-bit finaliser (the MurmurHash3 fmix64 mixing function).
