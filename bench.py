@@ -22,6 +22,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "distance-1 edges/sec and cells/sec at ℓ=1024, n=4M; % HBM roofline; p99"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes moved by one cg_edges call on this workload: rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE runs over one step, each counter scaled by what it
+# reads for a plain 512 MiB device copy (FETCH x2, WRITE x1); the per-kernel
+# table is in profiles/cg_edges_long_vectors_traffic.md.  It describes the
+# kernels as measured: set it to None when the cg_edges kernels change and
+# re-measure.
+EDGES_TRAFFIC_BYTES = 1_014_048_230
 
 
 def log(*a):
@@ -161,7 +168,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": EDGES_TRAFFIC_BYTES,
             "alg_bytes": alg_bytes,
         },
     }

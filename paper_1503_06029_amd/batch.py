@@ -148,6 +148,66 @@ class SceneBatch:
             return False
         return True
 
+    def host_buffers(self):
+        """Pinned host buffers sized to this batch's capacities (for fetch_into)."""
+        pin = lambda shape, dt: torch.empty(shape, dtype=dt).pin_memory()
+        return {
+            "scal": pin(4, torch.int64),
+            "cells": pin((max(self.cap_rows, 1), self.words), torch.int32),
+            "uv": pin((self.edge_cap, 2), torch.int32),
+            "bit": pin(self.edge_cap, torch.int16),
+            "offsets": pin(max(self.cap_rows, 1) + 1, torch.int64),
+            "r2c": pin(max(self.cap_rows, 1), torch.int32),
+            "cell_off": pin(self.cap_scenes + 1, torch.int64),
+            "edge_off": pin(self.cap_scenes + 1, torch.int64),
+        }
+
+    def fetch_into(self, host, stream):
+        """Per-scene results copied through pinned buffers `host` (from
+        host_buffers) on `stream`; the returned arrays are views into those
+        buffers, valid until they are filled again.  Raises if the edge
+        buffer overflowed."""
+        with torch.cuda.stream(stream):
+            sc = host["scal"]
+            sc[0:1].copy_(self.ncells, non_blocking=True)
+            sc[1:2].copy_(self.nedges, non_blocking=True)
+            sc[2:3].copy_(self.status.to(torch.int64), non_blocking=True)
+            k = self.n_scenes + 1
+            host["cell_off"][:k].copy_(self.cell_off[:k], non_blocking=True)
+            host["edge_off"][:k].copy_(self.edge_off[:k], non_blocking=True)
+            host["r2c"][:self.n_rows].copy_(self.r2c[:self.n_rows], non_blocking=True)
+            stream.synchronize()
+            nc, E, st = int(sc[0]), int(sc[1]), int(sc[2])
+            if st != 0:
+                raise RuntimeError("edge capacity of a batch exceeded; raise its footprint")
+            host["cells"][:nc].copy_(self.cells[:nc], non_blocking=True)
+            host["uv"][:E].copy_(self.uv[:E], non_blocking=True)
+            host["bit"][:E].copy_(self.bit[:E], non_blocking=True)
+            host["offsets"][:nc + 1].copy_(self.offsets[:nc + 1], non_blocking=True)
+            stream.synchronize()
+        cells = host["cells"].numpy().view(np.uint32)
+        uv = host["uv"].numpy().view(np.uint32)
+        bit = host["bit"].numpy().view(np.uint16)
+        off = host["offsets"].numpy()
+        r2c = host["r2c"].numpy().view(np.uint32)
+        co = host["cell_off"].numpy()
+        eo = host["edge_off"].numpy()
+        out = []
+        for j in range(self.n_scenes):
+            wj = -(-int(self.ells[j]) // 32)
+            a, b = int(co[j]), int(co[j + 1])
+            e0, e1 = int(eo[j]), int(eo[j + 1])
+            out.append({
+                "ncells": b - a,
+                "nedges": e1 - e0,
+                "cells": cells[a:b, 1:1 + wj],
+                "uv": uv[e0:e1],
+                "bit": bit[e0:e1],
+                "offsets": off[a:b + 1] - e0,
+                "row_to_cell": r2c[self.scene_rows_h[j]:self.scene_rows_h[j + 1]],
+            })
+        return out
+
     def fetch(self, sync: bool = True):
         """Per-scene host results: list of dicts (cells in the scene's own u32 layout).
         With sync=False the copies are ordered on the current stream only."""

@@ -4,9 +4,10 @@ Requests (arrival time, scene) are admitted into the next batch as soon as
 they have arrived and the batch has room: each width class has a fixed
 device footprint (rows, scenes, sign bytes, edges), and a request that does
 not fit waits for the next batch.  Two batch slots alternate: while one
-batch computes on its stream, the host admits the next arrivals, stages
-their sign bytes in pinned memory and launches them on the other slot, then
-collects the finished batch.  So requests that arrive while others are on
+batch computes on its stream, the host admits the next arrivals, copies
+their sign bytes (request payloads held in pinned host memory) straight into
+the other slot's device buffer and launches it, then collects the finished
+batch through pinned result buffers.  So requests that arrive while others are on
 the GPU are picked up as soon as a slot frees, and copies of one batch
 overlap the compute of the other.  Latency is measured from a request's
 arrival to the moment its results are on the host.
@@ -30,23 +31,26 @@ from . import pipeline
 
 
 class Slot:
-    """Device buffers for one in-flight batch: one SceneBatch per class."""
+    """Device buffers for one in-flight batch (one SceneBatch per class) and
+    the pinned host buffers its results come back through."""
 
     def __init__(self, class_caps, device="cuda"):
         self.stream = torch.cuda.Stream()
         self.batches = {}
-        self.pinned = {}
+        self.host = {}
         for w, (rows, scenes, nbytes) in class_caps.items():
             ell = 32 * (w - 1)
             sb = BT.SceneBatch([ell], [1], w, max_rows=rows, max_scenes=scenes, max_bytes=nbytes,
                                edge_cap=max(4096, 4 * rows), device=device)
             self.batches[w] = sb
-            self.pinned[w] = torch.empty(max(nbytes, 16), dtype=torch.uint8).pin_memory()
+            self.host[w] = sb.host_buffers()
         self.requests = None
         self.done = None
 
-    def launch(self, reqs, scenes):
-        """Stage and launch one batch: reqs = [(req_id, scene_idx)]."""
+    def launch(self, reqs, scenes, pinned):
+        """Copy and launch one batch: reqs = [(req_id, scene_idx)]; pinned[si]
+        is scene si's sign bytes in pinned host memory (one copy per request,
+        straight into the batch's device buffer)."""
         by_class = {}
         for rid, si in reqs:
             R = scenes[si]
@@ -56,30 +60,27 @@ class Slot:
             for w, items in by_class.items():
                 sb = self.batches[w]
                 sb.set_scenes([scenes[si].shape[1] for _, si in items], [scenes[si].shape[0] for _, si in items])
-                host = self.pinned[w].numpy()
                 o = 0
                 for _, si in items:
-                    R = scenes[si]
-                    host[o:o + R.size] = R.reshape(-1)
-                    o += R.size
-                if o:
-                    sb.bits[:o].copy_(self.pinned[w][:o], non_blocking=True)
+                    m = pinned[si].numel()
+                    if m:
+                        sb.bits[o:o + m].copy_(pinned[si], non_blocking=True)
+                    o += m
                 sb.run(self.stream)
             self.done = torch.cuda.Event()
             self.done.record(self.stream)
 
-    def collect(self):
+    def collect(self, copy: bool = False):
         """Wait for the batch; return {req_id: result dict}.  Copies go on the
-        slot's own stream, so the other slot's batch keeps running."""
+        slot's own stream, so the other slot's batch keeps running.  Results
+        are views into this slot's pinned buffers (valid until the slot runs
+        again) unless copy=True."""
         self.done.synchronize()
         out = {}
-        with torch.cuda.stream(self.stream):
-            for w, items in self.requests.items():
-                sb = self.batches[w]
-                if int(sb.status.item()) != 0:
-                    raise RuntimeError("edge capacity of a serving slot exceeded; raise its footprint")
-                for (rid, _), r in zip(items, sb.fetch(sync=False)):
-                    out[rid] = r
+        for w, items in self.requests.items():
+            res = self.batches[w].fetch_into(self.host[w], self.stream)
+            for (rid, _), r in zip(items, res):
+                out[rid] = {k: (v.copy() if copy and isinstance(v, np.ndarray) else v) for k, v in r.items()}
         self.requests = None
         return out
 
@@ -121,6 +122,9 @@ class Server:
             caps[w] = (rows_per_class, scenes_per_class, rows_per_class * 32 * (w - 1))
         self.caps = caps
         self.slots = [Slot(caps, device), Slot(caps, device)]
+        # the request payloads (sign bytes) live in pinned host memory
+        self.pinned = [torch.from_numpy(np.ascontiguousarray(R, dtype=np.uint8).reshape(-1)).pin_memory()
+                       for R in scenes]
 
     def _admit(self, queue: deque, now: float):
         return admit_requests(queue, now, self.caps, [R.shape for R in self.scenes])
@@ -142,12 +146,12 @@ class Server:
                 reqs = self._admit(queue, now)
                 if reqs:
                     slot = free.pop(0)
-                    slot.launch(reqs, self.scenes)
+                    slot.launch(reqs, self.scenes, self.pinned)
                     inflight.append(slot)
                     progressed = True
             if inflight and (not free or inflight[0].done.query()):
                 slot = inflight.pop(0)
-                out = slot.collect()
+                out = slot.collect(copy=keep_results)
                 tdone = time.perf_counter() - t0
                 for rid, r in out.items():
                     lat[rid] = tdone - arrivals[rid]
