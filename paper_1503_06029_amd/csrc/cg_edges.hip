@@ -142,34 +142,55 @@ __global__ void k_status(const int64_t *total, int64_t cap, int32_t *status) {
 
 // ------------------------------------------------------------- fast path
 //
-// No global atomics and no inter-block waiting (same-address device atomics
-// serialise at roughly 10 ns each, so tickets and shared cursors do not
-// scale).  The P pass keeps what it found in a per-tile stash; a one-block
-// scan over tile totals gives every tile its output offset; placement then
-// copies stashes to their final slots.
+// No inter-block waiting and no contended atomics (same-address device
+// atomics serialise at roughly 10 ns each, so tickets and shared cursors do
+// not scale).  The P pass keeps what it found in a per-tile stash and adds
+// its tile total to one of 64-tile super-tiles; a placement block gets its
+// output offset by summing the super-tiles and tiles before it, then copies
+// its stash to the final slots.
 //
-//   E0 init      zero cntS
+//   E0 init      zero cntS and the super-tile totals
 //   E1 S-count   per block of the suffix order: cntS[u] for cells followed by
-//                an equal suffix hash
-//   E2 P-find    persistent, per cell tile, rows in LDS: cntP[u] (bit 31:
-//                found by look-up, recomputed at placement), P edges (v - u,
-//                k) to the tile's P stash; tile total of cntP + cntS
-//   E3 scan      exclusive scan of tile totals; |E|, offsets[n], status
-//   E4 P-place   per cell tile: offsets (or the sparse next-offsets needed by
-//                E6), P edges from the stash, slot by slot
-//   E5 P-fix     tiles whose stash overflowed: rescan and write
-//   E6 S-write   the S pass again, writing at next(u) - cntS[u] + rank
+//                an equal suffix hash, found S edges (with ranks) to the
+//                block's S stash; starters of long runs to a list
+//   E2 P-find    persistent, per cell tile, rows in LDS: cntP[u], P edges
+//                (v - u, k) to the tile's P stash, tile and super-tile totals
+//                of cntP + cntS; cells of long groups to a list (flag BIG)
+//   E3 look-ups  listed cells, one wave each: their counts (and totals)
+//   E4 P-place   per cell tile: offsets, |E| and status (last tile), P edges
+//                from the stash slot by slot; listed cells' P edges after it
+//   E5 P-fix     tiles whose P stash overflowed: rescan and write
+//   E6 S-place   stashed S edges to next(u) - cntS[u] + rank (blocks whose
+//                stash overflowed run the S pass again in write mode)
 
 constexpr int PT = 256;              // items per tile = threads per block
 constexpr int P_STASH = 4 * PT;      // P edges kept per cell tile
 constexpr uint32_t BIG = 0x80000000u;
+constexpr int SUP = 64;              // tiles per super-tile
+
+// Output offset of a cell tile: the totals of all super-tiles before it plus
+// those of the tiles before it in its own super-tile (tile totals are final
+// once the P kernels ran; every tile also added its total to its
+// super-tile's).  Block-wide over 256 threads, contains barriers.
+__device__ __forceinline__ uint64_t tile_offset(int64_t tile, const uint64_t *__restrict__ tile_tot,
+                                                const uint64_t *__restrict__ sup_tot, uint64_t *tmp) {
+    const int64_t sidx = tile / SUP;
+    uint64_t part = 0;
+    for (int64_t k = threadIdx.x; k < sidx; k += blockDim.x) part += sup_tot[k];
+    const int64_t k2 = sidx * SUP + threadIdx.x;
+    if (static_cast<int>(threadIdx.x) < SUP && k2 < tile) part += tile_tot[k2];
+    uint64_t tot;
+    block256_excl_scan_u64(part, tmp, &tot);
+    return tot;
+}
 
 
 __global__ void k_edges_init(uint32_t *cntS, int64_t ncap, int64_t *d_nedges, int64_t *offsets, int32_t *status,
-                             unsigned long long *big_n) {
+                             unsigned long long *big_n, uint64_t *sup_tot, int64_t nsup) {
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t i = gid; i < ncap; i += stride) cntS[i] = 0;
+    for (int64_t i = gid; i < nsup; i += stride) sup_tot[i] = 0;
     if (gid == 0) {
         big_n[0] = 0;
         big_n[1] = 0;
@@ -195,6 +216,7 @@ __global__ void k_edges_init(uint32_t *cntS, int64_t ncap, int64_t *d_nedges, in
 constexpr int SC = 4 * PT;  // suffix-order positions per block
 constexpr int SRMAX = 64;   // most later run members scanned; more use look-ups
 constexpr int SG = 16;      // lanes per pair check
+constexpr int S_STASH = 512;  // S edges kept per block of the suffix order
 
 template <typename T, bool WRITE>
 __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, const uint64_t *__restrict__ sfx,
@@ -202,7 +224,8 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
                                                uint32_t *__restrict__ cntS, const int64_t *__restrict__ offsets,
                                                const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
                                                uint16_t *__restrict__ bit, int64_t cap, uint32_t *__restrict__ big_list,
-                                               unsigned long long *__restrict__ big_n) {
+                                               unsigned long long *__restrict__ big_n, uint4 *__restrict__ sstash,
+                                               uint32_t *__restrict__ sstash_n) {
     constexpr int B = Bits<T>::B;
     constexpr int PER = SC / PT;
     __shared__ uint32_t hs[SC + 1];
@@ -210,13 +233,18 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
     __shared__ uint16_t lst[SC];
     __shared__ uint32_t pofs[SC + 1];  // first pair of each starter; big starters own none
     __shared__ unsigned long long smask[SC];
+    __shared__ uint2 sfound[S_STASH];  // (v, starter | j << 10 | pos << 17) of found S edges
+    __shared__ uint32_t nfound;
     __shared__ uint64_t tmp[4];
     const int64_t n = load_n(d_n, ncap);
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * SC;
     if (c0 >= n) return;
+    // the write pass only redoes blocks whose edges overflowed the stash
+    if (WRITE && sstash_n[blockIdx.x] <= static_cast<uint32_t>(S_STASH)) return;
     const int cl = static_cast<int>(n - c0 < SC ? n - c0 : SC);
     const bool hasnx = c0 + cl < n;  // hs[cl] holds the next position's hash
     const int t = threadIdx.x;
+    if (t == 0) nfound = 0;
     {
         uint64_t v[PER];
 #pragma unroll
@@ -334,7 +362,15 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
             int li, j, pos;
             uint32_t u, v;
             const int d = check_pair(pidx, &li, &j, &u, &v, &pos);
-            if (lg == 0 && d == 1 && pos < s) atomicOr(&smask[li], 1ull << (j - 1));
+            if (lg == 0 && d == 1 && pos < s) {
+                atomicOr(&smask[li], 1ull << (j - 1));
+                if (!WRITE) {
+                    const uint32_t f = atomicAdd(&nfound, 1u);
+                    if (f < static_cast<uint32_t>(S_STASH))
+                        sfound[f] = make_uint2(v, static_cast<uint32_t>(li) | (static_cast<uint32_t>(j) << 10) |
+                                                      (static_cast<uint32_t>(pos) << 17));
+                }
+            }
         }
     }
     __syncthreads();
@@ -353,6 +389,18 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
 #pragma unroll
         for (int u = 0; u < PER; ++u)
             wave_append<uint32_t>(big_list, big_n, n, (flags & (1u << u)) && bigs[u], ids[t * PER + u < cl ? t * PER + u : 0]);
+        // found edges with their ranks to the block's stash (k_s_place drops them into place)
+        const uint32_t nf = nfound;
+        if (t == 0) sstash_n[blockIdx.x] = nf;
+        if (nf <= static_cast<uint32_t>(S_STASH)) {
+            uint4 *out = sstash + static_cast<int64_t>(blockIdx.x) * S_STASH;
+            for (uint32_t f = t; f < nf; f += PT) {
+                const uint2 e = sfound[f];
+                const int li = static_cast<int>(e.y & 1023u), j = static_cast<int>((e.y >> 10) & 127u);
+                const uint32_t rank = static_cast<uint32_t>(__popcll(smask[li] & ((1ull << (j - 1)) - 1ull)));
+                out[f] = make_uint4(ids[lst[li]], e.x, (e.y >> 17) | (rank << 16), 0u);
+            }
+        }
         return;
     }
     // write: found pairs again, at next(u) - cntS[u] + rank
@@ -372,6 +420,25 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
     }
 }
 
+// Drops each block's stashed S edges into their slots: next(u) - cntS[u] + rank.
+__global__ void __launch_bounds__(256) k_s_place(const int64_t *d_n, int64_t ncap, const uint4 *__restrict__ sstash,
+                                                 const uint32_t *__restrict__ sstash_n,
+                                                 const uint32_t *__restrict__ cntS,
+                                                 const int64_t *__restrict__ offsets,
+                                                 const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
+                                                 uint16_t *__restrict__ bit, int64_t cap) {
+    const int64_t n = load_n(d_n, ncap);
+    if (static_cast<int64_t>(blockIdx.x) * SC >= n) return;
+    const uint32_t m = sstash_n[blockIdx.x];
+    if (m > static_cast<uint32_t>(S_STASH)) return;  // the write pass redoes this block
+    const uint4 *src = sstash + static_cast<int64_t>(blockIdx.x) * S_STASH;
+    for (uint32_t f = threadIdx.x; f < m; f += blockDim.x) {
+        const uint4 e = src[f];
+        const int64_t next = offsets ? offsets[static_cast<int64_t>(e.x) + 1] : offnext[e.x];
+        emit(uv, bit, cap, next - cntS[e.x] + (e.z >> 16), e.x, e.y, static_cast<int>(e.z & 0xffffu));
+    }
+}
+
 // Cells whose group (P) or run (S) is too long to scan are listed by the
 // scanning kernels and handled here, one wave per cell, lanes over the bits
 // (wave_flip_lookups): MODE 0 counts S-neighbours (k < s) into cntS, MODE 1
@@ -385,7 +452,7 @@ __global__ void __launch_bounds__(256) k_big_lookup(const T *__restrict__ cells,
                                                     const uint32_t *__restrict__ list,
                                                     const unsigned long long *__restrict__ list_n, int64_t list_cap,
                                                     uint32_t *__restrict__ cntS, uint32_t *__restrict__ cntP,
-                                                    uint64_t *__restrict__ tile_tot,
+                                                    uint64_t *__restrict__ tile_tot, uint64_t *__restrict__ sup_tot,
                                                     const int64_t *__restrict__ offsets,
                                                     const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
                                                     uint16_t *__restrict__ bit, int64_t cap) {
@@ -407,6 +474,8 @@ __global__ void __launch_bounds__(256) k_big_lookup(const T *__restrict__ cells,
                 } else {
                     cntP[u] = BIG | c;
                     atomicAdd(reinterpret_cast<unsigned long long *>(&tile_tot[u / PT]),
+                              static_cast<unsigned long long>(c));
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&sup_tot[(u / PT) / SUP]),
                               static_cast<unsigned long long>(c));
                 }
             }
@@ -465,8 +534,8 @@ __device__ __forceinline__ void copy_rows_padded(T *lds, const T *__restrict__ s
     }
 }
 
-// s is uniform across the block, so the word loop's bound is a scalar branch:
-// only the ceil(s / B) words that hold the prefix are read.
+// Only the ceil(s / B) words that hold the prefix are read (s is the same
+// for every lane, so the per-word tests are uniform branches).
 template <typename T, int WT>
 __device__ __forceinline__ bool same_prefix_t(const T *a, const T *b, int s) {
     constexpr int B = Bits<T>::B;
@@ -601,8 +670,8 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
                                                const int64_t *d_n, int64_t ncap, int words, int ell, int s, int gmax,
                                                const uint32_t *__restrict__ cntS, uint32_t *__restrict__ cntP,
                                                uint32_t *__restrict__ stash, uint32_t *__restrict__ stash_n,
-                                               uint64_t *__restrict__ tile_tot, uint32_t *__restrict__ big_list,
-                                               unsigned long long *__restrict__ big_n) {
+                                               uint64_t *__restrict__ tile_tot, uint64_t *__restrict__ sup_tot,
+                                               uint32_t *__restrict__ big_list, unsigned long long *__restrict__ big_n) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint64_t tmp[4];
     __shared__ uint32_t s_nres;
@@ -634,13 +703,17 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
         const int avail = static_cast<int>(av < PROWS ? av : PROWS);
         const int tot = avail * WT;
         const T *src = cells + base * words;
+        // every load is issued (out-of-range ones read the tile's first word,
+        // which exists) and masked when stored to LDS: no branches around the
+        // loads and no wait for them here
 #pragma unroll
         for (int u = 0; u < NE; ++u) {
             const int e = t + u * PT;
             const int r = e / WT, w = e % WT;
-            pre[u] = (e < tot && w < words) ? src[static_cast<int64_t>(r) * words + w] : T(0);
+            const bool ok = e < tot && w < words;
+            pre[u] = src[ok ? r * words + w : 0];
         }
-        pre_cs = base + t < n ? cntS[base + t] : 0u;
+        pre_cs = cntS[base + t < n ? base + t : base];
     };
 
     int64_t tile = r0 + lb;
@@ -649,12 +722,16 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
         const int64_t base = tile * PT;
         const int tr = static_cast<int>(n - base < PT ? n - base : PT);
         const int tl = static_cast<int>(n - base < PROWS ? n - base : PROWS);  // loaded rows
+        {
+            const int tot = tl * WT;
 #pragma unroll
-        for (int u = 0; u < NE; ++u) {
-            const int e = t + u * PT;
-            if (e < PROWS * WT) rows[(e / WT) * LW + (e % WT)] = pre[u];
+            for (int u = 0; u < NE; ++u) {
+                const int e = t + u * PT;
+                const bool ok = e < tot && (e % WT) < words;
+                if (e < PROWS * WT) rows[(e / WT) * LW + (e % WT)] = ok ? pre[u] : T(0);
+            }
         }
-        const uint32_t cs = pre_cs;
+        const uint32_t cs = base + t < n ? pre_cs : 0u;
         mask[t] = 0;
         if (t == 0) s_nres = 0;
         __syncthreads();
@@ -680,11 +757,6 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
                 res[r] = (static_cast<uint32_t>(t0) << 24) | (static_cast<uint32_t>(d0) << 16) |
                          static_cast<uint32_t>(k);
         };
-        auto check = [&](uint32_t e) {
-            const int t0 = static_cast<int>(e >> 16), j0 = static_cast<int>(e & 0xffffu);
-            int pos;
-            if (dist_t4<T, WT>(rows + t0 * LW, rows + j0 * LW, &pos) == 1) found(t0, j0 - t0, pos);
-        };
 
         // Lock-step over the offset d = j - i: a lane stays alive while row
         // t + d is in its group; pairs whose popcounts differ by one set bit
@@ -694,15 +766,25 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
         bool big = false, spill = false;  // spill: the group runs past the loaded rows
         const uint32_t pc = pcs[t < tl ? t : tl] & 0x7fffffffu;
         unsigned long long cm = 0;
-        for (int d = 1; d <= gm && ballot64(alive) != 0; ++d) {
-            const int jj = t + d;
-            const bool past = jj >= tl;
-            const uint32_t x = pcs[past ? tl : jj];
-            spill = spill || (alive && past && more);
-            alive = alive && !past && (x >> 31) == 0;
-            const uint32_t po = x & 0x7fffffffu;
-            const bool cand = alive && (po == pc + 1 || po + 1 == pc);
-            cm |= cand ? (1ull << (d - 1)) : 0ull;
+        // four offsets per step: their four LDS reads are in flight together
+        for (int d0 = 1; d0 <= gm && ballot64(alive) != 0; d0 += 4) {
+            uint32_t x[4];
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const int jj = t + d0 + q4;
+                x[q4] = pcs[jj < tl ? jj : tl];
+            }
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const int d = d0 + q4;
+                const bool inr = d <= gm;  // the same for every lane
+                const bool past = t + d >= tl;
+                spill = spill || (inr && alive && past && more);
+                alive = alive && (!inr || (!past && (x[q4] >> 31) == 0));
+                const uint32_t po = x[q4] & 0x7fffffffu;
+                const bool cand = inr && alive && (po == pc + 1 || po + 1 == pc);
+                cm |= cand ? (1ull << (d - 1)) : 0ull;
+            }
         }
         if (alive) {  // still inside the group after gm rows: one more member means look-ups
             const int jj = t + gm + 1;
@@ -727,8 +809,25 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
                 }
                 __builtin_amdgcn_wave_barrier();
                 const uint32_t cnt = tot - done < static_cast<uint32_t>(CQ) ? tot - done : static_cast<uint32_t>(CQ);
-                for (uint32_t e0 = 0; e0 < cnt; e0 += 64)
-                    if (e0 + lane < cnt) check(q[e0 + lane]);
+                for (uint32_t e0 = 0; e0 < cnt; e0 += 64) {
+                    // every lane runs the test (idle lanes compare row 0 with itself)
+                    const bool act = e0 + lane < cnt;
+                    const uint32_t e = act ? q[e0 + lane] : 0u;
+                    const int t0 = static_cast<int>(e >> 16), j0 = static_cast<int>(e & 0xffffu);
+                    int pos;
+                    const bool hit = dist_t4<T, WT>(rows + t0 * LW, rows + j0 * LW, &pos) == 1;
+                    if (hit) atomicOr(&mask[t0], 1ull << (j0 - t0 - 1));
+                    const uint64_t hm = ballot64(hit);  // one counter update per wave
+                    uint32_t rb = 0;
+                    if (lane == 0 && hm) rb = atomicAdd(&s_nres, static_cast<uint32_t>(__popcll(hm)));
+                    rb = __shfl(rb, 0, 64);
+                    if (hit) {
+                        const uint32_t r = rb + static_cast<uint32_t>(__popcll(hm & lanemask_lt()));
+                        if (r < static_cast<uint32_t>(P_STASH))
+                            res[r] = (static_cast<uint32_t>(t0) << 24) | (static_cast<uint32_t>(j0 - t0) << 16) |
+                                     static_cast<uint32_t>(pos);
+                    }
+                }
                 __builtin_amdgcn_wave_barrier();
             }
         }
@@ -760,6 +859,8 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
         const uint32_t nres = s_nres;
         if (t == 0) {
             tile_tot[tile] = tot_all;
+            atomicAdd(reinterpret_cast<unsigned long long *>(&sup_tot[tile / SUP]),
+                      static_cast<unsigned long long>(tot_all));
             const uint64_t m = nres > tot_stash ? nres : tot_stash;
             stash_n[tile] = static_cast<uint32_t>(m > 0xffffffffull ? 0xffffffffull : m);
         }
@@ -779,71 +880,6 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
     }
 }
 
-// One block of 1024 threads: exclusive scan of the tile totals in place;
-// |E|, offsets[n], status.  Thread t owns a contiguous chunk; up to 16 per
-// thread (16,384 tiles) the chunk is read once and kept in registers.
-constexpr int TS_T = 1024;
-__global__ void __launch_bounds__(TS_T) k_tile_scan(uint64_t *tile_tot, const int64_t *d_n, int64_t ncap,
-                                                    int64_t cap, int64_t *d_nedges, int64_t *offsets,
-                                                    int32_t *status) {
-    __shared__ uint64_t wsum[TS_T / 64];
-    constexpr int U = 16;
-    const int64_t n = load_n(d_n, ncap);
-    const int64_t tiles = (n + PT - 1) / PT;
-    const int64_t per = (tiles + TS_T - 1) / TS_T;
-    const int64_t a = threadIdx.x * per;
-    uint64_t v[U];
-    uint64_t sum = 0;
-    if (per <= U) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            v[u] = (u < per && a + u < tiles) ? tile_tot[a + u] : 0;
-            sum += v[u];
-        }
-    } else {
-        for (int64_t k0 = a; k0 < a + per; k0 += U) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = (k0 + u < a + per && k0 + u < tiles) ? tile_tot[k0 + u] : 0;
-#pragma unroll
-            for (int u = 0; u < U; ++u) sum += v[u];
-        }
-    }
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const uint64_t inc = wave_incl_scan_u64(sum);
-    if (l == 63) wsum[w] = inc;
-    __syncthreads();
-    uint64_t run = inc - sum, total = 0;
-#pragma unroll
-    for (int k = 0; k < TS_T / 64; ++k) {
-        const uint64_t x = wsum[k];
-        if (k < w) run += x;
-        total += x;
-    }
-    if (per <= U) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (u < per && a + u < tiles) tile_tot[a + u] = run;
-            run += v[u];
-        }
-    } else {
-        for (int64_t k0 = a; k0 < a + per; k0 += U) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = (k0 + u < a + per && k0 + u < tiles) ? tile_tot[k0 + u] : 0;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (k0 + u < a + per && k0 + u < tiles) tile_tot[k0 + u] = run;
-                run += v[u];
-            }
-        }
-    }
-    if (threadIdx.x == 0) {
-        const int64_t tot = static_cast<int64_t>(total);
-        *d_nedges = tot;
-        if (offsets) offsets[n] = tot;
-        *status = tot > cap ? CG_ECAPACITY : CG_OK;
-    }
-}
-
 // Placement of P edges for tiles whose stash held them; offsets for all.
 // The tile's edges fill one contiguous range of slots: thread r takes slots
 // r, r + PT, ..., finds the owning cell by binary search over the tile's
@@ -854,9 +890,11 @@ __global__ void __launch_bounds__(PT) k_p_place(const int64_t *d_n, int64_t ncap
                                                 const uint32_t *__restrict__ cntS, const uint32_t *__restrict__ cntP,
                                                 const uint32_t *__restrict__ stash,
                                                 const uint32_t *__restrict__ stash_n,
-                                                const uint64_t *__restrict__ tile_off, int64_t *__restrict__ offsets,
+                                                const uint64_t *__restrict__ tile_tot,
+                                                const uint64_t *__restrict__ sup_tot, int64_t *__restrict__ offsets,
                                                 int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
-                                                uint16_t *__restrict__ bit, int64_t cap) {
+                                                uint16_t *__restrict__ bit, int64_t cap, int64_t *__restrict__ d_nedges,
+                                                int32_t *__restrict__ status) {
     __shared__ uint64_t tmp[4];
     __shared__ uint32_t sx[PT];   // tile-relative first slot of each cell
     __shared__ uint32_t ssb[PT];  // first stash entry of each cell
@@ -873,7 +911,7 @@ __global__ void __launch_bounds__(PT) k_p_place(const int64_t *d_n, int64_t ncap
         cp = cntP[i];
         cs = cntS[i];
     }
-    const uint64_t t_off = tile_off[tile];
+    const uint64_t t_off = tile_offset(tile, tile_tot, sup_tot, tmp);
     const uint32_t sn = stash_n[tile];
     const uint32_t c = cp & ~BIG;
     const uint32_t stashed = (cp & BIG) ? 0u : cp;
@@ -881,6 +919,12 @@ __global__ void __launch_bounds__(PT) k_p_place(const int64_t *d_n, int64_t ncap
     const uint64_t exa = block256_excl_scan_u64(static_cast<uint64_t>(c) + cs, tmp, &tot_all);
     const uint64_t exs = block256_excl_scan_u64(stashed, tmp, &tot_stash);
     const int64_t out0 = static_cast<int64_t>(t_off + exa);
+    if (t == 0 && base + tr == n) {  // the last tile: |E|, offsets[n], status
+        const int64_t tot = static_cast<int64_t>(t_off + tot_all);
+        *d_nedges = tot;
+        if (offsets) offsets[n] = tot;
+        *status = tot > cap ? CG_ECAPACITY : CG_OK;
+    }
     if (t < tr) {
         if (offsets) offsets[i] = out0;
         else if (cs || (cp & BIG)) offnext[i] = out0 + c + cs;
@@ -913,7 +957,8 @@ __global__ void __launch_bounds__(PT) k_p_fix(const T *__restrict__ cells, const
                                               int words, int s, int gmax, const uint32_t *__restrict__ cntS,
                                               const uint32_t *__restrict__ cntP,
                                               const uint32_t *__restrict__ stash_n,
-                                              const uint64_t *__restrict__ tile_off, uint32_t *__restrict__ uv,
+                                              const uint64_t *__restrict__ tile_tot,
+                                              const uint64_t *__restrict__ sup_tot, uint32_t *__restrict__ uv,
                                               uint16_t *__restrict__ bit, int64_t cap) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint64_t tmp[4];
@@ -938,8 +983,9 @@ __global__ void __launch_bounds__(PT) k_p_fix(const T *__restrict__ cells, const
     }
     uint64_t tot;
     const uint64_t exa = block256_excl_scan_u64(static_cast<uint64_t>(cp & ~BIG) + cs, tmp, &tot);
+    const uint64_t t_off = tile_offset(tile, tile_tot, sup_tot, tmp);  // block-wide: before any thread leaves
     if (t >= tr || (cp & BIG) || cp == 0) return;
-    const int64_t out0 = static_cast<int64_t>(tile_off[tile] + exa);
+    const int64_t out0 = static_cast<int64_t>(t_off + exa);
     p_scan_t<T, WT>(rows, pcs, heads, tr + th, t, i, base, n, cells, words, s, gmax,
                     [&](uint32_t d, int k, uint32_t r) {
                         emit(uv, bit, cap, out0 + r, static_cast<uint32_t>(i), static_cast<uint32_t>(i + d), k);
@@ -951,7 +997,11 @@ struct EdgesWs {
     int64_t *offsets;
     uint64_t *tile_sums;
     uint64_t *tile_tot;
+    uint64_t *sup_tot;
+    int64_t nsup;
     uint32_t *p_stash, *p_stash_n;
+    uint4 *s_stash;              // S edges per block of the suffix order
+    uint32_t *s_stash_n;
     uint32_t *s_big, *p_big;     // cells left to k_big_lookup
     unsigned long long *big_n;   // [0]: S list length, [1]: P list length
 };
@@ -977,8 +1027,13 @@ EdgesWs carve_edges(void *base, int64_t ncap, size_t *bytes) {
     w.offsets = c.take<int64_t>(n + 1);
     w.tile_sums = c.take<uint64_t>(scan_tiles(n));
     w.tile_tot = c.take<uint64_t>(tiles);
+    w.nsup = (tiles + SUP - 1) / SUP;
+    w.sup_tot = c.take<uint64_t>(w.nsup);
     w.p_stash = c.take<uint32_t>(tiles * P_STASH);
     w.p_stash_n = c.take<uint32_t>(tiles);
+    const int64_t sblocks = (n + SC - 1) / SC;
+    w.s_stash = c.take<uint4>(sblocks * S_STASH);
+    w.s_stash_n = c.take<uint32_t>(sblocks);
     w.s_big = c.take<uint32_t>(n);
     w.p_big = c.take<uint32_t>(n);
     w.big_n = c.take<unsigned long long>(2);
@@ -1012,45 +1067,46 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
     const int64_t ntiles = (ncap + PT - 1) / PT;
     const dim3 grid(static_cast<unsigned>(ntiles));
     const dim3 sgrid(static_cast<unsigned>((ncap + SC - 1) / SC));
-    const dim3 bgrid(blocks_for(ncap, 4, 2048));  // one wave per listed cell
+    const dim3 bgrid(blocks_for(ncap, 4, 512));  // one wave per listed cell
     const size_t lds = PTile<T, WT>::bytes;
     const size_t lds_find = PFind<T, WT>::bytes;
     const int rmax = gmax < SRMAX ? gmax : SRMAX;
     const int64_t *no_off = nullptr;
     if (sp > 0) {
         hipLaunchKernelGGL((k_s_scan<T, false>), sgrid, dim3(PT), 0, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
-                           rmax, w.cntS, no_off, no_off, uv, bit, cap, w.s_big, w.big_n);
+                           rmax, w.cntS, no_off, no_off, uv, bit, cap, w.s_big, w.big_n, w.s_stash, w.s_stash_n);
         CG_LAUNCHED("edges_s_count");
         hipLaunchKernelGGL((k_big_lookup<T, BIG_S_COUNT>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
-                           w.s_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, no_off, no_off, uv, bit, cap);
+                           w.s_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, no_off, no_off, uv, bit, cap);
         CG_LAUNCHED("edges_s_big_count");
     }
     const unsigned pblocks = persistent_blocks(reinterpret_cast<const void *>(&k_p_find<T, WT>), lds_find, ntiles);
     hipLaunchKernelGGL((k_p_find<T, WT>), dim3(pblocks), dim3(PT), lds_find, s, cells, d.d_ncells, ncap, words, ell,
-                       sp, gmax, w.cntS, w.cntP, w.p_stash, w.p_stash_n, w.tile_tot, w.p_big, w.big_n + 1);
+                       sp, gmax, w.cntS, w.cntP, w.p_stash, w.p_stash_n, w.tile_tot, w.sup_tot, w.p_big,
+                       w.big_n + 1);
     CG_LAUNCHED("edges_p_find");
     hipLaunchKernelGGL((k_big_lookup<T, BIG_P_COUNT>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
-                       w.p_big, w.big_n + 1, ncap, w.cntS, w.cntP, w.tile_tot, no_off, no_off, uv, bit, cap);
+                       w.p_big, w.big_n + 1, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, no_off, no_off, uv, bit, cap);
     CG_LAUNCHED("edges_p_big_count");
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(TS_T), 0, s, w.tile_tot, d.d_ncells, ncap, cap, d_nedges, d_offsets,
-                       d_status);
-    CG_LAUNCHED("edges_tile_scan");
     hipLaunchKernelGGL((k_p_place<T>), grid, dim3(PT), 0, s, d.d_ncells, ncap, w.cntS, w.cntP, w.p_stash,
-                       w.p_stash_n, w.tile_tot, d_offsets, offnext, uv, bit, cap);
+                       w.p_stash_n, w.tile_tot, w.sup_tot, d_offsets, offnext, uv, bit, cap, d_nedges, d_status);
     CG_LAUNCHED("edges_p_place");
     hipLaunchKernelGGL((k_big_lookup<T, BIG_P_WRITE>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
-                       w.p_big, w.big_n + 1, ncap, w.cntS, w.cntP, w.tile_tot, d_offsets, offnext, uv, bit, cap);
+                       w.p_big, w.big_n + 1, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, d_offsets, offnext, uv, bit, cap);
     CG_LAUNCHED("edges_p_big_write");
     const int gm = gmax < PSCAN ? gmax : PSCAN;  // same scan limit as k_p_find
     hipLaunchKernelGGL((k_p_fix<T, WT>), grid, dim3(PT), lds, s, cells, d.d_ncells, ncap, words, sp, gm, w.cntS,
-                       w.cntP, w.p_stash_n, w.tile_tot, uv, bit, cap);
+                       w.cntP, w.p_stash_n, w.tile_tot, w.sup_tot, uv, bit, cap);
     CG_LAUNCHED("edges_p_fix");
     if (sp > 0) {
+        hipLaunchKernelGGL(k_s_place, sgrid, dim3(256), 0, s, d.d_ncells, ncap, w.s_stash, w.s_stash_n, w.cntS,
+                           d_offsets, offnext, uv, bit, cap);
+        CG_LAUNCHED("edges_s_place");
         hipLaunchKernelGGL((k_s_scan<T, true>), sgrid, dim3(PT), 0, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
-                           rmax, w.cntS, d_offsets, offnext, uv, bit, cap, w.s_big, w.big_n);
+                           rmax, w.cntS, d_offsets, offnext, uv, bit, cap, w.s_big, w.big_n, w.s_stash, w.s_stash_n);
         CG_LAUNCHED("edges_s_write");
         hipLaunchKernelGGL((k_big_lookup<T, BIG_S_WRITE>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
-                           w.s_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, d_offsets, offnext, uv, bit, cap);
+                           w.s_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, d_offsets, offnext, uv, bit, cap);
         CG_LAUNCHED("edges_s_big_write");
     }
     return CG_OK;
@@ -1063,7 +1119,7 @@ cg_status edges_fast(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap,
     const int64_t ntiles = (ncap + PT - 1) / PT;
     int64_t *offnext = w.offsets;  // sparse next-offsets when the caller wants no offsets
     hipLaunchKernelGGL(k_edges_init, dim3(blocks_for(ncap, 256, 4096)), dim3(256), 0, s, w.cntS, ncap, d_nedges,
-                       d_offsets, d_status, w.big_n);
+                       d_offsets, d_status, w.big_n, w.sup_tot, w.nsup);
     CG_LAUNCHED("edges_init");
     if (ncap == 0) return CG_OK;
     const dim3 grid(static_cast<unsigned>(ntiles));

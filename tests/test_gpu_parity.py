@@ -382,3 +382,19 @@ def test_wide_rows_generic_paths(gpu):
     say("wide rows", R.shape)
     for wb in (32, 64):
         assert_same(P.cell_graph(R, 4000, wb), oracle_graph(R, 4000, wb))
+
+
+def test_stash_overflow_past_first_supertile(gpu):
+    """A 2^15-cell hypercube as one prefix group: every tile's P stash
+    overflows and tiles past the first 64 take their output offset from the
+    super-tile totals while most of their threads have nothing to write."""
+    torch, B, P = gpu
+    ell = 15
+    n = 2 ** ell
+    R = ((np.arange(n)[:, None] >> np.arange(ell - 1, -1, -1)[None, :]) & 1).astype(np.uint8)
+    R = R[np.random.default_rng(15).permutation(n)]
+    for wb in (32, 64):
+        say("cube 15, split 0", wb)
+        res = P.cell_graph(R, ell, wb, params=B.cg_dict_params_default(split_bit=0, group_max=1024))
+        assert res["nedges"] == ell * 2 ** (ell - 1)
+        assert_same(res, oracle_graph(R, ell, wb))
