@@ -216,16 +216,23 @@ __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, con
     const int64_t b0 = static_cast<int64_t>(blockIdx.x) * TT;
     const int t = threadIdx.x;
     const int64_t wend = (b0 + slots < n) ? b0 + slots : n;
+    // keys of the window and the row indices of its positions, loaded together
     for (int e0 = t; e0 <= slots; e0 += TT * 4) {
         uint64_t v[4];
+        uint32_t x[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t pos = b0 - 1 + e0 + u * TT;
-            v[u] = (e0 + u * TT <= slots && pos >= 0 && pos < wend) ? keys[pos] : 0;
+            const bool in = e0 + u * TT <= slots && pos >= 0 && pos < wend;
+            v[u] = in ? keys[pos] : 0;
+            x[u] = (in && pos >= b0) ? vals[pos] : 0u;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (e0 + u * TT <= slots) skeys[e0 + u * TT] = v[u];
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * TT;
+            if (e <= slots) skeys[e] = v[u];
+            if (e >= 1 && e <= slots) sval[e - 1] = x[u];
+        }
     }
     for (int r = t; r < slots; r += TT) segof[r] = -1;
     __syncthreads();
@@ -254,20 +261,7 @@ __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, con
     }
     wave_append<uint2>(large_list, &counters[1], n, large, seg);
     __syncthreads();
-    for (int r0 = t; r0 < slots; r0 += TT * 4) {
-        uint32_t v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int r = r0 + u * TT;
-            v[u] = (r < slots && segof[r] >= 0) ? vals[b0 + r] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int r = r0 + u * TT;
-            if (r < slots && segof[r] >= 0) sval[r] = v[u];
-        }
-    }
-    __syncthreads();
+
     constexpr int U = 16;
     const int tot = slots * WT;
     for (int e0 = t; e0 < tot; e0 += TT * U) {
@@ -286,48 +280,71 @@ __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, con
     }
     __syncthreads();
     // Summary of each row against its segment's first row a: the first word
-    // f (past the sort key) where they differ (WT if equal) and the row's
-    // word there.  Two rows then compare by their summaries alone unless
-    // they differ from row a first in the same word with the same value.
+    // f (past the sort key) where they differ (WT if equal), the row's word
+    // there and the first row's word there.  Two rows then compare by their
+    // summaries alone unless they differ from row a first in the same word
+    // with the same value (a tie, settled by comparing the rows).
     uint8_t *sf = reinterpret_cast<uint8_t *>(sval + slots);
-    T *sv = reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(sf + slots + 7) & ~uintptr_t(7));
+    // 8-byte aligned offset from the LDS base (offset arithmetic keeps the
+    // pointer in the LDS address space: a round trip through an integer
+    // address would turn every access into a flat memory access)
+    const ptrdiff_t sv_off = ((sf + slots) - reinterpret_cast<uint8_t *>(smem) + 7) & ~ptrdiff_t(7);
+    T *sv = reinterpret_cast<T *>(smem + sv_off);
+    T *shv = sv + slots;
     for (int r = t; r < slots; r += TT) {
         const int a = segof[r];
         if (a < 0) continue;
         const T *me = lrows + r * LW, *hd = lrows + a * LW;
         int f = WT;
-        T v = 0;
+        T v = 0, h = 0;
 #pragma unroll
         for (int w = WT - 1; w >= FROM; --w) {
-            const bool ne = me[w] != hd[w];
+            const T x = me[w], y = hd[w];
+            const bool ne = x != y;
             f = ne ? w : f;
-            v = ne ? me[w] : v;
+            v = ne ? x : v;
+            h = ne ? y : h;
         }
         sf[r] = static_cast<uint8_t>(f);
         sv[r] = v;
+        shv[r] = h;
     }
     __syncthreads();
     for (int r = t; r < slots; r += TT) {
         const int a = segof[r];
         if (a < 0) continue;
         const int len = seglen[r];
-        const T *me = lrows + r * LW, *hd = lrows + a * LW;
         const int fm = sf[r];
-        const T vm = sv[r];
-        const T hm = fm < WT ? hd[fm] : T(0);
+        const T vm = sv[r], hm = shv[r];
         int rank = 0;
         bool dup = false;
+        unsigned long long tie[2] = {0ull, 0ull};  // j - a of tied rows (len <= 128)
         for (int j = a; j < a + len; ++j) {
             const int fj = sf[j];
-            const T vj = sv[j];
-            int c;  // compare row j with row r
-            if (fj < fm) c = vj < hd[fj] ? -1 : 1;
-            else if (fj > fm) c = hm < vm ? -1 : 1;
-            else if (fj == WT) c = 0;
-            else if (vj != vm) c = vj < vm ? -1 : 1;
-            else c = lex_cmp_t<T, WT, FROM>(lrows + j * LW, me);
-            rank += (c < 0 || (c == 0 && j < r)) ? 1 : 0;
-            dup = dup || (c == 0 && j < r);
+            const T vj = sv[j], hj = shv[j];
+            // compare row j with row r, branch-free; 2 marks a tie
+            const int c_lt = vj < hj ? -1 : 1;   // j leaves the first row first
+            const int c_gt = hm < vm ? -1 : 1;   // r leaves it first
+            const int c_eq = fj == WT ? 0 : (vj != vm ? (vj < vm ? -1 : 1) : 2);
+            const int c = fj < fm ? c_lt : (fj > fm ? c_gt : c_eq);
+            const bool before = j < r;
+            rank += (c == -1 || (c == 0 && before)) ? 1 : 0;
+            dup = dup || (c == 0 && before);
+            const int o = j - a;
+            if (c == 2 && j != r) tie[o >> 6] |= 1ull << (o & 63);
+        }
+        // ties: compare the rows themselves
+        const T *me = lrows + r * LW;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            unsigned long long m = tie[h];
+            while (m) {
+                const int j = a + h * 64 + __ffsll(m) - 1;
+                m &= m - 1;
+                const int c = lex_cmp_t<T, WT, FROM>(lrows + j * LW, me);
+                rank += (c < 0 || (c == 0 && j < r)) ? 1 : 0;
+                dup = dup || (c == 0 && j < r);
+            }
         }
         vals[b0 + a + rank] = sval[r];
         uniq[b0 + a + rank] = dup ? 0 : 1;
@@ -337,14 +354,14 @@ __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, con
 template <typename T, int WT>
 size_t tiefix_t_lds(int smax) {
     const size_t slots = static_cast<size_t>(TT + smax);
-    return (slots + 1) * 8 + slots * ((WT + 1) * sizeof(T) + 12) + slots + 8 + slots * sizeof(T);
+    return (slots + 1) * 8 + slots * ((WT + 1) * sizeof(T) + 12) + slots + 8 + 2 * slots * sizeof(T);
 }
 
 template <typename T, int WT>
 int tiefix_t_smax() {
-    const int64_t per = (WT + 2) * static_cast<int64_t>(sizeof(T)) + 21;
+    const int64_t per = (WT + 3) * static_cast<int64_t>(sizeof(T)) + 21;
     int64_t smax = (TILE_LDS - 16) / per - TT - 1;
-    if (smax > 512) smax = 512;
+    if (smax > 128) smax = 128;  // the rank loop's tie masks cover 128 rows
     return static_cast<int>(smax);
 }
 

@@ -83,10 +83,22 @@ __global__ void __launch_bounds__(DT) k_dict_scan(const T *__restrict__ cells, c
     const int t = threadIdx.x;
     if (t >= tr) return;
     const int64_t i = base + t;
-    const T *row = stage ? lrows + t * LW : cells + i * words;
-    const int64_t gi = p ? static_cast<int64_t>(head64<T>(row, words) >> (64 - p)) : 0;
-    const T *prev = (stage && t > 0) ? lrows + (t - 1) * LW : cells + (i - 1) * words;
-    const int64_t gp = i == 0 ? -1 : (p ? static_cast<int64_t>(head64<T>(prev, words) >> (64 - p)) : 0);
+    // LDS and global rows take separate code so each access keeps its own
+    // address space (a pointer that may point to either becomes a flat access)
+    uint64_t hme, hprev = 0;
+    uint32_t hsh;
+    if (stage) {
+        const T *row = lrows + t * LW;
+        hme = head64<T>(row, words);
+        hsh = suffix_hash32<T>(row, words, s);
+    } else {
+        const T *row = cells + i * words;
+        hme = head64<T>(row, words);
+        hsh = suffix_hash32<T>(row, words, s);
+    }
+    if (i > 0) hprev = (stage && t > 0) ? head64<T>(lrows + (t - 1) * LW, words) : head64<T>(cells + (i - 1) * words, words);
+    const int64_t gi = p ? static_cast<int64_t>(hme >> (64 - p)) : 0;
+    const int64_t gp = i == 0 ? -1 : (p ? static_cast<int64_t>(hprev >> (64 - p)) : 0);
     // entries gp + 1 .. gi point at cell i
     const bool long_gap = gi - gp > GAPMIN;
     if (long_gap) {
@@ -105,7 +117,7 @@ __global__ void __launch_bounds__(DT) k_dict_scan(const T *__restrict__ cells, c
             for (int64_t g = gi + 1; g <= G; ++g) dir[g] = static_cast<uint32_t>(n);
         }
     }
-    sfx[i] = (static_cast<uint64_t>(suffix_hash32<T>(row, words, s)) << 32) | static_cast<uint64_t>(i);
+    sfx[i] = (static_cast<uint64_t>(hsh) << 32) | static_cast<uint64_t>(i);
 }
 
 // Fills the listed long gaps: gap (lo, hi, v) sets dir[lo .. hi] = v; one

@@ -158,6 +158,42 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint64_t *keys,
     hist[static_cast<int64_t>(t) * num_tiles + blockIdx.x] = h[t];
 }
 
+// Column scan of the digit-major tile histograms hist[d * num_tiles + tile]
+// into global scatter offsets, in two launches of one block per digit:
+// k_radix_dtot sums each digit's row; k_radix_dscan adds the totals of the
+// smaller digits and scans the row in place.
+__global__ void __launch_bounds__(RS_THREADS) k_radix_dtot(const uint32_t *hist, int num_tiles, uint32_t *dtot) {
+    __shared__ uint64_t tmp[4];
+    const int d = blockIdx.x;
+    const uint32_t *row = hist + static_cast<int64_t>(d) * num_tiles;
+    uint64_t part = 0;
+    for (int k = threadIdx.x; k < num_tiles; k += RS_THREADS) part += row[k];
+    uint64_t tot;
+    block256_excl_scan_u64(part, tmp, &tot);
+    if (threadIdx.x == 0) dtot[d] = static_cast<uint32_t>(tot);
+}
+
+__global__ void __launch_bounds__(RS_THREADS) k_radix_dscan(uint32_t *hist, int num_tiles, const uint32_t *dtot) {
+    __shared__ uint64_t tmp[4];
+    const int d = blockIdx.x, t = threadIdx.x;
+    // offset of digit d: the totals of the digits below it (thread t holds digit t)
+    uint64_t dbase;
+    block256_excl_scan_u64(t < d ? dtot[t] : 0u, tmp, &dbase);
+    // row scan: thread t owns a contiguous chunk of the row
+    uint32_t *row = hist + static_cast<int64_t>(d) * num_tiles;
+    const int per = (num_tiles + RS_THREADS - 1) / RS_THREADS;
+    const int a = t * per, b = a + per < num_tiles ? a + per : num_tiles;
+    uint64_t sum = 0;
+    for (int k = a; k < b; ++k) sum += row[k];
+    uint64_t tot;
+    uint64_t run = dbase + block256_excl_scan_u64(sum, tmp, &tot);
+    for (int k = a; k < b; ++k) {
+        const uint32_t x = row[k];
+        row[k] = static_cast<uint32_t>(run);
+        run += x;
+    }
+}
+
 template <bool HAS_VALS>
 __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *kin, const uint32_t *vin,
                                                               uint64_t *kout, uint32_t *vout, int64_t n_cap,
@@ -284,19 +320,23 @@ cg_status scan_rowpop_to_i64(const void *rows, int word_bits, int words, int64_t
 }
 
 int64_t radix_hist_entries(int64_t n_cap) {
-    return static_cast<int64_t>(RADIX) * blocks_for(n_cap, RS_TILE);
+    return static_cast<int64_t>(RADIX) * (blocks_for(n_cap, RS_TILE) + 1);  // tile rows + digit totals
 }
 
 cg_status radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], int64_t n_cap, const int64_t *d_n, int bit_lo,
                          int bit_hi, uint32_t *hist, uint64_t *tile_sums, int *which, hipStream_t s) {
     const int num_tiles = static_cast<int>(blocks_for(n_cap, RS_TILE));
-    const int64_t hist_n = static_cast<int64_t>(RADIX) * num_tiles;
+    (void)tile_sums;
     int cur = 0;
     for (int shift = bit_lo; shift < bit_hi; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3(num_tiles), dim3(RS_THREADS), 0, s, keys[cur], n_cap, d_n, shift,
                            hist, num_tiles);
         CG_LAUNCHED("radix_hist");
-        CG_TRY(scan_u32_to_u32(hist, hist, hist_n, nullptr, tile_sums, nullptr, s));
+        uint32_t *dtot = hist + static_cast<int64_t>(RADIX) * num_tiles;  // digit totals after the rows
+        hipLaunchKernelGGL(k_radix_dtot, dim3(RADIX), dim3(RS_THREADS), 0, s, hist, num_tiles, dtot);
+        CG_LAUNCHED("radix_dtot");
+        hipLaunchKernelGGL(k_radix_dscan, dim3(RADIX), dim3(RS_THREADS), 0, s, hist, num_tiles, dtot);
+        CG_LAUNCHED("radix_dscan");
         if (vals) {
             hipLaunchKernelGGL((k_radix_scatter<true>), dim3(num_tiles), dim3(RS_THREADS), 0, s, keys[cur],
                                vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_cap, d_n, shift, hist, num_tiles);
