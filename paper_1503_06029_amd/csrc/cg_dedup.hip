@@ -22,17 +22,50 @@ namespace {
 constexpr uint32_t SENT = 0xFFFFFFFFu;
 constexpr int64_t TILE_LDS = 53248;  // three blocks per CU
 constexpr int LMAX = 4096;          // longest segment sorted in one block's LDS
-#ifndef CG_DEDUP_KEY_BITS
-#define CG_DEDUP_KEY_BITS 64
-#endif
-// Leading bits sorted by the radix passes when rows are longer than 64 bits
-// (32 or 64); equal-key segments are then finished by full-row comparison.
-constexpr int KEY_BITS = CG_DEDUP_KEY_BITS;
-static_assert(KEY_BITS == 32 || KEY_BITS == 64, "sort key is 32 or 64 bits");
+// Rows longer than 64 bits are sorted on their first 64 bits, or on their
+// first 32 when a sample shows those already separate the rows (then the
+// four low radix passes are skipped); equal-key segments are finished by
+// full-row comparison either way.  counters[2] holds the choice (1: 32).
+constexpr int PROBE = 4096;        // sampled rows
+constexpr int PROBE_TIES = 128;    // at most this many equal neighbours (about 3 %) for 32-bit keys
+constexpr int64_t PROBE_MIN_N = 1 << 20;
+
+// One block: the top 32 bits of PROBE rows spread over the input go into an
+// LDS hash set; if at most PROBE_TIES of them were already present, 32-bit
+// keys are chosen (counters[2] = 1), else 64-bit keys (0).
+constexpr int PROBE_SLOTS = 2 * PROBE;
+template <typename T>
+__global__ void __launch_bounds__(1024) k_key_probe(const T *__restrict__ rows, int64_t n, int words,
+                                                    unsigned long long *__restrict__ counters) {
+    __shared__ uint32_t tab[PROBE_SLOTS];
+    __shared__ int ties;
+    const int t = threadIdx.x;
+    if (t == 0) ties = 0;
+    for (int i = t; i < PROBE_SLOTS; i += 1024) tab[i] = 0xFFFFFFFFu;
+    __syncthreads();
+    int local = 0;
+    for (int i = t; i < PROBE; i += 1024) {
+        const int64_t r = static_cast<int64_t>(i) * n / PROBE;
+        uint32_t k = static_cast<uint32_t>(head64<T>(rows + r * words, words) >> 32);
+        if (k == 0xFFFFFFFFu) k = 0xFFFFFFFEu;  // the empty mark
+        uint32_t h = (k * 0x9E3779B1u) >> 19;   // 13 bits: PROBE_SLOTS = 8192
+        for (int step = 0; step < PROBE_SLOTS; ++step) {
+            const uint32_t old = atomicCAS(&tab[h], 0xFFFFFFFFu, k);
+            if (old == 0xFFFFFFFFu) break;
+            if (old == k) { ++local; break; }
+            h = (h + 1) & (PROBE_SLOTS - 1);
+        }
+    }
+    if (local) atomicAdd(&ties, local);
+    __syncthreads();
+    if (t == 0) counters[2] = ties <= PROBE_TIES ? 1ull : 0ull;
+}
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_extract(const T *__restrict__ rows, int64_t n, int words, uint64_t kmask,
+__global__ void __launch_bounds__(256) k_extract(const T *__restrict__ rows, int64_t n, int words,
+                                                 const unsigned long long *__restrict__ key32,
                                                  uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const uint64_t kmask = (key32 && *key32) ? 0xFFFFFFFF00000000ull : ~0ull;
     for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
          j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         keys[j] = head64<T>(rows + j * words, words) & kmask;
@@ -80,10 +113,11 @@ constexpr int TT = 256;
 
 template <typename T>
 __global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, const uint64_t *__restrict__ keys,
-                                                    int64_t n, int words, int from, int smax,
+                                                    int64_t n, int words, int from64, int smax,
                                                     uint32_t *__restrict__ vals, uint8_t *__restrict__ uniq,
                                                     uint2 *__restrict__ large_list,
                                                     unsigned long long *__restrict__ counters) {
+    const int from = counters[2] ? from64 / 2 : from64;  // words covered by the sort key
     extern __shared__ __align__(16) unsigned char smem[];
     const int LW = words + ((words & 1) ? 0 : 1);
     const int slots = TT + smax;
@@ -200,13 +234,17 @@ __device__ __forceinline__ int lex_cmp_t(const T *a, const T *b) {
     return res;
 }
 
-template <typename T, int WT, int FROM>
+// KB is the sort key's width in bits (32 or 64); the kernel for the width
+// not chosen by the probe (counters[2]) returns at once.
+template <typename T, int WT, int KB>
 __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, const uint64_t *__restrict__ keys,
                                                  int64_t n, int words, int smax, uint32_t *__restrict__ vals,
                                                  uint8_t *__restrict__ uniq, uint2 *__restrict__ large_list,
                                                  unsigned long long *__restrict__ counters) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int LW = WT + 1;
+    if ((counters[2] != 0) != (KB == 32)) return;
+    constexpr int FROM = KB / Bits<T>::B;  // words covered by the sort key
     const int slots = TT + smax;
     uint64_t *skeys = reinterpret_cast<uint64_t *>(smem);  // positions b0 - 1 .. b0 + slots - 1
     T *lrows = reinterpret_cast<T *>(skeys + slots + 1);
@@ -319,6 +357,7 @@ __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, con
         int rank = 0;
         bool dup = false;
         unsigned long long tie[2] = {0ull, 0ull};  // j - a of tied rows (len <= 128)
+#pragma unroll 4
         for (int j = a; j < a + len; ++j) {
             const int fj = sf[j];
             const T vj = sv[j], hj = shv[j];
@@ -367,13 +406,17 @@ int tiefix_t_smax() {
 
 template <typename T, int WT>
 cg_status tiefix_t_launch(const T *rows, const uint64_t *keys, int64_t n, int words, uint32_t *vals, uint8_t *uniq,
-                          uint2 *large_list, unsigned long long *counters, hipStream_t s) {
+                          uint2 *large_list, unsigned long long *counters, bool probed, hipStream_t s) {
     const int smax = tiefix_t_smax<T, WT>();
     const size_t lds = tiefix_t_lds<T, WT>(smax);
-    constexpr int FROM = KEY_BITS / Bits<T>::B;
-    hipLaunchKernelGGL((k_tiefix_t<T, WT, FROM>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, keys, n, words, smax,
+    hipLaunchKernelGGL((k_tiefix_t<T, WT, 64>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, keys, n, words, smax,
                        vals, uniq, large_list, counters);
     CG_LAUNCHED("dedup_tiefix_t");
+    if (probed) {  // the probe may have chosen 32-bit keys
+        hipLaunchKernelGGL((k_tiefix_t<T, WT, 32>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, keys, n, words,
+                           smax, vals, uniq, large_list, counters);
+        CG_LAUNCHED("dedup_tiefix_t32");
+    }
     return CG_OK;
 }
 
@@ -389,10 +432,11 @@ __device__ __forceinline__ bool idx_less(const T *rows, int words, int from, uin
 // One block per long segment: bitonic network over its index array, kept in
 // global scratch at [2a, 2a + P), P = next power of two >= len.
 template <typename T>
-__global__ void __launch_bounds__(256) k_tiefix_large(const T *__restrict__ rows, int words, int from,
+__global__ void __launch_bounds__(256) k_tiefix_large(const T *__restrict__ rows, int words, int from64,
                                                       const uint2 *__restrict__ list,
                                                       const unsigned long long *__restrict__ counters, uint32_t *vals,
                                                       uint8_t *uniq, uint32_t *scratch) {
+    const int from = counters[2] ? from64 / 2 : from64;  // words covered by the sort key
     const uint32_t count = static_cast<uint32_t>(counters[1]);
     for (uint32_t s = blockIdx.x; s < count; s += gridDim.x) {
         const uint2 seg = list[s];
@@ -453,10 +497,11 @@ __device__ __forceinline__ uint64_t key2_of<uint32_t>(const uint32_t *row, int w
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) k_tiefix_mid(const T *__restrict__ rows, int words, int from,
+__global__ void __launch_bounds__(1024) k_tiefix_mid(const T *__restrict__ rows, int words, int from64,
                                                      const uint2 *__restrict__ list,
                                                      const unsigned long long *__restrict__ counters,
                                                      uint32_t *__restrict__ vals, uint8_t *__restrict__ uniq) {
+    const int from = counters[2] ? from64 / 2 : from64;  // words covered by the sort key
     __shared__ uint64_t sk[LMAX];
     __shared__ uint32_t si[LMAX];
     constexpr int K2 = 64 / Bits<T>::B;  // words covered by the second key
@@ -581,21 +626,28 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
     if (n == 0) return fill_i64(d_ncells, 0, 1, s);
 
     const bool tiefix = lay.ell > 64;
-    const uint64_t kmask = (tiefix && KEY_BITS < 64) ? ~((uint64_t(1) << (64 - KEY_BITS)) - 1) : ~uint64_t(0);
-    hipLaunchKernelGGL((k_extract<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words, kmask,
-                       w.keys[0], w.vals[0]);
+    const bool probe = tiefix && n >= PROBE_MIN_N;
+    CG_TRY(fill_i64(reinterpret_cast<int64_t *>(w.counters), 0, 4, s));
+    if (probe) {
+        hipLaunchKernelGGL((k_key_probe<T>), dim3(1), dim3(1024), 0, s, rows, n, words, w.counters);
+        CG_LAUNCHED("dedup_key_probe");
+    }
+    hipLaunchKernelGGL((k_extract<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words,
+                       probe ? w.counters + 2 : nullptr, w.keys[0], w.vals[0]);
     CG_LAUNCHED("dedup_extract");
 
-    // key bits that can be nonzero: [64 - sig, 64)
-    const int sig = tiefix ? KEY_BITS : lay.ell;
+    // key bits that can be nonzero: [64 - sig, 64); with 32-bit keys the four
+    // passes below bit 32 find every digit zero and are skipped on the device
+    const int sig = tiefix ? 64 : lay.ell;
     const int lo = ((64 - sig) / 8) * 8;
     int which = 0;
-    CG_TRY(radix_sort_u64(w.keys, w.vals, n, nullptr, lo, 64, w.hist, w.tile_sums, &which, s));
+    CG_TRY(radix_sort_u64(w.keys, w.vals, n, nullptr, lo, 64, w.hist, w.tile_sums, &which, s,
+                          probe ? w.counters + 2 : nullptr, 32));
     uint64_t *keys = w.keys[which];
     uint32_t *vals = w.vals[which];
 
     const int B = static_cast<int>(sizeof(T) * 8);
-    const int from = KEY_BITS / B;  // words covered by the sort key
+    const int from = 64 / B;  // words covered by a 64-bit sort key (the mid pass halves it for 32)
     if (!tiefix) {
         hipLaunchKernelGGL(k_heads, dim3(blocks_for(n, 256)), dim3(256), 0, s, keys, n, w.uniq);
         CG_LAUNCHED("dedup_heads");
@@ -609,17 +661,16 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
             smax = 1;
             lds = static_cast<size_t>(TT + 1) * 20 + 8;
         }
-        CG_TRY(fill_i64(reinterpret_cast<int64_t *>(w.counters), 0, 4, s));
         int wt = 1;
         while (wt < words) wt <<= 1;
         const int wcap = sizeof(T) == 8 ? 16 : 32;
         if (wt <= wcap) {  // every such width leaves room for segments of 80+ rows
             switch (wt) {
-            case 2: CG_TRY((tiefix_t_launch<T, 2>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, s))); break;
-            case 4: CG_TRY((tiefix_t_launch<T, 4>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, s))); break;
-            case 8: CG_TRY((tiefix_t_launch<T, 8>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, s))); break;
-            case 16: CG_TRY((tiefix_t_launch<T, 16>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, s))); break;
-            default: CG_TRY((tiefix_t_launch<T, 32>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, s))); break;
+            case 2: CG_TRY((tiefix_t_launch<T, 2>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
+            case 4: CG_TRY((tiefix_t_launch<T, 4>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
+            case 8: CG_TRY((tiefix_t_launch<T, 8>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
+            case 16: CG_TRY((tiefix_t_launch<T, 16>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
+            default: CG_TRY((tiefix_t_launch<T, 32>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
             }
         } else {
             hipLaunchKernelGGL((k_tiefix_tile<T>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, keys, n, words,

@@ -448,9 +448,9 @@ cg_status scan_rowpop_to_i64(const void *rows, int word_bits, int words, int64_t
 // keys[res] / vals[res], res returned in *which (0 or 1).  keys[1]/vals[1]
 // are scratch of the same size.  hist needs radix_hist_entries(n_cap).
 int64_t radix_hist_entries(int64_t n_cap);
-cg_status radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], int64_t n_cap, const int64_t *d_n,
-                         int bit_lo, int bit_hi, uint32_t *hist, uint64_t *tile_sums, int *which,
-                         hipStream_t s);
+cg_status radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], int64_t n_cap, const int64_t *d_n, int bit_lo,
+                         int bit_hi, uint32_t *hist, uint64_t *tile_sums, int *which, hipStream_t s,
+                         const unsigned long long *skip = nullptr, int skip_below = 0);
 
 // Fill kernel (graph-capture safe replacement for hipMemsetAsync).
 cg_status fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);

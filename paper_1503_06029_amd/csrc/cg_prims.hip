@@ -141,7 +141,9 @@ constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // 2048
 constexpr int RADIX = 256;
 
 __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint64_t *keys, int64_t n_cap, const int64_t *d_n,
-                                                           int shift, uint32_t *hist, int num_tiles) {
+                                                           int shift, uint32_t *hist, int num_tiles,
+                                                           const unsigned long long *skip) {
+    if (skip && *skip) return;
     __shared__ uint32_t h[RADIX];
     const int t = threadIdx.x;
     h[t] = 0;
@@ -162,7 +164,9 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint64_t *keys,
 // into global scatter offsets, in two launches of one block per digit:
 // k_radix_dtot sums each digit's row; k_radix_dscan adds the totals of the
 // smaller digits and scans the row in place.
-__global__ void __launch_bounds__(RS_THREADS) k_radix_dtot(const uint32_t *hist, int num_tiles, uint32_t *dtot) {
+__global__ void __launch_bounds__(RS_THREADS) k_radix_dtot(const uint32_t *hist, int num_tiles, uint32_t *dtot,
+                                                           const unsigned long long *skip) {
+    if (skip && *skip) return;
     __shared__ uint64_t tmp[4];
     const int d = blockIdx.x;
     const uint32_t *row = hist + static_cast<int64_t>(d) * num_tiles;
@@ -173,7 +177,9 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_dtot(const uint32_t *hist,
     if (threadIdx.x == 0) dtot[d] = static_cast<uint32_t>(tot);
 }
 
-__global__ void __launch_bounds__(RS_THREADS) k_radix_dscan(uint32_t *hist, int num_tiles, const uint32_t *dtot) {
+__global__ void __launch_bounds__(RS_THREADS) k_radix_dscan(uint32_t *hist, int num_tiles, const uint32_t *dtot,
+                                                            const unsigned long long *skip) {
+    if (skip && *skip) return;
     __shared__ uint64_t tmp[4];
     const int d = blockIdx.x, t = threadIdx.x;
     // offset of digit d: the totals of the digits below it (thread t holds digit t)
@@ -198,7 +204,9 @@ template <bool HAS_VALS>
 __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *kin, const uint32_t *vin,
                                                               uint64_t *kout, uint32_t *vout, int64_t n_cap,
                                                               const int64_t *d_n, int shift,
-                                                              const uint32_t *hist_off, int num_tiles) {
+                                                              const uint32_t *hist_off, int num_tiles,
+                                                              const unsigned long long *skip) {
+    if (skip && *skip) return;
     __shared__ uint32_t wcnt[RS_WAVES][RADIX];
     __shared__ uint32_t tile_start[RADIX];
     __shared__ uint32_t gbase[RADIX];
@@ -324,26 +332,30 @@ int64_t radix_hist_entries(int64_t n_cap) {
 }
 
 cg_status radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], int64_t n_cap, const int64_t *d_n, int bit_lo,
-                         int bit_hi, uint32_t *hist, uint64_t *tile_sums, int *which, hipStream_t s) {
+                         int bit_hi, uint32_t *hist, uint64_t *tile_sums, int *which, hipStream_t s,
+                         const unsigned long long *skip, int skip_below) {
     const int num_tiles = static_cast<int>(blocks_for(n_cap, RS_TILE));
     (void)tile_sums;
     int cur = 0;
     for (int shift = bit_lo; shift < bit_hi; shift += 8) {
+        // passes below skip_below do nothing when *skip is set; skipping an even
+        // number of leading passes leaves the data where the host expects it
+        const unsigned long long *sk = shift < skip_below ? skip : nullptr;
         hipLaunchKernelGGL(k_radix_hist, dim3(num_tiles), dim3(RS_THREADS), 0, s, keys[cur], n_cap, d_n, shift,
-                           hist, num_tiles);
+                           hist, num_tiles, sk);
         CG_LAUNCHED("radix_hist");
         uint32_t *dtot = hist + static_cast<int64_t>(RADIX) * num_tiles;  // digit totals after the rows
-        hipLaunchKernelGGL(k_radix_dtot, dim3(RADIX), dim3(RS_THREADS), 0, s, hist, num_tiles, dtot);
+        hipLaunchKernelGGL(k_radix_dtot, dim3(RADIX), dim3(RS_THREADS), 0, s, hist, num_tiles, dtot, sk);
         CG_LAUNCHED("radix_dtot");
-        hipLaunchKernelGGL(k_radix_dscan, dim3(RADIX), dim3(RS_THREADS), 0, s, hist, num_tiles, dtot);
+        hipLaunchKernelGGL(k_radix_dscan, dim3(RADIX), dim3(RS_THREADS), 0, s, hist, num_tiles, dtot, sk);
         CG_LAUNCHED("radix_dscan");
         if (vals) {
             hipLaunchKernelGGL((k_radix_scatter<true>), dim3(num_tiles), dim3(RS_THREADS), 0, s, keys[cur],
-                               vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_cap, d_n, shift, hist, num_tiles);
+                               vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_cap, d_n, shift, hist, num_tiles, sk);
         } else {
             hipLaunchKernelGGL((k_radix_scatter<false>), dim3(num_tiles), dim3(RS_THREADS), 0, s, keys[cur],
                                static_cast<const uint32_t *>(nullptr), keys[cur ^ 1], static_cast<uint32_t *>(nullptr),
-                               n_cap, d_n, shift, hist, num_tiles);
+                               n_cap, d_n, shift, hist, num_tiles, sk);
         }
         CG_LAUNCHED("radix_scatter");
         cur ^= 1;
