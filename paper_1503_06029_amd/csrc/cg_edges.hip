@@ -168,21 +168,19 @@ constexpr int P_STASH = 4 * PT;      // P edges kept per cell tile
 constexpr uint32_t BIG = 0x80000000u;
 constexpr int SUP = 64;              // tiles per super-tile
 
-// Output offset of a cell tile: the totals of all super-tiles before it plus
-// those of the tiles before it in its own super-tile (tile totals are final
-// once the P kernels ran; every tile also added its total to its
-// super-tile's).  Block-wide over 256 threads, contains barriers.
+// Output offset of a cell tile: the exclusive prefix of the super-tile
+// totals (k_sup_scan) at its super-tile plus the totals of the tiles before
+// it in that super-tile.  Block-wide over 256 threads, contains barriers.
 __device__ __forceinline__ uint64_t tile_offset(int64_t tile, const uint64_t *__restrict__ tile_tot,
-                                                const uint64_t *__restrict__ sup_tot, uint64_t *tmp) {
+                                                const uint64_t *__restrict__ sup_pre, uint64_t *tmp) {
     const int64_t sidx = tile / SUP;
-    uint64_t part = 0;
-    for (int64_t k = threadIdx.x; k < sidx; k += blockDim.x) part += sup_tot[k];
     const int64_t k2 = sidx * SUP + threadIdx.x;
-    if (static_cast<int>(threadIdx.x) < SUP && k2 < tile) part += tile_tot[k2];
+    const uint64_t part = (static_cast<int>(threadIdx.x) < SUP && k2 < tile) ? tile_tot[k2] : 0;
     uint64_t tot;
     block256_excl_scan_u64(part, tmp, &tot);
-    return tot;
+    return sup_pre[sidx] + tot;
 }
+
 
 
 __global__ void k_edges_init(uint32_t *cntS, int64_t ncap, int64_t *d_nedges, int64_t *offsets, int32_t *status,
@@ -240,7 +238,18 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * SC;
     if (c0 >= n) return;
     // the write pass only redoes blocks whose edges overflowed the stash
-    if (WRITE && sstash_n[blockIdx.x] <= static_cast<uint32_t>(S_STASH)) return;
+    if (WRITE) {
+        const uint32_t m = sstash_n[blockIdx.x];
+        if (m <= static_cast<uint32_t>(S_STASH)) {  // the stash holds this block's edges: drop them into place
+            const uint4 *src = sstash + static_cast<int64_t>(blockIdx.x) * S_STASH;
+            for (uint32_t f = threadIdx.x; f < m; f += PT) {
+                const uint4 e = src[f];
+                const int64_t next = offsets ? offsets[static_cast<int64_t>(e.x) + 1] : offnext[e.x];
+                emit(uv, bit, cap, next - cntS[e.x] + (e.z >> 16), e.x, e.y, static_cast<int>(e.z & 0xffffu));
+            }
+            return;
+        }
+    }
     const int cl = static_cast<int>(n - c0 < SC ? n - c0 : SC);
     const bool hasnx = c0 + cl < n;  // hs[cl] holds the next position's hash
     const int t = threadIdx.x;
@@ -420,31 +429,26 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
     }
 }
 
-// Drops each block's stashed S edges into their slots: next(u) - cntS[u] + rank.
-__global__ void __launch_bounds__(256) k_s_place(const int64_t *d_n, int64_t ncap, const uint4 *__restrict__ sstash,
-                                                 const uint32_t *__restrict__ sstash_n,
-                                                 const uint32_t *__restrict__ cntS,
-                                                 const int64_t *__restrict__ offsets,
-                                                 const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
-                                                 uint16_t *__restrict__ bit, int64_t cap) {
-    const int64_t n = load_n(d_n, ncap);
-    if (static_cast<int64_t>(blockIdx.x) * SC >= n) return;
-    const uint32_t m = sstash_n[blockIdx.x];
-    if (m > static_cast<uint32_t>(S_STASH)) return;  // the write pass redoes this block
-    const uint4 *src = sstash + static_cast<int64_t>(blockIdx.x) * S_STASH;
-    for (uint32_t f = threadIdx.x; f < m; f += blockDim.x) {
-        const uint4 e = src[f];
-        const int64_t next = offsets ? offsets[static_cast<int64_t>(e.x) + 1] : offnext[e.x];
-        emit(uv, bit, cap, next - cntS[e.x] + (e.z >> 16), e.x, e.y, static_cast<int>(e.z & 0xffffu));
-    }
-}
-
 // Cells whose group (P) or run (S) is too long to scan are listed by the
 // scanning kernels and handled here, one wave per cell, lanes over the bits
 // (wave_flip_lookups): MODE 0 counts S-neighbours (k < s) into cntS, MODE 1
 // counts P-neighbours (k >= s) into cntP (flagged BIG) and the cell's tile
 // total, MODE 2 and 3 write the S and P edges at their slots.
 enum { BIG_S_COUNT = 0, BIG_P_COUNT = 1, BIG_S_WRITE = 2, BIG_P_WRITE = 3 };
+
+// One block: exclusive prefix of the super-tile totals, in place.
+__global__ void __launch_bounds__(256) k_sup_scan(uint64_t *sup_tot, int64_t nsup) {
+    __shared__ uint64_t tmp[4];
+    uint64_t carry = 0;
+    for (int64_t k0 = 0; k0 < nsup; k0 += 256) {
+        const int64_t k = k0 + threadIdx.x;
+        const uint64_t x = k < nsup ? sup_tot[k] : 0;
+        uint64_t tot;
+        const uint64_t ex = block256_excl_scan_u64(x, tmp, &tot);
+        if (k < nsup) sup_tot[k] = carry + ex;
+        carry += tot;
+    }
+}
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256) k_big_lookup(const T *__restrict__ cells, const uint32_t *__restrict__ dir,
@@ -964,32 +968,38 @@ __global__ void __launch_bounds__(PT) k_p_fix(const T *__restrict__ cells, const
     __shared__ uint64_t tmp[4];
     __shared__ int s_th;
     const int64_t n = load_n(d_n, ncap);
-    const int64_t tile = blockIdx.x;
-    const int64_t base = tile * PT;
-    if (base >= n || stash_n[tile] <= static_cast<uint32_t>(P_STASH)) return;
+    const int64_t ntiles = (n + PT - 1) / PT;
     using L = PTile<T, WT>;
     T *rows = reinterpret_cast<T *>(smem);
     uint32_t *pcs = reinterpret_cast<uint32_t *>(smem + L::rows_bytes);
     uint32_t *nbl = pcs + PROWS;
     uint8_t *heads = reinterpret_cast<uint8_t *>(nbl + PT * NB);
-    int th;
-    const int tr = load_ptile<T, WT>(rows, pcs, heads, &s_th, cells, words, s, base, n, &th);
     const int t = threadIdx.x;
-    const int64_t i = base + t;
-    uint32_t cp = 0, cs = 0;
-    if (t < tr) {
-        cp = cntP[i];
-        cs = cntS[i];
+    // a few blocks walk the tiles; only overflowed ones have work
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        if (stash_n[tile] <= static_cast<uint32_t>(P_STASH)) continue;  // uniform over the block
+        const int64_t base = tile * PT;
+        int th;
+        const int tr = load_ptile<T, WT>(rows, pcs, heads, &s_th, cells, words, s, base, n, &th);
+        const int64_t i = base + t;
+        uint32_t cp = 0, cs = 0;
+        if (t < tr) {
+            cp = cntP[i];
+            cs = cntS[i];
+        }
+        uint64_t tot;
+        const uint64_t exa = block256_excl_scan_u64(static_cast<uint64_t>(cp & ~BIG) + cs, tmp, &tot);
+        const uint64_t t_off = tile_offset(tile, tile_tot, sup_tot, tmp);
+        if (t < tr && !(cp & BIG) && cp != 0) {
+            const int64_t out0 = static_cast<int64_t>(t_off + exa);
+            p_scan_t<T, WT>(rows, pcs, heads, tr + th, t, i, base, n, cells, words, s, gmax,
+                            [&](uint32_t d, int k, uint32_t r) {
+                                emit(uv, bit, cap, out0 + r, static_cast<uint32_t>(i), static_cast<uint32_t>(i + d),
+                                     k);
+                            });
+        }
+        __syncthreads();  // LDS is reloaded for the next tile
     }
-    uint64_t tot;
-    const uint64_t exa = block256_excl_scan_u64(static_cast<uint64_t>(cp & ~BIG) + cs, tmp, &tot);
-    const uint64_t t_off = tile_offset(tile, tile_tot, sup_tot, tmp);  // block-wide: before any thread leaves
-    if (t >= tr || (cp & BIG) || cp == 0) return;
-    const int64_t out0 = static_cast<int64_t>(t_off + exa);
-    p_scan_t<T, WT>(rows, pcs, heads, tr + th, t, i, base, n, cells, words, s, gmax,
-                    [&](uint32_t d, int k, uint32_t r) {
-                        emit(uv, bit, cap, out0 + r, static_cast<uint32_t>(i), static_cast<uint32_t>(i + d), k);
-                    });
 }
 
 struct EdgesWs {
@@ -1067,7 +1077,7 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
     const int64_t ntiles = (ncap + PT - 1) / PT;
     const dim3 grid(static_cast<unsigned>(ntiles));
     const dim3 sgrid(static_cast<unsigned>((ncap + SC - 1) / SC));
-    const dim3 bgrid(blocks_for(ncap, 4, 512));  // one wave per listed cell
+    const dim3 bgrid(blocks_for(ncap, 4, 256));  // one wave per listed cell
     const size_t lds = PTile<T, WT>::bytes;
     const size_t lds_find = PFind<T, WT>::bytes;
     const int rmax = gmax < SRMAX ? gmax : SRMAX;
@@ -1087,6 +1097,8 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
     CG_LAUNCHED("edges_p_find");
     hipLaunchKernelGGL((k_big_lookup<T, BIG_P_COUNT>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
                        w.p_big, w.big_n + 1, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, no_off, no_off, uv, bit, cap);
+    hipLaunchKernelGGL(k_sup_scan, dim3(1), dim3(256), 0, s, w.sup_tot, w.nsup);
+    CG_LAUNCHED("edges_sup_scan");
     CG_LAUNCHED("edges_p_big_count");
     hipLaunchKernelGGL((k_p_place<T>), grid, dim3(PT), 0, s, d.d_ncells, ncap, w.cntS, w.cntP, w.p_stash,
                        w.p_stash_n, w.tile_tot, w.sup_tot, d_offsets, offnext, uv, bit, cap, d_nedges, d_status);
@@ -1095,16 +1107,14 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
                        w.p_big, w.big_n + 1, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, d_offsets, offnext, uv, bit, cap);
     CG_LAUNCHED("edges_p_big_write");
     const int gm = gmax < PSCAN ? gmax : PSCAN;  // same scan limit as k_p_find
-    hipLaunchKernelGGL((k_p_fix<T, WT>), grid, dim3(PT), lds, s, cells, d.d_ncells, ncap, words, sp, gm, w.cntS,
+    hipLaunchKernelGGL((k_p_fix<T, WT>), dim3(blocks_for(ntiles, 1, 512)), dim3(PT), lds, s, cells, d.d_ncells, ncap,
+                       words, sp, gm, w.cntS,
                        w.cntP, w.p_stash_n, w.tile_tot, w.sup_tot, uv, bit, cap);
     CG_LAUNCHED("edges_p_fix");
     if (sp > 0) {
-        hipLaunchKernelGGL(k_s_place, sgrid, dim3(256), 0, s, d.d_ncells, ncap, w.s_stash, w.s_stash_n, w.cntS,
-                           d_offsets, offnext, uv, bit, cap);
-        CG_LAUNCHED("edges_s_place");
         hipLaunchKernelGGL((k_s_scan<T, true>), sgrid, dim3(PT), 0, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
                            rmax, w.cntS, d_offsets, offnext, uv, bit, cap, w.s_big, w.big_n, w.s_stash, w.s_stash_n);
-        CG_LAUNCHED("edges_s_write");
+        CG_LAUNCHED("edges_s_write_place");
         hipLaunchKernelGGL((k_big_lookup<T, BIG_S_WRITE>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
                            w.s_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, d_offsets, offnext, uv, bit, cap);
         CG_LAUNCHED("edges_s_big_write");
@@ -1170,7 +1180,7 @@ cg_status edges_generic(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t c
     if (sp > 0) {
         hipLaunchKernelGGL((k_s_pass<T, true>), dim3(grid), dim3(256), 0, s, cells, d.sfx, d.d_ncells, ncap, words,
                            sp, gmax, w.cntS, w.cntP, offsets, uv, bit, cap);
-        CG_LAUNCHED("edges_s_write");
+        CG_LAUNCHED("edges_s_write_place");
     }
     return CG_OK;
 }
