@@ -211,10 +211,10 @@ __global__ void k_edges_init(uint32_t *cntS, int64_t ncap, int64_t *d_nedges, in
 // followed by more than rmax members looks up u xor e_k for every k < s
 // instead.  The count pass writes cntS[u]; the write pass redoes the checks
 // and emits at next(u) - cntS[u] + rank.
-constexpr int SC = 4 * PT;  // suffix-order positions per block
+constexpr int SC = PT;      // suffix-order positions per block
 constexpr int SRMAX = 64;   // most later run members scanned; more use look-ups
-constexpr int SG = 16;      // lanes per pair check
-constexpr int S_STASH = 512;  // S edges kept per block of the suffix order
+constexpr int SG = 16;      // most lanes per pair check (fewer for short rows)
+constexpr int S_STASH = 256;  // S edges kept per block of the suffix order
 
 template <typename T, bool WRITE>
 __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, const uint64_t *__restrict__ sfx,
@@ -332,8 +332,10 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
     if (t == 0) pofs[nst] = npairs;
     __syncthreads();
 
-    // pair checks: group g of SG lanes takes pairs g, g + PT / SG, ...
-    const int lg = t % SG, g = t / SG;
+    // pair checks: group g of sg lanes takes pairs g, g + PT / sg, ... where sg
+    // is the smallest power of two >= words, at most SG (the same for every lane)
+    const int sg = words <= 2 ? 2 : (words <= 4 ? 4 : (words <= 8 ? 8 : SG));
+    const int lg = t % sg, g = t / sg, ng = PT / sg;
     auto check_pair = [&](uint32_t pidx, int *li_out, int *j_out, uint32_t *u_out, uint32_t *v_out, int *pos_out) {
         int lo = 0, hi = nst;  // last starter with pofs <= pidx
         while (hi - lo > 1) {
@@ -347,13 +349,12 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
         const T *a = cells + static_cast<int64_t>(u) * words;
         const T *b = cells + static_cast<int64_t>(v) * words;
         int d = 0, first = 0x7fffffff;
-        for (int w = lg; w < words; w += SG) {
+        for (int w = lg; w < words; w += sg) {
             const T x = a[w] ^ b[w];
             d += popc<T>(x);
             first = (x && first == 0x7fffffff) ? w * B + clz_t<T>(x) : first;
         }
-#pragma unroll
-        for (int m = SG / 2; m > 0; m >>= 1) {
+        for (int m = sg / 2; m > 0; m >>= 1) {
             d += __shfl_xor(d, m, 64);
             const int o = __shfl_xor(first, m, 64);
             first = o < first ? o : first;
@@ -365,9 +366,9 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
         *pos_out = first;
         return d;
     };
-    for (uint32_t p0 = 0; p0 < npairs; p0 += PT / SG) {
+    for (uint32_t p0 = 0; p0 < npairs; p0 += ng) {
         const uint32_t pidx = p0 + g;
-        if (pidx < npairs) {  // uniform across the SG lanes of a group
+        if (pidx < npairs) {  // uniform across the sg lanes of a group
             int li, j, pos;
             uint32_t u, v;
             const int d = check_pair(pidx, &li, &j, &u, &v, &pos);
@@ -413,7 +414,7 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
         return;
     }
     // write: found pairs again, at next(u) - cntS[u] + rank
-    for (uint32_t p0 = 0; p0 < npairs; p0 += PT / SG) {
+    for (uint32_t p0 = 0; p0 < npairs; p0 += ng) {
         const uint32_t pidx = p0 + g;
         if (pidx < npairs) {
             int li, j, pos;
