@@ -7,6 +7,19 @@
 
 namespace cg {
 
+cg_status allow_lds(const void *kernel, size_t bytes) {
+    int dev = 0, cap = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return set_error(CG_EHIP, "cannot query the LDS size per block");
+    if (bytes > static_cast<size_t>(cap))
+        return set_error(CG_EUNSUPPORTED, "kernel needs %zu bytes of LDS per block, device offers %d", bytes, cap);
+    if (bytes > 65536 &&
+        hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes)) != hipSuccess)
+        return set_error(CG_EHIP, "cannot raise the LDS limit of a kernel to %zu bytes", bytes);
+    return CG_OK;
+}
+
 namespace {
 thread_local char g_err[512] = {0};
 thread_local cg_status g_err_status = CG_OK;

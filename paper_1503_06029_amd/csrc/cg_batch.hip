@@ -40,13 +40,21 @@ __global__ void __launch_bounds__(256) k_batch_pack(const uint8_t *__restrict__ 
                                                     const int32_t *__restrict__ scene_ell,
                                                     const int64_t *__restrict__ scene_rows, int n_scenes,
                                                     int64_t n_rows, int words, uint32_t *__restrict__ out) {
+    __shared__ int s_j0;
     const int64_t total = n_rows * words;
     const bool aligned = (reinterpret_cast<uintptr_t>(bits) & 3) == 0;
-    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
-         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    for (int64_t g0 = static_cast<int64_t>(blockIdx.x) * blockDim.x; g0 < total;
+         g0 += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        // one binary search per block (its first row); each thread walks on from there
+        __syncthreads();
+        if (threadIdx.x == 0) s_j0 = scene_of(scene_rows, n_scenes, g0 / words);
+        __syncthreads();
+        const int64_t g = g0 + threadIdx.x;
+        if (g >= total) continue;
         const int64_t r = g / words;
         const int w = static_cast<int>(g - r * words);
-        const int j = scene_of(scene_rows, n_scenes, r);
+        int j = s_j0;
+        while (j + 1 < n_scenes && scene_rows[j + 1] <= r) ++j;
         uint32_t v;
         if (w == 0) {
             v = (static_cast<uint32_t>(j) << 16) | static_cast<uint32_t>(j);

@@ -21,7 +21,7 @@ namespace {
 
 constexpr uint32_t SENT = 0xFFFFFFFFu;
 constexpr int64_t TILE_LDS = 53248;  // three blocks per CU
-constexpr int LMAX = 4096;          // longest segment sorted in one block's LDS
+constexpr int LMAX = 8192;          // longest segment sorted in one block's LDS (96 KB of it)
 // Rows longer than 64 bits are sorted on their first 64 bits, or on their
 // first 32 when a sample shows those already separate the rows (then the
 // four low radix passes are skipped); equal-key segments are finished by
@@ -432,7 +432,7 @@ __device__ __forceinline__ bool idx_less(const T *rows, int words, int from, uin
 // One block per long segment: bitonic network over its index array, kept in
 // global scratch at [2a, 2a + P), P = next power of two >= len.
 template <typename T>
-__global__ void __launch_bounds__(256) k_tiefix_large(const T *__restrict__ rows, int words, int from64,
+__global__ void __launch_bounds__(1024) k_tiefix_large(const T *__restrict__ rows, int words, int from64,
                                                       const uint2 *__restrict__ list,
                                                       const unsigned long long *__restrict__ counters, uint32_t *vals,
                                                       uint8_t *uniq, uint32_t *scratch) {
@@ -502,8 +502,9 @@ __global__ void __launch_bounds__(1024) k_tiefix_mid(const T *__restrict__ rows,
                                                      const unsigned long long *__restrict__ counters,
                                                      uint32_t *__restrict__ vals, uint8_t *__restrict__ uniq) {
     const int from = counters[2] ? from64 / 2 : from64;  // words covered by the sort key
-    __shared__ uint64_t sk[LMAX];
-    __shared__ uint32_t si[LMAX];
+    extern __shared__ __align__(16) unsigned char smem[];  // LMAX keys, then LMAX indices
+    uint64_t *sk = reinterpret_cast<uint64_t *>(smem);
+    uint32_t *si = reinterpret_cast<uint32_t *>(smem + LMAX * sizeof(uint64_t));
     constexpr int K2 = 64 / Bits<T>::B;  // words covered by the second key
     const int from2 = from + K2;
     const uint32_t count = static_cast<uint32_t>(counters[1]);
@@ -677,10 +678,12 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
                                from, static_cast<int>(smax), vals, w.uniq, w.large_list, w.counters);
             CG_LAUNCHED("dedup_tiefix_tile");
         }
-        hipLaunchKernelGGL((k_tiefix_mid<T>), dim3(1024), dim3(1024), 0, s, rows, words, from, w.large_list,
+        const size_t mid_lds = static_cast<size_t>(LMAX) * (sizeof(uint64_t) + sizeof(uint32_t));
+        CG_TRY(allow_lds(reinterpret_cast<const void *>(&k_tiefix_mid<T>), mid_lds));
+        hipLaunchKernelGGL((k_tiefix_mid<T>), dim3(1024), dim3(1024), mid_lds, s, rows, words, from, w.large_list,
                            w.counters, vals, w.uniq);
         CG_LAUNCHED("dedup_tiefix_mid");
-        hipLaunchKernelGGL((k_tiefix_large<T>), dim3(256), dim3(256), 0, s, rows, words, from, w.large_list,
+        hipLaunchKernelGGL((k_tiefix_large<T>), dim3(256), dim3(1024), 0, s, rows, words, from, w.large_list,
                            w.counters, vals, w.uniq, w.scratch);
         CG_LAUNCHED("dedup_tiefix_large");
     }

@@ -43,6 +43,7 @@ __device__ __forceinline__ uint32_t suffix_hash32(const T *row, int words, int s
 // at most (2^p + 1) / (GAPMIN + 1) + 1 are listed.
 constexpr int DT = 256;
 constexpr int GAPMIN = 64;
+constexpr int64_t GAPHUGE = 65536;  // longer gaps are listed apart and filled by every block
 
 __device__ __forceinline__ void push_gap(uint4 *gaps, unsigned long long *gap_n, int64_t cap, bool want,
                                          int64_t lo, int64_t hi, uint32_t v) {
@@ -63,7 +64,8 @@ template <typename T>
 __global__ void __launch_bounds__(DT) k_dict_scan(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
                                                   int words, int p, int s, uint32_t *__restrict__ dir,
                                                   uint64_t *__restrict__ sfx, bool stage, uint4 *__restrict__ gaps,
-                                                  unsigned long long *gap_n, int64_t gap_cap) {
+                                                  unsigned long long *gap_n, int64_t gap_cap,
+                                                  uint4 *__restrict__ huge, int64_t huge_cap) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t n = load_n(d_n, ncap);
     const int64_t G = int64_t(1) << p;
@@ -106,13 +108,16 @@ __global__ void __launch_bounds__(DT) k_dict_scan(const T *__restrict__ cells, c
     } else {
         for (int64_t g = gp + 1; g <= gi; ++g) dir[g] = static_cast<uint32_t>(i);
     }
-    push_gap(gaps, gap_n, gap_cap, long_gap, gp + 1, gi - 1, static_cast<uint32_t>(i));
+    const bool huge_gap = gi - gp > GAPHUGE;
+    push_gap(gaps, gap_n, gap_cap, long_gap && !huge_gap, gp + 1, gi - 1, static_cast<uint32_t>(i));
+    push_gap(huge, gap_n + 1, huge_cap, huge_gap, gp + 1, gi - 1, static_cast<uint32_t>(i));
     if (i == n - 1) {  // entries gi + 1 .. G point past the end
         if (G - gi > GAPMIN) {
-            const unsigned long long k = atomicAdd(gap_n, 1ull);
-            if (static_cast<int64_t>(k) < gap_cap)
-                gaps[k] = make_uint4(static_cast<uint32_t>(gi + 1), static_cast<uint32_t>(G),
-                                     static_cast<uint32_t>(n), 0u);
+            const bool hg = G - gi > GAPHUGE;
+            const unsigned long long k = atomicAdd(hg ? gap_n + 1 : gap_n, 1ull);
+            if (static_cast<int64_t>(k) < (hg ? huge_cap : gap_cap))
+                (hg ? huge : gaps)[k] = make_uint4(static_cast<uint32_t>(gi + 1), static_cast<uint32_t>(G),
+                                                   static_cast<uint32_t>(n), 0u);
         } else {
             for (int64_t g = gi + 1; g <= G; ++g) dir[g] = static_cast<uint32_t>(n);
         }
@@ -121,14 +126,24 @@ __global__ void __launch_bounds__(DT) k_dict_scan(const T *__restrict__ cells, c
 }
 
 // Fills the listed long gaps: gap (lo, hi, v) sets dir[lo .. hi] = v; one
-// block per gap at a time, threads strided over it.
+// block per ordinary gap, and every block takes its share of each huge one.
 __global__ void __launch_bounds__(256) k_dir_gaps(uint32_t *__restrict__ dir, const uint4 *__restrict__ gaps,
-                                                  const unsigned long long *gap_n, int64_t gap_cap) {
-    int64_t cnt = static_cast<int64_t>(*gap_n);
+                                                  const unsigned long long *gap_n, int64_t gap_cap,
+                                                  const uint4 *__restrict__ huge, int64_t huge_cap) {
+    int64_t cnt = static_cast<int64_t>(gap_n[0]);
     if (cnt > gap_cap) cnt = gap_cap;
     for (int64_t k = blockIdx.x; k < cnt; k += gridDim.x) {
         const uint4 g = gaps[k];
         for (int64_t e = static_cast<int64_t>(g.x) + threadIdx.x; e <= static_cast<int64_t>(g.y); e += blockDim.x)
+            dir[e] = g.z;
+    }
+    int64_t hc = static_cast<int64_t>(gap_n[1]);
+    if (hc > huge_cap) hc = huge_cap;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t k = 0; k < hc; ++k) {
+        const uint4 g = huge[k];
+        for (int64_t e = static_cast<int64_t>(g.x) + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+             e <= static_cast<int64_t>(g.y); e += stride)
             dir[e] = g.z;
     }
 }
@@ -185,8 +200,10 @@ __global__ void __launch_bounds__(256) k_d1_query(const T *__restrict__ cells, c
 struct DictMem {
     uint32_t *dir;
     uint4 *gaps;
-    unsigned long long *gap_n;
+    unsigned long long *gap_n;  // [0]: gaps, [1]: huge gaps
     int64_t gap_cap;
+    uint4 *huge;
+    int64_t huge_cap;
     uint64_t *sfx[2];
     uint32_t *hist;
     uint64_t *tile_sums;
@@ -199,7 +216,9 @@ DictMem carve_dict(void *base, int64_t ncap, const cg_dict_params &p, size_t *by
     m.dir = c.take<uint32_t>((size_t(1) << p.dir_bits) + 1);
     m.gap_cap = (int64_t(1) << p.dir_bits) / (GAPMIN + 1) + 2;
     m.gaps = c.take<uint4>(m.gap_cap);
-    m.gap_n = c.take<unsigned long long>(1);
+    m.gap_n = c.take<unsigned long long>(2);
+    m.huge_cap = (int64_t(1) << p.dir_bits) / (GAPHUGE + 1) + 2;
+    m.huge = c.take<uint4>(m.huge_cap);
     m.sfx[0] = c.take<uint64_t>(n);
     m.sfx[1] = c.take<uint64_t>(n);
     m.hist = c.take<uint32_t>(radix_hist_entries(n));
@@ -246,12 +265,12 @@ template <typename T> static cg_status dict_build_impl(cg_dict &d, hipStream_t s
     const int64_t items = std::max<int64_t>(ncap, G + 1);
     const size_t lds = static_cast<size_t>(DT) * (d.lay.words | 1) * sizeof(T);
     const bool stage = lds <= 65536;
-    CG_TRY(fill_i64(reinterpret_cast<int64_t *>(m.gap_n), 0, 1, s));
+    CG_TRY(fill_i64(reinterpret_cast<int64_t *>(m.gap_n), 0, 2, s));
     hipLaunchKernelGGL((k_dict_scan<T>), dim3(blocks_for(items, DT)), dim3(DT), stage ? lds : 0, s,
                        static_cast<const T *>(d.cells), d.d_ncells, ncap, d.lay.words, d.params.dir_bits,
-                       d.params.split_bit, m.dir, m.sfx[0], stage, m.gaps, m.gap_n, m.gap_cap);
+                       d.params.split_bit, m.dir, m.sfx[0], stage, m.gaps, m.gap_n, m.gap_cap, m.huge, m.huge_cap);
     CG_LAUNCHED("dict_scan");
-    hipLaunchKernelGGL(k_dir_gaps, dim3(256), dim3(256), 0, s, m.dir, m.gaps, m.gap_n, m.gap_cap);
+    hipLaunchKernelGGL(k_dir_gaps, dim3(256), dim3(256), 0, s, m.dir, m.gaps, m.gap_n, m.gap_cap, m.huge, m.huge_cap);
     CG_LAUNCHED("dict_gaps");
     int which = 0;
     if (ncap > 0)

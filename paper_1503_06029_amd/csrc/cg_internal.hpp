@@ -41,6 +41,11 @@ struct Carver {
     size_t bytes() const { return (used + 255) & ~size_t(255); }
 };
 
+// Lets `kernel` be launched with `bytes` of dynamic LDS (above 64 KB the
+// runtime needs the kernel's limit raised first).  Fails with CG_EUNSUPPORTED
+// when the device offers less LDS per block.
+cg_status allow_lds(const void *kernel, size_t bytes);
+
 // ------------------------------------------------------------- lane helpers
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
