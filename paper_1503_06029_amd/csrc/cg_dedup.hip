@@ -6,11 +6,12 @@
 //    value = row index;
 // 2. LSD radix sort of (key, index) over the key bits that can be nonzero;
 // 3. rows with equal keys form segments; when l > 64 each segment of two or
-//    more rows is ordered by the full row: segments of up to `smax` rows in
-//    the LDS of the block whose tile holds their first position (rank sort),
-//    up to LMAX rows by one block each (bitonic network over (next 64 bits,
-//    index) pairs in LDS), longer ones by one block each (bitonic network over
-//    an index array in global memory);
+//    more rows is ordered by the full row: segments of up to 128 rows by the
+//    block whose tile holds their first position (rank sort over row
+//    summaries taken against the segment's first row), up to LMAX rows by one
+//    block each (bitonic network over (next 64 bits, index) pairs in LDS),
+//    longer ones by one block each (bitonic network over an index array in
+//    global memory);
 // 4. a row is a new cell iff it differs from its predecessor; a scan of those
 //    flags gives cell ids, and a gather writes the cells and row_to_cell.
 #include "cg_internal.hpp"
@@ -220,167 +221,243 @@ __global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, 
     }
 }
 
-// Same, with rows zero-padded to WT words in LDS (WT a power of two fixed at
-// compile time): the copy and every comparison are straight-line code.
-template <typename T, int WT, int FROM>
-__device__ __forceinline__ int lex_cmp_t(const T *a, const T *b) {
-    // words before FROM are covered by the sort key
-    int res = 0;
-#pragma unroll
-    for (int w = WT - 1; w >= FROM; --w) {
-        const T x = a[w], y = b[w];
-        res = (x != y) ? (x < y ? -1 : 1) : res;
-    }
-    return res;
-}
+// Segments of 2..WSMAX rows whose first position lies in the block's tile
+// of TT positions, ordered by the full row (WT: row words rounded up to a
+// power of two, fixed at compile time; KB: the sort key's width in bits, 32
+// or 64, and the kernel for the width the probe (counters[2]) did not choose
+// returns at once).  Only the first row of each segment, its head, is kept
+// in LDS; every other row streams in with WT lanes per row, each lane
+// comparing one word with the head's, and a ballot over the lanes gives the
+// words where the row and the head differ.  Each row keeps a two-level
+// summary against its head:
+//   level 1: the first word f1 past the sort key where they differ, as an
+//            order code (f1 if the row is below the head there, 2 WT - f1 if
+//            above, WT if the rows are equal) and the row's word there;
+//   level 2: the same for the next word where they differ, plus a flag set
+//            when they differ in at most two words.
+// Among rows that agree with the head up to some word, the one that leaves
+// it there downwards is the smaller, and of two rows leaving it downwards the
+// one leaving first is the smaller (upwards: the one leaving last), so rows
+// order as their summaries (code1, v1, code2, v2) do.  Equal summaries with
+// both flags set mean equal rows; without, the rows themselves are compared
+// (both differ from the head in three or more words and agree on the first
+// two of them).  A row's rank in its segment (ties broken by position) is
+// its sorted position; it is a duplicate iff an equal row precedes it.
+constexpr int WSMAX = 128;           // longest segment sorted here
+constexpr int WSLOTS = TT + WSMAX;   // window: the tile and the longest segment reaching past it
 
-// KB is the sort key's width in bits (32 or 64); the kernel for the width
-// not chosen by the probe (counters[2]) returns at once.
 template <typename T, int WT, int KB>
-__global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, const uint64_t *__restrict__ keys,
-                                                 int64_t n, int words, int smax, uint32_t *__restrict__ vals,
+__global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, const uint64_t *__restrict__ keys,
+                                                 int64_t n, int words, uint32_t *__restrict__ vals,
                                                  uint8_t *__restrict__ uniq, uint2 *__restrict__ large_list,
                                                  unsigned long long *__restrict__ counters) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int LW = WT + 1;
-    if ((counters[2] != 0) != (KB == 32)) return;
     constexpr int FROM = KB / Bits<T>::B;  // words covered by the sort key
-    const int slots = TT + smax;
-    uint64_t *skeys = reinterpret_cast<uint64_t *>(smem);  // positions b0 - 1 .. b0 + slots - 1
-    T *lrows = reinterpret_cast<T *>(skeys + slots + 1);
-    int32_t *segof = reinterpret_cast<int32_t *>(lrows + static_cast<size_t>(slots) * LW);
-    int32_t *seglen = segof + slots;
-    uint32_t *sval = reinterpret_cast<uint32_t *>(seglen + slots);
+    constexpr int HC = TT / 2;             // heads of 2+ row segments starting in a tile
+    constexpr int NCH = 2 * TT / 64;       // 64-slot chunks of start flags
+    constexpr uint32_t GMASK = (WT >= 32) ? 0xFFFFFFFFu : ((1u << WT) - 1u);
+    constexpr int RPS = TT / WT;           // rows per TT consecutive elements
+    __shared__ uint64_t skeys[WSLOTS + 1];  // positions b0 - 1 .. b0 + WSLOTS - 1
+    __shared__ uint32_t sval[WSLOTS];
+    __shared__ int16_t segof[WSLOTS];       // slot of the row's head, -1 if not sorted here
+    __shared__ int16_t seglen[WSLOTS];
+    __shared__ uint8_t hcof[TT];            // compact head index of a head slot
+    __shared__ uint8_t scode[2 * WSLOTS];   // per row: level-1 code, level-2 code | flag
+    __shared__ T sv[2 * WSLOTS];            // per row: level-1 word, level-2 word
+    __shared__ T heads[HC * WT];
+    __shared__ unsigned long long smask[NCH];
+    __shared__ int wcnt[TT / 64];
+    __shared__ int tail_end;                // one past the last row past the tile sorted here
+    if ((counters[2] != 0) != (KB == 32)) return;
     const int64_t b0 = static_cast<int64_t>(blockIdx.x) * TT;
-    const int t = threadIdx.x;
-    const int64_t wend = (b0 + slots < n) ? b0 + slots : n;
+    const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
+    const int64_t wend = (b0 + WSLOTS < n) ? b0 + WSLOTS : n;
+    const int nw = static_cast<int>(wend - b0);  // slots holding positions
+    if (t == 0) tail_end = TT;
     // keys of the window and the row indices of its positions, loaded together
-    for (int e0 = t; e0 <= slots; e0 += TT * 4) {
+    for (int e0 = t; e0 <= WSLOTS; e0 += TT * 4) {
         uint64_t v[4];
         uint32_t x[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t pos = b0 - 1 + e0 + u * TT;
-            const bool in = e0 + u * TT <= slots && pos >= 0 && pos < wend;
+            const bool in = e0 + u * TT <= WSLOTS && pos >= 0 && pos < wend;
             v[u] = in ? keys[pos] : 0;
             x[u] = (in && pos >= b0) ? vals[pos] : 0u;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = e0 + u * TT;
-            if (e <= slots) skeys[e] = v[u];
-            if (e >= 1 && e <= slots) sval[e - 1] = x[u];
+            if (e <= WSLOTS) skeys[e] = v[u];
+            if (e >= 1 && e <= WSLOTS) sval[e - 1] = x[u];
         }
     }
-    for (int r = t; r < slots; r += TT) segof[r] = -1;
     __syncthreads();
-    const int64_t p = b0 + t;
-    bool large = false;
-    uint2 seg = make_uint2(0u, 0u);
-    if (p < n) {
-        const uint64_t k = skeys[t + 1];
-        if (p == 0 || k != skeys[t]) {
-            int64_t e = p + 1;
-            while (e < wend && skeys[e - b0 + 1] == k) ++e;
-            if (e == wend && e < n) e = run_end(keys, p, n);
-            const int64_t len = e - p;
-            if (len == 1) {
-                uniq[p] = 1;
-            } else if (len <= smax) {
-                for (int r = 0; r < len; ++r) {
-                    segof[t + r] = t;
-                    seglen[t + r] = static_cast<int32_t>(len);
+    // a slot starts a segment if its key differs from the previous position's
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int e = t + k * TT;
+        const bool st = e < nw && (b0 + e == 0 || skeys[e + 1] != skeys[e]);
+        const unsigned long long m = ballot64(st);
+        if (lane == 0) smask[wv + k * (TT / 64)] = m;
+    }
+    __syncthreads();
+    // each slot's segment: its head (the last start at or before it) and its
+    // end (the next start, the end of the input, or open past the window);
+    // summaries start as "equal to the head"
+    bool head = false;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int e = t + k * TT;
+        int16_t so = -1, sl = 0;
+        bool large = false;
+        uint2 seg = make_uint2(0u, 0u);
+        if (e < nw) {
+            int st = -1, en = -1;
+            int c = e >> 6;
+            const unsigned long long upto = (2ull << (e & 63)) - 1ull;  // bits 0 .. e & 63
+            unsigned long long m = smask[c] & upto;
+            for (;;) {
+                if (m) { st = (c << 6) + 63 - __clzll(m); break; }
+                if (--c < 0) break;
+                m = smask[c];
+            }
+            c = e >> 6;
+            m = smask[c] & ~upto;
+            for (;;) {
+                if (m) { en = (c << 6) + __ffsll(m) - 1; break; }
+                if (++c >= NCH) break;
+                m = smask[c];
+            }
+            if (en < 0 && wend == n) en = nw;
+            if (st >= 0 && st < TT) {
+                // open (en < 0) only when the window is full, so longer than WSMAX
+                const int len = en < 0 ? WSMAX + 1 : en - st;
+                if (len == 1) {
+                    uniq[b0 + e] = 1;
+                } else if (len <= WSMAX) {
+                    so = static_cast<int16_t>(st);
+                    sl = static_cast<int16_t>(len);
+                    if (e == st) head = true;
+                } else if (e == st) {
+                    const int64_t p = b0 + st;
+                    const int64_t end = en < 0 ? run_end(keys, p, n) : b0 + en;
+                    large = true;
+                    seg = make_uint2(static_cast<uint32_t>(p), static_cast<uint32_t>(end - p));
                 }
-            } else {
-                large = true;
-                seg = make_uint2(static_cast<uint32_t>(p), static_cast<uint32_t>(len));
             }
         }
+        if (e < WSLOTS) {
+            segof[e] = so;
+            seglen[e] = sl;
+            if (so >= 0) {
+                scode[2 * e] = static_cast<uint8_t>(WT);
+                scode[2 * e + 1] = static_cast<uint8_t>(WT | 0x80);
+                sv[2 * e] = T(0);
+                sv[2 * e + 1] = T(0);
+            }
+        }
+        if (k == 0) {
+            // heads lie in the tile: slot e = t, one wave per 64 slots
+            wave_append<uint2>(large_list, &counters[1], n, large, seg);
+            const unsigned long long hb = ballot64(head);
+            if (lane == 0) wcnt[wv] = __popcll(hb);
+        } else {
+            const unsigned long long tb = ballot64(so >= 0);
+            if (tb && lane == 0) atomicMax(&tail_end, (t - lane) + TT + 64 - __clzll(tb));
+        }
     }
-    wave_append<uint2>(large_list, &counters[1], n, large, seg);
+    const unsigned long long hbits = ballot64(head);  // heads of this wave (slot t, k = 0)
     __syncthreads();
 
-    constexpr int U = 16;
-    const int tot = slots * WT;
-    for (int e0 = t; e0 < tot; e0 += TT * U) {
-        T v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * TT;
-            const int r = e / WT, w = e % WT;
-            v[u] = (e < tot && w < words && segof[r] >= 0) ? rows[static_cast<int64_t>(sval[r]) * words + w] : T(0);
+    // Rows stream in with WT lanes per row: lane w of a row holds word w.
+    const int w = t % WT;
+    const int rsub = t / WT;
+    const int gshift = lane & ~(WT - 1);
+    const uint32_t below_w = (1u << w) - 1u;  // the row's words before w
+    const bool wload = w < words, wcmp = w >= FROM;
+    auto summarize = [&](int r, int a, T x) {
+        const T y = a >= 0 ? heads[hcof[a] * WT + w] : T(0);
+        const bool ne = a >= 0 && wcmp && x != y;
+        const uint32_t gm = static_cast<uint32_t>(ballot64(ne) >> gshift) & GMASK;
+        const int c = __popc(gm & below_w);  // differing words before this one
+        if (ne && c < 2) {
+            const int code = (x < y) ? w : 2 * WT - w;
+            scode[2 * r + c] = static_cast<uint8_t>(code | ((c == 1 && __popc(gm) <= 2) ? 0x80 : 0));
+            sv[2 * r + c] = x;
         }
+    };
+    {
+        constexpr int UT = WT;                  // the tile's TT rows: WT elements per thread
+        constexpr int U = UT < 16 ? UT : 16;    // elements in flight per thread
+        static_assert(UT % U == 0, "tile batches");
+        for (int ub = 0; ub < UT; ub += U) {
+            T x[U];
+            int as[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * TT;
-            if (e < tot) lrows[(e / WT) * LW + (e % WT)] = v[u];
+            for (int u = 0; u < U; ++u) {
+                const int r = (ub + u) * RPS + rsub;
+                const int a = segof[r];
+                as[u] = a;
+                x[u] = (a >= 0 && wload) ? rows[static_cast<int64_t>(sval[r]) * words + w] : T(0);
+            }
+            if (ub == 0) {
+                // head rows into LDS (their loads overlap the first batch's)
+                if (head) {
+                    int hc = __popcll(hbits & lanemask_lt());
+                    for (int q = 0; q < wv; ++q) hc += wcnt[q];
+                    hcof[t] = static_cast<uint8_t>(hc);
+                    const T *src = rows + static_cast<int64_t>(sval[t]) * words;
+#pragma unroll
+                    for (int q = 0; q < WT; ++q) heads[hc * WT + q] = q < words ? src[q] : T(0);
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) summarize((ub + u) * RPS + rsub, as[u], x[u]);
+        }
+        // rows past the tile that belong to segments starting in it
+        const int te = tail_end;
+        for (int r0 = TT; r0 < te; r0 += RPS) {
+            const int r = r0 + rsub;
+            const int a = r < te ? segof[r] : -1;
+            const T x = (a >= 0 && wload) ? rows[static_cast<int64_t>(sval[r]) * words + w] : T(0);
+            summarize(r, a, x);
         }
     }
     __syncthreads();
-    // Summary of each row against its segment's first row a: the first word
-    // f (past the sort key) where they differ (WT if equal), the row's word
-    // there and the first row's word there.  Two rows then compare by their
-    // summaries alone unless they differ from row a first in the same word
-    // with the same value (a tie, settled by comparing the rows).
-    uint8_t *sf = reinterpret_cast<uint8_t *>(sval + slots);
-    // 8-byte aligned offset from the LDS base (offset arithmetic keeps the
-    // pointer in the LDS address space: a round trip through an integer
-    // address would turn every access into a flat memory access)
-    const ptrdiff_t sv_off = ((sf + slots) - reinterpret_cast<uint8_t *>(smem) + 7) & ~ptrdiff_t(7);
-    T *sv = reinterpret_cast<T *>(smem + sv_off);
-    T *shv = sv + slots;
-    for (int r = t; r < slots; r += TT) {
-        const int a = segof[r];
-        if (a < 0) continue;
-        const T *me = lrows + r * LW, *hd = lrows + a * LW;
-        int f = WT;
-        T v = 0, h = 0;
-#pragma unroll
-        for (int w = WT - 1; w >= FROM; --w) {
-            const T x = me[w], y = hd[w];
-            const bool ne = x != y;
-            f = ne ? w : f;
-            v = ne ? x : v;
-            h = ne ? y : h;
-        }
-        sf[r] = static_cast<uint8_t>(f);
-        sv[r] = v;
-        shv[r] = h;
-    }
-    __syncthreads();
-    for (int r = t; r < slots; r += TT) {
+    for (int r = t; r < WSLOTS; r += TT) {
         const int a = segof[r];
         if (a < 0) continue;
         const int len = seglen[r];
-        const int fm = sf[r];
-        const T vm = sv[r], hm = shv[r];
+        const int c1m = scode[2 * r], c2f = scode[2 * r + 1];
+        const int c2m = c2f & 0x7f;
+        const bool fm = (c2f & 0x80) != 0;
+        const T v1m = sv[2 * r], v2m = sv[2 * r + 1];
         int rank = 0;
-        bool dup = false;
-        unsigned long long tie[2] = {0ull, 0ull};  // j - a of tied rows (len <= 128)
+        bool dup = false, anytie = false;
 #pragma unroll 4
         for (int j = a; j < a + len; ++j) {
-            const int fj = sf[j];
-            const T vj = sv[j], hj = shv[j];
-            // compare row j with row r, branch-free; 2 marks a tie
-            const int c_lt = vj < hj ? -1 : 1;   // j leaves the first row first
-            const int c_gt = hm < vm ? -1 : 1;   // r leaves it first
-            const int c_eq = fj == WT ? 0 : (vj != vm ? (vj < vm ? -1 : 1) : 2);
-            const int c = fj < fm ? c_lt : (fj > fm ? c_gt : c_eq);
+            const int c1j = scode[2 * j], c2jf = scode[2 * j + 1];
+            const int c2j = c2jf & 0x7f;
+            const T v1j = sv[2 * j], v2j = sv[2 * j + 1];
+            const bool e1 = c1j == c1m, ev1 = v1j == v1m, e2 = c2j == c2m, ev2 = v2j == v2m;
+            const bool lt = (c1j < c1m) | (e1 & ((v1j < v1m) | (ev1 & ((c2j < c2m) | (e2 & (v2j < v2m))))));
+            const bool eq = e1 & ev1 & e2 & ev2;
+            const bool same = eq & fm & ((c2jf & 0x80) != 0);
             const bool before = j < r;
-            rank += (c == -1 || (c == 0 && before)) ? 1 : 0;
-            dup = dup || (c == 0 && before);
-            const int o = j - a;
-            if (c == 2 && j != r) tie[o >> 6] |= 1ull << (o & 63);
+            rank += (lt | (same & before)) ? 1 : 0;
+            dup = dup | (same & before);
+            anytie = anytie | (eq & !same & (j != r));
         }
-        // ties: compare the rows themselves
-        const T *me = lrows + r * LW;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            unsigned long long m = tie[h];
-            while (m) {
-                const int j = a + h * 64 + __ffsll(m) - 1;
-                m &= m - 1;
-                const int c = lex_cmp_t<T, WT, FROM>(lrows + j * LW, me);
+        if (anytie) {
+            // rows with equal summaries that may differ: compare them in full
+            const T *me = rows + static_cast<int64_t>(sval[r]) * words;
+            for (int j = a; j < a + len; ++j) {
+                const int c2jf = scode[2 * j + 1];
+                const bool eq = scode[2 * j] == c1m && sv[2 * j] == v1m && (c2jf & 0x7f) == c2m &&
+                                sv[2 * j + 1] == v2m;
+                if (!eq || j == r || (fm && (c2jf & 0x80) != 0)) continue;
+                const int c = row_cmp<T>(rows + static_cast<int64_t>(sval[j]) * words, me, words, FROM);
                 rank += (c < 0 || (c == 0 && j < r)) ? 1 : 0;
                 dup = dup || (c == 0 && j < r);
             }
@@ -391,31 +468,15 @@ __global__ void __launch_bounds__(TT) k_tiefix_t(const T *__restrict__ rows, con
 }
 
 template <typename T, int WT>
-size_t tiefix_t_lds(int smax) {
-    const size_t slots = static_cast<size_t>(TT + smax);
-    return (slots + 1) * 8 + slots * ((WT + 1) * sizeof(T) + 12) + slots + 8 + 2 * slots * sizeof(T);
-}
-
-template <typename T, int WT>
-int tiefix_t_smax() {
-    const int64_t per = (WT + 3) * static_cast<int64_t>(sizeof(T)) + 21;
-    int64_t smax = (TILE_LDS - 16) / per - TT - 1;
-    if (smax > 128) smax = 128;  // the rank loop's tie masks cover 128 rows
-    return static_cast<int>(smax);
-}
-
-template <typename T, int WT>
-cg_status tiefix_t_launch(const T *rows, const uint64_t *keys, int64_t n, int words, uint32_t *vals, uint8_t *uniq,
+cg_status tiefix_w_launch(const T *rows, const uint64_t *keys, int64_t n, int words, uint32_t *vals, uint8_t *uniq,
                           uint2 *large_list, unsigned long long *counters, bool probed, hipStream_t s) {
-    const int smax = tiefix_t_smax<T, WT>();
-    const size_t lds = tiefix_t_lds<T, WT>(smax);
-    hipLaunchKernelGGL((k_tiefix_t<T, WT, 64>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, keys, n, words, smax,
-                       vals, uniq, large_list, counters);
-    CG_LAUNCHED("dedup_tiefix_t");
+    hipLaunchKernelGGL((k_tiefix_w<T, WT, 64>), dim3(blocks_for(n, TT)), dim3(TT), 0, s, rows, keys, n, words, vals,
+                       uniq, large_list, counters);
+    CG_LAUNCHED("dedup_tiefix_w");
     if (probed) {  // the probe may have chosen 32-bit keys
-        hipLaunchKernelGGL((k_tiefix_t<T, WT, 32>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, keys, n, words,
-                           smax, vals, uniq, large_list, counters);
-        CG_LAUNCHED("dedup_tiefix_t32");
+        hipLaunchKernelGGL((k_tiefix_w<T, WT, 32>), dim3(blocks_for(n, TT)), dim3(TT), 0, s, rows, keys, n, words,
+                           vals, uniq, large_list, counters);
+        CG_LAUNCHED("dedup_tiefix_w32");
     }
     return CG_OK;
 }
@@ -664,14 +725,13 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
         }
         int wt = 1;
         while (wt < words) wt <<= 1;
-        const int wcap = sizeof(T) == 8 ? 16 : 32;
-        if (wt <= wcap) {  // every such width leaves room for segments of 80+ rows
+        if (wt <= 32) {  // head rows of up to 32 words fit the summary kernel's LDS
             switch (wt) {
-            case 2: CG_TRY((tiefix_t_launch<T, 2>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
-            case 4: CG_TRY((tiefix_t_launch<T, 4>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
-            case 8: CG_TRY((tiefix_t_launch<T, 8>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
-            case 16: CG_TRY((tiefix_t_launch<T, 16>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
-            default: CG_TRY((tiefix_t_launch<T, 32>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
+            case 2: CG_TRY((tiefix_w_launch<T, 2>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
+            case 4: CG_TRY((tiefix_w_launch<T, 4>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
+            case 8: CG_TRY((tiefix_w_launch<T, 8>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
+            case 16: CG_TRY((tiefix_w_launch<T, 16>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
+            default: CG_TRY((tiefix_w_launch<T, 32>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
             }
         } else {
             hipLaunchKernelGGL((k_tiefix_tile<T>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, keys, n, words,
