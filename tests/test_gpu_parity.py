@@ -398,3 +398,57 @@ def test_stash_overflow_past_first_supertile(gpu):
         res = P.cell_graph(R, ell, wb, params=B.cg_dict_params_default(split_bit=0, group_max=1024))
         assert res["nedges"] == ell * 2 ** (ell - 1)
         assert_same(res, oracle_graph(R, ell, wb))
+
+
+def _tie_segments(rng, ell, lens, dup_frac=0.1):
+    """Rows in segments that share their first 64 bits.  The first row of
+    each segment (placed before the rest, so a stable key sort keeps it
+    first) is a base; the others agree with each other on two bit blocks
+    where they differ from the base and differ among themselves in a third
+    block further on, so they are ordered only by a full-row comparison.
+    Every fourth segment uses one-bit flips of the base instead."""
+    bases, rest = [], []
+    for s, L in enumerate(lens):
+        base = rng.integers(0, 2, ell).astype(np.uint8)
+        bases.append(base)
+        if s % 4 == 3:
+            for k in rng.choice(np.arange(64, ell), size=min(L - 1, ell - 64), replace=False):
+                r = base.copy()
+                r[k] ^= 1
+                rest.append(r)
+            continue
+        a = rng.integers(0, 2, 10).astype(np.uint8)
+        b = rng.integers(0, 2, 10).astype(np.uint8)
+        for _ in range(L - 1):
+            r = base.copy()
+            r[100:110] = 1 - base[100:110]
+            r[100:110] |= a
+            r[300:310] = 1 - base[300:310]
+            r[300:310] |= b
+            o = int(rng.integers(400, ell - 16))
+            r[o:o + 16] = rng.integers(0, 2, 16)
+            rest.append(r)
+    rest = np.array(rest)
+    rest = rest[rng.permutation(len(rest))]
+    nd = int(dup_frac * len(rest))
+    dups = rest[rng.integers(0, len(rest), nd)]
+    return np.concatenate([np.array(bases), rest, dups])
+
+
+@pytest.mark.parametrize("ell", [600, 2048])
+def test_dedup_full_row_ties(gpu, ell):
+    """Equal-key segments of 1..300 rows whose order needs full-row
+    comparisons, across tile boundaries and around the longest segment the
+    summary kernel sorts (128 rows)."""
+    torch, B, P = gpu
+    rng = np.random.default_rng(ell)
+    lens = [1, 2, 3, 17, 64, 127, 128, 129, 300, 2, 5, 128, 40, 1, 129, 77] * 3
+    R = _tie_segments(rng, ell, lens)
+    for wb in (32, 64):
+        say("full-row ties", ell, wb, R.shape)
+        rows = oracle.pack(R, wb)
+        cells, r2c = oracle.dedup(rows, ell, wb)
+        res = P.cell_graph(R, ell, wb)
+        assert res["ncells"] == cells.shape[0]
+        assert np.array_equal(res["cells"], cells)
+        assert np.array_equal(res["row_to_cell"], r2c)
