@@ -160,52 +160,37 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint64_t *keys,
     hist[static_cast<int64_t>(t) * num_tiles + blockIdx.x] = h[t];
 }
 
-// Column scan of the digit-major tile histograms hist[d * num_tiles + tile]
-// into global scatter offsets, in two launches of one block per digit:
-// k_radix_dtot sums each digit's row; k_radix_dscan adds the totals of the
-// smaller digits and scans the row in place.
-__global__ void __launch_bounds__(RS_THREADS) k_radix_dtot(const uint32_t *hist, int num_tiles, uint32_t *dtot,
-                                                           const unsigned long long *skip) {
-    if (skip && *skip) return;
-    __shared__ uint64_t tmp[4];
-    const int d = blockIdx.x;
-    const uint32_t *row = hist + static_cast<int64_t>(d) * num_tiles;
-    uint64_t part = 0;
-    for (int k = threadIdx.x; k < num_tiles; k += RS_THREADS) part += row[k];
-    uint64_t tot;
-    block256_excl_scan_u64(part, tmp, &tot);
-    if (threadIdx.x == 0) dtot[d] = static_cast<uint32_t>(tot);
-}
-
-__global__ void __launch_bounds__(RS_THREADS) k_radix_dscan(uint32_t *hist, int num_tiles, const uint32_t *dtot,
+// Column scan of the digit-major tile histograms hist[d * num_tiles + tile],
+// one block per digit: each row is scanned in place (exclusive, from 0) and
+// its total goes to dtot[d]; the scatter adds the totals of the smaller
+// digits.
+__global__ void __launch_bounds__(RS_THREADS) k_radix_dscan(uint32_t *hist, int num_tiles, uint32_t *dtot,
                                                             const unsigned long long *skip) {
     if (skip && *skip) return;
     __shared__ uint64_t tmp[4];
     const int d = blockIdx.x, t = threadIdx.x;
-    // offset of digit d: the totals of the digits below it (thread t holds digit t)
-    uint64_t dbase;
-    block256_excl_scan_u64(t < d ? dtot[t] : 0u, tmp, &dbase);
-    // row scan: thread t owns a contiguous chunk of the row
+    // thread t owns a contiguous chunk of the row
     uint32_t *row = hist + static_cast<int64_t>(d) * num_tiles;
     const int per = (num_tiles + RS_THREADS - 1) / RS_THREADS;
     const int a = t * per, b = a + per < num_tiles ? a + per : num_tiles;
     uint64_t sum = 0;
     for (int k = a; k < b; ++k) sum += row[k];
     uint64_t tot;
-    uint64_t run = dbase + block256_excl_scan_u64(sum, tmp, &tot);
+    uint64_t run = block256_excl_scan_u64(sum, tmp, &tot);
     for (int k = a; k < b; ++k) {
         const uint32_t x = row[k];
         row[k] = static_cast<uint32_t>(run);
         run += x;
     }
+    if (t == 0) dtot[d] = static_cast<uint32_t>(tot);
 }
 
 template <bool HAS_VALS>
 __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *kin, const uint32_t *vin,
                                                               uint64_t *kout, uint32_t *vout, int64_t n_cap,
                                                               const int64_t *d_n, int shift,
-                                                              const uint32_t *hist_off, int num_tiles,
-                                                              const unsigned long long *skip) {
+                                                              const uint32_t *hist_off, const uint32_t *dtot,
+                                                              int num_tiles, const unsigned long long *skip) {
     if (skip && *skip) return;
     __shared__ uint32_t wcnt[RS_WAVES][RADIX];
     __shared__ uint32_t tile_start[RADIX];
@@ -263,7 +248,10 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *ki
         uint64_t tot;
         uint64_t ex = block256_excl_scan_u64(run, tmp, &tot);
         tile_start[t] = static_cast<uint32_t>(ex);
-        gbase[t] = hist_off[static_cast<int64_t>(t) * num_tiles + blockIdx.x];
+        // first output position of digit t: the totals of the smaller digits
+        // plus this digit's count in the tiles before this one
+        const uint64_t dbase = block256_excl_scan_u64(dtot[t], tmp, &tot);
+        gbase[t] = static_cast<uint32_t>(dbase) + hist_off[static_cast<int64_t>(t) * num_tiles + blockIdx.x];
     }
     __syncthreads();
 #pragma unroll
@@ -345,17 +333,15 @@ cg_status radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], int64_t n_cap, co
                            hist, num_tiles, sk);
         CG_LAUNCHED("radix_hist");
         uint32_t *dtot = hist + static_cast<int64_t>(RADIX) * num_tiles;  // digit totals after the rows
-        hipLaunchKernelGGL(k_radix_dtot, dim3(RADIX), dim3(RS_THREADS), 0, s, hist, num_tiles, dtot, sk);
-        CG_LAUNCHED("radix_dtot");
         hipLaunchKernelGGL(k_radix_dscan, dim3(RADIX), dim3(RS_THREADS), 0, s, hist, num_tiles, dtot, sk);
         CG_LAUNCHED("radix_dscan");
         if (vals) {
             hipLaunchKernelGGL((k_radix_scatter<true>), dim3(num_tiles), dim3(RS_THREADS), 0, s, keys[cur],
-                               vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_cap, d_n, shift, hist, num_tiles, sk);
+                               vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_cap, d_n, shift, hist, dtot, num_tiles, sk);
         } else {
             hipLaunchKernelGGL((k_radix_scatter<false>), dim3(num_tiles), dim3(RS_THREADS), 0, s, keys[cur],
                                static_cast<const uint32_t *>(nullptr), keys[cur ^ 1], static_cast<uint32_t *>(nullptr),
-                               n_cap, d_n, shift, hist, num_tiles, sk);
+                               n_cap, d_n, shift, hist, dtot, num_tiles, sk);
         }
         CG_LAUNCHED("radix_scatter");
         cur ^= 1;
