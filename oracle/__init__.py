@@ -9,8 +9,9 @@ Two independent pieces live here:
 
 * ``cg_oracle.c`` -- plain C brute force (pack, sort + unique, all-pairs
   Hamming scan, distance-1 queries, Algorithm 1 distances, the heuristic of
-  Algorithm 2 with the corrected filter, and the level structure of
-  Algorithm 3), loaded through ctypes by the thin wrappers below;
+  Algorithm 2 with the corrected filter, the level structure of
+  Algorithm 3, and adjacency lists and breadth-first search on the cell
+  graph), loaded through ctypes by the thin wrappers below;
 * ``twin.py`` -- a pure numpy / Python restatement used to pin the C oracle.
 
 Each C function names the passage of the paper it follows.  Parity status of
@@ -72,6 +73,10 @@ def lib():
         L.cgo_digits.argtypes = [vp, i32, i32, i32, vp]
         L.cgo_digits.restype = i32
         L.cgo_threads.restype = i32
+        L.cgo_adjacency.argtypes = [i64, i64, vp, vp, vp]
+        L.cgo_adjacency.restype = i32
+        L.cgo_bfs.argtypes = [i64, vp, vp, ctypes.c_uint32, vp, vp]
+        L.cgo_bfs.restype = i64
         _lib = L
     return _lib
 
@@ -229,3 +234,27 @@ def cell_graph(bits_or_rows: np.ndarray, ell: int, word_bits: int = 64, packed: 
     cells, r2c = dedup(rows, ell, word_bits)
     uv, bit, off = edges(cells, word_bits)
     return cells, r2c, uv, bit, off
+
+
+def adjacency(n: int, uv: np.ndarray):
+    """O6: undirected adjacency lists of the edge list: (adj_off (n+1,) int64,
+    adj (2E,) uint32), each cell's neighbours ascending."""
+    uv = np.ascontiguousarray(uv, dtype=np.uint32).reshape(-1, 2)
+    E = uv.shape[0]
+    adj_off = np.zeros(n + 1, dtype=np.int64)
+    adj = np.zeros(max(2 * E, 1), dtype=np.uint32)
+    assert lib().cgo_adjacency(n, E, _p(uv), _p(adj_off), _p(adj)) == 0
+    return adj_off, adj[:2 * E]
+
+
+def bfs(n: int, uv: np.ndarray, source: int):
+    """O6: breadth-first search from `source`: (dist, parent, levels); dist and
+    parent are 0xFFFFFFFF for unreached cells."""
+    adj_off, adj = adjacency(n, uv)
+    dist = np.zeros(n, dtype=np.uint32)
+    parent = np.zeros(n, dtype=np.uint32)
+    if adj.size == 0:
+        adj = np.zeros(1, dtype=np.uint32)
+    far = lib().cgo_bfs(n, _p(adj_off), _p(adj), source, _p(dist), _p(parent))
+    assert far >= 0
+    return dist, parent, int(far)

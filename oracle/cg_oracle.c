@@ -491,3 +491,89 @@ int cgo_digits(const void *row, int ell, int word_bits, int r, int32_t *out)
     for (int i = 0; i < depth; ++i) out[i] = digit_of(row, word_bits, ell, r, i);
     return depth;
 }
+
+/* ---------------------------------------------------------------------- */
+/* O6: search on the cell graph.  Section 2.1: once the cells and their    */
+/* neighbours are known, a graph algorithm finds the route; Section 6: a   */
+/* path in the cell graph is an approximate solution of the motion-        */
+/* planning problem.                                                       */
+/*                                                                         */
+/* cgo_adjacency: the undirected graph of the edge list uv[0..E) (pairs of */
+/* cell ids < n) as adjacency lists: cell u's neighbours are              */
+/* adj[adj_off[u] .. adj_off[u+1]), ascending.  Degrees are counted, each  */
+/* edge is placed in both lists, and each list is sorted.  Returns 0, or   */
+/* -1 on bad arguments.                                                    */
+/* ---------------------------------------------------------------------- */
+static int cmp_u32(const void *a, const void *b)
+{
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return (x > y) - (x < y);
+}
+
+int cgo_adjacency(int64_t n, int64_t E, const uint32_t *uv, int64_t *adj_off, uint32_t *adj)
+{
+    if (n < 0 || E < 0 || !adj_off || (E > 0 && (!uv || !adj))) return -1;
+    for (int64_t u = 0; u <= n; ++u) adj_off[u] = 0;
+    for (int64_t e = 0; e < E; ++e) {
+        if (uv[2 * e] >= (uint64_t)n || uv[2 * e + 1] >= (uint64_t)n) return -1;
+        adj_off[uv[2 * e] + 1] += 1;
+        adj_off[uv[2 * e + 1] + 1] += 1;
+    }
+    for (int64_t u = 0; u < n; ++u) adj_off[u + 1] += adj_off[u];
+    int64_t *fill = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!fill) return -1;
+    for (int64_t u = 0; u < n; ++u) fill[u] = adj_off[u];
+    for (int64_t e = 0; e < E; ++e) {
+        uint32_t a = uv[2 * e], b = uv[2 * e + 1];
+        adj[fill[a]++] = b;
+        adj[fill[b]++] = a;
+    }
+    for (int64_t u = 0; u < n; ++u)
+        qsort(adj + adj_off[u], (size_t)(adj_off[u + 1] - adj_off[u]), sizeof(uint32_t), cmp_u32);
+    free(fill);
+    return 0;
+}
+
+/* cgo_bfs: breadth-first search from `source` over such lists.            */
+/* dist[v] = the fewest edges on a path from the source to v, or           */
+/* 0xFFFFFFFF if there is none (a FIFO queue visits the cells in order of  */
+/* distance).  parent[v] = the smallest neighbour w of v with              */
+/* dist[w] = dist[v] - 1 (the source is its own parent; unreached cells    */
+/* get 0xFFFFFFFF), chosen after the search from that definition.         */
+/* Returns the largest distance, or -1 on bad arguments.                   */
+int64_t cgo_bfs(int64_t n, const int64_t *adj_off, const uint32_t *adj, uint32_t source, uint32_t *dist,
+                uint32_t *parent)
+{
+    const uint32_t NONE = 0xFFFFFFFFu;
+    if (n <= 0 || (int64_t)source >= n || !adj_off || !dist) return -1;
+    uint32_t *queue = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    if (!queue) return -1;
+    for (int64_t v = 0; v < n; ++v) dist[v] = NONE;
+    int64_t head = 0, tail = 0, far = 0;
+    dist[source] = 0;
+    queue[tail++] = source;
+    while (head < tail) {
+        uint32_t u = queue[head++];
+        if ((int64_t)dist[u] > far) far = dist[u];
+        for (int64_t j = adj_off[u]; j < adj_off[u + 1]; ++j) {
+            uint32_t v = adj[j];
+            if (dist[v] == NONE) {
+                dist[v] = dist[u] + 1;
+                queue[tail++] = v;
+            }
+        }
+    }
+    free(queue);
+    if (parent) {
+        for (int64_t v = 0; v < n; ++v) {
+            parent[v] = NONE;
+            if (dist[v] == NONE) continue;
+            if (v == (int64_t)source) { parent[v] = source; continue; }
+            for (int64_t j = adj_off[v]; j < adj_off[v + 1]; ++j) {
+                uint32_t w = adj[j];
+                if (dist[w] + 1 == dist[v] && (parent[v] == NONE || w < parent[v])) parent[v] = w;
+            }
+        }
+    }
+    return far;
+}

@@ -265,3 +265,77 @@ def test_c2_structure_small():
     assert len(uv) == want_E
     deg = np.bincount(uv.reshape(-1), minlength=want_cells)
     assert sorted(np.bincount(deg).nonzero()[0].tolist()) == [1, 15]
+
+
+# ------------------------------------------------- search on the cell graph
+
+def _grid_bits(k):
+    """Cells of k - 1 vertical and k - 1 horizontal lines cutting a square
+    into a k x k grid: cell (i, j) has the thermometer code of i followed by
+    that of j, so the cell graph is the k x k grid graph and the lexicographic
+    rank of cell (i, j) is i * k + j."""
+    rows = []
+    for i in range(k):
+        for j in range(k):
+            rows.append([1 if i > a else 0 for a in range(k - 1)] + [1 if j > b else 0 for b in range(k - 1)])
+    return np.array(rows, dtype=np.uint8)
+
+
+@pytest.mark.parametrize("ell", [1, 4, 9])
+def test_bfs_full_hypercube_closed_form(ell):
+    # all 2^l vectors: cell id = the vector read as an integer (x(0) most
+    # significant); from cell 0 the distance is the popcount, and the
+    # smallest neighbour one step closer clears the highest set bit
+    n = 2 ** ell
+    R = ((np.arange(n)[:, None] >> np.arange(ell - 1, -1, -1)[None, :]) & 1).astype(np.uint8)
+    cells, r2c, uv, bit, off = oracle.cell_graph(R[::-1].copy(), ell, 64)
+    adj_off, adj = oracle.adjacency(n, uv)
+    assert np.all(np.diff(adj_off) == ell)
+    dist, parent, far = oracle.bfs(n, uv, 0)
+    ids = np.arange(n)
+    assert np.array_equal(dist, [bin(i).count("1") for i in ids])
+    want_parent = [0] + [i & ~(1 << (i.bit_length() - 1)) for i in range(1, n)]
+    assert np.array_equal(parent, want_parent)
+    assert far == ell
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 12])
+def test_bfs_grid_arrangement_closed_form(k):
+    R = _grid_bits(k)
+    ell = max(2 * (k - 1), 1)
+    if k == 1:
+        R = np.zeros((1, 1), dtype=np.uint8)
+    cells, r2c, uv, bit, off = oracle.cell_graph(R, ell, 32)
+    n = k * k
+    assert cells.shape[0] == n and len(uv) == 2 * k * (k - 1)
+    adj_off, adj = oracle.adjacency(n, uv)
+    for src in {0, n - 1, (k // 2) * k + k // 3}:
+        si, sj = divmod(src, k)
+        dist, parent, far = oracle.bfs(n, uv, src)
+        for c in range(n):
+            i, j = divmod(c, k)
+            assert dist[c] == abs(i - si) + abs(j - sj)
+            # the grid cells one step closer to the source; the parent is the
+            # one of smallest rank
+            closer = [(i - 1) * k + j] * (i > si) + [(i + 1) * k + j] * (i < si) + \
+                     [i * k + j - 1] * (j > sj) + [i * k + j + 1] * (j < sj)
+            assert parent[c] == (min(closer) if closer else src)
+        assert far == max(abs(i - si) + abs(j - sj) for i in range(k) for j in range(k))
+        # every list ascending and symmetric
+        for u in range(n):
+            lst = adj[adj_off[u]:adj_off[u + 1]]
+            assert np.all(np.diff(lst.astype(np.int64)) > 0)
+            for v in lst:
+                assert u in adj[adj_off[v]:adj_off[v + 1]]
+
+
+def test_bfs_disconnected_and_path():
+    # a path 0-1-...-9 and an isolated pair 10-11; cell 12 alone
+    uv = np.array([[i, i + 1] for i in range(9)] + [[10, 11]], dtype=np.uint32)
+    dist, parent, far = oracle.bfs(13, uv, 4)
+    assert list(dist[:10]) == [abs(i - 4) for i in range(10)]
+    assert list(parent[:10]) == [i + 1 for i in range(4)] + [4] + [i - 1 for i in range(5, 10)]
+    assert np.all(dist[10:] == 0xFFFFFFFF) and np.all(parent[10:] == 0xFFFFFFFF)
+    assert far == 5
+    dist, parent, far = oracle.bfs(13, uv, 12)
+    assert dist[12] == 0 and np.sum(dist != 0xFFFFFFFF) == 1 and far == 0
