@@ -245,6 +245,62 @@ cg_status cg_batch_split(const cg_dict *dict, int32_t n_scenes, const int64_t *d
                          int32_t localize, uint32_t *d_uv, uint16_t *d_bit, uint32_t *d_row_to_cell,
                          const int64_t *d_scene_rows, int64_t n_rows, cg_stream_t stream);
 
+/* ------------------------------------------------------- cell graph search
+ * Section 2.1: once the cells and their neighbours are known, a graph
+ * algorithm finds the route; Section 6: a path in the cell graph is an
+ * approximate solution of the motion-planning problem, and traversing the
+ * graph on the GPU is the next problem.  These calls work on the output of
+ * cg_edges (with d_offsets) for one scene.
+ *
+ * cg_graph_csr: the undirected adjacency of G_X in CSR form.
+ *   d_uv, d_offsets, d_nedges, d_ncells: as written by cg_edges (and the
+ *              dictionary's cell count); nedges_cap = the cap given to it.
+ *   d_adj_off (ncells_cap + 1 int64) <- adj_off[u] = first entry of cell u's
+ *              list, adj_off[*d_ncells] = 2 |E|;
+ *   d_adj     (2 x nedges_cap uint32) <- each cell's neighbours, ascending;
+ *   *d_status (device int32) <- CG_OK, or CG_ECAPACITY if *d_nedges >
+ *              nedges_cap (the edge list was cut short: the lists then hold
+ *              only the edges below the cap).
+ * Workspace: cg_graph_csr_workspace(ncells_cap, nedges_cap, &bytes).
+ * Errors: CG_EINVAL (NULL buffers, capacities out of 0 .. 2^32-1),
+ * CG_EWORKSPACE. */
+cg_status cg_graph_csr_workspace(int64_t ncells_cap, int64_t nedges_cap, size_t *bytes);
+cg_status cg_graph_csr(const uint32_t *d_uv, const int64_t *d_offsets, const int64_t *d_ncells, int64_t ncells_cap,
+                       const int64_t *d_nedges, int64_t nedges_cap, int64_t *d_adj_off, uint32_t *d_adj,
+                       int32_t *d_status, void *d_ws, size_t ws_bytes, cg_stream_t stream);
+
+/* cg_bfs: breadth-first search over a cg_graph_csr adjacency from cell
+ * `source`, one level per launch, max_levels levels per call:
+ *   d_dist   (ncells_cap uint32)           <- hops from the source, or
+ *            0xFFFFFFFF if not reached;
+ *   d_parent (nullable, ncells_cap uint32) <- the smallest neighbour one hop
+ *            closer to the source (the source is its own parent), or
+ *            0xFFFFFFFF; with it, every shortest path is the parent chain;
+ *   *d_levels (nullable, device int32)     <- the largest distance found;
+ *   *d_status (device int32) <- CG_OK when the search is complete,
+ *            CG_ECAPACITY when cells remain on the frontier after
+ *            max_levels levels (cells on that frontier have their distance
+ *            but not yet their parent), CG_EINVAL if source >= *d_ncells.
+ * After CG_ECAPACITY, calling again with resume = 1 and the same buffers and
+ * workspace continues the search; resume = 0 starts a new one.  Levels past
+ * the end of the search cost one empty launch each, so the call never waits
+ * for the device.  The workspace holds the search state between calls.
+ * Workspace: cg_bfs_workspace(ncells_cap, &bytes).
+ * Errors: CG_EINVAL (NULL buffers, max_levels outside 1 .. 65536),
+ * CG_EWORKSPACE. */
+cg_status cg_bfs_workspace(int64_t ncells_cap, size_t *bytes);
+cg_status cg_bfs(const int64_t *d_adj_off, const uint32_t *d_adj, const int64_t *d_ncells, int64_t ncells_cap,
+                 uint32_t source, int32_t max_levels, int32_t resume, uint32_t *d_dist, uint32_t *d_parent,
+                 int32_t *d_levels, int32_t *d_status, void *d_ws, size_t ws_bytes, cg_stream_t stream);
+
+/* cg_bfs_path: after a complete cg_bfs with parents, the shortest path from
+ * the source to `target` by the parent chain: *d_len <- its number of cells
+ * (0 if the target is unreached or out of range), and, if it fits in
+ * path_cap, d_path[0 .. len) <- source .. target.
+ * Errors: CG_EINVAL (NULL buffers, path_cap < 0). */
+cg_status cg_bfs_path(const uint32_t *d_dist, const uint32_t *d_parent, const int64_t *d_ncells, int64_t ncells_cap,
+                      uint32_t target, uint32_t *d_path, int64_t path_cap, int64_t *d_len, cg_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,11 +76,17 @@ _sig("cg_batch_layout", [c_i32, ctypes.POINTER(Layout)])
 _sig("cg_batch_pack", [c_vp, c_vp, c_vp, c_vp, c_i32, c_i64, Layout, c_vp, c_vp])
 _sig("cg_batch_split", [ctypes.POINTER(Dict), c_i32, c_vp, c_vp, c_i64, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
                         c_i64, c_vp])
+_sig("cg_graph_csr_workspace", [c_i64, c_i64, ctypes.POINTER(c_sz)])
+_sig("cg_graph_csr", [c_vp, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
+_sig("cg_bfs_workspace", [c_i64, ctypes.POINTER(c_sz)])
+_sig("cg_bfs", [c_vp, c_vp, c_vp, c_i64, ctypes.c_uint32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
+_sig("cg_bfs_path", [c_vp, c_vp, c_vp, c_i64, ctypes.c_uint32, c_vp, c_i64, c_vp, c_vp])
 
 EXPORTS = ("cg_version", "cg_status_string", "cg_last_error", "cg_make_layout", "cg_pack",
            "cg_dedup_workspace", "cg_dedup", "cg_dict_params_default", "cg_dict_size",
            "cg_dict_build", "cg_neighbors_d1", "cg_edges_workspace", "cg_edges",
-           "cg_batch_layout", "cg_batch_pack", "cg_batch_split")
+           "cg_batch_layout", "cg_batch_pack", "cg_batch_split", "cg_graph_csr_workspace", "cg_graph_csr",
+           "cg_bfs_workspace", "cg_bfs", "cg_bfs_path")
 
 
 def lib():
@@ -201,3 +207,34 @@ def cg_batch_split(d: Dict, n_scenes: int, d_offsets, d_nedges, cap: int, d_cell
     _check(_lib.cg_batch_split(ctypes.byref(d), n_scenes, _ptr(d_offsets), _ptr(d_nedges), cap, _ptr(d_cell_off),
                                _ptr(d_edge_off), 1 if localize else 0, _ptr(d_uv), _ptr(d_bit),
                                _ptr(d_row_to_cell), _ptr(d_scene_rows), n_rows, _stream(stream)))
+
+
+def cg_graph_csr_workspace(ncells_cap: int, nedges_cap: int) -> int:
+    b = c_sz()
+    _check(_lib.cg_graph_csr_workspace(ncells_cap, nedges_cap, ctypes.byref(b)))
+    return b.value
+
+
+def cg_graph_csr(d_uv, d_offsets, d_ncells, ncells_cap: int, d_nedges, nedges_cap: int, d_adj_off, d_adj,
+                 d_status, d_ws, ws_bytes: int, stream=None):
+    _check(_lib.cg_graph_csr(_ptr(d_uv), _ptr(d_offsets), _ptr(d_ncells), ncells_cap, _ptr(d_nedges), nedges_cap,
+                             _ptr(d_adj_off), _ptr(d_adj), _ptr(d_status), _ptr(d_ws), ws_bytes, _stream(stream)))
+
+
+def cg_bfs_workspace(ncells_cap: int) -> int:
+    b = c_sz()
+    _check(_lib.cg_bfs_workspace(ncells_cap, ctypes.byref(b)))
+    return b.value
+
+
+def cg_bfs(d_adj_off, d_adj, d_ncells, ncells_cap: int, source: int, max_levels: int, resume: bool, d_dist,
+           d_parent, d_levels, d_status, d_ws, ws_bytes: int, stream=None):
+    _check(_lib.cg_bfs(_ptr(d_adj_off), _ptr(d_adj), _ptr(d_ncells), ncells_cap, source, max_levels,
+                       1 if resume else 0, _ptr(d_dist), _ptr(d_parent), _ptr(d_levels), _ptr(d_status),
+                       _ptr(d_ws), ws_bytes, _stream(stream)))
+
+
+def cg_bfs_path(d_dist, d_parent, d_ncells, ncells_cap: int, target: int, d_path, path_cap: int, d_len,
+                stream=None):
+    _check(_lib.cg_bfs_path(_ptr(d_dist), _ptr(d_parent), _ptr(d_ncells), ncells_cap, target, _ptr(d_path),
+                            path_cap, _ptr(d_len), _stream(stream)))

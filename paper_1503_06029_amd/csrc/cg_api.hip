@@ -248,4 +248,53 @@ cg_status cg_batch_split(const cg_dict *dict, int32_t n_scenes, const int64_t *d
                            d_row_to_cell, d_scene_rows, n_rows, reinterpret_cast<hipStream_t>(stream));
 }
 
+cg_status cg_graph_csr_workspace(int64_t ncells_cap, int64_t nedges_cap, size_t *bytes) {
+    if (ncells_cap < 0 || ncells_cap >= (int64_t(1) << 32) || nedges_cap < 0 || nedges_cap >= (int64_t(1) << 32))
+        return set_error(CG_EINVAL, "cg_graph_csr_workspace: capacity out of range");
+    if (!bytes) return set_error(CG_EINVAL, "cg_graph_csr_workspace: bytes is NULL");
+    *bytes = csr_workspace_bytes(ncells_cap, nedges_cap);
+    return CG_OK;
+}
+
+cg_status cg_graph_csr(const uint32_t *d_uv, const int64_t *d_offsets, const int64_t *d_ncells, int64_t ncells_cap,
+                       const int64_t *d_nedges, int64_t nedges_cap, int64_t *d_adj_off, uint32_t *d_adj,
+                       int32_t *d_status, void *d_ws, size_t ws_bytes, cg_stream_t stream) {
+    size_t need = 0;
+    CG_TRY(cg_graph_csr_workspace(ncells_cap, nedges_cap, &need));
+    if (!d_offsets || !d_ncells || !d_nedges || !d_adj_off || !d_status)
+        return set_error(CG_EINVAL, "cg_graph_csr: NULL buffer");
+    if (nedges_cap > 0 && (!d_uv || !d_adj)) return set_error(CG_EINVAL, "cg_graph_csr: d_uv / d_adj is NULL");
+    if (!d_ws || ws_bytes < need) return set_error(CG_EWORKSPACE, "cg_graph_csr: workspace %zu < %zu bytes", ws_bytes, need);
+    return run_graph_csr(d_uv, d_offsets, d_ncells, ncells_cap, d_nedges, nedges_cap, d_adj_off, d_adj, d_status, d_ws,
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+cg_status cg_bfs_workspace(int64_t ncells_cap, size_t *bytes) {
+    if (ncells_cap < 0 || ncells_cap >= (int64_t(1) << 32))
+        return set_error(CG_EINVAL, "cg_bfs_workspace: ncells_cap out of range");
+    if (!bytes) return set_error(CG_EINVAL, "cg_bfs_workspace: bytes is NULL");
+    *bytes = bfs_workspace_bytes(ncells_cap);
+    return CG_OK;
+}
+
+cg_status cg_bfs(const int64_t *d_adj_off, const uint32_t *d_adj, const int64_t *d_ncells, int64_t ncells_cap,
+                 uint32_t source, int32_t max_levels, int32_t resume, uint32_t *d_dist, uint32_t *d_parent,
+                 int32_t *d_levels, int32_t *d_status, void *d_ws, size_t ws_bytes, cg_stream_t stream) {
+    size_t need = 0;
+    CG_TRY(cg_bfs_workspace(ncells_cap, &need));
+    if (!d_adj_off || !d_adj || !d_ncells || !d_dist || !d_status) return set_error(CG_EINVAL, "cg_bfs: NULL buffer");
+    if (max_levels < 1 || max_levels > 65536) return set_error(CG_EINVAL, "cg_bfs: max_levels=%d out of 1..65536", max_levels);
+    if (!d_ws || ws_bytes < need) return set_error(CG_EWORKSPACE, "cg_bfs: workspace %zu < %zu bytes", ws_bytes, need);
+    return run_bfs(d_adj_off, d_adj, d_ncells, ncells_cap, source, max_levels, resume, d_dist, d_parent, d_levels,
+                   d_status, d_ws, reinterpret_cast<hipStream_t>(stream));
+}
+
+cg_status cg_bfs_path(const uint32_t *d_dist, const uint32_t *d_parent, const int64_t *d_ncells, int64_t ncells_cap,
+                      uint32_t target, uint32_t *d_path, int64_t path_cap, int64_t *d_len, cg_stream_t stream) {
+    if (!d_dist || !d_parent || !d_ncells || !d_len) return set_error(CG_EINVAL, "cg_bfs_path: NULL buffer");
+    if (path_cap < 0 || (path_cap > 0 && !d_path)) return set_error(CG_EINVAL, "cg_bfs_path: bad path buffer");
+    return run_bfs_path(d_dist, d_parent, d_ncells, ncells_cap, target, d_path, path_cap, d_len,
+                        reinterpret_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

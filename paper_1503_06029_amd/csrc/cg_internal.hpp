@@ -494,4 +494,15 @@ cg_status run_batch_split(const cg_dict &d, int32_t n_scenes, const int64_t *off
                           int64_t cap, int64_t *cell_off, int64_t *edge_off, int32_t localize, uint32_t *uv,
                           uint16_t *bit, uint32_t *r2c, const int64_t *scene_rows, int64_t n_rows, hipStream_t s);
 
+size_t csr_workspace_bytes(int64_t ncap, int64_t ecap);
+cg_status run_graph_csr(const uint32_t *uv, const int64_t *offsets, const int64_t *d_ncells, int64_t ncap,
+                        const int64_t *d_nedges, int64_t ecap, int64_t *adj_off, uint32_t *adj, int32_t *status,
+                        void *ws, hipStream_t s);
+size_t bfs_workspace_bytes(int64_t ncap);
+cg_status run_bfs(const int64_t *adj_off, const uint32_t *adj, const int64_t *d_ncells, int64_t ncap,
+                  uint32_t source, int32_t max_levels, int32_t resume, uint32_t *dist, uint32_t *parent,
+                  int32_t *levels, int32_t *status, void *ws, hipStream_t s);
+cg_status run_bfs_path(const uint32_t *dist, const uint32_t *parent, const int64_t *d_ncells, int64_t ncap,
+                       uint32_t target, uint32_t *path, int64_t path_cap, int64_t *len, hipStream_t s);
+
 }  // namespace cg

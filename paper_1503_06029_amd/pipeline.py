@@ -140,6 +140,78 @@ class CellGraph:
                 _np_words(mask[:nq], self.word_bits))
 
 
+class GraphSearch:
+    """Undirected adjacency (CSR) of a built CellGraph's edges and
+    breadth-first search over it, all in device buffers.  The CellGraph must
+    have been run with offsets and must outlive this object."""
+
+    UNREACHED = 0xFFFFFFFF
+
+    def __init__(self, g: CellGraph):
+        if g.offsets is None:
+            raise ValueError("GraphSearch needs a CellGraph made with offsets")
+        self.g = g
+        dev = g.device
+        self.ncap = g.n
+        self.ecap = g.edge_cap
+        self.adj_off = torch.empty(self.ncap + 1, dtype=torch.int64, device=dev)
+        self.adj = torch.empty(max(2 * self.ecap, 1), dtype=torch.int32, device=dev)
+        self.csr_status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.ws_csr_bytes = B.cg_graph_csr_workspace(self.ncap, self.ecap)
+        self.ws_csr = torch.empty(self.ws_csr_bytes, dtype=torch.uint8, device=dev)
+        self.dist = torch.empty(max(self.ncap, 1), dtype=torch.int32, device=dev)
+        self.parent = torch.empty(max(self.ncap, 1), dtype=torch.int32, device=dev)
+        self.levels = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.ws_bfs_bytes = B.cg_bfs_workspace(self.ncap)
+        self.ws_bfs = torch.empty(self.ws_bfs_bytes, dtype=torch.uint8, device=dev)
+
+    def build(self, stream=None):
+        g = self.g
+        B.cg_graph_csr(g.uv, g.offsets, g.ncells, self.ncap, g.nedges, self.ecap, self.adj_off, self.adj,
+                       self.csr_status, self.ws_csr, self.ws_csr_bytes, stream)
+
+    def bfs(self, source: int, max_levels: int = 64, resume: bool = False, stream=None):
+        """Enqueue max_levels levels of the search (no host wait)."""
+        B.cg_bfs(self.adj_off, self.adj, self.g.ncells, self.ncap, source, max_levels, resume, self.dist,
+                 self.parent, self.levels, self.status, self.ws_bfs, self.ws_bfs_bytes, stream)
+
+    def bfs_complete(self, source: int, chunk: int = 64, stream=None) -> int:
+        """Search until the frontier is empty, checking the status after each
+        chunk of levels; returns the final status."""
+        self.bfs(source, chunk, False, stream)
+        while True:
+            torch.cuda.synchronize()
+            st = int(self.status.item())
+            if st != B.CG_ECAPACITY:
+                return st
+            self.bfs(source, chunk, True, stream)
+
+    def path(self, target: int, stream=None) -> np.ndarray:
+        """Cells of the shortest path source .. target along the parents."""
+        cap = max(int(self.levels.item()) + 1, 1)
+        out = torch.empty(cap, dtype=torch.int32, device=self.g.device)
+        ln = torch.zeros(1, dtype=torch.int64, device=self.g.device)
+        B.cg_bfs_path(self.dist, self.parent, self.g.ncells, self.ncap, target, out, cap, ln, stream)
+        torch.cuda.synchronize()
+        L = int(ln.item())
+        return out[:min(L, cap)].cpu().numpy().view(np.uint32).copy() if L <= cap else None
+
+    def fetch(self):
+        torch.cuda.synchronize()
+        nc = int(self.g.ncells.item())
+        off = self.adj_off[:nc + 1].cpu().numpy()
+        return {
+            "csr_status": int(self.csr_status.item()),
+            "adj_off": off,
+            "adj": self.adj[:int(off[-1]) if nc else 0].cpu().numpy().view(np.uint32),
+            "dist": self.dist[:nc].cpu().numpy().view(np.uint32),
+            "parent": self.parent[:nc].cpu().numpy().view(np.uint32),
+            "levels": int(self.levels.item()),
+            "status": int(self.status.item()),
+        }
+
+
 def to_device_words(rows: np.ndarray, device="cuda") -> torch.Tensor:
     """Host packed rows (uint32 / uint64) -> device tensor of the same bytes."""
     rows = np.ascontiguousarray(rows)
