@@ -124,11 +124,18 @@ __global__ void k_bfs_source(const int64_t *d_n, int64_t ncap, uint32_t source, 
 
 // Level base + step: expand the frontier, claim unreached neighbours with a
 // compare-and-swap on their distance, append the claimed ones (one counter
-// update per wave), and record each expanded cell's parent.
+// update per wave), and record each expanded cell's parent.  A wave takes 64
+// frontier cells and flattens their lists: entry k of the wave's
+// concatenated lists goes to lane k mod 64, which finds the owning cell by
+// binary search over the lists' starts, so every (cell, neighbour) pair of
+// the wave is read in parallel rather than list by list.
 __global__ void __launch_bounds__(ST) k_bfs_level(const int64_t *__restrict__ adj_off, const uint32_t *__restrict__ adj,
                                                   int64_t ncap, uint32_t *__restrict__ dist,
                                                   uint32_t *__restrict__ parent, uint32_t *fa, uint32_t *fb,
                                                   BfsState *st, int step) {
+    __shared__ uint32_t s_start[ST];  // per wave: exclusive scan of the 64 list lengths
+    __shared__ int64_t s_first[ST];   // per wave: each cell's first list entry
+    __shared__ uint32_t s_par[ST];    // per wave: smallest neighbour one level closer
     const int level = st->base + step;
     const unsigned long long cur = st->cnt[level % 3];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -140,27 +147,41 @@ __global__ void __launch_bounds__(ST) k_bfs_level(const int64_t *__restrict__ ad
     uint32_t *out = (level & 1) ? fa : fb;
     unsigned long long *ocnt = &st->cnt[(level + 1) % 3];
     const uint32_t prev = static_cast<uint32_t>(level - 1), next = static_cast<uint32_t>(level + 1);
+    const int lane = lane_id(), wbase = threadIdx.x & ~63;
     for (int64_t b = static_cast<int64_t>(blockIdx.x) * ST; b < static_cast<int64_t>(cur);
          b += static_cast<int64_t>(gridDim.x) * ST) {
         const int64_t f = b + threadIdx.x;
         const bool act = f < static_cast<int64_t>(cur);
         const uint32_t u = act ? in[f] : 0u;
-        int64_t j = act ? adj_off[u] : 0;
-        const int64_t j1 = act ? adj_off[u + 1] : 0;
-        uint32_t par = UNREACHED;
-        // lanes walk their lists in step so the appends stay wave-wide
-        for (; ballot64(j < j1) != 0; ++j) {
+        const int64_t j0 = act ? adj_off[u] : 0;
+        const uint32_t deg = act ? static_cast<uint32_t>(adj_off[u + 1] - j0) : 0u;
+        const uint32_t incl = wave_incl_scan_u32(deg);
+        const uint32_t tot = static_cast<uint32_t>(__shfl(static_cast<int>(incl), 63, 64));
+        s_start[threadIdx.x] = incl - deg;
+        s_first[threadIdx.x] = j0;
+        s_par[threadIdx.x] = UNREACHED;
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t k0 = 0; k0 < tot; k0 += 64) {
+            const uint32_t k = k0 + static_cast<uint32_t>(lane);
             bool claim = false;
             uint32_t v = 0;
-            if (j < j1) {
-                v = adj[j];
+            if (k < tot) {
+                // owner: the last lane whose list starts at or before k
+                int lo = 0, hi = 63;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_start[wbase + mid] <= k) lo = mid; else hi = mid - 1;
+                }
+                v = adj[s_first[wbase + lo] + (k - s_start[wbase + lo])];
                 const uint32_t d = dist[v];
-                if (level > 0 && d == prev && par == UNREACHED) par = v;
+                if (level > 0 && d == prev) atomicMin(&s_par[wbase + lo], v);
                 if (d == UNREACHED) claim = atomicCAS(&dist[v], UNREACHED, next) == UNREACHED;
             }
             wave_append<uint32_t>(out, ocnt, ncap, claim, v);
         }
-        if (act && parent && level > 0) parent[u] = par;
+        __builtin_amdgcn_wave_barrier();
+        if (act && parent && level > 0) parent[u] = s_par[threadIdx.x];
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -287,7 +308,9 @@ cg_status run_bfs(const int64_t *adj_off, const uint32_t *adj, const int64_t *d_
                            status);
         CG_LAUNCHED("bfs_source");
     }
-    const unsigned gb = blocks_for(ncap, ST, 2048);
+    // one block per CU at most: a level's grid-stride loop covers any
+    // frontier, and small frontiers (most levels) waste few empty blocks
+    const unsigned gb = blocks_for(ncap, ST, 256);
     for (int step = 0; step < max_levels; ++step) {
         hipLaunchKernelGGL(k_bfs_level, dim3(gb), dim3(ST), 0, s, adj_off, adj, ncap, dist, parent, w.fa, w.fb, w.st,
                            step);

@@ -187,6 +187,21 @@ class GraphSearch:
                 return st
             self.bfs(source, chunk, True, stream)
 
+    def capture(self, source: int, max_levels: int):
+        """Record build() and a max_levels-level search from `source` into
+        one graph; replay() reruns both without per-launch host work."""
+        self.graph = torch.cuda.CUDAGraph()
+        cap_stream = torch.cuda.Stream()
+        cap_stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(self.graph, stream=cap_stream):
+            self.build()
+            self.bfs(source, max_levels, False)
+        torch.cuda.synchronize()
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()
+
     def path(self, target: int, stream=None) -> np.ndarray:
         """Cells of the shortest path source .. target along the parents."""
         cap = max(int(self.levels.item()) + 1, 1)

@@ -149,3 +149,28 @@ def test_config2_sampled_sources(gpu):
     res = {"ncells": nc, "uv": uv}
     rng = np.random.default_rng(5)
     check_search(torch, B, P, res, g, [int(x) for x in rng.integers(0, nc, 3)])
+
+
+def test_captured_search_replays(gpu):
+    """build() + a full search captured as one graph: every replay (with
+    eager work and synchronisation between them) gives the oracle's result."""
+    torch, B, P = gpu
+    R = inputs.planes_in_cube(np.random.default_rng(31), 32, 30000)
+    res, g = graph_of(P, R, 32, 32)
+    n = res["ncells"]
+    S = P.GraphSearch(g)
+    src = n // 2
+    S.capture(src, 40)
+    dist, parent, far = oracle.bfs(n, res["uv"], src)
+    for rep in range(3):
+        say("replay", rep)
+        S.replay()
+        torch.cuda.synchronize()
+        got = S.fetch()
+        assert got["status"] == B.CG_OK
+        assert np.array_equal(got["dist"], dist)
+        assert np.array_equal(got["parent"], parent)
+        assert got["levels"] == far
+        # eager work in between: a search from another cell on the same buffers
+        S.bfs_complete(0)
+        assert not np.array_equal(S.fetch()["dist"], dist)
