@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-ffp-contract=off",
              "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
@@ -77,6 +77,12 @@ def lib():
         L.cgo_adjacency.restype = i32
         L.cgo_bfs.argtypes = [i64, vp, vp, ctypes.c_uint32, vp, vp]
         L.cgo_bfs.restype = i64
+        L.cgo_philox4x64.argtypes = [vp, vp, vp]
+        L.cgo_philox4x64.restype = None
+        L.cgo_sample_point.argtypes = [i64, ctypes.c_uint64, ctypes.c_uint64, vp, vp]
+        L.cgo_sample_point.restype = None
+        L.cgo_sample_signs.argtypes = [vp, i32, i64, ctypes.c_uint64, ctypes.c_uint64, vp, vp]
+        L.cgo_sample_signs.restype = i32
         _lib = L
     return _lib
 
@@ -258,3 +264,29 @@ def bfs(n: int, uv: np.ndarray, source: int):
     far = lib().cgo_bfs(n, _p(adj_off), _p(adj), source, _p(dist), _p(parent))
     assert far >= 0
     return dist, parent, int(far)
+
+
+def philox4x64(counter, key) -> np.ndarray:
+    """O7: one Philox4x64-10 block (4 x uint64) for a counter (4) and key (2)."""
+    c = np.ascontiguousarray(counter, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().cgo_philox4x64(_p(c), _p(k), _p(out))
+    return out
+
+
+def sample_point(i: int, seed: int, scene: int, lohi) -> np.ndarray:
+    lohi = np.ascontiguousarray(lohi, dtype=np.float64)
+    p = np.zeros(3, dtype=np.float64)
+    lib().cgo_sample_point(i, seed, scene, _p(lohi), _p(p))
+    return p
+
+
+def sample_signs(planes: np.ndarray, n: int, seed: int, scene: int, lohi) -> np.ndarray:
+    """O7: (n, ell) uint8 signs of n sampled points against planes (ell, 4)."""
+    planes = np.ascontiguousarray(planes, dtype=np.float64).reshape(-1, 4)
+    lohi = np.ascontiguousarray(lohi, dtype=np.float64)
+    ell = planes.shape[0]
+    bits = np.zeros((n, ell), dtype=np.uint8)
+    assert lib().cgo_sample_signs(_p(planes), ell, n, seed, scene, _p(lohi), _p(bits)) == 0
+    return bits

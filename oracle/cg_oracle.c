@@ -577,3 +577,73 @@ int64_t cgo_bfs(int64_t n, const int64_t *adj_off, const uint32_t *adj, uint32_t
     }
     return far;
 }
+
+/* ---------------------------------------------------------------------- */
+/* O7: sampled points -> sign vectors (Section 2.1: bit i of v_P is 1 iff  */
+/* the point P satisfies constraint c_i; the paper samples the             */
+/* configuration space, Section 2.1 and Section 5).  Constraints are       */
+/* half-spaces a_i . p >= c_i of R^3; points are uniform in a box.        */
+/*                                                                         */
+/* Random numbers: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel */
+/* random numbers: as easy as 1, 2, 3", SC 2011), written here from its    */
+/* definition: ten rounds, each multiplying words 0 and 2 by the two round */
+/* constants into 128-bit products and recombining the halves with words   */
+/* 1 and 3 and the key, the key advancing by the two Weyl constants        */
+/* between rounds.                                                         */
+/* Float contract (every operation rounded to nearest float64, no fused    */
+/* multiply-add -- this file is compiled with -ffp-contract=off):          */
+/*   x = philox(counter = (i, 0, 0, 0), key = (seed, scene));              */
+/*   u_j = (x_j >> 11) * 2^-53;  p_j = lo_j + (hi_j - lo_j) * u_j;          */
+/*   r_i = ((a_i0 * p0 + a_i1 * p1) + a_i2 * p2) - c_i;  bit i = r_i >= 0.  */
+/* ---------------------------------------------------------------------- */
+void cgo_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        unsigned __int128 p0 = (unsigned __int128)M0 * c0, p1 = (unsigned __int128)M1 * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Point i of stream (seed, scene) in the box lohi = (lo0, lo1, lo2, hi0,  */
+/* hi1, hi2). */
+void cgo_sample_point(int64_t i, uint64_t seed, uint64_t scene, const double lohi[6], double p[3])
+{
+    uint64_t ctr[4] = {(uint64_t)i, 0, 0, 0}, key[2] = {seed, scene}, x[4];
+    cgo_philox4x64(ctr, key, x);
+    for (int j = 0; j < 3; ++j) {
+        double u = (double)(x[j] >> 11) * 0x1.0p-53;
+        double d = lohi[3 + j] - lohi[j];
+        double m = d * u;
+        p[j] = lohi[j] + m;
+    }
+}
+
+/* Sign bytes (n x ell, row-major) of n sampled points against ell planes  */
+/* given as (a0, a1, a2, c) rows.  Returns 0, or -1 on bad arguments.      */
+int cgo_sample_signs(const double *planes, int ell, int64_t n, uint64_t seed, uint64_t scene,
+                     const double lohi[6], uint8_t *bits)
+{
+    if (ell < 1 || n < 0 || !planes || !lohi || (n > 0 && !bits)) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double p[3];
+        cgo_sample_point(i, seed, scene, lohi, p);
+        for (int k = 0; k < ell; ++k) {
+            const double *a = planes + 4 * (int64_t)k;
+            double t0 = a[0] * p[0], t1 = a[1] * p[1], t2 = a[2] * p[2];
+            double s = t0 + t1;
+            s = s + t2;
+            double r = s - a[3];
+            bits[i * ell + k] = r >= 0.0 ? 1 : 0;
+        }
+    }
+    return 0;
+}

@@ -339,3 +339,51 @@ def test_bfs_disconnected_and_path():
     assert far == 5
     dist, parent, far = oracle.bfs(13, uv, 12)
     assert dist[12] == 0 and np.sum(dist != 0xFFFFFFFF) == 1 and far == 0
+
+
+# ------------------------------------------- sampled points -> sign vectors
+
+def test_philox4x64_against_numpy_and_published_answer():
+    # numpy's Philox is Philox4x64-10 and advances the counter before each
+    # block, so its block b is the oracle's counter + b + 1
+    for key in ([0, 0], [123, 456], [2 ** 64 - 1, 2 ** 63 + 5]):
+        for start in (0, 41, 2 ** 40):
+            bg = np.random.Philox(counter=[start, 0, 0, 0], key=key)
+            raw = bg.random_raw(12).astype(np.uint64)
+            for b in range(3):
+                got = oracle.philox4x64([start + b + 1, 0, 0, 0], key)
+                assert np.array_equal(got, raw[4 * b:4 * b + 4]), (key, start, b)
+    # the generator's known answer for counter 0, key 0
+    assert [int(x) for x in oracle.philox4x64([0, 0, 0, 0], [0, 0])] == [
+        0x16554d9eca36314c, 0xdb20fe9d672d0fdc, 0xd7e772cee186176b, 0x7e68b68aec7ba23b]
+
+
+def test_sample_points_from_numpy_stream():
+    lohi = np.array([-1.0, -2.0, 0.5, 1.0, 3.0, 0.75])
+    seed, scene = 99, 7
+    for i in (0, 1, 1000, 2 ** 33):
+        # numpy's counter is one 256-bit number incremented before each block
+        before = [i - 1, 0, 0, 0] if i > 0 else [2 ** 64 - 1] * 4
+        raw = np.random.Philox(counter=before, key=[seed, scene]).random_raw(4)
+        u = (raw[:3] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+        want = lohi[:3] + (lohi[3:] - lohi[:3]) * u
+        p = oracle.sample_point(i, seed, scene, lohi)
+        assert np.array_equal(p, want), i
+        assert np.all(p >= lohi[:3]) and np.all(p < lohi[3:])
+
+
+def test_sample_signs_axis_planes_and_arrangement():
+    lohi = [-1.0, -1.0, -1.0, 1.0, 1.0, 1.0]
+    ts = np.linspace(-0.9, 0.9, 13)
+    planes = np.array([[1.0, 0.0, 0.0, t] for t in ts] + [[0.0, 0.0, 0.0, 0.0], [0.0, 0.0, 0.0, 1e-300],
+                                                          [0.0, -1.0, 0.0, 0.25]])
+    n = 3000
+    bits = oracle.sample_signs(planes, n, 5, 0, lohi)
+    P = np.array([oracle.sample_point(i, 5, 0, lohi) for i in range(n)])
+    for k, t in enumerate(ts):
+        assert np.array_equal(bits[:, k], (P[:, 0] >= t).astype(np.uint8))
+    assert np.all(bits[:, len(ts)] == 1) and np.all(bits[:, len(ts) + 1] == 0)
+    assert np.array_equal(bits[:, -1], (-P[:, 1] >= 0.25).astype(np.uint8))
+    # thirteen parallel planes cut the box into at most 14 slabs
+    cells, r2c = oracle.dedup(oracle.pack(bits[:, :len(ts)], 32), len(ts), 32)
+    assert cells.shape[0] <= len(ts) + 1
