@@ -301,6 +301,26 @@ cg_status cg_bfs(const int64_t *d_adj_off, const uint32_t *d_adj, const int64_t 
 cg_status cg_bfs_path(const uint32_t *d_dist, const uint32_t *d_parent, const int64_t *d_ncells, int64_t ncells_cap,
                       uint32_t target, uint32_t *d_path, int64_t path_cap, int64_t *d_len, cg_stream_t stream);
 
+/* --------------------------------------------------- sampling + packing
+ * The step before the path (Section 2.1: bit i of a sampled point's vector
+ * is 1 iff the point satisfies constraint c_i).  Constraints are the
+ * half-spaces a_i . p >= c_i of R^3, d_planes = lay.ell rows of four
+ * float64 (a_i0, a_i1, a_i2, c_i), device memory.  Point i (0 <= i < n) of
+ * the stream (seed, scene) is uniform in the box lo .. hi, box = host array
+ * (lo0, lo1, lo2, hi0, hi1, hi2), drawn from Philox4x64-10 (Salmon et al.,
+ * SC 2011) with counter (i, 0, 0, 0) and key (seed, scene).  Float
+ * contract, each operation rounded to nearest float64, no fused
+ * multiply-add:
+ *   u_j = (x_j >> 11) * 2^-53 for the block's words x_0, x_1, x_2;
+ *   p_j = lo_j + (hi_j - lo_j) * u_j;
+ *   r_i = ((a_i0 * p0 + a_i1 * p1) + a_i2 * p2) - c_i;  bit i = (r_i >= 0).
+ * Writes n packed rows (layout lay, as cg_pack) to d_packed; no sign bytes
+ * are formed.
+ * Errors: CG_EINVAL (bad layout, n out of 0 .. 2^32-1, NULL pointers, a box
+ * with lo > hi). */
+cg_status cg_sample_pack(const double *d_planes, int64_t n, uint64_t seed, uint64_t scene, const double *box,
+                         cg_layout lay, void *d_packed, cg_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,12 +81,14 @@ _sig("cg_graph_csr", [c_vp, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp, c_
 _sig("cg_bfs_workspace", [c_i64, ctypes.POINTER(c_sz)])
 _sig("cg_bfs", [c_vp, c_vp, c_vp, c_i64, ctypes.c_uint32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
 _sig("cg_bfs_path", [c_vp, c_vp, c_vp, c_i64, ctypes.c_uint32, c_vp, c_i64, c_vp, c_vp])
+_sig("cg_sample_pack", [c_vp, c_i64, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), Layout,
+                        c_vp, c_vp])
 
 EXPORTS = ("cg_version", "cg_status_string", "cg_last_error", "cg_make_layout", "cg_pack",
            "cg_dedup_workspace", "cg_dedup", "cg_dict_params_default", "cg_dict_size",
            "cg_dict_build", "cg_neighbors_d1", "cg_edges_workspace", "cg_edges",
            "cg_batch_layout", "cg_batch_pack", "cg_batch_split", "cg_graph_csr_workspace", "cg_graph_csr",
-           "cg_bfs_workspace", "cg_bfs", "cg_bfs_path")
+           "cg_bfs_workspace", "cg_bfs", "cg_bfs_path", "cg_sample_pack")
 
 
 def lib():
@@ -238,3 +240,9 @@ def cg_bfs_path(d_dist, d_parent, d_ncells, ncells_cap: int, target: int, d_path
                 stream=None):
     _check(_lib.cg_bfs_path(_ptr(d_dist), _ptr(d_parent), _ptr(d_ncells), ncells_cap, target, _ptr(d_path),
                             path_cap, _ptr(d_len), _stream(stream)))
+
+
+def cg_sample_pack(d_planes, n: int, seed: int, scene: int, box, lay: Layout, d_packed, stream=None):
+    """box: (lo0, lo1, lo2, hi0, hi1, hi2) on the host."""
+    b = (ctypes.c_double * 6)(*[float(v) for v in box])
+    _check(_lib.cg_sample_pack(_ptr(d_planes), n, seed, scene, b, lay, _ptr(d_packed), _stream(stream)))

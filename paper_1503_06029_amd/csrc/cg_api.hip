@@ -297,4 +297,16 @@ cg_status cg_bfs_path(const uint32_t *d_dist, const uint32_t *d_parent, const in
                         reinterpret_cast<hipStream_t>(stream));
 }
 
+cg_status cg_sample_pack(const double *d_planes, int64_t n, uint64_t seed, uint64_t scene, const double *box,
+                         cg_layout lay, void *d_packed, cg_stream_t stream) {
+    CG_TRY(check_layout(lay));
+    if (n < 0 || n >= (int64_t(1) << 32)) return set_error(CG_EINVAL, "cg_sample_pack: n=%lld out of range", (long long)n);
+    if (!box) return set_error(CG_EINVAL, "cg_sample_pack: box is NULL");
+    if (n > 0 && (!d_planes || !d_packed)) return set_error(CG_EINVAL, "cg_sample_pack: NULL buffer");
+    for (int j = 0; j < 3; ++j)
+        if (!(box[j] <= box[3 + j])) return set_error(CG_EINVAL, "cg_sample_pack: box lo > hi in axis %d", j);
+    return run_sample_pack(d_planes, lay.ell, n, seed, scene, box, lay, d_packed,
+                           reinterpret_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

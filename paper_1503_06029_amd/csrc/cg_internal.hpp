@@ -505,4 +505,7 @@ cg_status run_bfs(const int64_t *adj_off, const uint32_t *adj, const int64_t *d_
 cg_status run_bfs_path(const uint32_t *dist, const uint32_t *parent, const int64_t *d_ncells, int64_t ncap,
                        uint32_t target, uint32_t *path, int64_t path_cap, int64_t *len, hipStream_t s);
 
+cg_status run_sample_pack(const double *planes, int32_t ell, int64_t n, uint64_t seed, uint64_t scene,
+                          const double lohi[6], cg_layout lay, void *out, hipStream_t s);
+
 }  // namespace cg

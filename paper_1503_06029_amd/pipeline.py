@@ -62,6 +62,11 @@ class CellGraph:
         assert bits.dtype == torch.uint8 and bits.shape[0] == self.n and bits.shape[1] == self.lay.ell
         B.cg_pack(bits, self.n, bits.stride(0), self.lay, self.packed, stream)
 
+    def sample(self, planes: torch.Tensor, seed: int, scene: int, box, stream=None):
+        """Fill the packed rows with n sampled points' sign vectors
+        (planes: (ell, 4) float64 on the device; box: lo0, lo1, lo2, hi0, hi1, hi2)."""
+        B.cg_sample_pack(planes, self.n, seed, scene, box, self.lay, self.packed, stream)
+
     def dedup(self, packed: torch.Tensor | None = None, stream=None):
         src = self.packed if packed is None else packed
         B.cg_dedup(src, self.n, self.lay, self.cells, self.r2c, self.ncells, self.ws_dedup,
