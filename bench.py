@@ -72,7 +72,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-dedup-rows", type=int, default=400_000)
     ap.add_argument("--cpu-pair-samples", type=int, default=96)
-    ap.add_argument("--workload", choices=("long", "batched", "served", "search", "sample"), default="long",
+    ap.add_argument("--workload", choices=("long", "batched", "served", "search", "sample", "queries"),
+                    default="long",
                     help="long: 1024-bit vectors (the headline); batched: 512 plane scenes in one graph; "
                          "served: Poisson stream of those scenes")
     ap.add_argument("--scenes", type=int, default=512)
@@ -88,6 +89,8 @@ def main():
         return bench_search(args)
     if args.workload == "sample":
         return bench_sample(args)
+    if args.workload == "queries":
+        return bench_queries(args)
     if args.workload == "served":
         return bench_served(args)
 
@@ -447,6 +450,93 @@ def bench_sample(args):
                      "traffic": None},
         "cpu_baseline": {"value": sample_rows / cpu_s, "unit": "rows/s", "cores": int(oracle.threads()),
                          "kind": "oracle", "sample": f"{sample_rows} of {n} points ({cpu_s:.3f} s)"},
+        "correct": bool(ok),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_queries(args):
+    """Resident dictionary over the long-vector cells (4,194,304 cells of
+    1,024 bits): batches of membership + distance-1 queries (half cells,
+    half one-position flips of cells), a served trace of query requests with
+    continuous batching, and an insert-by-rebuild of 1 % new rows."""
+    import torch
+    from paper_1503_06029_amd import inputs, pipeline, service
+    log("generating workload")
+    rows = inputs.c2()
+    n, W = rows.shape
+    ell = 1024
+    svc = service.DictService(ell, 64, capacity=n + n // 100 + 1024)
+    svc.build(pipeline.to_device_words(rows))
+    nc = svc.n
+    cells = svc.cells[:nc]
+    rng = np.random.default_rng(7)
+    m = 1 << 16
+
+    def make_queries(k):
+        idx = torch.from_numpy(rng.integers(0, nc, k)).cuda()
+        q = cells[idx].clone()
+        f = torch.from_numpy(rng.integers(0, ell, k // 2)).cuda()
+        rows_ = torch.arange(k // 2, device="cuda")
+        bit = (torch.ones(k // 2, dtype=torch.int64, device="cuda") << (63 - f % 64))
+        q[rows_, f // 64] ^= bit
+        return q
+
+    q = make_queries(m)
+    me = torch.empty(m, dtype=torch.int32, device="cuda")
+    cnt = torch.empty(m, dtype=torch.int32, device="cuda")
+    mask = torch.empty((m, W), dtype=torch.int64, device="cuda")
+    for _ in range(args.warmup):
+        svc.query(q, me, cnt, mask)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for k in range(args.steps):
+        svc.query(q, me, cnt, mask)
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    ms = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]))
+    # check a sample against the oracle
+    import oracle
+    hs = 2000
+    hq = q[:hs].cpu().numpy().view(np.uint64)
+    hcells = cells.cpu().numpy().view(np.uint64)
+    t0 = time.perf_counter()
+    want_cnt, want_self, want_mask = oracle.d1_queries(hcells, hq, 64)
+    cpu_s = time.perf_counter() - t0
+    ok = (np.array_equal(me[:hs].cpu().numpy().view(np.uint32), want_self) and
+          np.array_equal(cnt[:hs].cpu().numpy().view(np.uint32), want_cnt) and
+          np.array_equal(mask[:hs].cpu().numpy().view(np.uint64), want_mask))
+    # served trace: requests of 64 queries, Poisson arrivals
+    rate, secs, k_req = 20000.0, 2.0, 64
+    arr = np.cumsum(rng.exponential(1.0 / rate, int(rate * secs)))
+    pool = make_queries(1 << 14).cpu().numpy().view(np.uint64)
+    reqs = [pool[(i * k_req) % pool.shape[0]:(i * k_req) % pool.shape[0] + k_req] for i in range(len(arr))]
+    srv = service.QueryServer(svc, max_batch=1 << 16)
+    srv.serve(arr[:50] - arr[0], reqs[:50])
+    lat, _, wall = srv.serve(arr, reqs)
+    # insert-by-rebuild of 1 % new rows (fresh random vectors)
+    new = torch.from_numpy(rng.integers(0, 2 ** 63, (n // 100, W), dtype=np.int64)).cuda()
+    t0 = time.perf_counter()
+    svc.insert(new)
+    ins_s = time.perf_counter() - t0
+    alg = m * (2 * 8 * W + 8)
+    out = {
+        "metric": "resident-dictionary queries/s (membership + all one-position flips per query)",
+        "value": m / (ms / 1e3), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"dictionary over {nc} cells of {ell} bits (long-vector workload); batches of {m} "
+                               "queries, half cells and half one-position flips of cells", "cells": nc},
+        "flips_per_s": m * ell / (ms / 1e3),
+        "served": {"requests_per_s": len(arr) / wall, "offered_per_s": rate, "queries_per_request": k_req,
+                   "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)},
+        "insert_rebuild_s": ins_s, "inserted_rows": int(n // 100), "cells_after_insert": svc.n,
+        "roofline": {"bound": "hbm", "kernel": "k_d1_query", "achieved": alg / (ms / 1e3) / 1e9, "peak": 8000.0,
+                     "unit": "GB/s", "frac": alg / (ms / 1e3) / 8e12, "traffic": None, "alg_bytes": alg,
+                     "note": "query rows in + masks, ids and counts out; dictionary probes not counted"},
+        "cpu_baseline": {"value": hs / cpu_s, "unit": "queries/s", "cores": int(oracle.threads()),
+                         "kind": "oracle", "sample": f"{hs} queries by full scan of the cells ({cpu_s:.2f} s)"},
         "correct": bool(ok),
     }
     print(json.dumps(out), flush=True)
