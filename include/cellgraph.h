@@ -321,6 +321,21 @@ cg_status cg_bfs_path(const uint32_t *d_dist, const uint32_t *d_parent, const in
 cg_status cg_sample_pack(const double *d_planes, int64_t n, uint64_t seed, uint64_t scene, const double *box,
                          cg_layout lay, void *d_packed, cg_stream_t stream);
 
+/* Batched sampling: cg_batch_pack's virtual rows made from scene
+ * descriptions instead of sign bytes.  Scene j (0 <= j < n_scenes) has
+ * d_scene_ell[j] planes at d_planes + 4 * d_planes_off[j] (rows of (a0, a1,
+ * a2, c) float64) and d_scene_rows[j+1] - d_scene_rows[j] points; its point
+ * i is the one cg_sample_pack draws with seed = d_scene_key[2j] and scene =
+ * d_scene_key[2j+1], in the box shared by all scenes (host array as for
+ * cg_sample_pack); it becomes virtual row d_scene_rows[j] + i (word 0 the
+ * scene tag, words 1.. its bits).  All d_* arrays are device memory.  Scene
+ * l above the layout's is not checked (extra planes are dropped).
+ * Errors: CG_EINVAL (layout not from cg_batch_layout, n_scenes out of
+ * 0 .. 65536, n_rows out of range, NULL pointers, lo > hi). */
+cg_status cg_batch_sample_pack(const double *d_planes, const int64_t *d_planes_off, const int32_t *d_scene_ell,
+                               const int64_t *d_scene_rows, const uint64_t *d_scene_key, int32_t n_scenes,
+                               int64_t n_rows, const double *box, cg_layout lay, void *d_packed, cg_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,6 +64,9 @@ class SceneBatch:
         self.scene_rows = torch.zeros(self.cap_scenes + 1, dtype=torch.int64, device=dev)
         self.bits_off = torch.zeros(max(self.cap_scenes, 1), dtype=torch.int64, device=dev)
         self.scene_ell = torch.zeros(max(self.cap_scenes, 1), dtype=torch.int32, device=dev)
+        # sampled scenes: each scene's first plane in a device plane pool and its generator key
+        self.planes_off = torch.zeros(max(self.cap_scenes, 1), dtype=torch.int64, device=dev)
+        self.keys = torch.zeros((max(self.cap_scenes, 1), 2), dtype=torch.int64, device=dev)
         self.bits = torch.empty(max(self.cap_bytes, 16), dtype=torch.uint8, device=dev)
         self.packed = torch.empty((m, words), dtype=torch.int32, device=dev)
         self.cells = torch.empty((m, words), dtype=torch.int32, device=dev)
@@ -87,7 +90,16 @@ class SceneBatch:
         self.ws_edges_bytes = 0
         self.set_scenes(ells, ns)
 
-    def set_scenes(self, ells, ns):
+    def set_sampled(self, ells, ns, planes_off, keys):
+        """Point the batch at scenes described by planes (offsets into a
+        device plane pool) and generator keys, to be sampled on the GPU."""
+        self.set_scenes(ells, ns, check_bytes=False)
+        k = self.n_scenes
+        self.planes_off[:k].copy_(torch.from_numpy(np.asarray(planes_off, dtype=np.int64)))
+        kk = np.asarray(keys, dtype=np.uint64).reshape(k, 2).view(np.int64)
+        self.keys[:k].copy_(torch.from_numpy(np.ascontiguousarray(kk)))
+
+    def set_scenes(self, ells, ns, check_bytes: bool = True):
         """Point the batch at a new set of scenes (within capacity)."""
         self.ells = np.asarray(ells, dtype=np.int32)
         self.ns = np.asarray(ns, dtype=np.int64)
@@ -100,7 +112,7 @@ class SceneBatch:
         boff[1:] = np.cumsum(bytes_per)[:-1]
         self.n_rows = int(rows[-1])
         self.total_bytes = int(bytes_per.sum())
-        assert self.n_rows <= self.cap_rows and self.total_bytes <= self.cap_bytes
+        assert self.n_rows <= self.cap_rows and (self.total_bytes <= self.cap_bytes or not check_bytes)
         assert int(self.ells.max()) <= 32 * (self.words - 1)
         self.scene_rows_h = rows
         self.bits_off_h = boff
@@ -127,6 +139,16 @@ class SceneBatch:
     def run(self, stream=None):
         B.cg_batch_pack(self.bits, self.bits_off, self.scene_ell, self.scene_rows, self.n_scenes, self.n_rows,
                         self.lay, self.packed, stream)
+        self._run_path(stream)
+
+    def run_sampled(self, planes, box, stream=None):
+        """Sample the scenes set by set_sampled (plane pool `planes`, (P, 4)
+        float64 on the device) straight into the packed rows, then the path."""
+        B.cg_batch_sample_pack(planes, self.planes_off, self.scene_ell, self.scene_rows, self.keys, self.n_scenes,
+                               self.n_rows, box, self.lay, self.packed, stream)
+        self._run_path(stream)
+
+    def _run_path(self, stream=None):
         B.cg_dedup(self.packed, self.n_rows, self.lay, self.cells, self.r2c, self.ncells, self.ws_dedup,
                    self.ws_dedup_bytes, stream)
         self.dict = B.cg_dict_build(self.cells, self.ncells, self.n_rows, self.lay, self.params, self.dict_mem,

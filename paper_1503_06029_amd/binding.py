@@ -83,12 +83,15 @@ _sig("cg_bfs", [c_vp, c_vp, c_vp, c_i64, ctypes.c_uint32, c_i32, c_i32, c_vp, c_
 _sig("cg_bfs_path", [c_vp, c_vp, c_vp, c_i64, ctypes.c_uint32, c_vp, c_i64, c_vp, c_vp])
 _sig("cg_sample_pack", [c_vp, c_i64, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), Layout,
                         c_vp, c_vp])
+_sig("cg_batch_sample_pack", [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i64, ctypes.POINTER(ctypes.c_double), Layout,
+                              c_vp, c_vp])
 
 EXPORTS = ("cg_version", "cg_status_string", "cg_last_error", "cg_make_layout", "cg_pack",
            "cg_dedup_workspace", "cg_dedup", "cg_dict_params_default", "cg_dict_size",
            "cg_dict_build", "cg_neighbors_d1", "cg_edges_workspace", "cg_edges",
            "cg_batch_layout", "cg_batch_pack", "cg_batch_split", "cg_graph_csr_workspace", "cg_graph_csr",
-           "cg_bfs_workspace", "cg_bfs", "cg_bfs_path", "cg_sample_pack")
+           "cg_bfs_workspace", "cg_bfs", "cg_bfs_path", "cg_sample_pack",
+           "cg_batch_sample_pack")
 
 
 def lib():
@@ -246,3 +249,10 @@ def cg_sample_pack(d_planes, n: int, seed: int, scene: int, box, lay: Layout, d_
     """box: (lo0, lo1, lo2, hi0, hi1, hi2) on the host."""
     b = (ctypes.c_double * 6)(*[float(v) for v in box])
     _check(_lib.cg_sample_pack(_ptr(d_planes), n, seed, scene, b, lay, _ptr(d_packed), _stream(stream)))
+
+
+def cg_batch_sample_pack(d_planes, d_planes_off, d_scene_ell, d_scene_rows, d_scene_key, n_scenes: int,
+                         n_rows: int, box, lay: Layout, d_packed, stream=None):
+    b = (ctypes.c_double * 6)(*[float(v) for v in box])
+    _check(_lib.cg_batch_sample_pack(_ptr(d_planes), _ptr(d_planes_off), _ptr(d_scene_ell), _ptr(d_scene_rows),
+                                     _ptr(d_scene_key), n_scenes, n_rows, b, lay, _ptr(d_packed), _stream(stream)))

@@ -309,4 +309,21 @@ cg_status cg_sample_pack(const double *d_planes, int64_t n, uint64_t seed, uint6
                            reinterpret_cast<hipStream_t>(stream));
 }
 
+cg_status cg_batch_sample_pack(const double *d_planes, const int64_t *d_planes_off, const int32_t *d_scene_ell,
+                               const int64_t *d_scene_rows, const uint64_t *d_scene_key, int32_t n_scenes,
+                               int64_t n_rows, const double *box, cg_layout lay, void *d_packed, cg_stream_t stream) {
+    CG_TRY(check_layout(lay));
+    if (lay.word_bits != 32 || lay.ell != 32 * lay.words || lay.words < 2)
+        return set_error(CG_EINVAL, "cg_batch_sample_pack: layout not made by cg_batch_layout");
+    if (n_scenes < 0 || n_scenes > 65536) return set_error(CG_EINVAL, "cg_batch_sample_pack: n_scenes=%d", n_scenes);
+    if (n_rows < 0 || n_rows >= (int64_t(1) << 32)) return set_error(CG_EINVAL, "cg_batch_sample_pack: n_rows out of range");
+    if (!box) return set_error(CG_EINVAL, "cg_batch_sample_pack: box is NULL");
+    for (int j = 0; j < 3; ++j)
+        if (!(box[j] <= box[3 + j])) return set_error(CG_EINVAL, "cg_batch_sample_pack: box lo > hi in axis %d", j);
+    if (n_rows > 0 && (!d_planes || !d_planes_off || !d_scene_ell || !d_scene_rows || !d_scene_key || !d_packed))
+        return set_error(CG_EINVAL, "cg_batch_sample_pack: NULL buffer");
+    return run_batch_sample_pack(d_planes, d_planes_off, d_scene_ell, d_scene_rows, d_scene_key, n_scenes, n_rows, box,
+                                 lay, d_packed, reinterpret_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

@@ -507,5 +507,8 @@ cg_status run_bfs_path(const uint32_t *dist, const uint32_t *parent, const int64
 
 cg_status run_sample_pack(const double *planes, int32_t ell, int64_t n, uint64_t seed, uint64_t scene,
                           const double lohi[6], cg_layout lay, void *out, hipStream_t s);
+cg_status run_batch_sample_pack(const double *planes, const int64_t *planes_off, const int32_t *scene_ell,
+                                const int64_t *scene_rows, const uint64_t *keys, int32_t n_scenes, int64_t n_rows,
+                                const double lohi[6], cg_layout lay, void *out, hipStream_t s);
 
 }  // namespace cg

@@ -74,7 +74,82 @@ __global__ void __launch_bounds__(256) k_sample_pack(const double *__restrict__ 
     }
 }
 
+// Batched scenes: virtual row r belongs to the scene j with scene_rows[j] <=
+// r < scene_rows[j + 1] and is that scene's point r - scene_rows[j], drawn
+// with the scene's own key; word 0 is the scene tag (j << 16 | j), words
+// 1 .. the scene's bits (32 planes per word, MSB first, zero past its l),
+// the layout cg_batch_pack writes.  One block looks its first row's scene up
+// by binary search; each thread walks on from there.
+__global__ void __launch_bounds__(256) k_batch_sample_pack(const double *__restrict__ planes,
+                                                           const int64_t *__restrict__ planes_off,
+                                                           const int32_t *__restrict__ scene_ell,
+                                                           const int64_t *__restrict__ scene_rows,
+                                                           const uint64_t *__restrict__ keys, int n_scenes,
+                                                           int64_t n_rows, Box box, int words,
+                                                           uint32_t *__restrict__ out) {
+#pragma clang fp contract(off)
+    __shared__ int s_j0;
+    for (int64_t r0 = static_cast<int64_t>(blockIdx.x) * blockDim.x; r0 < n_rows;
+         r0 += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int lo = 0, hi = n_scenes;  // the scene of row r0: in [lo, hi)
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (scene_rows[mid] <= r0) lo = mid; else hi = mid;
+            }
+            s_j0 = lo;
+        }
+        __syncthreads();
+        const int64_t r = r0 + threadIdx.x;
+        if (r >= n_rows) continue;
+        int j = s_j0;
+        while (j + 1 < n_scenes && scene_rows[j + 1] <= r) ++j;
+        const int64_t i = r - scene_rows[j];
+        const int ell = scene_ell[j];
+        const double *pl = planes + 4 * planes_off[j];
+        uint64_t x[4] = {static_cast<uint64_t>(i), 0ull, 0ull, 0ull};
+        philox4x64_10(x, keys[2 * j], keys[2 * j + 1]);
+        double p[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double u = static_cast<double>(x[d] >> 11) * 0x1.0p-53;
+            p[d] = box.lo[d] + (box.hi[d] - box.lo[d]) * u;
+        }
+        uint32_t *row = out + r * words;
+        row[0] = (static_cast<uint32_t>(j) << 16) | static_cast<uint32_t>(j);
+        for (int w = 1; w < words; ++w) {
+            const int k0 = (w - 1) * 32;
+            const int kn = ell - k0 < 32 ? ell - k0 : 32;
+            uint32_t acc = 0;
+            for (int b = 0; b < kn; ++b) {
+                const double *a = pl + 4 * (k0 + b);
+                const double sum = (a[0] * p[0] + a[1] * p[1]) + a[2] * p[2];
+                const double res = sum - a[3];
+                acc |= (res >= 0.0 ? 1u : 0u) << (31 - b);
+            }
+            row[w] = acc;
+        }
+    }
+}
+
 }  // namespace
+
+cg_status run_batch_sample_pack(const double *planes, const int64_t *planes_off, const int32_t *scene_ell,
+                                const int64_t *scene_rows, const uint64_t *keys, int32_t n_scenes, int64_t n_rows,
+                                const double lohi[6], cg_layout lay, void *out, hipStream_t s) {
+    if (n_rows == 0 || n_scenes == 0) return CG_OK;
+    Box box;
+    for (int j = 0; j < 3; ++j) {
+        box.lo[j] = lohi[j];
+        box.hi[j] = lohi[3 + j];
+    }
+    hipLaunchKernelGGL(k_batch_sample_pack, dim3(blocks_for(n_rows, 256, 1 << 20)), dim3(256), 0, s, planes,
+                       planes_off, scene_ell, scene_rows, keys, n_scenes, n_rows, box, lay.words,
+                       static_cast<uint32_t *>(out));
+    CG_LAUNCHED("batch_sample_pack");
+    return CG_OK;
+}
 
 cg_status run_sample_pack(const double *planes, int32_t ell, int64_t n, uint64_t seed, uint64_t scene,
                           const double lohi[6], cg_layout lay, void *out, hipStream_t s) {

@@ -148,6 +148,23 @@ def c3_scene(i: int) -> np.ndarray:
     return planes_in_cube(rng, ell, n)
 
 
+def c3_scene_desc(i: int):
+    """Scene i of config 3 as a description for the GPU sampler: the same l,
+    n and planes as c3_scene(i) (rows (a0, a1, a2, c), float64), points to
+    be drawn in [-1, 1]^3 with Philox key (MASTER_SEED, i).  Returns
+    (planes, n, key)."""
+    rng = _rng(3, i)
+    ell = int(rng.integers(16, 512, endpoint=True))
+    n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(2e5)))))
+    g = rng.standard_normal((ell, 3))
+    a = g / np.linalg.norm(g, axis=1, keepdims=True)
+    c = rng.uniform(-0.5, 0.5, ell)
+    return np.concatenate([a, c[:, None]], axis=1), n, (MASTER_SEED, i)
+
+
+SAMPLE_BOX = (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0)
+
+
 def c4_trace(rate: float = 2000.0, seconds: float = 60.0, pool: int = C3_SCENES):
     """Config 4: (arrival times in s, scene index in the config-3 pool)."""
     rng = _rng(4)

@@ -70,6 +70,24 @@ class Slot:
             self.done = torch.cuda.Event()
             self.done.record(self.stream)
 
+    def launch_sampled(self, reqs, descs, planes, plane_off, box):
+        """Launch one batch of sampled scenes: descs[si] = (planes, n, key);
+        the scenes' planes sit in the device pool `planes` from plane_off[si].
+        Only the scene table (offsets, sizes, keys) crosses PCIe."""
+        by_class = {}
+        for rid, si in reqs:
+            ell = descs[si][0].shape[0]
+            by_class.setdefault(BT.class_words(ell), []).append((rid, si))
+        self.requests = by_class
+        with torch.cuda.stream(self.stream):
+            for w, items in by_class.items():
+                sb = self.batches[w]
+                sb.set_sampled([descs[si][0].shape[0] for _, si in items], [descs[si][1] for _, si in items],
+                               [plane_off[si] for _, si in items], [descs[si][2] for _, si in items])
+                sb.run_sampled(planes, box, self.stream)
+            self.done = torch.cuda.Event()
+            self.done.record(self.stream)
+
     def collect(self, copy: bool = False):
         """Wait for the batch; return {req_id: result dict}.  Copies go on the
         slot's own stream, so the other slot's batch keeps running.  Results
@@ -129,6 +147,9 @@ class Server:
     def _admit(self, queue: deque, now: float):
         return admit_requests(queue, now, self.caps, [R.shape for R in self.scenes])
 
+    def _launch(self, slot, reqs):
+        slot.launch(reqs, self.scenes, self.pinned)
+
     def serve(self, arrivals, scene_idx, keep_results: bool = False):
         """Serve a trace in real time.  Returns (latencies in s, results or None, wall seconds)."""
         n = len(arrivals)
@@ -146,7 +167,7 @@ class Server:
                 reqs = self._admit(queue, now)
                 if reqs:
                     slot = free.pop(0)
-                    slot.launch(reqs, self.scenes, self.pinned)
+                    self._launch(slot, reqs)
                     inflight.append(slot)
                     progressed = True
             if inflight and (not free or inflight[0].done.query()):
@@ -165,6 +186,34 @@ class Server:
                 time.sleep(min(max(wait, 0.0), 0.0002))
         wall = time.perf_counter() - t0
         return lat, results, wall
+
+
+class SampledServer(Server):
+    """The same continuous batching with scenes given as descriptions
+    (planes, points, generator key) and sampled on the GPU: a request moves
+    a few bytes of scene table instead of its sign bytes."""
+
+    def __init__(self, descs, box, rows_per_class: int = 1 << 21, scenes_per_class: int = 4096, device="cuda"):
+        self.descs = descs
+        self.box = box
+        caps, slot_caps = {}, {}
+        for pl, n, key in descs:
+            w = BT.class_words(pl.shape[0])
+            caps[w] = (rows_per_class, scenes_per_class, 1 << 62)  # no sign bytes to hold
+            slot_caps[w] = (rows_per_class, scenes_per_class, 4096)
+        self.caps = caps
+        self.slots = [Slot(slot_caps, device), Slot(slot_caps, device)]
+        off = np.zeros(len(descs) + 1, dtype=np.int64)
+        off[1:] = np.cumsum([d[0].shape[0] for d in descs])
+        self.plane_off = off
+        self.planes = torch.from_numpy(np.concatenate([d[0] for d in descs]).astype(np.float64)).to(device)
+        self.shapes = [(d[1], d[0].shape[0]) for d in descs]
+
+    def _admit(self, queue: deque, now: float):
+        return admit_requests(queue, now, self.caps, self.shapes)
+
+    def _launch(self, slot, reqs):
+        slot.launch_sampled(reqs, self.descs, self.planes, self.plane_off, self.box)
 
 
 class PerSceneBaseline:

@@ -93,3 +93,63 @@ def test_sample_edge_cases(gpu):
     # invalid box is rejected on the host
     with pytest.raises(B.CellGraphError):
         g.sample(torch.from_numpy(planes).cuda(), 0, 0, [1.0, 0, 0, 0.0, 1, 1])
+
+
+def test_batch_sample_pack_parity(gpu):
+    """Many scenes in one launch: each scene's rows equal its oracle signs
+    (tag word, then the packed vector), and equal cg_sample_pack's."""
+    torch, B, P = gpu
+    rng = np.random.default_rng(17)
+    ells = [16, 33, 64, 100, 31, 1, 70]
+    ns = [500, 1, 0, 2000, 777, 40, 1500]
+    box = [-1.0, -1.0, -1.0, 1.0, 1.0, 1.0]
+    lay = B.cg_batch_layout(max(ells))
+    planes = [random_planes(rng, l) for l in ells]
+    pool = np.concatenate(planes)
+    off = np.concatenate([[0], np.cumsum(ells)[:-1]]).astype(np.int64)
+    rows = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    keys = np.array([[1503 + j, 7 * j] for j in range(len(ells))], dtype=np.uint64)
+    N = int(rows[-1])
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = torch.full((N, lay.words), -1, dtype=torch.int32, device="cuda")
+    B.cg_batch_sample_pack(d(pool), d(off), d(np.array(ells, dtype=np.int32)), d(rows), d(keys.view(np.int64)),
+                           len(ells), N, box, lay, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    for j, (l, n) in enumerate(zip(ells, ns)):
+        say("scene", j, l, n)
+        seg = got[rows[j]:rows[j + 1]]
+        assert np.all(seg[:, 0] == (j << 16 | j))
+        signs = oracle.sample_signs(planes[j], n, int(keys[j, 0]), int(keys[j, 1]), box)
+        want = oracle.pack(signs, 32) if n else np.zeros((0, -(-l // 32)), dtype=np.uint32)
+        wpad = np.zeros((n, lay.words - 1), dtype=np.uint32)
+        wpad[:, :want.shape[1]] = want
+        assert np.array_equal(seg[:, 1:], wpad)
+
+
+def test_sampled_server_matches_single_scenes(gpu):
+    """Requests served from scene descriptions (sampled on the GPU in
+    batches) give each scene's cells and edges as the oracle computes them
+    from the same samples."""
+    torch, B, P = gpu
+    from paper_1503_06029_amd import serve
+    rng = np.random.default_rng(23)
+    box = [-1.0, -1.0, -1.0, 1.0, 1.0, 1.0]
+    descs = []
+    for j in range(6):
+        l = int(rng.integers(16, 120))
+        descs.append((random_planes(rng, l), int(rng.integers(200, 3000)), (99, j)))
+    srv = serve.SampledServer(descs, box, rows_per_class=1 << 15, scenes_per_class=64)
+    arr = np.sort(rng.uniform(0, 0.02, 30))
+    sc = rng.integers(0, len(descs), 30)
+    lat, res, wall = srv.serve(arr, sc, keep_results=True)
+    want = {}
+    for j, (pl, n, key) in enumerate(descs):
+        bits = oracle.sample_signs(pl, n, key[0], key[1], box)
+        want[j] = oracle.cell_graph(bits, pl.shape[0], 32)
+    for rid, si in enumerate(sc):
+        cells, r2c, uv, bit, off = want[int(si)]
+        r = res[rid]
+        assert r["ncells"] == cells.shape[0]
+        assert np.array_equal(r["uv"], uv)
+        assert np.array_equal(r["row_to_cell"], r2c)
