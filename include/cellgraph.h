@@ -170,6 +170,20 @@ cg_status cg_dict_build(const void *d_cells, const int64_t *d_ncells, int64_t nc
                         cg_layout lay, const cg_dict_params *p, void *d_mem,
                         size_t mem_bytes, cg_dict *out, cg_stream_t stream);
 
+/* Fused dedup + dictionary build: the same cells, row_to_cell, cell count
+ * and dictionary as cg_dedup followed by cg_dict_build(d_cells, d_ncells,
+ * n, lay, p, ...), in fewer passes over the rows: suffix hashes are taken
+ * while the sort keys are extracted and the directory comes from the sorted
+ * keys, so the cells are not read back.  Arguments as for the two calls
+ * (the dictionary's ncells_cap is n; d_mem needs cg_dict_size(n, lay, p));
+ * the workspace needs cg_dedup_dict_workspace(n, lay) bytes.  *out is a
+ * dictionary handle exactly like cg_dict_build's.
+ * Errors: CG_EINVAL, CG_EWORKSPACE. */
+cg_status cg_dedup_dict_workspace(int64_t n, cg_layout lay, size_t *bytes);
+cg_status cg_dedup_dict(const void *d_packed, int64_t n, cg_layout lay, void *d_cells, uint32_t *d_row_to_cell,
+                        int64_t *d_ncells, void *d_ws, size_t ws_bytes, const cg_dict_params *p, void *d_mem,
+                        size_t mem_bytes, cg_dict *out, cg_stream_t stream);
+
 /* ----------------------------------------------------- distance-1 queries
  * Section 3.2 (Algorithm 4): for every query vector q and every bit k, is
  * q with bit k negated a cell?  For each of the nq rows at d_queries (same

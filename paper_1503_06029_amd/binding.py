@@ -69,6 +69,9 @@ _sig("cg_dict_params_default", [ctypes.POINTER(DictParams)])
 _sig("cg_dict_size", [c_i64, Layout, ctypes.POINTER(DictParams), ctypes.POINTER(c_sz)])
 _sig("cg_dict_build", [c_vp, c_vp, c_i64, Layout, ctypes.POINTER(DictParams), c_vp, c_sz,
                        ctypes.POINTER(Dict), c_vp])
+_sig("cg_dedup_dict_workspace", [c_i64, Layout, ctypes.POINTER(c_sz)])
+_sig("cg_dedup_dict", [c_vp, c_i64, Layout, c_vp, c_vp, c_vp, c_vp, c_sz, ctypes.POINTER(DictParams), c_vp, c_sz,
+                       ctypes.POINTER(Dict), c_vp])
 _sig("cg_neighbors_d1", [ctypes.POINTER(Dict), c_vp, c_i64, c_vp, c_vp, c_vp, c_vp])
 _sig("cg_edges_workspace", [ctypes.POINTER(Dict), c_i64, ctypes.POINTER(c_sz)])
 _sig("cg_edges", [ctypes.POINTER(Dict), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp])
@@ -91,7 +94,7 @@ EXPORTS = ("cg_version", "cg_status_string", "cg_last_error", "cg_make_layout", 
            "cg_dict_build", "cg_neighbors_d1", "cg_edges_workspace", "cg_edges",
            "cg_batch_layout", "cg_batch_pack", "cg_batch_split", "cg_graph_csr_workspace", "cg_graph_csr",
            "cg_bfs_workspace", "cg_bfs", "cg_bfs_path", "cg_sample_pack",
-           "cg_batch_sample_pack")
+           "cg_batch_sample_pack", "cg_dedup_dict_workspace", "cg_dedup_dict")
 
 
 def lib():
@@ -174,6 +177,21 @@ def cg_dict_build(d_cells, d_ncells, ncells_cap: int, lay: Layout, params: DictP
     _check(_lib.cg_dict_build(_ptr(d_cells), _ptr(d_ncells), ncells_cap, lay,
                               ctypes.byref(params) if params is not None else None, _ptr(d_mem), mem_bytes,
                               ctypes.byref(out), _stream(stream)))
+    return out
+
+
+def cg_dedup_dict_workspace(n: int, lay: Layout) -> int:
+    b = c_sz()
+    _check(_lib.cg_dedup_dict_workspace(n, lay, ctypes.byref(b)))
+    return b.value
+
+
+def cg_dedup_dict(d_packed, n: int, lay: Layout, d_cells, d_row_to_cell, d_ncells, d_ws, ws_bytes: int,
+                  params: DictParams | None, d_mem, mem_bytes: int, stream=None) -> Dict:
+    out = Dict()
+    _check(_lib.cg_dedup_dict(_ptr(d_packed), n, lay, _ptr(d_cells), _ptr(d_row_to_cell), _ptr(d_ncells),
+                              _ptr(d_ws), ws_bytes, ctypes.byref(params) if params is not None else None,
+                              _ptr(d_mem), mem_bytes, ctypes.byref(out), _stream(stream)))
     return out
 
 

@@ -326,4 +326,42 @@ cg_status cg_batch_sample_pack(const double *d_planes, const int64_t *d_planes_o
                                  lay, d_packed, reinterpret_cast<hipStream_t>(stream));
 }
 
+cg_status cg_dedup_dict_workspace(int64_t n, cg_layout lay, size_t *bytes) {
+    CG_TRY(check_layout(lay));
+    if (n < 0 || n >= (int64_t(1) << 32)) return set_error(CG_EINVAL, "cg_dedup_dict_workspace: n out of range");
+    if (!bytes) return set_error(CG_EINVAL, "cg_dedup_dict_workspace: bytes is NULL");
+    *bytes = dedup_fused_workspace_bytes(n, lay);
+    return CG_OK;
+}
+
+cg_status cg_dedup_dict(const void *d_packed, int64_t n, cg_layout lay, void *d_cells, uint32_t *d_row_to_cell,
+                        int64_t *d_ncells, void *d_ws, size_t ws_bytes, const cg_dict_params *p, void *d_mem,
+                        size_t mem_bytes, cg_dict *out, cg_stream_t stream) {
+    CG_TRY(check_layout(lay));
+    CG_TRY(check_params(p, lay));
+    if (n < 0 || n >= (int64_t(1) << 32)) return set_error(CG_EINVAL, "cg_dedup_dict: n=%lld out of range", (long long)n);
+    if (!d_ncells || !out || (n > 0 && (!d_packed || !d_cells)))
+        return set_error(CG_EINVAL, "cg_dedup_dict: NULL buffer");
+    size_t need = 0;
+    CG_TRY(cg_dedup_dict_workspace(n, lay, &need));
+    if (!d_ws || ws_bytes < need) return set_error(CG_EWORKSPACE, "cg_dedup_dict: workspace %zu < %zu bytes", ws_bytes, need);
+    cg_dict d;
+    memset(&d, 0, sizeof(d));
+    d.params = resolve_params(n, lay, p);
+    const size_t mneed = dict_mem_bytes(n, lay, d.params);
+    if (!d_mem || mem_bytes < mneed)
+        return set_error(CG_EWORKSPACE, "cg_dedup_dict: dictionary memory %zu < %zu bytes", mem_bytes, mneed);
+    d.magic = DICT_MAGIC;
+    d.lay = lay;
+    d.ncells_cap = n;
+    d.cells = d_cells;
+    d.d_ncells = d_ncells;
+    d.mem = d_mem;
+    d.mem_bytes = mem_bytes;
+    CG_TRY(run_dedup_dict(d_packed, n, lay, d_cells, d_row_to_cell, d_ncells, d_ws, d,
+                          reinterpret_cast<hipStream_t>(stream)));
+    *out = d;
+    return CG_OK;
+}
+
 }  // extern "C"

@@ -74,6 +74,40 @@ __global__ void __launch_bounds__(256) k_extract(const T *__restrict__ rows, int
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_hash_rows(const T *__restrict__ rows, int64_t n, int words, int hash_s,
+                                                   uint32_t *__restrict__ rhash) {
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
+         j += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        rhash[j] = suffix_hash32<T>(rows + j * words, words, hash_s);
+}
+
+// Key extraction for the fused dedup + dictionary build: a block's 256 rows
+// are read whole (coalesced) into LDS, and each thread takes its row's sort
+// key and the dictionary's suffix hash of bits hash_s .. from there, so the
+// rows' lines are read once for both (the key alone would fetch them anyway).
+template <typename T>
+__global__ void __launch_bounds__(256) k_extract_hash(const T *__restrict__ rows, int64_t n, int words,
+                                                      const unsigned long long *__restrict__ key32,
+                                                      uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                      int hash_s, uint32_t *__restrict__ rhash) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *lrows = reinterpret_cast<T *>(smem);
+    const int LW = words | 1;
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * 256;
+    if (base >= n) return;
+    const int tr = static_cast<int>(n - base < 256 ? n - base : 256);
+    copy_rows_to_lds<T, 256>(lrows, LW, rows + base * words, tr, words);
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t >= tr) return;
+    const uint64_t kmask = (key32 && *key32) ? 0xFFFFFFFF00000000ull : ~0ull;
+    const T *row = lrows + t * LW;
+    keys[base + t] = head64<T>(row, words) & kmask;
+    vals[base + t] = static_cast<uint32_t>(base + t);
+    rhash[base + t] = suffix_hash32<T>(row, words, hash_s);
+}
+
 // End of the run of keys equal to keys[j] (keys sorted ascending): the first
 // index e > j with keys[e] != keys[j], or n.
 __device__ __forceinline__ int64_t run_end(const uint64_t *keys, int64_t j, int64_t n) {
@@ -626,21 +660,64 @@ __global__ void __launch_bounds__(1024) k_tiefix_mid(const T *__restrict__ rows,
     }
 }
 
-template <typename V>
+// Suffix-hash terms of one gathered piece (PW words of type T).
+template <typename T, typename V>
+__device__ __forceinline__ uint64_t piece_terms(const V &v, int piece, int s) {
+    constexpr int PW = static_cast<int>(sizeof(V) / sizeof(T));
+    const T *x = reinterpret_cast<const T *>(&v);
+    uint64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < PW; ++k) sum += suffix_term<T>(x[k], piece * PW + k, s);
+    return sum;
+}
+
+// sfx (when not null): each cell's suffix-order key (hash << 32 | id).  With
+// hash_lanes > 0 (a row's pieces a power of two, at most 64, so a row's
+// lanes are adjacent within one wave) the lanes of a row add their pieces'
+// hash terms; otherwise the hash comes from rhash[row].  All lanes of a wave
+// stay in the loop together so the shuffles see every lane.
+template <typename T, typename V>
 __global__ void __launch_bounds__(256) k_gather(const V *__restrict__ rows, int64_t n, int pieces,
                                                 const uint32_t *__restrict__ vals, const uint8_t *__restrict__ uniq,
                                                 const uint32_t *__restrict__ cidx, V *__restrict__ cells,
-                                                uint32_t *__restrict__ row_to_cell) {
+                                                uint32_t *__restrict__ row_to_cell, const uint32_t *__restrict__ rhash,
+                                                uint64_t *__restrict__ sfx, int hash_lanes, int hash_s) {
+    // GU pieces per thread per step, each step's pieces a whole number of
+    // waves apart, so their loads are in flight together and a row's lanes
+    // stay adjacent for the hash shuffles
+    constexpr int GU = 4;
     const int64_t total = n * pieces;
-    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
-         g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int64_t j = g / pieces;
-        const int w = static_cast<int>(g - j * pieces);
-        const uint32_t u = uniq[j];
-        const uint32_t cid = cidx[j] + u - 1;
-        const uint32_t src = vals[j];
-        if (u) cells[static_cast<int64_t>(cid) * pieces + w] = rows[static_cast<int64_t>(src) * pieces + w];
-        if (w == 0 && row_to_cell) row_to_cell[src] = cid;
+    const int64_t span = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t g0 = static_cast<int64_t>(blockIdx.x) * blockDim.x; g0 < total; g0 += span * GU) {
+        V v[GU];
+        uint32_t uu[GU], cid[GU], src[GU];
+        int wp[GU];
+#pragma unroll
+        for (int q = 0; q < GU; ++q) {
+            const int64_t g = g0 + q * span + threadIdx.x;
+            const bool in = g < total;
+            const int64_t j = in ? g / pieces : 0;
+            wp[q] = static_cast<int>(g - j * pieces);
+            uu[q] = in ? uniq[j] : 0u;
+            cid[q] = in ? cidx[j] + uu[q] - 1 : 0u;
+            src[q] = in ? vals[j] : 0u;
+            v[q] = uu[q] ? rows[static_cast<int64_t>(src[q]) * pieces + wp[q]] : V{};
+        }
+#pragma unroll
+        for (int q = 0; q < GU; ++q) {
+            const int64_t g = g0 + q * span + threadIdx.x;
+            if (uu[q]) cells[static_cast<int64_t>(cid[q]) * pieces + wp[q]] = v[q];
+            if (g < total && wp[q] == 0 && row_to_cell) row_to_cell[src[q]] = cid[q];
+            if (sfx) {
+                if (hash_lanes > 0) {
+                    uint64_t t = uu[q] ? piece_terms<T, V>(v[q], wp[q], hash_s) : 0ull;
+                    for (int d = 1; d < hash_lanes; d <<= 1) t += shfl_u64_xor(t, d);
+                    if (uu[q] && wp[q] == 0) sfx[cid[q]] = (static_cast<uint64_t>(suffix_finish(t)) << 32) | cid[q];
+                } else if (uu[q] && wp[q] == 0) {
+                    sfx[cid[q]] = (static_cast<uint64_t>(rhash[src[q]]) << 32) | cid[q];
+                }
+            }
+        }
     }
 }
 
@@ -654,9 +731,10 @@ struct DedupWs {
     uint2 *large_list;
     unsigned long long *counters;
     uint32_t *scratch;
+    uint32_t *rhash;
 };
 
-DedupWs carve_dedup(void *base, int64_t n, cg_layout lay, size_t *bytes) {
+DedupWs carve_dedup(void *base, int64_t n, cg_layout lay, size_t *bytes, bool with_hash = false) {
     Carver c(base);
     DedupWs w{};
     const int64_t m = n > 0 ? n : 1;
@@ -675,15 +753,27 @@ DedupWs carve_dedup(void *base, int64_t n, cg_layout lay, size_t *bytes) {
         w.large_list = c.take<uint2>(m / 2 + 1);
         w.scratch = c.take<uint32_t>(2 * m);
     }
+    if (with_hash) w.rhash = c.take<uint32_t>(m);
     *bytes = c.bytes();
     return w;
 }
 
+// With hash_s >= 0 (the fused dedup + dictionary build) the suffix hash of
+// every row is taken during key extraction and the gather writes each
+// cell's suffix-order key to sfx; *view then names the sorted keys, the
+// new-cell flags and the cell numbering for the directory.
 template <typename T>
 cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t *row_to_cell, int64_t *d_ncells,
-                     void *ws, hipStream_t s) {
+                     void *ws, hipStream_t s, int hash_s = -1, uint64_t *sfx = nullptr, DedupView *view = nullptr) {
     size_t bytes;
-    DedupWs w = carve_dedup(ws, n, lay, &bytes);
+    DedupWs w = carve_dedup(ws, n, lay, &bytes, hash_s >= 0);
+    // the gather hashes a row from its pieces when they are a power of two
+    // (at most 64, so a row's lanes sit together in one wave); otherwise the
+    // hashes are taken per row at key extraction
+    const size_t rowbytes = static_cast<size_t>(lay.words) * sizeof(T);
+    const int pieces = rowbytes % 16 == 0 ? static_cast<int>(rowbytes / 16) : lay.words;
+    const int hash_lanes = (hash_s >= 0 && pieces <= 64 && (pieces & (pieces - 1)) == 0) ? pieces : 0;
+    uint32_t *rhash = (hash_s >= 0 && hash_lanes == 0) ? w.rhash : nullptr;
     const int words = lay.words;
     if (n == 0) return fill_i64(d_ncells, 0, 1, s);
 
@@ -694,8 +784,19 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
         hipLaunchKernelGGL((k_key_probe<T>), dim3(1), dim3(1024), 0, s, rows, n, words, w.counters);
         CG_LAUNCHED("dedup_key_probe");
     }
-    hipLaunchKernelGGL((k_extract<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words,
-                       probe ? w.counters + 2 : nullptr, w.keys[0], w.vals[0]);
+    const size_t xlds = static_cast<size_t>(256) * (words | 1) * sizeof(T);
+    if (rhash && xlds <= 65536) {
+        hipLaunchKernelGGL((k_extract_hash<T>), dim3(blocks_for(n, 256)), dim3(256), xlds, s, rows, n, words,
+                           probe ? w.counters + 2 : nullptr, w.keys[0], w.vals[0], hash_s, rhash);
+    } else {
+        hipLaunchKernelGGL((k_extract<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words,
+                           probe ? w.counters + 2 : nullptr, w.keys[0], w.vals[0]);
+        if (rhash) {  // rows too wide to stage: hash them in place
+            hipLaunchKernelGGL((k_hash_rows<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words,
+                               hash_s, rhash);
+            CG_LAUNCHED("dedup_hash_rows");
+        }
+    }
     CG_LAUNCHED("dedup_extract");
 
     // key bits that can be nonzero: [64 - sig, 64); with 32-bit keys the four
@@ -748,17 +849,20 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
         CG_LAUNCHED("dedup_tiefix_large");
     }
     CG_TRY(scan_u8_to_u32(w.uniq, w.cidx, n, nullptr, w.tile_sums, d_ncells, s));
-    const size_t rowbytes = static_cast<size_t>(words) * sizeof(T);
     if (rowbytes % 16 == 0) {
-        const int pieces = static_cast<int>(rowbytes / 16);
-        hipLaunchKernelGGL((k_gather<uint4>), dim3(blocks_for(n * pieces, 256, 65536)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_gather<T, uint4>), dim3(blocks_for(n * pieces, 256, 65536)), dim3(256), 0, s,
                            reinterpret_cast<const uint4 *>(rows), n, pieces, vals, w.uniq, w.cidx,
-                           reinterpret_cast<uint4 *>(cells), row_to_cell);
+                           reinterpret_cast<uint4 *>(cells), row_to_cell, rhash, sfx, hash_lanes, hash_s);
     } else {
-        hipLaunchKernelGGL((k_gather<T>), dim3(blocks_for(n * words, 256, 65536)), dim3(256), 0, s, rows, n, words,
-                           vals, w.uniq, w.cidx, cells, row_to_cell);
+        hipLaunchKernelGGL((k_gather<T, T>), dim3(blocks_for(n * words, 256, 65536)), dim3(256), 0, s, rows, n,
+                           words, vals, w.uniq, w.cidx, cells, row_to_cell, rhash, sfx, hash_lanes, hash_s);
     }
     CG_LAUNCHED("dedup_gather");
+    if (view) {
+        view->keys = keys;
+        view->uniq = w.uniq;
+        view->cidx = w.cidx;
+    }
     return CG_OK;
 }
 
@@ -768,6 +872,21 @@ size_t dedup_workspace_bytes(int64_t n, cg_layout lay) {
     size_t b;
     carve_dedup(nullptr, n, lay, &b);
     return b;
+}
+
+size_t dedup_fused_workspace_bytes(int64_t n, cg_layout lay) {
+    size_t b;
+    carve_dedup(nullptr, n, lay, &b, true);
+    return b;
+}
+
+cg_status run_dedup_fused(const void *rows, int64_t n, cg_layout lay, void *cells, uint32_t *row_to_cell,
+                          int64_t *d_ncells, void *ws, int hash_s, uint64_t *sfx, DedupView *view, hipStream_t s) {
+    if (lay.word_bits == 64)
+        return dedup_impl<uint64_t>(static_cast<const uint64_t *>(rows), n, lay, static_cast<uint64_t *>(cells),
+                                    row_to_cell, d_ncells, ws, s, hash_s, sfx, view);
+    return dedup_impl<uint32_t>(static_cast<const uint32_t *>(rows), n, lay, static_cast<uint32_t *>(cells),
+                                row_to_cell, d_ncells, ws, s, hash_s, sfx, view);
 }
 
 cg_status run_dedup(const void *rows, int64_t n, cg_layout lay, void *cells, uint32_t *row_to_cell,

@@ -20,19 +20,6 @@ namespace cg {
 
 namespace {
 
-template <typename T>
-__device__ __forceinline__ uint32_t suffix_hash32(const T *row, int words, int s) {
-    constexpr int B = Bits<T>::B;
-    uint64_t h = 0x243f6a8885a308d3ull;
-    const int w0 = s / B;
-    for (int w = w0; w < words; ++w) {
-        T x = row[w];
-        if (w == w0 && (s % B)) x &= (T(~T(0)) >> (s % B));
-        h = fmix64(h ^ (static_cast<uint64_t>(x) + static_cast<uint64_t>(w + 1) * 0x9e3779b97f4a7c15ull));
-    }
-    return static_cast<uint32_t>(h >> 32);
-}
-
 // One block per 256-cell tile.  The tile's rows are read once, coalesced,
 // into LDS (when they fit; wide rows are read in place), then each thread
 // hashes its cell's suffix and writes the directory entries that point at it:
@@ -257,6 +244,52 @@ size_t dict_mem_bytes(int64_t ncap, cg_layout, const cg_dict_params &p) {
     return b;
 }
 
+// Directory from the dedup's sorted keys (the fused dedup + dictionary
+// build): the position that starts cell c writes the entries from just past
+// the previous position's top p bits up to its own, as k_dict_scan does from
+// the cells.  The previous position holds the previous cell or a copy of it
+// (equal rows have equal keys), and the sort key always keeps the top 32
+// bits, so no cell row is read.
+__global__ void __launch_bounds__(DT) k_dir_from_keys(const uint64_t *__restrict__ keys,
+                                                      const uint8_t *__restrict__ uniq,
+                                                      const uint32_t *__restrict__ cidx, int64_t n,
+                                                      const int64_t *d_ncells, int p, uint32_t *__restrict__ dir,
+                                                      uint4 *__restrict__ gaps, unsigned long long *gap_n,
+                                                      int64_t gap_cap, uint4 *__restrict__ huge, int64_t huge_cap) {
+    const int64_t G = int64_t(1) << p;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * DT + threadIdx.x;
+    const bool act = i < n && uniq[i] != 0;
+    int64_t gi = 0, gp = 0;
+    uint32_t c = 0;
+    bool long_gap = false, huge_gap = false;
+    if (act) {
+        c = cidx[i];
+        gi = p ? static_cast<int64_t>(keys[i] >> (64 - p)) : 0;
+        gp = i == 0 ? -1 : (p ? static_cast<int64_t>(keys[i - 1] >> (64 - p)) : 0);
+        long_gap = gi - gp > GAPMIN;
+        huge_gap = gi - gp > GAPHUGE;
+        if (long_gap) {
+            dir[gi] = c;
+        } else {
+            for (int64_t g = gp + 1; g <= gi; ++g) dir[g] = c;
+        }
+    }
+    push_gap(gaps, gap_n, gap_cap, act && long_gap && !huge_gap, gp + 1, gi - 1, c);
+    push_gap(huge, gap_n + 1, huge_cap, act && huge_gap, gp + 1, gi - 1, c);
+    const int64_t nc = *d_ncells;
+    if (act && static_cast<int64_t>(c) == nc - 1) {  // entries gi + 1 .. G point past the end
+        if (G - gi > GAPMIN) {
+            const bool hg = G - gi > GAPHUGE;
+            const unsigned long long k = atomicAdd(hg ? gap_n + 1 : gap_n, 1ull);
+            if (static_cast<int64_t>(k) < (hg ? huge_cap : gap_cap))
+                (hg ? huge : gaps)[k] = make_uint4(static_cast<uint32_t>(gi + 1), static_cast<uint32_t>(G),
+                                                   static_cast<uint32_t>(nc), 0u);
+        } else {
+            for (int64_t g = gi + 1; g <= G; ++g) dir[g] = static_cast<uint32_t>(nc);
+        }
+    }
+}
+
 template <typename T> static cg_status dict_build_impl(cg_dict &d, hipStream_t s) {
     size_t b;
     DictMem m = carve_dict(d.mem, d.ncells_cap, d.params, &b);
@@ -276,6 +309,36 @@ template <typename T> static cg_status dict_build_impl(cg_dict &d, hipStream_t s
     if (ncap > 0)
         CG_TRY(radix_sort_u64(m.sfx, nullptr, ncap, d.d_ncells, 32, 64, m.hist, m.tile_sums, &which, s));
     d.dir = m.dir;
+    d.sfx = m.sfx[which];
+    return CG_OK;
+}
+
+// Fused dedup + dictionary build: the same cells, row_to_cell, directory
+// and suffix order as cg_dedup followed by cg_dict_build, without reading
+// the cells back (suffix hashes come from key extraction, the directory
+// from the sorted keys).  d is filled as by cg_dict_build (cells = the
+// dedup output, ncells_cap = n).
+cg_status run_dedup_dict(const void *rows, int64_t n, cg_layout lay, void *cells, uint32_t *row_to_cell,
+                         int64_t *d_ncells, void *ws, cg_dict &d, hipStream_t s) {
+    size_t b;
+    DictMem m = carve_dict(d.mem, d.ncells_cap, d.params, &b);
+    const int64_t G = int64_t(1) << d.params.dir_bits;
+    CG_TRY(fill_i64(reinterpret_cast<int64_t *>(m.gap_n), 0, 2, s));
+    d.dir = m.dir;
+    d.sfx = m.sfx[0];
+    if (n == 0) {
+        CG_TRY(fill_i64(d_ncells, 0, 1, s));
+        return fill_u32(m.dir, 0u, G + 1, s);
+    }
+    DedupView v{};
+    CG_TRY(run_dedup_fused(rows, n, lay, cells, row_to_cell, d_ncells, ws, d.params.split_bit, m.sfx[0], &v, s));
+    hipLaunchKernelGGL(k_dir_from_keys, dim3(blocks_for(n, DT)), dim3(DT), 0, s, v.keys, v.uniq, v.cidx, n, d_ncells,
+                       d.params.dir_bits, m.dir, m.gaps, m.gap_n, m.gap_cap, m.huge, m.huge_cap);
+    CG_LAUNCHED("dir_from_keys");
+    hipLaunchKernelGGL(k_dir_gaps, dim3(256), dim3(256), 0, s, m.dir, m.gaps, m.gap_n, m.gap_cap, m.huge, m.huge_cap);
+    CG_LAUNCHED("dict_gaps");
+    int which = 0;
+    CG_TRY(radix_sort_u64(m.sfx, nullptr, d.ncells_cap, d_ncells, 32, 64, m.hist, m.tile_sums, &which, s));
     d.sfx = m.sfx[which];
     return CG_OK;
 }

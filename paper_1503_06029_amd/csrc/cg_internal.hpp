@@ -352,6 +352,31 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t x) {
     return x;
 }
 
+// 32-bit hash of bits s .. l-1 of a row (the suffix-grouped order of the
+// dictionary sorts cells by it; equal suffixes give equal hashes).  It is a
+// sum of per-word terms, finished by one mix, so lanes holding different
+// words of a row can add their terms and combine them in any order.
+template <typename T>
+__device__ __forceinline__ uint64_t suffix_term(T x, int w, int s) {
+    constexpr int B = Bits<T>::B;
+    const int w0 = s / B;
+    if (w < w0) return 0;
+    if (w == w0 && (s % B)) x &= (T(~T(0)) >> (s % B));
+    // one multiply per word by a word-dependent odd constant; the sum is
+    // mixed once at the end
+    const uint64_t y = static_cast<uint64_t>(x) ^ (static_cast<uint64_t>(x) >> 29);
+    return y * (0x9e3779b97f4a7c15ull + 2ull * static_cast<uint64_t>(w)) + static_cast<uint64_t>(w);
+}
+__device__ __forceinline__ uint32_t suffix_finish(uint64_t sum) {
+    return static_cast<uint32_t>(fmix64(sum ^ 0x243f6a8885a308d3ull) >> 32);
+}
+template <typename T>
+__device__ __forceinline__ uint32_t suffix_hash32(const T *row, int words, int s) {
+    uint64_t sum = 0;
+    for (int w = 0; w < words; ++w) sum += suffix_term<T>(row[w], w, s);
+    return suffix_finish(sum);
+}
+
 __device__ __forceinline__ int64_t load_n(const int64_t *d_n, int64_t cap) {
     if (!d_n) return cap;
     int64_t n = *d_n;
@@ -467,12 +492,26 @@ cg_status launch_pack(const uint8_t *bits, int64_t n, int64_t row_stride, cg_lay
                       hipStream_t s);
 
 size_t dedup_workspace_bytes(int64_t n, cg_layout lay);
+// The dedup half of the fused dedup + dictionary build: as run_dedup, plus
+// the suffix-order keys of the cells (hash of bits hash_s .. << 32 | id) in
+// sfx, and in *view the sorted keys, new-cell flags and exclusive cell
+// numbering (device arrays in the workspace, n entries) for the directory.
+struct DedupView {
+    const uint64_t *keys;
+    const uint8_t *uniq;
+    const uint32_t *cidx;
+};
+size_t dedup_fused_workspace_bytes(int64_t n, cg_layout lay);
+cg_status run_dedup_fused(const void *rows, int64_t n, cg_layout lay, void *cells, uint32_t *row_to_cell,
+                          int64_t *d_ncells, void *ws, int hash_s, uint64_t *sfx, DedupView *view, hipStream_t s);
 cg_status run_dedup(const void *rows, int64_t n, cg_layout lay, void *cells, uint32_t *row_to_cell,
                     int64_t *d_ncells, void *ws, size_t ws_bytes, hipStream_t s);
 
 size_t dict_mem_bytes(int64_t ncap, cg_layout lay, const cg_dict_params &p);
 cg_dict_params resolve_params(int64_t ncap, cg_layout lay, const cg_dict_params *p);
 cg_status run_dict_build(cg_dict &d, hipStream_t s);
+cg_status run_dedup_dict(const void *rows, int64_t n, cg_layout lay, void *cells, uint32_t *row_to_cell,
+                         int64_t *d_ncells, void *ws, cg_dict &d, hipStream_t s);
 
 cg_status run_neighbors_d1(const cg_dict &d, const void *q, int64_t nq, uint32_t *count, uint32_t *self,
                            void *mask, hipStream_t s);

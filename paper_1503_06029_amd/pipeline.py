@@ -40,7 +40,8 @@ class CellGraph:
         self.cells = torch.empty((m, W), dtype=wdt, device=dev)
         self.r2c = torch.empty(m, dtype=torch.int32, device=dev) if with_row_to_cell else None
         self.ncells = torch.zeros(1, dtype=torch.int64, device=dev)
-        self.ws_dedup_bytes = B.cg_dedup_workspace(self.n, self.lay)
+        # the fused dedup + dictionary build needs a little more than dedup alone
+        self.ws_dedup_bytes = max(B.cg_dedup_workspace(self.n, self.lay), B.cg_dedup_dict_workspace(self.n, self.lay))
         self.ws_dedup = torch.empty(self.ws_dedup_bytes, dtype=torch.uint8, device=dev)
         self.dict_bytes = B.cg_dict_size(self.n, self.lay, self.params)
         self.dict_mem = torch.empty(self.dict_bytes, dtype=torch.uint8, device=dev)
@@ -72,9 +73,19 @@ class CellGraph:
         B.cg_dedup(src, self.n, self.lay, self.cells, self.r2c, self.ncells, self.ws_dedup,
                    self.ws_dedup_bytes, stream)
 
+    def dedup_dict(self, packed: torch.Tensor | None = None, stream=None):
+        """dedup() and build_dict() as one fused call (same results)."""
+        src = self.packed if packed is None else packed
+        self.dict = B.cg_dedup_dict(src, self.n, self.lay, self.cells, self.r2c, self.ncells, self.ws_dedup,
+                                    self.ws_dedup_bytes, self.params, self.dict_mem, self.dict_bytes, stream)
+        self._edges_ws()
+
     def build_dict(self, stream=None):
         self.dict = B.cg_dict_build(self.cells, self.ncells, self.n, self.lay, self.params, self.dict_mem,
                                     self.dict_bytes, stream)
+        self._edges_ws()
+
+    def _edges_ws(self):
         need = B.cg_edges_workspace(self.dict, self.edge_cap)
         if self.ws_edges is None or need > self.ws_edges_bytes:
             self.ws_edges = torch.empty(need, dtype=torch.uint8, device=self.device)

@@ -1,0 +1,127 @@
+"""The fused dedup + dictionary build (cg_dedup_dict) against cg_dedup
+followed by cg_dict_build: the same cells, row_to_cell, directory and
+suffix order, byte for byte, and the same edges; and against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_06029_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_1503_06029_amd import binding, pipeline
+    return torch, binding, pipeline
+
+
+def dict_arrays(torch, g):
+    """Directory and suffix order of g's dictionary (views into its memory)."""
+    d = g.dict
+    base = g.dict_mem.data_ptr()
+    G = (1 << d.params.dir_bits) + 1
+    nc = int(g.ncells.item())
+    o_dir, o_sfx = d.dir - base, d.sfx - base
+    dir_ = g.dict_mem[o_dir:o_dir + 4 * G].cpu().numpy().view(np.uint32).copy()
+    sfx = g.dict_mem[o_sfx:o_sfx + 8 * nc].cpu().numpy().view(np.uint64).copy()
+    return dir_, sfx
+
+
+def both(torch, P, rows, ell, wb, params=None, edge_cap=None):
+    dev = P.to_device_words(rows)
+    out = []
+    for fused in (False, True):
+        g = P.CellGraph(rows.shape[0], ell, wb, params, edge_cap=edge_cap or max(4096, 4 * rows.shape[0]))
+        if fused:
+            g.dedup_dict(dev)
+        else:
+            g.dedup(dev)
+            g.build_dict()
+        g.edges()
+        torch.cuda.synchronize()
+        res = g.fetch()
+        res["dir"], res["sfx"] = dict_arrays(torch, g)
+        out.append(res)
+    return out
+
+
+def assert_same_build(a, b):
+    for k in ("ncells", "nedges", "status"):
+        assert a[k] == b[k], k
+    for k in ("cells", "row_to_cell", "uv", "bit", "offsets", "dir", "sfx"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+CASES = [("l20", 20, 200, 4, 100, 32), ("l40", 40, 300, 6, 100, 32), ("l64", 64, 300, 6, 100, 64),
+         ("l65", 65, 300, 6, 100, 64), ("l130", 130, 700, 10, 700, 64), ("l300", 300, 400, 12, 300, 32),
+         ("l1024", 1024, 300, 15, 500, 64)]
+
+
+@pytest.mark.parametrize("name,ell,nb,fam,dups,wb", CASES)
+def test_fused_equals_separate(gpu, name, ell, nb, fam, dups, wb):
+    torch, B, P = gpu
+    rng = np.random.default_rng(abs(hash(name)) % (2 ** 32))
+    R = inputs.clustered_multiset(rng, nb, ell, fam, dups)
+    rows = oracle.pack(R, wb)
+    say("fused", name, wb, rows.shape)
+    a, b = both(torch, P, rows, ell, wb)
+    assert_same_build(a, b)
+    cells, r2c = oracle.dedup(rows, ell, wb)
+    assert np.array_equal(b["cells"], cells) and np.array_equal(b["row_to_cell"], r2c)
+
+
+@pytest.mark.parametrize("kw", [dict(split_bit=0, dir_bits=1), dict(split_bit=7, dir_bits=12),
+                                dict(split_bit=100, dir_bits=3)])
+def test_fused_parameters(gpu, kw):
+    torch, B, P = gpu
+    rng = np.random.default_rng(5)
+    ell = 150
+    rows = oracle.pack(inputs.clustered_multiset(rng, 400, ell, 8, 300), 64)
+    a, b = both(torch, P, rows, ell, 64, params=B.cg_dict_params_default(**kw))
+    assert_same_build(a, b)
+
+
+def test_fused_heavy_duplicates_and_tiny(gpu):
+    torch, B, P = gpu
+    rng = np.random.default_rng(9)
+    for ell, n, nd in ((70, 20000, 12), (200, 5000, 3), (33, 1, 1), (2000, 3000, 40)):
+        rows = oracle.pack(inputs.random_multiset(rng, n, ell, n_distinct=nd), 32)
+        say("dups", ell, n, nd)
+        a, b = both(torch, P, rows, ell, 32)
+        assert_same_build(a, b)
+
+
+def test_fused_batched_layout(gpu):
+    """Tagged virtual rows (scene number in word 0): the directory over the
+    tag has long empty stretches (listed gaps)."""
+    torch, B, P = gpu
+    from paper_1503_06029_amd import batch
+    scenes = [inputs.c3_scene(i)[:2000] for i in range(6)]
+    sb = batch.SceneBatch([R.shape[1] for R in scenes], [R.shape[0] for R in scenes],
+                          batch.class_words(max(R.shape[1] for R in scenes)))
+    sb.upload(scenes)
+    B.cg_batch_pack(sb.bits, sb.bits_off, sb.scene_ell, sb.scene_rows, sb.n_scenes, sb.n_rows, sb.lay, sb.packed)
+    torch.cuda.synchronize()
+    rows = sb.packed[:sb.n_rows].cpu().numpy().view(np.uint32)
+    a, b = both(torch, P, rows, sb.lay.ell, 32, params=sb.params)
+    assert_same_build(a, b)
+
+
+def test_fused_config2_full_size(gpu):
+    """The long-vector workload (probe picks 32-bit sort keys)."""
+    torch, B, P = gpu
+    rows = inputs.c2()
+    want_cells, want_E = inputs.c2_expected()
+    a, b = both(torch, P, rows, 1024, 64, edge_cap=want_E + 1024)
+    assert b["ncells"] == want_cells and b["nedges"] == want_E
+    assert_same_build(a, b)
