@@ -258,14 +258,19 @@ __global__ void __launch_bounds__(DT) k_dir_from_keys(const uint64_t *__restrict
                                                       int64_t gap_cap, uint4 *__restrict__ huge, int64_t huge_cap) {
     const int64_t G = int64_t(1) << p;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * DT + threadIdx.x;
-    const bool act = i < n && uniq[i] != 0;
+    // all loads issued together (in range), used only by positions that start a cell
+    const int64_t ii = i < n ? i : n - 1;
+    const uint8_t un = uniq[ii];
+    const uint64_t k = keys[ii], kp = keys[ii > 0 ? ii - 1 : 0];
+    const uint32_t ci = cidx[ii];
+    const bool act = i < n && un != 0;
     int64_t gi = 0, gp = 0;
     uint32_t c = 0;
     bool long_gap = false, huge_gap = false;
     if (act) {
-        c = cidx[i];
-        gi = p ? static_cast<int64_t>(keys[i] >> (64 - p)) : 0;
-        gp = i == 0 ? -1 : (p ? static_cast<int64_t>(keys[i - 1] >> (64 - p)) : 0);
+        c = ci;
+        gi = p ? static_cast<int64_t>(k >> (64 - p)) : 0;
+        gp = i == 0 ? -1 : (p ? static_cast<int64_t>(kp >> (64 - p)) : 0);
         long_gap = gi - gp > GAPMIN;
         huge_gap = gi - gp > GAPHUGE;
         if (long_gap) {
