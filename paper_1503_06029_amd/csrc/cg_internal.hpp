@@ -383,69 +383,6 @@ __device__ __forceinline__ int64_t load_n(const int64_t *d_n, int64_t cap) {
     return n < cap ? (n < 0 ? 0 : n) : cap;
 }
 
-// ------------------------------------------------ decoupled look-back scan
-
-// Tile status words: value in the low 62 bits, flag in the top two.
-constexpr uint64_t LB_AGG = 1ull << 62;   // tile aggregate published
-constexpr uint64_t LB_INC = 2ull << 62;   // inclusive prefix published
-constexpr uint64_t LB_VAL = (1ull << 62) - 1;
-constexpr int LB_SPIN_LIMIT = 1 << 22;
-
-__device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Block-wide: given this tile's aggregate (same value in every thread) and
-// its ticket t (tiles are taken in ticket order, so every tile below t is
-// already running), returns the sum of the aggregates of tiles 0 .. t-1.
-// status[] must be zero before the launch.  A wait that exceeds the spin
-// limit sets *err and gives up (the result is then invalid, never a hang).
-// Contains __syncthreads().
-__device__ __forceinline__ uint64_t lookback_exclusive(uint64_t *status, int64_t t, uint64_t agg, uint32_t *err,
-                                                       uint64_t *slot) {
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        uint64_t excl = 0;
-        if (t == 0) {
-            if (lane == 0) lb_store(&status[0], LB_INC | agg);
-        } else {
-            if (lane == 0) lb_store(&status[t], LB_AGG | agg);
-            int64_t look = t - 1;
-            int spins = 0;
-            while (true) {
-                const int64_t idx = look - lane;
-                const uint64_t v = idx >= 0 ? lb_load(&status[idx]) : LB_INC;
-                const uint64_t fl = v >> 62;
-                const uint64_t pmask = ballot64(fl == 2);
-                const uint64_t xmask = ballot64(fl == 0);
-                const int firstP = pmask ? __builtin_ctzll(pmask) : 64;
-                const uint64_t need = firstP >= 63 ? ~0ull : ((2ull << firstP) - 1);
-                if (xmask & need) {
-                    if (++spins > LB_SPIN_LIMIT) {
-                        if (lane == 0) atomicOr(err, 1u);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                uint64_t val = lane <= firstP ? (v & LB_VAL) : 0;
-#pragma unroll
-                for (int d = 32; d >= 1; d >>= 1) val += shfl_u64_xor(val, d);
-                excl += val;
-                if (firstP < 64) break;
-                look -= 64;
-            }
-            if (lane == 0) lb_store(&status[t], LB_INC | ((excl + agg) & LB_VAL));
-        }
-        if (lane == 0) *slot = excl;
-    }
-    __syncthreads();
-    return *slot;
-}
-
 // -------------------------------------------------------- host-side helpers
 
 inline unsigned blocks_for(int64_t items, int64_t per_block, int64_t max_blocks = 1 << 30) {
