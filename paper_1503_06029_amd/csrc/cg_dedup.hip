@@ -491,7 +491,7 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
                 const bool eq = scode[2 * j] == c1m && sv[2 * j] == v1m && (c2jf & 0x7f) == c2m &&
                                 sv[2 * j + 1] == v2m;
                 if (!eq || j == r || (fm && (c2jf & 0x80) != 0)) continue;
-                const int c = row_cmp<T>(rows + static_cast<int64_t>(sval[j]) * words, me, words, FROM);
+                const int c = row_cmp4<T>(rows + static_cast<int64_t>(sval[j]) * words, me, words, FROM);
                 rank += (c < 0 || (c == 0 && j < r)) ? 1 : 0;
                 dup = dup || (c == 0 && j < r);
             }
@@ -519,7 +519,7 @@ template <typename T>
 __device__ __forceinline__ bool idx_less(const T *rows, int words, int from, uint32_t x, uint32_t y) {
     if (x == SENT) return false;
     if (y == SENT) return true;
-    const int c = row_cmp<T>(rows + static_cast<int64_t>(x) * words, rows + static_cast<int64_t>(y) * words,
+    const int c = row_cmp4<T>(rows + static_cast<int64_t>(x) * words, rows + static_cast<int64_t>(y) * words,
                              words, from);
     return c < 0 || (c == 0 && x < y);
 }
@@ -564,7 +564,7 @@ __global__ void __launch_bounds__(1024) k_tiefix_large(const T *__restrict__ row
             bool u = true;
             if (i > 0) {
                 const uint32_t y = scr[i - 1];
-                u = row_cmp<T>(rows + static_cast<int64_t>(x) * words, rows + static_cast<int64_t>(y) * words,
+                u = row_cmp4<T>(rows + static_cast<int64_t>(x) * words, rows + static_cast<int64_t>(y) * words,
                                words, from) != 0;
             }
             uniq[a + i] = u ? 1 : 0;
@@ -634,7 +634,7 @@ __global__ void __launch_bounds__(1024) k_tiefix_mid(const T *__restrict__ rows,
                         } else if (ia == SENT || ib == SENT) {
                             a_gt = ia == SENT;
                         } else {
-                            const int c = row_cmp<T>(rows + static_cast<int64_t>(ia) * words,
+                            const int c = row_cmp4<T>(rows + static_cast<int64_t>(ia) * words,
                                                      rows + static_cast<int64_t>(ib) * words, words, from2);
                             a_gt = c > 0 || (c == 0 && ia > ib);
                         }
@@ -652,7 +652,7 @@ __global__ void __launch_bounds__(1024) k_tiefix_mid(const T *__restrict__ rows,
             vals[a + i] = x;
             bool u = true;
             if (i > 0 && sk[i - 1] == sk[i])
-                u = row_cmp<T>(rows + static_cast<int64_t>(x) * words, rows + static_cast<int64_t>(si[i - 1]) * words,
+                u = row_cmp4<T>(rows + static_cast<int64_t>(x) * words, rows + static_cast<int64_t>(si[i - 1]) * words,
                                words, from2) != 0;
             uniq[a + i] = u ? 1 : 0;
         }

@@ -177,6 +177,26 @@ __device__ __forceinline__ int row_cmp(const T *a, const T *b, int words, int fr
     return 0;
 }
 
+// Same order for rows in global memory: four words of each row are loaded
+// together per step, so a comparison waits for one round trip per four
+// words instead of one per word.
+template <typename T>
+__device__ __forceinline__ int row_cmp4(const T *a, const T *b, int words, int from = 0) {
+    for (int w0 = from; w0 < words; w0 += 4) {
+        T x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int w = w0 + u;
+            x[u] = w < words ? a[w] : T(0);
+            y[u] = w < words ? b[w] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (x[u] != y[u]) return x[u] < y[u] ? -1 : 1;
+    }
+    return 0;
+}
+
 // Compare cell row `c` with (q xor e_k), k < 0 meaning q itself.
 template <typename T>
 __device__ __forceinline__ int row_cmp_flip(const T *c, const T *q, int words, int kw, T km) {
