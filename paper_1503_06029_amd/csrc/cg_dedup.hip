@@ -9,7 +9,8 @@
 //    more rows is ordered by the full row: segments of up to 128 rows by the
 //    block whose tile holds their first position (rank sort over row
 //    summaries taken against the segment's first row), up to LMAX rows by one
-//    block each (bitonic network over (next 64 bits, index) pairs in LDS),
+//    block each (bitonic network over (next 64 bits, index) pairs in LDS;
+//    256-thread blocks up to 2,048 rows, 1,024-thread blocks beyond),
 //    longer ones by one block each (bitonic network over an index array in
 //    global memory);
 // 4. a row is a new cell iff it differs from its predecessor; a scan of those
@@ -577,7 +578,8 @@ __global__ void __launch_bounds__(1024) k_tiefix_large(const T *__restrict__ row
 // segment sorts (next 64 bits of the row, row index) pairs by a bitonic
 // network in LDS; pairs whose 64-bit values tie compare the rest of the rows
 // in global memory.  Then a row is flagged new iff it differs from its
-// predecessor in the segment.
+// predecessor in the segment.  Short segments get small blocks (a bitonic
+// stage over P pairs keeps only P / 2 threads busy), so several share a CU.
 template <typename T>
 __device__ __forceinline__ uint64_t key2_of(const T *row, int words, int from);
 template <>
@@ -591,15 +593,18 @@ __device__ __forceinline__ uint64_t key2_of<uint32_t>(const uint32_t *row, int w
     return (hi << 32) | lo;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(1024) k_tiefix_mid(const T *__restrict__ rows, int words, int from64,
+// NT threads and room for LM rows per block; segments of LO < len <= LM
+// rows are this launch's (two launches: 256 threads for up to 2,048 rows,
+// several blocks per CU; 1,024 threads for the rest up to LMAX).
+template <typename T, int NT, int LM, int LO>
+__global__ void __launch_bounds__(NT) k_tiefix_mid(const T *__restrict__ rows, int words, int from64,
                                                      const uint2 *__restrict__ list,
                                                      const unsigned long long *__restrict__ counters,
                                                      uint32_t *__restrict__ vals, uint8_t *__restrict__ uniq) {
     const int from = counters[2] ? from64 / 2 : from64;  // words covered by the sort key
-    extern __shared__ __align__(16) unsigned char smem[];  // LMAX keys, then LMAX indices
+    extern __shared__ __align__(16) unsigned char smem[];  // LM keys, then LM indices
     uint64_t *sk = reinterpret_cast<uint64_t *>(smem);
-    uint32_t *si = reinterpret_cast<uint32_t *>(smem + LMAX * sizeof(uint64_t));
+    uint32_t *si = reinterpret_cast<uint32_t *>(smem + LM * sizeof(uint64_t));
     constexpr int K2 = 64 / Bits<T>::B;  // words covered by the second key
     const int from2 = from + K2;
     const uint32_t count = static_cast<uint32_t>(counters[1]);
@@ -607,7 +612,7 @@ __global__ void __launch_bounds__(1024) k_tiefix_mid(const T *__restrict__ rows,
         const uint2 seg = list[sgi];
         const int64_t a = seg.x;
         const int len = static_cast<int>(seg.y);
-        if (len > LMAX) continue;  // k_tiefix_large takes it
+        if (len > LM || len <= LO) continue;  // another launch takes it
         int P = 1;
         while (P < len) P <<= 1;
         for (int i = threadIdx.x; i < P; i += blockDim.x) {
@@ -839,10 +844,15 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
                                from, static_cast<int>(smax), vals, w.uniq, w.large_list, w.counters);
             CG_LAUNCHED("dedup_tiefix_tile");
         }
+        constexpr int MID_S = 2048;  // segments up to this many rows: 256-thread blocks, 24 KB of LDS each
+        const size_t mid_lds_s = static_cast<size_t>(MID_S) * (sizeof(uint64_t) + sizeof(uint32_t));
+        hipLaunchKernelGGL((k_tiefix_mid<T, 256, MID_S, 0>), dim3(2048), dim3(256), mid_lds_s, s, rows, words, from,
+                           w.large_list, w.counters, vals, w.uniq);
+        CG_LAUNCHED("dedup_tiefix_mid_s");
         const size_t mid_lds = static_cast<size_t>(LMAX) * (sizeof(uint64_t) + sizeof(uint32_t));
-        CG_TRY(allow_lds(reinterpret_cast<const void *>(&k_tiefix_mid<T>), mid_lds));
-        hipLaunchKernelGGL((k_tiefix_mid<T>), dim3(1024), dim3(1024), mid_lds, s, rows, words, from, w.large_list,
-                           w.counters, vals, w.uniq);
+        CG_TRY(allow_lds(reinterpret_cast<const void *>(&k_tiefix_mid<T, 1024, LMAX, MID_S>), mid_lds));
+        hipLaunchKernelGGL((k_tiefix_mid<T, 1024, LMAX, MID_S>), dim3(1024), dim3(1024), mid_lds, s, rows, words, from,
+                           w.large_list, w.counters, vals, w.uniq);
         CG_LAUNCHED("dedup_tiefix_mid");
         hipLaunchKernelGGL((k_tiefix_large<T>), dim3(256), dim3(1024), 0, s, rows, words, from, w.large_list,
                            w.counters, vals, w.uniq, w.scratch);
