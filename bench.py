@@ -83,7 +83,7 @@ def main():
                     help="served: scenes as descriptions sampled on the GPU (no sign bytes over PCIe)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU: --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "batched":
         return bench_batched(args)

@@ -64,7 +64,7 @@ typedef int32_t cg_status;
 #define CG_EWORKSPACE   -2  /* workspace / dictionary memory smaller than reported size   */
 #define CG_ECAPACITY    -3  /* (device status only) more edges than the output capacity  */
 #define CG_EHIP         -4  /* HIP launch or runtime error; see cg_last_error()           */
-#define CG_EUNSUPPORTED -5  /* valid request this build does not implement               */
+#define CG_EUNSUPPORTED -5  /* valid request the library does not implement             */
 
 typedef struct cg_layout {
     int32_t ell;       /* vector length l, 1 <= l <= 65535                    */
@@ -114,7 +114,7 @@ cg_status cg_dedup(const void *d_packed, int64_t n, cg_layout lay, void *d_cells
 /* ------------------------------------------------------------ dictionary
  * A device dictionary over the sorted distinct cells (Section 3.2: the
  * sorted set makes every vectors(C, v) a contiguous index range; the paper's
- * tree stores its values, the cell ids, in the leaves).  This build keeps:
+ * tree stores its values, the cell ids, in the leaves).  The library keeps:
  *   - the sorted cells themselves (borrowed, not copied);
  *   - a directory over the first p bits: dir[g] = first cell whose first p
  *     bits are >= g, for g = 0 .. 2^p (the top levels of a 2^p-ary tree of
