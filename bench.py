@@ -334,7 +334,7 @@ def bench_search(args):
     count equals the number of separating planes), captured as one graph."""
     import torch
     from paper_1503_06029_amd import inputs, pipeline
-    log("generating config-1 scene")
+    log("generating the plane-arrangement scene")
     R = inputs.c1()
     ell = R.shape[1]
     g = pipeline.CellGraph(R.shape[0], ell, 32, edge_cap=1_100_000)
@@ -393,7 +393,7 @@ def bench_search(args):
         "value": traversed / (ms / 1e3), "unit": "traversed edges/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"config-1 plane arrangement: {R.shape[0]} points, {ell} planes, {nc} cells, "
+        "config": {"workload": f"plane arrangement: {R.shape[0]} points in [-1,1]^3, {ell} planes, {nc} cells, "
                                f"{E} edges; BFS from cell 0", "cells": nc, "edges": E, "levels": got["levels"],
                    "launched_levels": levels},
         "bfs_only_ms": bms, "csr_plus_bfs_ms": ms,
@@ -407,7 +407,7 @@ def bench_search(args):
 
 
 def bench_sample(args):
-    """Sampling fused with packing at the config-1 shape (10^6 points in
+    """Sampling fused with packing at the plane-arrangement shape (10^6 points in
     [-1, 1]^3, 128 planes): points drawn and signs evaluated on the GPU and
     written as packed rows, against the host route (sign bytes made on the
     host, copied from pinned memory, then packed on the GPU)."""

@@ -72,12 +72,14 @@ def planes_in_cube(rng: np.random.Generator, ell: int, n: int) -> np.ndarray:
 
 
 def c0() -> np.ndarray:
-    """Config 0: uint8 (10000, 32) sign matrix, duplicates kept."""
+    """Lines workload: uint8 (10000, 32) sign matrix of 10,000 points in the unit
+    square against 32 lines, duplicates kept."""
     return lines_in_square(_rng(0), 32, 10_000)
 
 
 def c1(n: int = 1_000_000) -> np.ndarray:
-    """Config 1: uint8 (1e6, 128) sign matrix."""
+    """Plane-arrangement workload: uint8 (1e6, 128) sign matrix of 10^6 points
+    in [-1, 1]^3 against 128 planes."""
     return planes_in_cube(_rng(1), 128, n)
 
 
@@ -92,7 +94,7 @@ def flip_bit_u64(rows: np.ndarray, bit: np.ndarray) -> None:
 
 def c2(n_bases: int = 262_144, ell: int = 1024, n_flips: int = 15,
        dup_frac: float = 0.10, seed_extra: int = 0) -> np.ndarray:
-    """Config 2: packed uint64 rows (n_bases * 16 * 1.1, ell / 64).
+    """Long-vector workload: packed uint64 rows (n_bases * 16 * 1.1, ell / 64).
 
     Bases are uniform in [2]^l; each gets ``n_flips`` neighbours made by
     flipping distinct uniformly chosen positions.  Rows are shuffled, then
@@ -123,7 +125,7 @@ def c2(n_bases: int = 262_144, ell: int = 1024, n_flips: int = 15,
 
 
 def c2_expected(n_bases: int = 262_144, n_flips: int = 15):
-    """Cells and edges of config 2 by construction: bases and planted
+    """Cells and edges of the long-vector workload by construction: bases and planted
     neighbours are all distinct, and the only distance-1 pairs are
     (base, planted neighbour), unless two independent uniform 1024-bit bases
     fall within distance 2 of each other (probability below 2^-900)."""
@@ -141,7 +143,7 @@ def c3_scene_params(i: int):
 
 
 def c3_scene(i: int) -> np.ndarray:
-    """Scene i of config 3: uint8 (n_i, l_i) sign matrix."""
+    """Scene i of the 512-scene batch workload: uint8 (n_i, l_i) sign matrix."""
     rng = _rng(3, i)
     ell = int(rng.integers(16, 512, endpoint=True))
     n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(2e5)))))
@@ -149,7 +151,7 @@ def c3_scene(i: int) -> np.ndarray:
 
 
 def c3_scene_desc(i: int):
-    """Scene i of config 3 as a description for the GPU sampler: the same l,
+    """Scene i of the 512-scene batch workload as a description for the GPU sampler: the same l,
     n and planes as c3_scene(i) (rows (a0, a1, a2, c), float64), points to
     be drawn in [-1, 1]^3 with Philox key (MASTER_SEED, i).  Returns
     (planes, n, key)."""
@@ -166,7 +168,7 @@ SAMPLE_BOX = (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0)
 
 
 def c4_trace(rate: float = 2000.0, seconds: float = 60.0, pool: int = C3_SCENES):
-    """Config 4: (arrival times in s, scene index in the config-3 pool)."""
+    """Served trace: (arrival times in s, scene index in the 512-scene pool)."""
     rng = _rng(4)
     gaps = rng.exponential(1.0 / rate, int(rate * seconds * 1.2) + 100)
     t = np.cumsum(gaps)

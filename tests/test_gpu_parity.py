@@ -292,7 +292,7 @@ def test_config1(gpu):
 
 @pytest.mark.timeout(600)
 def test_config2_full_size(gpu):
-    """Config 2 at its real size: dedup checked against the oracle in full,
+    """The long-vector workload at its real size: dedup checked against the oracle in full,
     edges by properties plus sampled oracle neighbour lists."""
     torch, B, P = gpu
     say("config2: generate")

@@ -104,7 +104,7 @@ def test_clustered_components(gpu, name, ell, nb, fam, dups):
 
 
 def test_plane_arrangement_levels_in_chunks(gpu):
-    # an arrangement of planes (config-1 style, smaller): one connected graph
+    # an arrangement of planes (the plane-arrangement workload, smaller): one connected graph
     # with many levels, searched one level per call and in chunks of 5
     torch, B, P = gpu
     R = inputs.planes_in_cube(np.random.default_rng(24), 24, 20000)
