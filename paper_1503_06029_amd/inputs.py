@@ -31,8 +31,10 @@ import numpy as np
 MASTER_SEED = 150306029
 
 
-def _rng(config: int, *extra: int) -> np.random.Generator:
-    ss = np.random.SeedSequence(MASTER_SEED).spawn(5)[config]
+def _rng(workload: int, *extra: int) -> np.random.Generator:
+    """Independent seeded stream per workload (0 lines, 1 plane arrangement,
+    2 long vectors, 3 scene batch, 4 served trace) and sub-stream."""
+    ss = np.random.SeedSequence(MASTER_SEED).spawn(5)[workload]
     for e in extra:
         ss = ss.spawn(e + 1)[e]
     return np.random.Generator(np.random.PCG64(ss))
