@@ -296,8 +296,11 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
     __shared__ int16_t segof[WSLOTS];       // slot of the row's head, -1 if not sorted here
     __shared__ int16_t seglen[WSLOTS];
     __shared__ uint8_t hcof[TT];            // compact head index of a head slot
-    __shared__ uint8_t scode[2 * WSLOTS];   // per row: level-1 code, level-2 code | flag
-    __shared__ T sv[2 * WSLOTS];            // per row: level-1 word, level-2 word
+    // summary levels per row: 32-bit words keep four for the LDS two 64-bit
+    // words take (rows of 32-bit words tend to share more leading words)
+    constexpr int LV = sizeof(T) == 4 ? 4 : 2;
+    __shared__ uint8_t scode[LV * WSLOTS];  // per row and level: code (| flag on the last level)
+    __shared__ T sv[LV * WSLOTS];           // per row and level: the row's word there
     __shared__ T heads[HC * WT];
     __shared__ unsigned long long smask[NCH];
     __shared__ int wcnt[TT / 64];
@@ -385,10 +388,11 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
             segof[e] = so;
             seglen[e] = sl;
             if (so >= 0) {
-                scode[2 * e] = static_cast<uint8_t>(WT);
-                scode[2 * e + 1] = static_cast<uint8_t>(WT | 0x80);
-                sv[2 * e] = T(0);
-                sv[2 * e + 1] = T(0);
+#pragma unroll
+                for (int c = 0; c < LV; ++c) {
+                    scode[LV * e + c] = static_cast<uint8_t>(c == LV - 1 ? (WT | 0x80) : WT);
+                    sv[LV * e + c] = T(0);
+                }
             }
         }
         if (k == 0) {
@@ -415,10 +419,10 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
         const bool ne = a >= 0 && wcmp && x != y;
         const uint32_t gm = static_cast<uint32_t>(ballot64(ne) >> gshift) & GMASK;
         const int c = __popc(gm & below_w);  // differing words before this one
-        if (ne && c < 2) {
+        if (ne && c < LV) {
             const int code = (x < y) ? w : 2 * WT - w;
-            scode[2 * r + c] = static_cast<uint8_t>(code | ((c == 1 && __popc(gm) <= 2) ? 0x80 : 0));
-            sv[2 * r + c] = x;
+            scode[LV * r + c] = static_cast<uint8_t>(code | ((c == LV - 1 && __popc(gm) <= LV) ? 0x80 : 0));
+            sv[LV * r + c] = x;
         }
     };
     {
@@ -464,21 +468,36 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
         const int a = segof[r];
         if (a < 0) continue;
         const int len = seglen[r];
-        const int c1m = scode[2 * r], c2f = scode[2 * r + 1];
-        const int c2m = c2f & 0x7f;
-        const bool fm = (c2f & 0x80) != 0;
-        const T v1m = sv[2 * r], v2m = sv[2 * r + 1];
+        int cm[LV];
+        T vm[LV];
+#pragma unroll
+        for (int c = 0; c < LV; ++c) {
+            cm[c] = scode[LV * r + c] & 0x7f;
+            vm[c] = sv[LV * r + c];
+        }
+        const bool fm = (scode[LV * r + LV - 1] & 0x80) != 0;
+        // lexicographic over the levels: (code, word) pairs
+        auto cmp_levels = [&](int j, bool &lt, bool &eq, bool &fj) {
+            lt = false;
+            eq = true;
+#pragma unroll
+            for (int c = 0; c < LV; ++c) {
+                const int cf = scode[LV * j + c];
+                const int cj = cf & 0x7f;
+                const T vj = sv[LV * j + c];
+                const bool e = (cj == cm[c]) & (vj == vm[c]);
+                lt = lt | (eq & ((cj < cm[c]) | ((cj == cm[c]) & (vj < vm[c]))));
+                eq = eq & e;
+                if (c == LV - 1) fj = (cf & 0x80) != 0;
+            }
+        };
         int rank = 0;
         bool dup = false, anytie = false;
-#pragma unroll 4
+#pragma unroll 2
         for (int j = a; j < a + len; ++j) {
-            const int c1j = scode[2 * j], c2jf = scode[2 * j + 1];
-            const int c2j = c2jf & 0x7f;
-            const T v1j = sv[2 * j], v2j = sv[2 * j + 1];
-            const bool e1 = c1j == c1m, ev1 = v1j == v1m, e2 = c2j == c2m, ev2 = v2j == v2m;
-            const bool lt = (c1j < c1m) | (e1 & ((v1j < v1m) | (ev1 & ((c2j < c2m) | (e2 & (v2j < v2m))))));
-            const bool eq = e1 & ev1 & e2 & ev2;
-            const bool same = eq & fm & ((c2jf & 0x80) != 0);
+            bool lt, eq, fj;
+            cmp_levels(j, lt, eq, fj);
+            const bool same = eq & fm & fj;
             const bool before = j < r;
             rank += (lt | (same & before)) ? 1 : 0;
             dup = dup | (same & before);
@@ -488,10 +507,9 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
             // rows with equal summaries that may differ: compare them in full
             const T *me = rows + static_cast<int64_t>(sval[r]) * words;
             for (int j = a; j < a + len; ++j) {
-                const int c2jf = scode[2 * j + 1];
-                const bool eq = scode[2 * j] == c1m && sv[2 * j] == v1m && (c2jf & 0x7f) == c2m &&
-                                sv[2 * j + 1] == v2m;
-                if (!eq || j == r || (fm && (c2jf & 0x80) != 0)) continue;
+                bool lt, eq, fj;
+                cmp_levels(j, lt, eq, fj);
+                if (!eq || j == r || (fm && fj)) continue;
                 const int c = row_cmp4<T>(rows + static_cast<int64_t>(sval[j]) * words, me, words, FROM);
                 rank += (c < 0 || (c == 0 && j < r)) ? 1 : 0;
                 dup = dup || (c == 0 && j < r);
