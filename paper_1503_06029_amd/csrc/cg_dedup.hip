@@ -263,21 +263,22 @@ __global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, 
 // returns at once).  Only the first row of each segment, its head, is kept
 // in LDS; every other row streams in with WT lanes per row, each lane
 // comparing one word with the head's, and a ballot over the lanes gives the
-// words where the row and the head differ.  Each row keeps a two-level
-// summary against its head:
-//   level 1: the first word f1 past the sort key where they differ, as an
-//            order code (f1 if the row is below the head there, 2 WT - f1 if
-//            above, WT if the rows are equal) and the row's word there;
-//   level 2: the same for the next word where they differ, plus a flag set
-//            when they differ in at most two words.
+// words where the row and the head differ.  Each row keeps an LV-level
+// summary against its head (LV = 2 for 64-bit words, 4 for 32-bit words):
+//   level c: the (c+1)-th word past the sort key where they differ, as an
+//            order code (its index f if the row is below the head there,
+//            2 WT - f if above, WT once the rows agree on every word left)
+//            and the row's word there;
+//   the last level also carries a flag set when they differ in at most LV
+//   words.
 // Among rows that agree with the head up to some word, the one that leaves
 // it there downwards is the smaller, and of two rows leaving it downwards the
 // one leaving first is the smaller (upwards: the one leaving last), so rows
-// order as their summaries (code1, v1, code2, v2) do.  Equal summaries with
-// both flags set mean equal rows; without, the rows themselves are compared
-// (both differ from the head in three or more words and agree on the first
-// two of them).  A row's rank in its segment (ties broken by position) is
-// its sorted position; it is a duplicate iff an equal row precedes it.
+// order as their summaries (code, word) level by level do.  Equal summaries
+// with both flags set mean equal rows; without, the rows themselves are
+// compared (both differ from the head in more than LV words and agree on the
+// first LV of them).  A row's rank in its segment (ties broken by position)
+// is its sorted position; it is a duplicate iff an equal row precedes it.
 constexpr int WSMAX = 128;           // longest segment sorted here
 constexpr int WSLOTS = TT + WSMAX;   // window: the tile and the longest segment reaching past it
 
