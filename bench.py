@@ -67,7 +67,7 @@ def cpu_baseline(rows: np.ndarray, n_cells: int, n_edges: int, dedup_rows: int, 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-dedup-rows", type=int, default=400_000)
