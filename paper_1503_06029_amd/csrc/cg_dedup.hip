@@ -260,10 +260,12 @@ __global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, 
 // of TT positions, ordered by the full row (WT: row words rounded up to a
 // power of two, fixed at compile time; KB: the sort key's width in bits, 32
 // or 64, and the kernel for the width the probe (counters[2]) did not choose
-// returns at once).  Only the first row of each segment, its head, is kept
-// in LDS; every other row streams in with WT lanes per row, each lane
-// comparing one word with the head's, and a ballot over the lanes gives the
-// words where the row and the head differ.  Each row keeps an LV-level
+// returns at once; HB: rows in flight per thread).  Rows stream in with WT
+// lanes per row, each lane loading one word of the row and the same word of
+// the segment's first row, its head (loaded by every row of the segment, so
+// mostly served from cache; no LDS copy of the heads keeps the block at 13 KB
+// of LDS), and a ballot over the lanes gives the words where the row and the
+// head differ.  Each row keeps an LV-level
 // summary against its head (LV = 2 for 64-bit words, 4 for 32-bit words):
 //   level c: the (c+1)-th word past the sort key where they differ, as an
 //            order code (its index f if the row is below the head there,
@@ -282,13 +284,12 @@ __global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, 
 constexpr int WSMAX = 128;           // longest segment sorted here
 constexpr int WSLOTS = TT + WSMAX;   // window: the tile and the longest segment reaching past it
 
-template <typename T, int WT, int KB>
+template <typename T, int WT, int KB, int HB = 8>
 __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, const uint64_t *__restrict__ keys,
                                                  int64_t n, int words, uint32_t *__restrict__ vals,
                                                  uint8_t *__restrict__ uniq, uint2 *__restrict__ large_list,
                                                  unsigned long long *__restrict__ counters) {
     constexpr int FROM = KB / Bits<T>::B;  // words covered by the sort key
-    constexpr int HC = TT / 2;             // heads of 2+ row segments starting in a tile
     constexpr int NCH = 2 * TT / 64;       // 64-slot chunks of start flags
     constexpr uint32_t GMASK = (WT >= 32) ? 0xFFFFFFFFu : ((1u << WT) - 1u);
     constexpr int RPS = TT / WT;           // rows per TT consecutive elements
@@ -296,15 +297,12 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
     __shared__ uint32_t sval[WSLOTS];
     __shared__ int16_t segof[WSLOTS];       // slot of the row's head, -1 if not sorted here
     __shared__ int16_t seglen[WSLOTS];
-    __shared__ uint8_t hcof[TT];            // compact head index of a head slot
     // summary levels per row: 32-bit words keep four for the LDS two 64-bit
     // words take (rows of 32-bit words tend to share more leading words)
     constexpr int LV = sizeof(T) == 4 ? 4 : 2;
     __shared__ uint8_t scode[LV * WSLOTS];  // per row and level: code (| flag on the last level)
     __shared__ T sv[LV * WSLOTS];           // per row and level: the row's word there
-    __shared__ T heads[HC * WT];
     __shared__ unsigned long long smask[NCH];
-    __shared__ int wcnt[TT / 64];
     __shared__ int tail_end;                // one past the last row past the tile sorted here
     if ((counters[2] != 0) != (KB == 32)) return;
     const int64_t b0 = static_cast<int64_t>(blockIdx.x) * TT;
@@ -343,7 +341,6 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
     // each slot's segment: its head (the last start at or before it) and its
     // end (the next start, the end of the input, or open past the window);
     // summaries start as "equal to the head"
-    bool head = false;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int e = t + k * TT;
@@ -376,7 +373,6 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
                 } else if (len <= WSMAX) {
                     so = static_cast<int16_t>(st);
                     sl = static_cast<int16_t>(len);
-                    if (e == st) head = true;
                 } else if (e == st) {
                     const int64_t p = b0 + st;
                     const int64_t end = en < 0 ? run_end(keys, p, n) : b0 + en;
@@ -399,14 +395,11 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
         if (k == 0) {
             // heads lie in the tile: slot e = t, one wave per 64 slots
             wave_append<uint2>(large_list, &counters[1], n, large, seg);
-            const unsigned long long hb = ballot64(head);
-            if (lane == 0) wcnt[wv] = __popcll(hb);
         } else {
             const unsigned long long tb = ballot64(so >= 0);
             if (tb && lane == 0) atomicMax(&tail_end, (t - lane) + TT + 64 - __clzll(tb));
         }
     }
-    const unsigned long long hbits = ballot64(head);  // heads of this wave (slot t, k = 0)
     __syncthreads();
 
     // Rows stream in with WT lanes per row: lane w of a row holds word w.
@@ -415,8 +408,7 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
     const int gshift = lane & ~(WT - 1);
     const uint32_t below_w = (1u << w) - 1u;  // the row's words before w
     const bool wload = w < words, wcmp = w >= FROM;
-    auto summarize = [&](int r, int a, T x) {
-        const T y = a >= 0 ? heads[hcof[a] * WT + w] : T(0);
+    auto summarize = [&](int r, int a, T x, T y) {
         const bool ne = a >= 0 && wcmp && x != y;
         const uint32_t gm = static_cast<uint32_t>(ballot64(ne) >> gshift) & GMASK;
         const int c = __popc(gm & below_w);  // differing words before this one
@@ -428,40 +420,32 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
     };
     {
         constexpr int UT = WT;                  // the tile's TT rows: WT elements per thread
-        constexpr int U = UT < 16 ? UT : 16;    // elements in flight per thread
+        constexpr int U = UT < HB ? UT : HB;    // rows in flight per thread (and as many head words)
         static_assert(UT % U == 0, "tile batches");
         for (int ub = 0; ub < UT; ub += U) {
-            T x[U];
+            T x[U], y[U];
             int as[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int r = (ub + u) * RPS + rsub;
                 const int a = segof[r];
                 as[u] = a;
-                x[u] = (a >= 0 && wload) ? rows[static_cast<int64_t>(sval[r]) * words + w] : T(0);
-            }
-            if (ub == 0) {
-                // head rows into LDS (their loads overlap the first batch's)
-                if (head) {
-                    int hc = __popcll(hbits & lanemask_lt());
-                    for (int q = 0; q < wv; ++q) hc += wcnt[q];
-                    hcof[t] = static_cast<uint8_t>(hc);
-                    const T *src = rows + static_cast<int64_t>(sval[t]) * words;
-#pragma unroll
-                    for (int q = 0; q < WT; ++q) heads[hc * WT + q] = q < words ? src[q] : T(0);
-                }
-                __syncthreads();
+                const bool ld = a >= 0 && wload;
+                x[u] = ld ? rows[static_cast<int64_t>(sval[r]) * words + w] : T(0);
+                y[u] = ld ? rows[static_cast<int64_t>(sval[a]) * words + w] : T(0);
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) summarize((ub + u) * RPS + rsub, as[u], x[u]);
+            for (int u = 0; u < U; ++u) summarize((ub + u) * RPS + rsub, as[u], x[u], y[u]);
         }
         // rows past the tile that belong to segments starting in it
         const int te = tail_end;
         for (int r0 = TT; r0 < te; r0 += RPS) {
             const int r = r0 + rsub;
             const int a = r < te ? segof[r] : -1;
-            const T x = (a >= 0 && wload) ? rows[static_cast<int64_t>(sval[r]) * words + w] : T(0);
-            summarize(r, a, x);
+            const bool ld = a >= 0 && wload;
+            const T x = ld ? rows[static_cast<int64_t>(sval[r]) * words + w] : T(0);
+            const T y = ld ? rows[static_cast<int64_t>(sval[a]) * words + w] : T(0);
+            summarize(r, a, x, y);
         }
     }
     __syncthreads();
