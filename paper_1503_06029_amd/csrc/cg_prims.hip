@@ -151,10 +151,16 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint64_t *keys,
     const int64_t n = load_n(d_n, n_cap);
     const int64_t base = static_cast<int64_t>(blockIdx.x) * RS_TILE;
     if (base < n) {
+        // the tile's loads are issued together, then counted
+        uint64_t k[RS_ITEMS];
+#pragma unroll
         for (int j = 0; j < RS_ITEMS; ++j) {
-            int64_t i = base + j * RS_THREADS + t;
-            if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
+            const int64_t i = base + j * RS_THREADS + t;
+            k[j] = i < n ? keys[i] : 0;
         }
+#pragma unroll
+        for (int j = 0; j < RS_ITEMS; ++j)
+            if (base + j * RS_THREADS + t < n) atomicAdd(&h[(k[j] >> shift) & (RADIX - 1)], 1u);
     }
     __syncthreads();
     hist[static_cast<int64_t>(t) * num_tiles + blockIdx.x] = h[t];
@@ -163,26 +169,56 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint64_t *keys,
 // Column scan of the digit-major tile histograms hist[d * num_tiles + tile],
 // one block per digit: each row is scanned in place (exclusive, from 0) and
 // its total goes to dtot[d]; the scatter adds the totals of the smaller
-// digits.
+// digits.  The row passes through LDS in chunks of DS_CHUNK entries, loaded
+// and stored coalesced; within a chunk thread t scans entries
+// [t * DS_PER, (t + 1) * DS_PER), one pad word per DS_PER entries keeping
+// the threads on distinct banks.
+constexpr int DS_PER = 16;
+constexpr int DS_CHUNK = RS_THREADS * DS_PER;
+
 __global__ void __launch_bounds__(RS_THREADS) k_radix_dscan(uint32_t *hist, int num_tiles, uint32_t *dtot,
                                                             const unsigned long long *skip) {
     if (skip && *skip) return;
     __shared__ uint64_t tmp[4];
+    __shared__ uint32_t sr[DS_CHUNK + DS_CHUNK / DS_PER];
     const int d = blockIdx.x, t = threadIdx.x;
-    // thread t owns a contiguous chunk of the row
     uint32_t *row = hist + static_cast<int64_t>(d) * num_tiles;
-    const int per = (num_tiles + RS_THREADS - 1) / RS_THREADS;
-    const int a = t * per, b = a + per < num_tiles ? a + per : num_tiles;
-    uint64_t sum = 0;
-    for (int k = a; k < b; ++k) sum += row[k];
-    uint64_t tot;
-    uint64_t run = block256_excl_scan_u64(sum, tmp, &tot);
-    for (int k = a; k < b; ++k) {
-        const uint32_t x = row[k];
-        row[k] = static_cast<uint32_t>(run);
-        run += x;
+    auto pad = [](int k) { return k + k / DS_PER; };
+    uint64_t carry = 0;
+    for (int c0 = 0; c0 < num_tiles; c0 += DS_CHUNK) {
+        const int len = num_tiles - c0 < DS_CHUNK ? num_tiles - c0 : DS_CHUNK;
+        uint32_t x[DS_PER];
+#pragma unroll
+        for (int j = 0; j < DS_PER; ++j) {
+            const int k = j * RS_THREADS + t;
+            x[j] = k < len ? row[c0 + k] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < DS_PER; ++j) sr[pad(j * RS_THREADS + t)] = x[j];
+        __syncthreads();
+        uint64_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < DS_PER; ++j) {
+            x[j] = sr[pad(t * DS_PER + j)];
+            sum += x[j];
+        }
+        uint64_t tot;
+        uint64_t run = carry + block256_excl_scan_u64(sum, tmp, &tot);
+#pragma unroll
+        for (int j = 0; j < DS_PER; ++j) {
+            sr[pad(t * DS_PER + j)] = static_cast<uint32_t>(run);
+            run += x[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < DS_PER; ++j) {
+            const int k = j * RS_THREADS + t;
+            if (k < len) row[c0 + k] = sr[pad(k)];
+        }
+        carry += tot;
+        __syncthreads();
     }
-    if (t == 0) dtot[d] = static_cast<uint32_t>(tot);
+    if (t == 0) dtot[d] = static_cast<uint32_t>(carry);
 }
 
 template <bool HAS_VALS>
@@ -212,13 +248,21 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *ki
     uint32_t val[RS_ITEMS];
     uint32_t rank[RS_ITEMS];
     const uint64_t lt = lanemask_lt();
+    // wave w owns the contiguous sub-tile [w * 64 * ITEMS, (w + 1) * 64 * ITEMS);
+    // all of a thread's loads are issued before the ranking (whose wave
+    // barriers would otherwise hold each load back until the previous item
+    // is ranked)
 #pragma unroll
     for (int j = 0; j < RS_ITEMS; ++j) {
-        // wave w owns the contiguous sub-tile [w * 64 * ITEMS, (w + 1) * 64 * ITEMS)
-        int li = (w * RS_ITEMS + j) * 64 + lane;
-        bool valid = li < tile_n;
+        const int li = (w * RS_ITEMS + j) * 64 + lane;
+        const bool valid = li < tile_n;
         key[j] = valid ? kin[base + li] : 0;
         if (HAS_VALS) val[j] = valid ? vin[base + li] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        int li = (w * RS_ITEMS + j) * 64 + lane;
+        bool valid = li < tile_n;
         int d = static_cast<int>((key[j] >> shift) & (RADIX - 1));
         uint64_t m = ballot64(valid);
 #pragma unroll
