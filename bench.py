@@ -100,9 +100,9 @@ def main():
     from paper_1503_06029_amd import binding as B, inputs, pipeline
 
     log("generating workload")
-    rows = inputs.c2()
+    rows = inputs.long_vectors()
     n = rows.shape[0]
-    want_cells, want_E = inputs.c2_expected()
+    want_cells, want_E = inputs.long_vectors_expected()
     dev_rows = pipeline.to_device_words(rows)
     g = pipeline.CellGraph(n, 1024, 64, edge_cap=want_E + 1024, with_bits=True)
     torch.cuda.synchronize()
@@ -192,7 +192,7 @@ def main():
 
 def scene_pool(k):
     from paper_1503_06029_amd import inputs
-    return [inputs.c3_scene(i) for i in range(k)]
+    return [inputs.batch_scene(i) for i in range(k)]
 
 
 def bench_batched(args):
@@ -272,8 +272,8 @@ def bench_served_sampled(args):
     batch: a request moves a few bytes of scene table, not its sign bytes."""
     from paper_1503_06029_amd import inputs, serve
     log("scene descriptions")
-    descs = [inputs.c3_scene_desc(i) for i in range(args.scenes)]
-    t, sc = inputs.c4_trace(seconds=args.seconds)
+    descs = [inputs.batch_scene_desc(i) for i in range(args.scenes)]
+    t, sc = inputs.served_trace(seconds=args.seconds)
     t = np.asarray(t)
     srv = serve.SampledServer(descs, inputs.SAMPLE_BOX)
     srv.serve(np.zeros(8), sc[:8])
@@ -301,7 +301,7 @@ def bench_served(args):
     from paper_1503_06029_amd import inputs, serve
     log("generating scene pool")
     pool = scene_pool(args.scenes)
-    t, sc = inputs.c4_trace(seconds=args.seconds)
+    t, sc = inputs.served_trace(seconds=args.seconds)
     t = np.asarray(t)
     log(f"{len(t)} requests over {args.seconds} s")
     srv = serve.Server(pool)
@@ -335,7 +335,7 @@ def bench_search(args):
     import torch
     from paper_1503_06029_amd import inputs, pipeline
     log("generating the plane-arrangement scene")
-    R = inputs.c1()
+    R = inputs.plane_arrangement()
     ell = R.shape[1]
     g = pipeline.CellGraph(R.shape[0], ell, 32, edge_cap=1_100_000)
     g.pack(torch.from_numpy(np.ascontiguousarray(R)).cuda())
@@ -493,7 +493,7 @@ def bench_queries(args):
     import torch
     from paper_1503_06029_amd import inputs, pipeline, service
     log("generating workload")
-    rows = inputs.c2()
+    rows = inputs.long_vectors()
     n, W = rows.shape
     ell = 1024
     svc = service.DictService(ell, 64, capacity=n + n // 100 + 1024)

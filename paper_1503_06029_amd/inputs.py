@@ -10,15 +10,15 @@ The paper's own workloads (a sample generator over SO(3) rotations and
 real-life scenes) are not available, so these stand in for them at the scale
 the paper assumes (n up to a few million, l up to a few hundred):
 
-* ``c0``: 32 random lines in the unit square, 10,000 uniform points;
-* ``c1``: 128 random planes in [-1, 1]^3, 1,000,000 uniform points;
-* ``c2``: 262,144 random 1024-bit base vectors, each with 15 neighbours made
+* ``line_arrangement``: 32 random lines in the unit square, 10,000 uniform points;
+* ``plane_arrangement``: 128 random planes in [-1, 1]^3, 1,000,000 uniform points;
+* ``long_vectors``: 262,144 random 1024-bit base vectors, each with 15 neighbours made
   by flipping 15 distinct uniformly chosen bits, rows shuffled, 10% duplicate
   rows appended and shuffled again (4,613,734 rows, already packed as
   16 x uint64, most significant bit first);
-* ``c3_scene``: one scene of the batched distribution (l uniform in 16..512
+* ``batch_scene``: one scene of the batched distribution (l uniform in 16..512
   random planes in R^3, sample count log-uniform in [1,000, 200,000]);
-* ``c4_trace``: Poisson arrivals at 2,000 scenes/s for 60 s over a pool of
+* ``served_trace``: Poisson arrivals at 2,000 scenes/s for 60 s over a pool of
   512 scenes of the batched distribution.
 
 A sign is 1 iff the point satisfies the constraint a . p - c >= 0, computed
@@ -73,13 +73,13 @@ def planes_in_cube(rng: np.random.Generator, ell: int, n: int) -> np.ndarray:
     return _signs(pts, a, c)
 
 
-def c0() -> np.ndarray:
+def line_arrangement() -> np.ndarray:
     """Lines workload: uint8 (10000, 32) sign matrix of 10,000 points in the unit
     square against 32 lines, duplicates kept."""
     return lines_in_square(_rng(0), 32, 10_000)
 
 
-def c1(n: int = 1_000_000) -> np.ndarray:
+def plane_arrangement(n: int = 1_000_000) -> np.ndarray:
     """Plane-arrangement workload: uint8 (1e6, 128) sign matrix of 10^6 points
     in [-1, 1]^3 against 128 planes."""
     return planes_in_cube(_rng(1), 128, n)
@@ -94,7 +94,7 @@ def flip_bit_u64(rows: np.ndarray, bit: np.ndarray) -> None:
     rows[idx, w] ^= m
 
 
-def c2(n_bases: int = 262_144, ell: int = 1024, n_flips: int = 15,
+def long_vectors(n_bases: int = 262_144, ell: int = 1024, n_flips: int = 15,
        dup_frac: float = 0.10, seed_extra: int = 0) -> np.ndarray:
     """Long-vector workload: packed uint64 rows (n_bases * 16 * 1.1, ell / 64).
 
@@ -126,7 +126,7 @@ def c2(n_bases: int = 262_144, ell: int = 1024, n_flips: int = 15,
     return np.ascontiguousarray(rows)
 
 
-def c2_expected(n_bases: int = 262_144, n_flips: int = 15):
+def long_vectors_expected(n_bases: int = 262_144, n_flips: int = 15):
     """Cells and edges of the long-vector workload by construction: bases and planted
     neighbours are all distinct, and the only distance-1 pairs are
     (base, planted neighbour), unless two independent uniform 1024-bit bases
@@ -134,17 +134,17 @@ def c2_expected(n_bases: int = 262_144, n_flips: int = 15):
     return n_bases * (n_flips + 1), n_bases * n_flips
 
 
-C3_SCENES = 512
+BATCH_SCENES = 512
 
 
-def c3_scene_params(i: int):
+def batch_scene_params(i: int):
     rng = _rng(3, i)
     ell = int(rng.integers(16, 512, endpoint=True))
     n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(2e5)))))
     return ell, n
 
 
-def c3_scene(i: int) -> np.ndarray:
+def batch_scene(i: int) -> np.ndarray:
     """Scene i of the 512-scene batch workload: uint8 (n_i, l_i) sign matrix."""
     rng = _rng(3, i)
     ell = int(rng.integers(16, 512, endpoint=True))
@@ -152,9 +152,9 @@ def c3_scene(i: int) -> np.ndarray:
     return planes_in_cube(rng, ell, n)
 
 
-def c3_scene_desc(i: int):
+def batch_scene_desc(i: int):
     """Scene i of the 512-scene batch workload as a description for the GPU sampler: the same l,
-    n and planes as c3_scene(i) (rows (a0, a1, a2, c), float64), points to
+    n and planes as batch_scene(i) (rows (a0, a1, a2, c), float64), points to
     be drawn in [-1, 1]^3 with Philox key (MASTER_SEED, i).  Returns
     (planes, n, key)."""
     rng = _rng(3, i)
@@ -169,7 +169,7 @@ def c3_scene_desc(i: int):
 SAMPLE_BOX = (-1.0, -1.0, -1.0, 1.0, 1.0, 1.0)
 
 
-def c4_trace(rate: float = 2000.0, seconds: float = 60.0, pool: int = C3_SCENES):
+def served_trace(rate: float = 2000.0, seconds: float = 60.0, pool: int = BATCH_SCENES):
     """Served trace: (arrival times in s, scene index in the 512-scene pool)."""
     rng = _rng(4)
     gaps = rng.exponential(1.0 / rate, int(rate * seconds * 1.2) + 100)

@@ -106,7 +106,7 @@ def test_fused_batched_layout(gpu):
     tag has long empty stretches (listed gaps)."""
     torch, B, P = gpu
     from paper_1503_06029_amd import batch
-    scenes = [inputs.c3_scene(i)[:2000] for i in range(6)]
+    scenes = [inputs.batch_scene(i)[:2000] for i in range(6)]
     sb = batch.SceneBatch([R.shape[1] for R in scenes], [R.shape[0] for R in scenes],
                           batch.class_words(max(R.shape[1] for R in scenes)))
     sb.upload(scenes)
@@ -117,11 +117,11 @@ def test_fused_batched_layout(gpu):
     assert_same_build(a, b)
 
 
-def test_fused_config2_full_size(gpu):
+def test_fused_long_vectors_full_size(gpu):
     """The long-vector workload (probe picks 32-bit sort keys)."""
     torch, B, P = gpu
-    rows = inputs.c2()
-    want_cells, want_E = inputs.c2_expected()
+    rows = inputs.long_vectors()
+    want_cells, want_E = inputs.long_vectors_expected()
     a, b = both(torch, P, rows, 1024, 64, edge_cap=want_E + 1024)
     assert b["ncells"] == want_cells and b["nedges"] == want_E
     assert_same_build(a, b)

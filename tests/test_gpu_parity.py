@@ -268,42 +268,42 @@ def test_repeatable_bytes(gpu):
 
 # -------------------------------------------------------- the workloads
 
-def test_config0(gpu):
+def test_line_arrangement(gpu):
     torch, B, P = gpu
-    say("config0")
-    R = inputs.c0()
+    say("line arrangement")
+    R = inputs.line_arrangement()
     ref = oracle_graph(R, 32, 32)
     assert_same(P.cell_graph(R, 32, 32), ref)
     assert_same(P.cell_graph(R, 32, 64), oracle_graph(R, 32, 64))
 
 
 @pytest.mark.timeout(600)
-def test_config1(gpu):
+def test_plane_arrangement(gpu):
     torch, B, P = gpu
-    say("config1: generate")
-    R = inputs.c1()
-    say("config1: oracle")
+    say("plane arrangement: generate")
+    R = inputs.plane_arrangement()
+    say("plane arrangement: oracle")
     ref = oracle_graph(R, 128, 32)
-    say("config1: gpu")
+    say("plane arrangement: gpu")
     res = P.cell_graph(R, 128, 32)
     assert_same(res, ref)
     assert res["nedges"] <= 1_040_512
 
 
 @pytest.mark.timeout(600)
-def test_config2_full_size(gpu):
+def test_long_vectors_full_size(gpu):
     """The long-vector workload at its real size: dedup checked against the oracle in full,
     edges by properties plus sampled oracle neighbour lists."""
     torch, B, P = gpu
-    say("config2: generate")
-    rows = inputs.c2()
+    say("long vectors: generate")
+    rows = inputs.long_vectors()
     n = rows.shape[0]
-    want_cells, want_E = inputs.c2_expected()
-    say("config2: gpu")
+    want_cells, want_E = inputs.long_vectors_expected()
+    say("long vectors: gpu")
     res = P.cell_graph(rows, 1024, 64, packed=True)
     cells, r2c, uv, bit, off = res["cells"], res["row_to_cell"], res["uv"], res["bit"], res["offsets"]
     assert res["ncells"] == want_cells and res["nedges"] == want_E and res["status"] == 0
-    say("config2: properties")
+    say("long vectors: properties")
     # cells strictly increasing (lexicographic = unsigned word order), every row maps to an equal cell,
     # and every cell is hit: so the cells are exactly the distinct rows, sorted
     diff = cells[1:] != cells[:-1]
@@ -326,10 +326,10 @@ def test_config2_full_size(gpu):
     key = u * (1 << 32) + v
     assert (np.diff(key) > 0).all()
     assert off[-1] == want_E and np.array_equal(np.diff(off), np.bincount(u, minlength=want_cells))
-    say("config2: oracle dedup")
+    say("long vectors: oracle dedup")
     ocells, or2c = oracle.dedup(rows, 1024, 64)
     assert np.array_equal(ocells, cells) and np.array_equal(or2c, r2c)
-    say("config2: sampled neighbour lists")
+    say("long vectors: sampled neighbour lists")
     rng = np.random.default_rng(2)
     sample = np.sort(rng.choice(want_cells, 300, replace=False))
     nbrs, cnt = oracle.neighbors_of(cells, sample, 64)
@@ -344,13 +344,13 @@ def test_config2_full_size(gpu):
 
 
 @pytest.mark.parametrize("i", [0, 1, 2, 3, 5, 8, 13])
-def test_config3_scenes(gpu, i):
+def test_batch_scenes(gpu, i):
     torch, B, P = gpu
-    ell, n = inputs.c3_scene_params(i)
+    ell, n = inputs.batch_scene_params(i)
     if n > 60000:
         pytest.skip("large scene: covered by the batched tests")
-    say("config3 scene", i, ell, n)
-    R = inputs.c3_scene(i)
+    say("batch scene", i, ell, n)
+    R = inputs.batch_scene(i)
     wb = 32 if i % 2 else 64
     assert_same(P.cell_graph(R, ell, wb), oracle_graph(R, ell, wb))
 

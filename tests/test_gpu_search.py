@@ -135,13 +135,13 @@ def test_edge_cases(gpu):
     assert np.sum(d != NONE) == 1
 
 
-def test_config2_sampled_sources(gpu):
+def test_long_vectors_sampled_sources(gpu):
     """The long-vector workload at full size (4,194,304 cells, 3,932,160
     edges): adjacency against the oracle, and searches from sampled cells
     (each base's star of neighbours is one component)."""
     torch, B, P = gpu
-    rows = inputs.c2()
-    want_cells, want_E = inputs.c2_expected()
+    rows = inputs.long_vectors()
+    want_cells, want_E = inputs.long_vectors_expected()
     g = P.CellGraph(rows.shape[0], 1024, 64, edge_cap=want_E + 1024)
     g.run_checked(P.to_device_words(rows))
     nc = int(g.ncells.item())

@@ -256,10 +256,10 @@ def test_heuristic_equals_naive_and_ref_dists():
         assert np.array_equal(D, (cb[None, :3, :] != cb[:, None, :]).sum(-1).T)
 
 
-def test_c2_structure_small():
-    rows = inputs.c2(n_bases=1024, seed_extra=3)
+def test_long_vectors_structure_small():
+    rows = inputs.long_vectors(n_bases=1024, seed_extra=3)
     cells, r2c = oracle.dedup(rows, 1024, 64)
-    want_cells, want_E = inputs.c2_expected(1024)
+    want_cells, want_E = inputs.long_vectors_expected(1024)
     assert cells.shape[0] == want_cells
     uv, bit, off = oracle.edges(cells, 64)
     assert len(uv) == want_E
