@@ -452,3 +452,21 @@ def test_dedup_full_row_ties(gpu, ell):
         assert res["ncells"] == cells.shape[0]
         assert np.array_equal(res["cells"], cells)
         assert np.array_equal(res["row_to_cell"], r2c)
+
+
+@pytest.mark.parametrize("ell,dup_frac", [(600, 0.0), (600, 0.1), (2048, 0.0)])
+def test_dedup_many_short_segments(gpu, ell, dup_frac):
+    """Tiles dense with segment heads: 2- and 3-row equal-key segments (up
+    to 128 heads in a 256-position tile), beside two long segments."""
+    torch, B, P = gpu
+    rng = np.random.default_rng(ell + int(100 * dup_frac))
+    lens = [2] * 600 + [3] * 200 + [129, 64]
+    R = _tie_segments(rng, ell, lens, dup_frac)
+    for wb in (32, 64):
+        say("short segments", ell, dup_frac, wb, R.shape)
+        rows = oracle.pack(R, wb)
+        cells, r2c = oracle.dedup(rows, ell, wb)
+        res = P.cell_graph(R, ell, wb)
+        assert res["ncells"] == cells.shape[0]
+        assert np.array_equal(res["cells"], cells)
+        assert np.array_equal(res["row_to_cell"], r2c)
