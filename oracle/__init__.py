@@ -60,6 +60,8 @@ def lib():
         L.cgo_dist_bitwise.restype = i64
         L.cgo_edges.argtypes = [vp, i64, i32, i32, i64, vp, vp, vp, vp]
         L.cgo_edges.restype = i64
+        L.cgo_edges_search.argtypes = [vp, i64, i32, i32, i32, i64, vp, vp, vp, vp]
+        L.cgo_edges_search.restype = i64
         L.cgo_neighbors_of.argtypes = [vp, i64, i32, i32, vp, i64, i32, vp, vp]
         L.cgo_neighbors_of.restype = i32
         L.cgo_d1_queries.argtypes = [vp, i64, vp, i64, i32, i32, vp, vp, vp]
@@ -143,6 +145,24 @@ def edges(cells: np.ndarray, word_bits: int = 64, with_bits: bool = True):
     bit = np.zeros(E, dtype=np.uint16)
     E2 = lib().cgo_edges(_p(cells), nc, word_bits, W, E, _p(uv),
                          _p(bit) if with_bits else None, None, None)
+    assert E2 == E
+    return uv, bit, offsets
+
+
+def edges_search(cells: np.ndarray, ell: int, word_bits: int = 64):
+    """O3/O4 by Algorithm 4's search (flip each 0 bit, look the result up
+    among the sorted cells).  Cells must be sorted and distinct.  Same
+    result as ``edges``; used where the all-pairs scan is too slow.
+
+    Returns (uv (E, 2) uint32, bit (E,) uint16, offsets (n+1,) int64)."""
+    cells = np.ascontiguousarray(cells)
+    nc, W = cells.shape
+    offsets = np.zeros(nc + 1, dtype=np.int64)
+    E = lib().cgo_edges_search(_p(cells), nc, ell, word_bits, W, 0, None, None, _p(offsets), None)
+    assert E >= 0
+    uv = np.zeros((E, 2), dtype=np.uint32)
+    bit = np.zeros(E, dtype=np.uint16)
+    E2 = lib().cgo_edges_search(_p(cells), nc, ell, word_bits, W, E, _p(uv), _p(bit), None, None)
     assert E2 == E
     return uv, bit, offsets
 

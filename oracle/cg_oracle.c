@@ -33,6 +33,7 @@
  * by one iteration, so results do not depend on the thread count.
  */
 #define _GNU_SOURCE
+#include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -260,6 +261,117 @@ int64_t cgo_edges(const void *cells, int64_t nc, int word_bits, int words,
             }
         }
     }
+    if (offsets) memcpy(offsets, off, (size_t)(nc + 1) * sizeof(int64_t));
+    if (deg_up && nc) memcpy(deg_up, deg, (size_t)nc * sizeof(uint32_t));
+    free(deg);
+    free(off);
+    return E;
+}
+
+/* ---------------------------------------------------------------------- */
+/* O3/O4 by the search of Section 3.2 (Algorithm 4): for every cell x and   */
+/* every position k, the vector x' = x with bit k negated is looked up in   */
+/* the dictionary of cells; (x, x') is an edge iff x' is a cell.  Only      */
+/* positions with x(k) = 0 are searched, so x' > x and each edge is found   */
+/* once, from its smaller end (the paper's loop would report it from both   */
+/* ends).  The dictionary is the sorted cell array searched with the C      */
+/* library's bsearch: the tree T of Section 3.2 is built over the same      */
+/* lexicographic order, and a leaf's value (the cell id) is the rank found  */
+/* here.  With the packed layout (x(0) = most significant bit of word 0),   */
+/* comparing words as unsigned integers from word 0 up is that order.       */
+/* Cells must be sorted and distinct (as cgo_dedup writes them).            */
+/* For cell u, the found v ascend as k descends, so u's edges are written   */
+/* in ascending (u, v).  Output arguments and return value as cgo_edges.    */
+/* ---------------------------------------------------------------------- */
+
+struct search_key {
+    const void *row;
+    int word_bits, words;
+};
+
+static int cmp_key_with_cell(const void *pk, const void *pcell)
+{
+    const struct search_key *k = (const struct search_key *)pk;
+    for (int w = 0; w < k->words; ++w) {
+        uint64_t a, b;
+        if (k->word_bits == 64) {
+            a = ((const uint64_t *)k->row)[w];
+            b = ((const uint64_t *)pcell)[w];
+        } else {
+            a = ((const uint32_t *)k->row)[w];
+            b = ((const uint32_t *)pcell)[w];
+        }
+        if (a != b) return a < b ? -1 : 1;
+    }
+    return 0;
+}
+
+/* Id of the cell equal to `row` with position k negated, or -1. */
+static int64_t search_flip(const void *cells, int64_t nc, int word_bits, int words,
+                           const void *row, int64_t k, void *tmp)
+{
+    size_t rb = (size_t)words * (size_t)(word_bits / 8);
+    memcpy(tmp, row, rb);
+    if (word_bits == 64)
+        ((uint64_t *)tmp)[k / 64] ^= (uint64_t)1 << (63 - k % 64);
+    else
+        ((uint32_t *)tmp)[k / 32] ^= (uint32_t)1 << (31 - k % 32);
+    struct search_key key = { tmp, word_bits, words };
+    const char *hit = (const char *)bsearch(&key, cells, (size_t)nc, rb, cmp_key_with_cell);
+    return hit ? (int64_t)((hit - (const char *)cells) / (ptrdiff_t)rb) : -1;
+}
+
+int64_t cgo_edges_search(const void *cells, int64_t nc, int ell, int word_bits, int words,
+                         int64_t cap, uint32_t *uv, uint16_t *bit, int64_t *offsets,
+                         uint32_t *deg_up)
+{
+    if (word_bits != 32 && word_bits != 64) return -1;
+    if (ell < 1 || (int64_t)words * word_bits < ell) return -1;
+    uint32_t *deg = (uint32_t *)calloc((size_t)(nc > 0 ? nc : 1), sizeof(uint32_t));
+    int64_t *off = (int64_t *)malloc((size_t)(nc + 1) * sizeof(int64_t));
+    if (!deg || !off) { free(deg); free(off); return -1; }
+    size_t rb = (size_t)words * (size_t)(word_bits / 8);
+
+    #pragma omp parallel
+    {
+        uint64_t tmp[(65536 + 63) / 64];
+        #pragma omp for schedule(dynamic, 256)
+        for (int64_t u = 0; u < nc; ++u) {
+            const void *ru = row_ptr(cells, words, word_bits, u);
+            uint32_t c = 0;
+            for (int64_t k = ell - 1; k >= 0; --k)
+                if (!get_bit(ru, word_bits, k) && search_flip(cells, nc, word_bits, words, ru, k, tmp) >= 0)
+                    ++c;
+            deg[u] = c;
+        }
+    }
+    off[0] = 0;
+    for (int64_t u = 0; u < nc; ++u) off[u + 1] = off[u] + deg[u];
+    int64_t E = off[nc];
+
+    if (uv || bit) {
+        #pragma omp parallel
+        {
+            uint64_t tmp[(65536 + 63) / 64];
+            #pragma omp for schedule(dynamic, 256)
+            for (int64_t u = 0; u < nc; ++u) {
+                if (!deg[u]) continue;
+                const void *ru = row_ptr(cells, words, word_bits, u);
+                int64_t pos = off[u];
+                for (int64_t k = ell - 1; k >= 0 && pos < off[u + 1]; --k) {
+                    if (get_bit(ru, word_bits, k)) continue;
+                    int64_t v = search_flip(cells, nc, word_bits, words, ru, k, tmp);
+                    if (v < 0) continue;
+                    if (pos < cap) {
+                        if (uv) { uv[2 * pos] = (uint32_t)u; uv[2 * pos + 1] = (uint32_t)v; }
+                        if (bit) bit[pos] = (uint16_t)k;
+                    }
+                    ++pos;
+                }
+            }
+        }
+    }
+    (void)rb;
     if (offsets) memcpy(offsets, off, (size_t)(nc + 1) * sizeof(int64_t));
     if (deg_up && nc) memcpy(deg_up, deg, (size_t)nc * sizeof(uint32_t));
     free(deg);

@@ -387,3 +387,150 @@ def test_sample_signs_axis_planes_and_arrangement():
     # thirteen parallel planes cut the box into at most 14 slabs
     cells, r2c = oracle.dedup(oracle.pack(bits[:, :len(ts)], 32), len(ts), 32)
     assert cells.shape[0] <= len(ts) + 1
+
+
+# ------------------------------------------- Algorithm 4's search form (O3)
+
+@pytest.mark.parametrize("ell", [1, 3, 8, 13, 32, 33, 64, 65, 100])
+def test_edges_search_matches_integer_xor(ell):
+    # the search form (flip each 0 bit and look the vector up, Section 3.2,
+    # Algorithm 4) against the power-of-two XOR test on Python integers
+    rng = np.random.default_rng(300 + ell)
+    R = inputs.clustered_multiset(rng, 40, ell, fam=4, dups=25)
+    cells_np, _, e_int = twin.cell_graph_np(R)
+    for wb in (32, 64):
+        cells, r2c = oracle.dedup(oracle.pack(R, wb), ell, wb)
+        uv, bit, off = oracle.edges_search(cells, ell, wb)
+        got = [(int(u), int(v), int(b)) for (u, v), b in zip(uv.tolist(), bit.tolist())]
+        assert got == e_int
+        assert off[-1] == len(e_int)
+        assert np.array_equal(np.diff(off), np.bincount(uv[:, 0], minlength=cells.shape[0]))
+
+
+@pytest.mark.parametrize("ell", [1, 2, 5, 9])
+def test_edges_search_full_hypercube_and_figures(ell):
+    n = 2 ** ell
+    R = ((np.arange(n)[:, None] >> np.arange(ell - 1, -1, -1)[None, :]) & 1).astype(np.uint8)
+    cells, r2c = oracle.dedup(oracle.pack(R, 32), ell, 32)
+    uv, bit, off = oracle.edges_search(cells, ell, 32)
+    assert len(uv) == ell * 2 ** (ell - 1)
+    assert (np.bincount(uv.reshape(-1), minlength=n) == ell).all()
+    # cell id = the vector as an integer; edge (u, u | 2^(l-1-b)) for every 0 bit b of u
+    assert all(v == u | (1 << (ell - 1 - b)) and not (u >> (ell - 1 - b)) & 1
+               for (u, v), b in zip(uv.tolist(), bit.tolist()))
+    # Figure 1 (4-cycle) and Figure 2 (edges (3, 4) bit 4 and (4, 5) bit 5)
+    g = read_golden("fig1.txt")
+    cells1, _ = oracle.dedup(oracle.pack(rows_from_strings([r[1] for r in g]), 64), 3, 64)
+    uv1, bit1, _ = oracle.edges_search(cells1, 3, 64)
+    assert [tuple(e) for e in uv1.tolist()] == [(0, 1), (0, 2), (1, 3), (2, 3)] and bit1.tolist() == [2, 1, 1, 2]
+    g2 = [r for r in read_golden("fig2.txt") if r[0] not in ("levels", "path")]
+    cells2, _ = oracle.dedup(oracle.pack(rows_from_strings([r[0] for r in g2]), 32), 6, 32)
+    uv2, bit2, _ = oracle.edges_search(cells2, 6, 32)
+    assert [tuple(e) for e in uv2.tolist()] == [(3, 4), (4, 5)] and bit2.tolist() == [4, 5]
+
+
+@pytest.mark.parametrize("ell", [1, 2, 3])
+def test_edges_search_exhaustive_subsets(ell):
+    n = 2 ** ell
+    codes = np.arange(n)
+    R_all = ((codes[:, None] >> np.arange(ell - 1, -1, -1)[None, :]) & 1).astype(np.uint8)
+    for mask in range(1, 2 ** n):
+        members = [c for c in range(n) if (mask >> c) & 1]
+        cells, _ = oracle.dedup(oracle.pack(R_all[members], 64), ell, 64)
+        uv, bit, off = oracle.edges_search(cells, ell, 64)
+        want = [(i, j) for i in range(len(members)) for j in range(i + 1, len(members))
+                if bin(members[i] ^ members[j]).count("1") == 1]
+        assert [tuple(e) for e in uv.tolist()] == want
+
+
+def test_edges_search_long_vectors_structure():
+    # bases and their planted one-bit neighbours (distinct flips): the only
+    # distance-1 pairs are (base, planted), so |E| and the degree profile are fixed
+    rows = inputs.long_vectors(n_bases=2048, seed_extra=5)
+    cells, r2c = oracle.dedup(rows, 1024, 64)
+    want_cells, want_E = inputs.long_vectors_expected(2048)
+    assert cells.shape[0] == want_cells
+    uv, bit, off = oracle.edges_search(cells, 1024, 64)
+    assert len(uv) == want_E
+    deg = np.bincount(uv.reshape(-1), minlength=want_cells)
+    assert sorted(np.bincount(deg).nonzero()[0].tolist()) == [1, 15]
+    # the first 300 cells' lists against the all-pairs form
+    a_uv, a_bit, a_off = oracle.edges(cells[:300], 64)
+    inside = (uv[:, 1] < 300)
+    assert np.array_equal(uv[inside], a_uv) and np.array_equal(bit[inside], a_bit)
+
+
+# ----------------------------------------------------- neighbours of cells
+
+@pytest.mark.parametrize("ell", [4, 11, 40, 70])
+def test_neighbors_of_matches_integer_xor_both_directions(ell):
+    # every neighbour of each sampled cell, ascending, in both directions:
+    # the symmetrised integer-XOR edge list
+    rng = np.random.default_rng(400 + ell)
+    R = inputs.clustered_multiset(rng, 30, ell, fam=5, dups=10)
+    cells_np, _, e_int = twin.cell_graph_np(R)
+    nc = cells_np.shape[0]
+    adj = [[] for _ in range(nc)]
+    for u, v, _ in e_int:
+        adj[u].append(v)
+        adj[v].append(u)
+    for wb in (32, 64):
+        cells, _ = oracle.dedup(oracle.pack(R, wb), ell, wb)
+        sample = np.arange(nc, dtype=np.int64)[::-1]
+        lists, cnt = oracle.neighbors_of(cells, sample, wb, max_deg=ell)
+        for s, u in enumerate(sample.tolist()):
+            assert cnt[s] == len(adj[u])
+            assert lists[s].tolist() == sorted(adj[u])
+        # truncation: counts stay exact, only the first max_deg ids are kept
+        lists2, cnt2 = oracle.neighbors_of(cells, sample, wb, max_deg=1)
+        assert np.array_equal(cnt2, cnt)
+        for s, u in enumerate(sample.tolist()):
+            assert lists2[s].tolist() == sorted(adj[u])[:1]
+
+
+def test_neighbors_of_full_hypercube():
+    # on [2]^l every cell has the l neighbours u xor 2^b (ids = values)
+    ell = 7
+    n = 2 ** ell
+    R = ((np.arange(n)[:, None] >> np.arange(ell - 1, -1, -1)[None, :]) & 1).astype(np.uint8)
+    cells, _ = oracle.dedup(oracle.pack(R, 64), ell, 64)
+    sample = np.array([0, 5, 77, n - 1], dtype=np.int64)
+    lists, cnt = oracle.neighbors_of(cells, sample, 64, max_deg=16)
+    for s, u in enumerate(sample.tolist()):
+        assert cnt[s] == ell
+        assert lists[s].tolist() == sorted(u ^ (1 << b) for b in range(ell))
+
+
+# ------------------------------------- sampled signs on general planes (O7)
+
+def test_sample_signs_general_planes_operation_order():
+    # bit i = [((a0 p0 + a1 p1) + a2 p2) - c >= 0], every operation rounded to
+    # nearest float64, no fused multiply-add.  numpy's elementwise float64
+    # arithmetic is exactly that, with the points taken from numpy's own
+    # Philox stream.  Half of the planes pass exactly through a sample point
+    # (c = the stated sum at that point), so r = 0 there and any other order
+    # of the additions, or a fused multiply-add, changes some signs.
+    lohi = np.array([-1.0, -1.0, -1.0, 1.0, 1.0, 1.0])
+    seed, scene, n = 1234, 17, 4000
+    raw = np.random.Philox(counter=[2 ** 64 - 1] * 4, key=[seed, scene]).random_raw(4 * n).reshape(n, 4)
+    u = (raw[:, :3] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    P = lohi[:3] + (lohi[3:] - lohi[:3]) * u
+    rng = np.random.default_rng(77)
+    g = rng.standard_normal((96, 3))
+    a = g / np.linalg.norm(g, axis=1, keepdims=True)
+    c = rng.uniform(-0.5, 0.5, 96)
+    through = rng.choice(n, 48, replace=False)
+    for k in range(48):
+        p = P[through[k]]
+        c[k] = (a[k, 0] * p[0] + a[k, 1] * p[1]) + a[k, 2] * p[2]
+    planes = np.concatenate([a, c[:, None]], axis=1)
+    bits = oracle.sample_signs(planes, n, seed, scene, lohi)
+    t0 = P[:, None, 0] * a[None, :, 0]
+    t1 = P[:, None, 1] * a[None, :, 1]
+    t2 = P[:, None, 2] * a[None, :, 2]
+    want = (((t0 + t1) + t2) - c[None, :]) >= 0.0
+    assert np.array_equal(bits, want.astype(np.uint8))
+    assert all(bits[through[k], k] == 1 for k in range(48))
+    # the pin is sensitive: another association of the sum differs here
+    other = ((t0 + (t1 + t2)) - c[None, :]) >= 0.0
+    assert not np.array_equal(other, want)
