@@ -214,6 +214,12 @@ cg_status cg_neighbors_d1(const cg_dict *dict, const void *d_queries, int64_t nq
  * Workspace: cg_edges_workspace(dict, cap) bytes.
  * Errors: CG_EINVAL, CG_EWORKSPACE.                                         */
 cg_status cg_edges_workspace(const cg_dict *dict, int64_t cap, size_t *bytes);
+/* The same size before any dictionary exists (for planning device memory):
+ * the workspace cg_edges will need for a dictionary of up to ncells_cap cells
+ * in layout lay built with parameters p (NULL = defaults).
+ * Errors: CG_EINVAL, CG_EUNSUPPORTED (as cg_dict_size). */
+cg_status cg_edges_workspace_size(int64_t ncells_cap, cg_layout lay, const cg_dict_params *p, int64_t cap,
+                                  size_t *bytes);
 cg_status cg_edges(const cg_dict *dict, uint32_t *d_uv, uint16_t *d_bit, int64_t cap,
                    int64_t *d_nedges, int64_t *d_offsets, void *d_ws, size_t ws_bytes,
                    int32_t *d_status, cg_stream_t stream);

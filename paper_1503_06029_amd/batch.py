@@ -19,6 +19,7 @@ from . import binding as B
 
 CLASS_WORDS = (2, 4, 8, 16, 32)  # tag word + data words, a power of two
 TAG_BITS = 32
+MAX_ELL = 32 * (CLASS_WORDS[-1] - 1)  # longest vector a class holds
 
 # Data bits of the default split per class: the P pass (flips at or after
 # the split) sees groups of cells that agree on the tag and the first
@@ -38,6 +39,26 @@ def class_words(ell: int) -> int:
         if need <= w:
             return w
     raise ValueError(f"l = {ell} is too long for a batch class (max {32 * (CLASS_WORDS[-1] - 1)})")
+
+
+def class_footprint(rows: int, scenes: int, nbytes: int, words: int, edge_cap: int | None = None) -> int:
+    """Device bytes of one SceneBatch of `words`-word rows with capacity for
+    `rows` rows, `scenes` scenes and `nbytes` sign bytes (the edge capacity
+    defaults to SceneBatch's, 4 per row): buffers plus the dedup, dictionary
+    and edge workspaces the library reports for those sizes."""
+    lay = B.cg_batch_layout(32 * (words - 1))
+    m = max(rows, 1)
+    ecap = int(edge_cap if edge_cap is not None else max(4096, 4 * rows))
+    params = default_params(words)
+    tot = 0
+    tot += 8 * (scenes + 1) + 8 * scenes * 3 + 4 * scenes + 16 * scenes  # scene tables
+    tot += max(nbytes, 16)                                            # sign bytes
+    tot += 2 * 4 * m * words + 4 * m                                  # packed rows, cells, row_to_cell
+    tot += B.cg_dedup_workspace(rows, lay) + B.cg_dict_size(rows, lay, params)
+    tot += ecap * (8 + 2) + 8 * (m + 1)                               # uv, bit, offsets
+    tot += B.cg_edges_workspace_for(rows, lay, params, ecap)
+    tot += 16 * (scenes + 1)                                          # cell and edge offsets
+    return int(tot)
 
 
 class SceneBatch:
@@ -139,13 +160,23 @@ class SceneBatch:
     def run(self, stream=None):
         B.cg_batch_pack(self.bits, self.bits_off, self.scene_ell, self.scene_rows, self.n_scenes, self.n_rows,
                         self.lay, self.packed, stream)
+        self._last = ("bits",)
         self._run_path(stream)
+
+    def rerun(self, stream=None):
+        """Run the last batch again (its inputs are still in place), e.g.
+        after grow_edges."""
+        if self._last[0] == "bits":
+            self.run(stream)
+        else:
+            self.run_sampled(self._last[1], self._last[2], stream)
 
     def run_sampled(self, planes, box, stream=None):
         """Sample the scenes set by set_sampled (plane pool `planes`, (P, 4)
         float64 on the device) straight into the packed rows, then the path."""
         B.cg_batch_sample_pack(planes, self.planes_off, self.scene_ell, self.scene_rows, self.keys, self.n_scenes,
                                self.n_rows, box, self.lay, self.packed, stream)
+        self._last = ("sampled", planes, box)
         self._run_path(stream)
 
     def _run_path(self, stream=None):
@@ -159,14 +190,24 @@ class SceneBatch:
         B.cg_batch_split(self.dict, self.n_scenes, self.offsets, self.nedges, self.edge_cap, self.cell_off,
                          self.edge_off, True, self.uv, self.bit, self.r2c, self.scene_rows, self.n_rows, stream)
 
+    def needed_edges(self) -> int:
+        """Edge count of the last run (exact even when it overflowed)."""
+        return int(self.nedges.item())
+
+    def grow_edges(self, cap: int):
+        """Edge buffers for at least `cap` edges (a re-run is needed)."""
+        if cap <= self.edge_cap:
+            return
+        self.edge_cap = int(cap)
+        self.uv = torch.empty((self.edge_cap, 2), dtype=torch.int32, device=self.device)
+        self.bit = torch.empty(self.edge_cap, dtype=torch.int16, device=self.device)
+        self._edges_ws()
+
     def ensure_capacity(self):
         """After a run: grow the edge buffers if they overflowed (needs a re-run)."""
         torch.cuda.synchronize()
         if int(self.status.item()) == B.CG_ECAPACITY:
-            self.edge_cap = int(self.nedges.item())
-            self.uv = torch.empty((self.edge_cap, 2), dtype=torch.int32, device=self.device)
-            self.bit = torch.empty(self.edge_cap, dtype=torch.int16, device=self.device)
-            self._edges_ws()
+            self.grow_edges(self.needed_edges())
             return False
         return True
 
@@ -187,8 +228,8 @@ class SceneBatch:
     def fetch_into(self, host, stream):
         """Per-scene results copied through pinned buffers `host` (from
         host_buffers) on `stream`; the returned arrays are views into those
-        buffers, valid until they are filled again.  Raises if the edge
-        buffer overflowed."""
+        buffers, valid until they are filled again.  Returns None if the
+        edge buffer overflowed (grow_edges, rerun, then fetch again)."""
         with torch.cuda.stream(stream):
             sc = host["scal"]
             sc[0:1].copy_(self.ncells, non_blocking=True)
@@ -201,7 +242,7 @@ class SceneBatch:
             stream.synchronize()
             nc, E, st = int(sc[0]), int(sc[1]), int(sc[2])
             if st != 0:
-                raise RuntimeError("edge capacity of a batch exceeded; raise its footprint")
+                return None
             host["cells"][:nc].copy_(self.cells[:nc], non_blocking=True)
             host["uv"][:E].copy_(self.uv[:E], non_blocking=True)
             host["bit"][:E].copy_(self.bit[:E], non_blocking=True)
@@ -258,6 +299,15 @@ class SceneBatch:
                 "row_to_cell": r2c[self.scene_rows_h[j]:self.scene_rows_h[j + 1]].copy(),
             })
         return out
+
+
+def tuned_params_for(path: str | None = None):
+    """params_for(words, rows) for BatchRunner from the autotuner's persisted
+    table (tuner.DEFAULT_TABLE unless `path`); classes without an entry get
+    the defaults."""
+    from . import tuner
+    tn = tuner.Tuner(path if path is not None else tuner.DEFAULT_TABLE)
+    return lambda words, rows: tn.params_for(words, rows)
 
 
 class BatchRunner:

@@ -74,6 +74,7 @@ _sig("cg_dedup_dict", [c_vp, c_i64, Layout, c_vp, c_vp, c_vp, c_vp, c_sz, ctypes
                        ctypes.POINTER(Dict), c_vp])
 _sig("cg_neighbors_d1", [ctypes.POINTER(Dict), c_vp, c_i64, c_vp, c_vp, c_vp, c_vp])
 _sig("cg_edges_workspace", [ctypes.POINTER(Dict), c_i64, ctypes.POINTER(c_sz)])
+_sig("cg_edges_workspace_size", [c_i64, Layout, ctypes.POINTER(DictParams), c_i64, ctypes.POINTER(c_sz)])
 _sig("cg_edges", [ctypes.POINTER(Dict), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp])
 _sig("cg_batch_layout", [c_i32, ctypes.POINTER(Layout)])
 _sig("cg_batch_pack", [c_vp, c_vp, c_vp, c_vp, c_i32, c_i64, Layout, c_vp, c_vp])
@@ -91,7 +92,7 @@ _sig("cg_batch_sample_pack", [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i64, ctypes
 
 EXPORTS = ("cg_version", "cg_status_string", "cg_last_error", "cg_make_layout", "cg_pack",
            "cg_dedup_workspace", "cg_dedup", "cg_dict_params_default", "cg_dict_size",
-           "cg_dict_build", "cg_neighbors_d1", "cg_edges_workspace", "cg_edges",
+           "cg_dict_build", "cg_neighbors_d1", "cg_edges_workspace", "cg_edges_workspace_size", "cg_edges",
            "cg_batch_layout", "cg_batch_pack", "cg_batch_split", "cg_graph_csr_workspace", "cg_graph_csr",
            "cg_bfs_workspace", "cg_bfs", "cg_bfs_path", "cg_sample_pack",
            "cg_batch_sample_pack", "cg_dedup_dict_workspace", "cg_dedup_dict")
@@ -203,6 +204,14 @@ def cg_neighbors_d1(d: Dict, d_queries, nq: int, d_count=None, d_self=None, d_ma
 def cg_edges_workspace(d: Dict, cap: int) -> int:
     b = c_sz()
     _check(_lib.cg_edges_workspace(ctypes.byref(d), cap, ctypes.byref(b)))
+    return b.value
+
+
+def cg_edges_workspace_for(ncells_cap: int, lay: Layout, params: DictParams | None, cap: int) -> int:
+    """cg_edges_workspace_size: the edges workspace before a dictionary exists."""
+    b = c_sz()
+    _check(_lib.cg_edges_workspace_size(ncells_cap, lay, ctypes.byref(params) if params is not None else None, cap,
+                                        ctypes.byref(b)))
     return b.value
 
 

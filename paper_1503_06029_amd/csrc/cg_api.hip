@@ -200,6 +200,23 @@ cg_status cg_edges_workspace(const cg_dict *dict, int64_t cap, size_t *bytes) {
     return CG_OK;
 }
 
+cg_status cg_edges_workspace_size(int64_t ncells_cap, cg_layout lay, const cg_dict_params *p, int64_t cap,
+                                  size_t *bytes) {
+    CG_TRY(check_layout(lay));
+    CG_TRY(check_params(p, lay));
+    if (ncells_cap < 0 || ncells_cap >= (int64_t(1) << 32))
+        return set_error(CG_EINVAL, "ncells_cap=%lld out of range", (long long)ncells_cap);
+    if (cap < 0) return set_error(CG_EINVAL, "cg_edges_workspace_size: cap < 0");
+    if (!bytes) return set_error(CG_EINVAL, "cg_edges_workspace_size: bytes is NULL");
+    cg_dict d;
+    memset(&d, 0, sizeof(d));
+    d.magic = DICT_MAGIC;
+    d.lay = lay;
+    d.ncells_cap = ncells_cap;
+    d.params = resolve_params(ncells_cap, lay, p);
+    return cg_edges_workspace(&d, cap, bytes);
+}
+
 cg_status cg_edges(const cg_dict *dict, uint32_t *d_uv, uint16_t *d_bit, int64_t cap, int64_t *d_nedges,
                    int64_t *d_offsets, void *d_ws, size_t ws_bytes, int32_t *d_status, cg_stream_t stream) {
     CG_TRY(check_dict(dict));

@@ -92,13 +92,25 @@ class Slot:
         """Wait for the batch; return {req_id: result dict}.  Copies go on the
         slot's own stream, so the other slot's batch keeps running.  Results
         are views into this slot's pinned buffers (valid until the slot runs
-        again) unless copy=True."""
+        again) unless copy=True.  A class whose edges overflowed its edge
+        buffer is grown and run again (its inputs are still in place), so
+        every request gets its exact result; each result has "status": "ok"."""
         self.done.synchronize()
         out = {}
         for w, items in self.requests.items():
-            res = self.batches[w].fetch_into(self.host[w], self.stream)
+            sb = self.batches[w]
+            res = sb.fetch_into(self.host[w], self.stream)
+            if res is None:
+                with torch.cuda.stream(self.stream):
+                    sb.grow_edges(sb.needed_edges())
+                    self.host[w] = sb.host_buffers()
+                    sb.rerun(self.stream)
+                self.stream.synchronize()
+                res = sb.fetch_into(self.host[w], self.stream)
+                assert res is not None
             for (rid, _), r in zip(items, res):
                 out[rid] = {k: (v.copy() if copy and isinstance(v, np.ndarray) else v) for k, v in r.items()}
+                out[rid]["status"] = "ok"
         self.requests = None
         return out
 
@@ -107,15 +119,34 @@ def admit_requests(queue: deque, now: float, caps, shapes):
     """Take the requests that have arrived by `now`, in arrival order, while
     their width class has room (rows, scenes, sign bytes); the others stay
     queued, still in arrival order.  queue holds (req_id, arrival, scene);
-    shapes[scene] = (rows, l).  Returns [(req_id, scene)]."""
+    shapes[scene] = (rows, l).
+
+    A request that no batch can ever hold (its l is longer than any width
+    class, its class has no capacity here, or its rows or sign bytes alone
+    exceed the class's capacity) is taken off the queue and rejected, so it
+    never blocks the loop.  Returns (taken [(req_id, scene)], rejected
+    [(req_id, scene, reason)])."""
     used = {w: [0, 0, 0] for w in caps}
-    taken = []
+    taken, rejected = [], []
     keep = deque()
     while queue and queue[0][1] <= now:
         rid, t, si = queue.popleft()
         n, ell = shapes[si]
-        w = BT.class_words(ell)
-        rows, nsc, nb = caps[w]
+        reason = None
+        try:
+            w = BT.class_words(ell)
+        except ValueError:
+            w = None
+            reason = f"l = {ell} is longer than any batch class"
+        if w is not None and w not in caps:
+            reason = f"no capacity for {w}-word rows"
+        if reason is None:
+            rows, nsc, nb = caps[w]
+            if n > rows or n * ell > nb or nsc < 1:
+                reason = f"{n} rows of l = {ell} exceed the batch footprint ({rows} rows, {nb} sign bytes)"
+        if reason is not None:
+            rejected.append((rid, si, reason))
+            continue
         u = used[w]
         if u[0] + n <= rows and u[1] + 1 <= nsc and u[2] + n * ell <= nb:
             u[0] += n
@@ -127,14 +158,43 @@ def admit_requests(queue: deque, now: float, caps, shapes):
     keep.extend(queue)  # skipped requests arrived first: order is kept
     queue.clear()
     queue.extend(keep)
-    return taken
+    return taken, rejected
+
+
+def plan_capacity(class_words, free_bytes: int, fraction: float = 0.5, slots: int = 2,
+                  max_rows: int = 1 << 21, scenes_per_class: int = 4096):
+    """Rows per width class so that `slots` batch slots, each holding one
+    batch of every class at that capacity, fit in `fraction` of `free_bytes`
+    of device memory (the device footprint of a class batch, from the
+    library's workspace sizes, is batch.class_footprint).  Returns (rows,
+    footprint in bytes of all slots)."""
+    budget = int(free_bytes * fraction)
+    rows = max_rows
+    while rows > 1024:
+        tot = slots * sum(BT.class_footprint(rows, scenes_per_class, rows * 32 * (w - 1), w)
+                          for w in class_words)
+        if tot <= budget:
+            return rows, tot
+        rows //= 2
+    tot = slots * sum(BT.class_footprint(rows, scenes_per_class, rows * 32 * (w - 1), w) for w in class_words)
+    return rows, tot
 
 
 class Server:
-    def __init__(self, scenes, rows_per_class: int = 1 << 21, scenes_per_class: int = 4096,
+    """Continuous batching over a pool of scenes given as sign bytes.
+
+    Class capacities: `rows_per_class` rows (and 32 (w - 1) sign bytes per
+    row) per width class w, or, with rows_per_class=None, the largest power
+    of two whose two slots fit in half of the device memory that is free
+    when the server starts (plan_capacity)."""
+
+    def __init__(self, scenes, rows_per_class: int | None = 1 << 21, scenes_per_class: int = 4096,
                  device="cuda"):
         self.scenes = scenes
-        ells = {BT.class_words(R.shape[1]) for R in scenes}
+        ells = sorted({BT.class_words(R.shape[1]) for R in scenes if R.shape[1] <= BT.MAX_ELL})
+        if rows_per_class is None:
+            free, _ = torch.cuda.mem_get_info()
+            rows_per_class, self.footprint = plan_capacity(ells, free, scenes_per_class=scenes_per_class)
         caps = {}
         for w in ells:
             caps[w] = (rows_per_class, scenes_per_class, rows_per_class * 32 * (w - 1))
@@ -150,12 +210,18 @@ class Server:
     def _launch(self, slot, reqs):
         slot.launch(reqs, self.scenes, self.pinned)
 
-    def serve(self, arrivals, scene_idx, keep_results: bool = False):
-        """Serve a trace in real time.  Returns (latencies in s, results or None, wall seconds)."""
+    def serve(self, arrivals, scene_idx, keep_results: bool = False, sink=None):
+        """Serve a trace in real time.  Returns (latencies in s, results or
+        None, wall seconds).  Every request ends with a result whose "status"
+        is "ok", or "rejected" (with a "reason") for a request no batch can
+        hold; rejected requests are answered at once.  sink(req_id, result),
+        if given, sees every result as it arrives (its arrays are views that
+        stay valid only during the call)."""
         n = len(arrivals)
         queue = deque((i, float(arrivals[i]), int(scene_idx[i])) for i in range(n))
         lat = np.zeros(n)
         results = {} if keep_results else None
+        self.rejected = []
         inflight = []  # slots with a launched batch, oldest first
         free = list(self.slots)
         t0 = time.perf_counter()
@@ -164,7 +230,18 @@ class Server:
             now = time.perf_counter() - t0
             progressed = False
             if free and queue and queue[0][1] <= now:
-                reqs = self._admit(queue, now)
+                reqs, rej = self._admit(queue, now)
+                tnow = time.perf_counter() - t0
+                for rid, si, why in rej:
+                    lat[rid] = tnow - arrivals[rid]
+                    self.rejected.append(rid)
+                    r = {"status": "rejected", "reason": why}
+                    if keep_results:
+                        results[rid] = r
+                    if sink is not None:
+                        sink(rid, r)
+                served += len(rej)
+                progressed = bool(rej)
                 if reqs:
                     slot = free.pop(0)
                     self._launch(slot, reqs)
@@ -178,6 +255,8 @@ class Server:
                     lat[rid] = tdone - arrivals[rid]
                     if keep_results:
                         results[rid] = r
+                    if sink is not None:
+                        sink(rid, r)
                 served += len(out)
                 free.append(slot)
                 progressed = True
