@@ -35,33 +35,108 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(rows: np.ndarray, n_cells: int, n_edges: int, dedup_rows: int, pair_samples: int):
-    """The oracle, timed on a bounded sample of the same workload and scaled
-    to the whole job: sort + unique of the first `dedup_rows` rows (scaled
-    linearly in rows, which flatters the n log n sort), plus the all-pairs
-    distance scan of `pair_samples` rows against the first n_cells rows
-    (scaled to n_cells (n_cells - 1) / 2 pair tests)."""
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline(rows: np.ndarray, n_cells: int, n_edges: int, dedup_rows: int, search_cells: int):
+    """The oracle on a bounded sample of the long-vector workload, extrapolated
+    to the whole job (a full run takes minutes on the host):
+
+    * sort + unique (the oracle's qsort) of the first `dedup_rows` rows,
+      scaled to all rows as n log n;
+    * the oracle's Algorithm-4 search form of the edges (every 0 bit of every
+      cell flipped and looked up by binary search) over the first
+      `search_cells` cells of that sorted sample, scaled to all cells linearly and
+      by log2(cells) for the depth of each binary search.
+    """
     import oracle
     sub = np.ascontiguousarray(rows[:dedup_rows])
     t0 = time.perf_counter()
-    oracle.dedup(sub, 1024, 64)
+    cells_sub, _ = oracle.dedup(sub, 1024, 64)
     t_dedup = time.perf_counter() - t0
-    pool = np.ascontiguousarray(rows[:n_cells])
-    sample = np.arange(pair_samples, dtype=np.int64) * (n_cells // pair_samples)
+    # the sample's sorted cells (rows are shuffled, so these are spread over the whole cell set)
+    pool = np.ascontiguousarray(cells_sub[:search_cells])
     t0 = time.perf_counter()
-    oracle.neighbors_of(pool, sample, 64, max_deg=64)
-    t_pairs = time.perf_counter() - t0
+    oracle.edges_search(pool, 1024, 64)
+    t_search = time.perf_counter() - t0
     n = rows.shape[0]
-    full = t_dedup * (n / dedup_rows) + t_pairs * (n_cells * (n_cells - 1) / 2) / (pair_samples * n_cells)
-    return {
+    m = pool.shape[0]
+    full_dedup = t_dedup * (n * np.log2(n)) / (dedup_rows * np.log2(dedup_rows))
+    full_search = t_search * (n_cells / m) * (np.log2(n_cells) / np.log2(m))
+    full = full_dedup + full_search
+    out = {
         "value": n_edges / full,
         "unit": "edges/s",
         "cores": oracle.threads(),
         "kind": "oracle",
-        "sample": (f"sort+unique of {dedup_rows} of {n} rows ({t_dedup:.2f} s, scaled linearly in rows) + "
-                   f"distance scan of {pair_samples} rows against {n_cells} rows ({t_pairs:.2f} s, scaled to "
-                   f"n_cells(n_cells-1)/2 pair tests); extrapolated whole job {full:.0f} s"),
+        "extrapolated": True,
+        "sample": (f"sort+unique of {dedup_rows} of {n} rows ({t_dedup:.2f} s, scaled as n log n) + "
+                   f"Algorithm-4 search edges over {m} of {n_cells} sorted cells ({t_search:.2f} s, scaled "
+                   f"linearly in cells and by log2 of the cell count); extrapolated whole job {full:.1f} s"),
+        "cells_per_s": n_cells / full,
     }
+    out.update(cpu_info())
+    return out
+
+
+def small_configs(steps: int, with_cpu: bool):
+    """The two small workloads (32 lines in the unit square, 10,000 points;
+    128 planes in [-1,1]^3, 10^6 points), whole path from sign bytes on the
+    GPU (pack, dedup, dictionary, edges) against the oracle's full run on the
+    host cores and on one core; results compared with the oracle's."""
+    import torch
+    import oracle
+    from paper_1503_06029_amd import inputs, pipeline
+    out = {}
+    for name, gen, ell in (("lines_l32_n10k", inputs.line_arrangement, 32),
+                           ("planes_l128_n1M", inputs.plane_arrangement, 128)):
+        R = gen()
+        n = R.shape[0]
+        g = pipeline.CellGraph(n, ell, 32, edge_cap=max(4096, 2 * n))
+        bits = torch.from_numpy(np.ascontiguousarray(R)).cuda()
+        g.pack(bits)
+        g.run_checked()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for k in range(steps):
+            g.run_bits(bits)
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+        res = g.fetch()
+        line = {"rows": n, "ell": ell, "cells": res["ncells"], "edges": res["nedges"],
+                "gpu_ms_per_step": float(ms.mean()), "gpu_p99_ms": float(np.percentile(ms, 99)),
+                "edges_per_s": res["nedges"] / (ms.mean() / 1e3), "cells_per_s": res["ncells"] / (ms.mean() / 1e3)}
+        if with_cpu:
+            threads = oracle.threads()
+            timings = {}
+            for th, mode in ((threads, "all-pairs"), (threads, "search"), (1, "search")):
+                oracle.set_threads(th)
+                t0 = time.perf_counter()
+                rows = oracle.pack(R, 32)
+                cells, r2c = oracle.dedup(rows, ell, 32)
+                uv, bit, off = oracle.edges(cells, 32) if mode == "all-pairs" else oracle.edges_search(cells, ell, 32)
+                timings[f"{mode}_{th}t_s"] = time.perf_counter() - t0
+            oracle.set_threads(threads)
+            line["correct"] = bool(np.array_equal(res["cells"], cells) and np.array_equal(res["row_to_cell"], r2c)
+                                   and np.array_equal(res["uv"], uv) and np.array_equal(res["bit"], bit)
+                                   and np.array_equal(res["offsets"], off))
+            line["oracle"] = {k: round(v, 4) for k, v in timings.items()}
+            line["oracle_cores"] = threads
+        out[name] = line
+        log(f"{name}: {line}")
+    return out
 
 
 def main():
@@ -71,7 +146,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-dedup-rows", type=int, default=400_000)
-    ap.add_argument("--cpu-pair-samples", type=int, default=96)
+    ap.add_argument("--cpu-search-cells", type=int, default=131072)
+    ap.add_argument("--no-small-configs", action="store_true")
     ap.add_argument("--workload", choices=("long", "batched", "served", "search", "sample", "queries"),
                     default="long",
                     help="long: 1024-bit vectors (the headline); batched: 512 plane scenes in one graph; "
@@ -183,7 +259,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
-        out["cpu_baseline"] = cpu_baseline(rows, want_cells, want_E, args.cpu_dedup_rows, args.cpu_pair_samples)
+        out["cpu_baseline"] = cpu_baseline(rows, want_cells, want_E, args.cpu_dedup_rows, args.cpu_search_cells)
+    if not args.no_small_configs:
+        log("small workloads (GPU whole path, oracle in full)")
+        out["small_workloads"] = small_configs(20, not args.no_cpu_baseline)
     print(json.dumps(out), flush=True)
     if not ok:
         log(f"WRONG RESULT: cells {nc} (want {want_cells}), edges {E} (want {want_E}), status {status}")

@@ -75,6 +75,8 @@ def lib():
         L.cgo_digits.argtypes = [vp, i32, i32, i32, vp]
         L.cgo_digits.restype = i32
         L.cgo_threads.restype = i32
+        L.cgo_set_threads.argtypes = [i32]
+        L.cgo_set_threads.restype = None
         L.cgo_adjacency.argtypes = [i64, i64, vp, vp, vp]
         L.cgo_adjacency.restype = i32
         L.cgo_bfs.argtypes = [i64, vp, vp, ctypes.c_uint32, vp, vp]
@@ -107,6 +109,11 @@ def words_for(ell: int, word_bits: int) -> int:
 
 def threads() -> int:
     return int(lib().cgo_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads for the parallel loops from now on (results do not depend on it)."""
+    lib().cgo_set_threads(int(n))
 
 
 def pack(bits: np.ndarray, word_bits: int = 64) -> np.ndarray:

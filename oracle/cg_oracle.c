@@ -73,6 +73,17 @@ int cgo_threads(void)
 #endif
 }
 
+/* Threads used by the parallel loops from now on (timing runs only; the
+ * results do not depend on it). */
+void cgo_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ---------------------------------------------------------------------- */
 /* O1: bits -> packed words.                                               */
 /* Section 2.1: bit i of v_P is 1 iff P satisfies constraint c_i; a byte   */
