@@ -27,7 +27,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cg_oracle.c")
-_LIB = os.path.join(_HERE, "libcg_oracle.so")
+# CG_ORACLE_LIB points at another build of cg_oracle.c (the sanitizer test uses it)
+_LIB = os.environ.get("CG_ORACLE_LIB") or os.path.join(_HERE, "libcg_oracle.so")
 
 _lib = None
 
