@@ -383,10 +383,22 @@ def bench_served(args):
     t, sc = inputs.served_trace(seconds=args.seconds)
     t = np.asarray(t)
     log(f"{len(t)} requests over {args.seconds} s")
+    # without resident dictionaries: every request packs, deduplicates and builds in a batch
+    srv = serve.Server(pool, resident_budget=0)
+    srv.serve(np.zeros(8), sc[:8])
+    lat0, _, wall0 = srv.serve(t, sc)
+    del srv
+    torch.cuda.empty_cache()
+    log("with resident dictionaries")
     srv = serve.Server(pool)
     # warm-up: a short burst
     srv.serve(np.zeros(8), sc[:8])
     lat, _, wall = srv.serve(t, sc)
+    pool_stats = {"budget_bytes": srv.pool.budget, "resident_scenes": len(srv.pool.scenes),
+                  "resident_bytes": srv.pool.used, "hits": srv.pool.hits, "misses": srv.pool.misses,
+                  "evictions": srv.pool.evictions}
+    del srv
+    torch.cuda.empty_cache()
     log("per-scene baseline")
     base = serve.PerSceneBaseline(pool)
     base.serve(np.zeros(4), sc[:4])
@@ -400,6 +412,9 @@ def bench_served(args):
         "config": {"workload": f"Poisson 2000/s for {args.seconds} s over {len(pool)} scenes "
                                "(l 16..512, 1e3..2e5 points)", "requests": int(len(t)), "rows": int(rows)},
         "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "resident": pool_stats,
+        "no_resident": {"requests_per_s": len(t) / wall0, "p50_ms": float(np.percentile(lat0, 50) * 1e3),
+                        "p99_ms": float(np.percentile(lat0, 99) * 1e3)},
         "baseline": {"requests_per_s": len(t) / bwall, "p50_ms": float(np.percentile(blat, 50) * 1e3),
                      "p99_ms": float(np.percentile(blat, 99) * 1e3)},
     }
