@@ -224,6 +224,25 @@ cg_status cg_edges(const cg_dict *dict, uint32_t *d_uv, uint16_t *d_bit, int64_t
                    int64_t *d_nedges, int64_t *d_offsets, void *d_ws, size_t ws_bytes,
                    int32_t *d_status, cg_stream_t stream);
 
+/* ------------------------------------------------- edges, no allocation
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that forbid
+ * it): cg_edges with the same arguments and output bytes, minus the
+ * workspace.  The scratch lives in a static device array of
+ * CG_NOALLOC_SCRATCH_BYTES per GPU, held from the first call on that GPU
+ * until the process ends (64 MiB: the edge passes of about one million
+ * cells; cg_edges_workspace(dict, cap) reports what a call needs).  Nothing
+ * is allocated or freed.  Every call on a GPU shares that GPU's array, so
+ * calls that overlap on one GPU (other streams, other host threads) race;
+ * calls on one stream are ordered and safe.
+ * Errors: as cg_edges; CG_EWORKSPACE when the call needs more scratch than
+ * the array holds (use cg_edges with a workspace then); CG_EHIP if the
+ * array's device address cannot be taken. */
+#define CG_NOALLOC_SCRATCH_BYTES (64u << 20)
+cg_status cg_edges_noalloc(const cg_dict *dict, uint32_t *d_uv, uint16_t *d_bit, int64_t cap,
+                           int64_t *d_nedges, int64_t *d_offsets, int32_t *d_status,
+                           cg_stream_t stream);
+
 /* --------------------------------------------------------- batched scenes
  * Many independent scenes (each its own multiset of sign vectors, with its
  * own l, Section 2.2) in one pass.  The scenes of a batch are packed into one

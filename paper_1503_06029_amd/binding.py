@@ -76,6 +76,7 @@ _sig("cg_neighbors_d1", [ctypes.POINTER(Dict), c_vp, c_i64, c_vp, c_vp, c_vp, c_
 _sig("cg_edges_workspace", [ctypes.POINTER(Dict), c_i64, ctypes.POINTER(c_sz)])
 _sig("cg_edges_workspace_size", [c_i64, Layout, ctypes.POINTER(DictParams), c_i64, ctypes.POINTER(c_sz)])
 _sig("cg_edges", [ctypes.POINTER(Dict), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp])
+_sig("cg_edges_noalloc", [ctypes.POINTER(Dict), c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp])
 _sig("cg_batch_layout", [c_i32, ctypes.POINTER(Layout)])
 _sig("cg_batch_pack", [c_vp, c_vp, c_vp, c_vp, c_i32, c_i64, Layout, c_vp, c_vp])
 _sig("cg_batch_split", [ctypes.POINTER(Dict), c_i32, c_vp, c_vp, c_i64, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
@@ -95,7 +96,7 @@ EXPORTS = ("cg_version", "cg_status_string", "cg_last_error", "cg_make_layout", 
            "cg_dict_build", "cg_neighbors_d1", "cg_edges_workspace", "cg_edges_workspace_size", "cg_edges",
            "cg_batch_layout", "cg_batch_pack", "cg_batch_split", "cg_graph_csr_workspace", "cg_graph_csr",
            "cg_bfs_workspace", "cg_bfs", "cg_bfs_path", "cg_sample_pack",
-           "cg_batch_sample_pack", "cg_dedup_dict_workspace", "cg_dedup_dict")
+           "cg_batch_sample_pack", "cg_dedup_dict_workspace", "cg_dedup_dict", "cg_edges_noalloc")
 
 
 def lib():
@@ -219,6 +220,15 @@ def cg_edges(d: Dict, d_uv, d_bit, cap: int, d_nedges, d_offsets, d_ws, ws_bytes
              stream=None):
     _check(_lib.cg_edges(ctypes.byref(d), _ptr(d_uv), _ptr(d_bit), cap, _ptr(d_nedges), _ptr(d_offsets),
                          _ptr(d_ws), ws_bytes, _ptr(d_status), _stream(stream)))
+
+
+def cg_edges_noalloc(d: Dict, d_uv, d_bit, cap: int, d_nedges, d_offsets, d_status, stream=None):
+    _check(_lib.cg_edges_noalloc(ctypes.byref(d), _ptr(d_uv), _ptr(d_bit), cap, _ptr(d_nedges), _ptr(d_offsets),
+                                 _ptr(d_status), _stream(stream)))
+
+
+# Bytes of the static scratch cg_edges_noalloc uses per device (CG_NOALLOC_SCRATCH_BYTES).
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def cg_batch_layout(ell_max: int) -> Layout:
