@@ -684,7 +684,10 @@ __device__ __forceinline__ uint64_t piece_terms(const V &v, int piece, int s) {
 // lanes are adjacent within one wave) the lanes of a row add their pieces'
 // hash terms; otherwise the hash comes from rhash[row].  All lanes of a wave
 // stay in the loop together so the shuffles see every lane.
-template <typename T, typename V>
+//
+// PL >= 0: pieces == 1 << PL, so a piece's row and position are a shift and
+// a mask (the general form divides a 64-bit index, dozens of instructions).
+template <typename T, typename V, int PL>
 __global__ void __launch_bounds__(256) k_gather(const V *__restrict__ rows, int64_t n, int pieces,
                                                 const uint32_t *__restrict__ vals, const uint8_t *__restrict__ uniq,
                                                 const uint32_t *__restrict__ cidx, V *__restrict__ cells,
@@ -704,17 +707,27 @@ __global__ void __launch_bounds__(256) k_gather(const V *__restrict__ rows, int6
         for (int q = 0; q < GU; ++q) {
             const int64_t g = g0 + q * span + threadIdx.x;
             const bool in = g < total;
-            const int64_t j = in ? g / pieces : 0;
-            wp[q] = static_cast<int>(g - j * pieces);
+            int64_t j;
+            if constexpr (PL >= 0) {
+                j = in ? (g >> PL) : 0;
+                wp[q] = static_cast<int>(g & ((int64_t(1) << PL) - 1));
+            } else {
+                j = in ? g / pieces : 0;
+                wp[q] = static_cast<int>(g - j * pieces);
+            }
             uu[q] = in ? uniq[j] : 0u;
             cid[q] = in ? cidx[j] + uu[q] - 1 : 0u;
             src[q] = in ? vals[j] : 0u;
-            v[q] = uu[q] ? rows[static_cast<int64_t>(src[q]) * pieces + wp[q]] : V{};
+            const int64_t so = PL >= 0 ? (static_cast<int64_t>(src[q]) << (PL >= 0 ? PL : 0))
+                                       : static_cast<int64_t>(src[q]) * pieces;
+            v[q] = uu[q] ? rows[so + wp[q]] : V{};
         }
 #pragma unroll
         for (int q = 0; q < GU; ++q) {
             const int64_t g = g0 + q * span + threadIdx.x;
-            if (uu[q]) cells[static_cast<int64_t>(cid[q]) * pieces + wp[q]] = v[q];
+            const int64_t co = PL >= 0 ? (static_cast<int64_t>(cid[q]) << (PL >= 0 ? PL : 0))
+                                       : static_cast<int64_t>(cid[q]) * pieces;
+            if (uu[q]) cells[co + wp[q]] = v[q];
             if (g < total && wp[q] == 0 && row_to_cell) row_to_cell[src[q]] = cid[q];
             if (sfx) {
                 if (hash_lanes > 0) {
@@ -863,12 +876,34 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
     }
     CG_TRY(scan_u8_to_u32(w.uniq, w.cidx, n, nullptr, w.tile_sums, d_ncells, s));
     if (rowbytes % 16 == 0) {
-        hipLaunchKernelGGL((k_gather<T, uint4>), dim3(blocks_for(n * pieces, 256, 65536)), dim3(256), 0, s,
-                           reinterpret_cast<const uint4 *>(rows), n, pieces, vals, w.uniq, w.cidx,
-                           reinterpret_cast<uint4 *>(cells), row_to_cell, rhash, sfx, hash_lanes, hash_s);
+        const dim3 g(blocks_for(n * pieces, 256, 65536));
+        const uint4 *r4 = reinterpret_cast<const uint4 *>(rows);
+        uint4 *c4 = reinterpret_cast<uint4 *>(cells);
+#define CG_GATHER4(PLV)                                                                                            \
+    hipLaunchKernelGGL((k_gather<T, uint4, PLV>), g, dim3(256), 0, s, r4, n, pieces, vals, w.uniq, w.cidx, c4,     \
+                       row_to_cell, rhash, sfx, hash_lanes, hash_s)
+        switch (pieces) {
+        case 1: CG_GATHER4(0); break;
+        case 2: CG_GATHER4(1); break;
+        case 4: CG_GATHER4(2); break;
+        case 8: CG_GATHER4(3); break;
+        case 16: CG_GATHER4(4); break;
+        case 32: CG_GATHER4(5); break;
+        case 64: CG_GATHER4(6); break;
+        default: CG_GATHER4(-1); break;
+        }
+#undef CG_GATHER4
     } else {
-        hipLaunchKernelGGL((k_gather<T, T>), dim3(blocks_for(n * words, 256, 65536)), dim3(256), 0, s, rows, n,
-                           words, vals, w.uniq, w.cidx, cells, row_to_cell, rhash, sfx, hash_lanes, hash_s);
+        const dim3 g(blocks_for(n * words, 256, 65536));
+#define CG_GATHER1(PLV)                                                                                            \
+    hipLaunchKernelGGL((k_gather<T, T, PLV>), g, dim3(256), 0, s, rows, n, words, vals, w.uniq, w.cidx, cells,     \
+                       row_to_cell, rhash, sfx, hash_lanes, hash_s)
+        switch (words) {
+        case 1: CG_GATHER1(0); break;
+        case 2: CG_GATHER1(1); break;
+        default: CG_GATHER1(-1); break;
+        }
+#undef CG_GATHER1
     }
     CG_LAUNCHED("dedup_gather");
     if (view) {

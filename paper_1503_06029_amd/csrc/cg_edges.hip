@@ -192,6 +192,7 @@ __global__ void k_edges_init(uint32_t *cntS, int64_t ncap, int64_t *d_nedges, in
     if (gid == 0) {
         big_n[0] = 0;
         big_n[1] = 0;
+        big_n[2] = 0;
         *d_nedges = 0;
         if (offsets) offsets[0] = 0;
         *status = CG_OK;
@@ -640,55 +641,88 @@ __device__ __forceinline__ uint32_t p_lookup(const T *__restrict__ cells, int64_
     return c;
 }
 
-// Count and record the P-neighbours of one tile.  Lanes walk their groups in
-// lock-step over the offset d = j - i (branch-free: one step costs a few
-// vector instructions), keeping only pairs whose popcounts differ by one (the
-// bound (*) against the zero vector).  Those candidates are queued per wave
-// and checked 64 at a time, so the full-row test runs on dense lanes.  A
-// found pair sets bit d - 1 of the cell's offset mask and is listed with its
-// position; since in-tile scans stop at d = PSCAN, a cell's rank of an edge
-// is the popcount of its mask below d.
-constexpr int CQ = 128;    // per-wave candidate ring
-constexpr int PSCAN = 64;  // longest in-tile scan; longer groups use look-ups
+// Count and record the P-neighbours of one tile.  Each wave owns 64 cells of
+// the tile and works alone after the tile is in LDS (two block barriers per
+// tile: LDS reuse and LDS fill).  A lane walks its cell's prefix group over
+// the offset d = j - i, four offsets per step, keeping pairs whose popcounts
+// differ by exactly one (the bound (*) of Section 1.1 against the zero
+// vector); each step's candidates go straight into the wave's ring queue,
+// which is verified (full-row distance in LDS) 64 entries at a time, so the
+// row comparisons run on full waves.  A hit sets bit d - 1 of the cell's
+// offset mask and is listed with its position; since scans stop at
+// d = PSCAN, a cell's rank of an edge is the popcount of its mask below d.
+// Row popcounts carry two flags: HEADF (the row starts a prefix group) and
+// PASTF (past the loaded rows), so a lane stops at either with one compare.
+constexpr int CQ = 128;                // per-wave candidate ring (a power of two, at least 128)
+constexpr int PSCAN = 64;              // longest in-tile scan; longer groups use look-ups
+constexpr int PWAVES = PT / 64;        // waves per block, 64 cells each
+constexpr int WST = P_STASH / PWAVES;  // stash entries per wave
+constexpr int PCS = PT + PSCAN + 8;    // popcount entries: rows, then PASTF padding for the scans
+constexpr uint32_t HEADF = 0x40000000u;
+constexpr uint32_t PASTF = 0x80000000u;
 
 template <typename T, int WT> struct PFind {
     static constexpr int LW = WT + 1;
     static constexpr size_t rows_bytes = static_cast<size_t>(PROWS) * LW * sizeof(T);
-    // rows | mask[PT] (u64) | pcs[PROWS + 1] | res[P_STASH] | cq[4][CQ] | heads[PROWS + 4]
-    static constexpr size_t bytes = rows_bytes + PT * 8 + (PROWS + 1) * 4 + P_STASH * 4 + 4 * CQ * 4 + PROWS + 4;
+    // rows | mask[PT] (u64) | pcs[PCS] | res[P_STASH] | ring[PWAVES][CQ] | sbase[PT]
+    static constexpr size_t bytes = rows_bytes + PT * 8 + PCS * 4 + P_STASH * 4 + PWAVES * CQ * 4 + PT * 4;
 };
+
+// Distance of two LDS rows of WT words; *pos = the first differing position
+// when the distance is 1 (the word index is kept while summing popcounts and
+// the word is read once more at the end).
+template <typename T, int WT>
+__device__ __forceinline__ int dist_lds(const T *a, const T *b, int *pos) {
+    constexpr int B = Bits<T>::B;
+    constexpr int C = WT < 4 ? WT : 4;  // words per step: few registers live at once
+    int d = 0, wi = 0;
+#pragma unroll 1
+    for (int w0 = 0; w0 < WT; w0 += C) {
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+            const T x = a[w0 + u] ^ b[w0 + u];
+            d += popc<T>(x);
+            wi = x ? w0 + u : wi;
+        }
+    }
+    const T x = a[wi] ^ b[wi];
+    *pos = wi * B + clz_t<T>(x | T(1));
+    return d;
+}
 
 // Persistent: each block walks a strided sequence of tiles and, while it
 // works on one tile in LDS, already has the next tile's rows (tile plus
-// HALO rows, padded to WT words) and cntS values in flight in registers, so
-// the stream of rows never waits for the comparisons.  Tiles are dealt out
-// per XCD (workgroups go round-robin over the 8 XCDs): XCD x takes the x-th
-// eighth of the tiles, so a tile and the one after it (whose first rows are
-// the tile's halo) are read on the same XCD at about the same time and the
-// halo comes from that XCD's L2.
-// Blocks per CU the register budget is sized for: three (the LDS allows
-// three), except 32-word u32 rows, whose unrolled row work needs two.
+// HALO rows) and cntS values in flight in registers, so the stream of rows
+// never waits for the comparisons.  Tiles are dealt out per XCD (workgroups
+// go round-robin over the 8 XCDs): XCD x takes the x-th eighth of the
+// tiles, so a tile and the one after it (whose first rows are the tile's
+// halo) are read on the same XCD at about the same time and the halo comes
+// from that XCD's L2.  FULLW: rows are exactly WT words, so a tile is one
+// contiguous run of words and loads and LDS stores need no index arithmetic.
 template <typename T, int WT> constexpr int p_find_blocks() { return (sizeof(T) == 4 && WT == 32) ? 2 : 3; }
 
-template <typename T, int WT>
+template <typename T, int WT, bool FULLW>
 __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T *__restrict__ cells,
                                                const int64_t *d_n, int64_t ncap, int words, int ell, int s, int gmax,
                                                const uint32_t *__restrict__ cntS, uint32_t *__restrict__ cntP,
                                                uint32_t *__restrict__ stash, uint32_t *__restrict__ stash_n,
                                                uint64_t *__restrict__ tile_tot, uint64_t *__restrict__ sup_tot,
-                                               uint32_t *__restrict__ big_list, unsigned long long *__restrict__ big_n) {
+                                               uint32_t *__restrict__ big_list, unsigned long long *__restrict__ big_n,
+                                               uint32_t *__restrict__ fix_list, unsigned long long *__restrict__ fix_n) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint64_t tmp[4];
-    __shared__ uint32_t s_nres;
-    __shared__ uint32_t sbase[PT];
+    __shared__ uint32_t s_nres[PWAVES];
+    __shared__ uint64_t s_tot;
+    __shared__ uint32_t s_ovf;
     using L = PFind<T, WT>;
     constexpr int LW = L::LW;
     constexpr int NE = (PROWS * WT + PT - 1) / PT;  // prefetched words per thread
+    constexpr int RPU = PT / WT;                     // rows per prefetch step (PT is a multiple of WT)
     T *rows = reinterpret_cast<T *>(smem);
     unsigned long long *mask = reinterpret_cast<unsigned long long *>(smem + L::rows_bytes);
     uint32_t *pcs = reinterpret_cast<uint32_t *>(mask + PT);
-    uint32_t *res = pcs + PROWS + 1;
-    uint32_t *cq = res + P_STASH;
+    uint32_t *res = pcs + PCS;
+    uint32_t *ring = res + P_STASH;
+    uint32_t *sbase = ring + PWAVES * CQ;
     const int64_t n = load_n(d_n, ncap);
     const int64_t ntiles = (n + PT - 1) / PT;
     const int G8 = static_cast<int>(gridDim.x >> 3);
@@ -697,7 +731,8 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
     const int64_t r0 = xcd * T8;
     const int64_t r1 = r0 + T8 < ntiles ? r0 + T8 : ntiles;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    uint32_t *q = cq + wv * CQ;
+    uint32_t *q = ring + wv * CQ;
+    uint32_t *wres = res + wv * WST;
     const int gm = gmax < PSCAN ? gmax : PSCAN;
 
     T pre[NE];
@@ -706,137 +741,140 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
         const int64_t base = tile * PT;
         const int64_t av = n - base;
         const int avail = static_cast<int>(av < PROWS ? av : PROWS);
-        const int tot = avail * WT;
         const T *src = cells + base * words;
-        // every load is issued (out-of-range ones read the tile's first word,
-        // which exists) and masked when stored to LDS: no branches around the
-        // loads and no wait for them here
+        if (FULLW && avail == PROWS) {  // the tile and its halo are all there: plain loads
 #pragma unroll
-        for (int u = 0; u < NE; ++u) {
-            const int e = t + u * PT;
-            const int r = e / WT, w = e % WT;
-            const bool ok = e < tot && w < words;
-            pre[u] = src[ok ? r * words + w : 0];
+            for (int u = 0; u < NE; ++u) {
+                const int e = t + u * PT;
+                pre[u] = e < PROWS * WT ? src[e] : T(0);
+            }
+        } else {
+            // every load is issued (out-of-range ones read the tile's first
+            // word, which exists) and masked when stored to LDS
+            const int tot = avail * WT;
+#pragma unroll
+            for (int u = 0; u < NE; ++u) {
+                const int e = t + u * PT;
+                const int r = e / WT, w = e % WT;
+                const bool ok = e < tot && w < words;
+                pre[u] = src[ok ? r * words + w : 0];
+            }
         }
         pre_cs = cntS[base + t < n ? base + t : base];
     };
 
     int64_t tile = r0 + lb;
+    int64_t prev = -1;
     if (tile < r1) prefetch(tile);
+    if (t == 0) {
+        s_tot = 0;
+        s_ovf = 0;
+    }
     for (; tile < r1; tile += G8) {
         const int64_t base = tile * PT;
         const int tr = static_cast<int>(n - base < PT ? n - base : PT);
         const int tl = static_cast<int>(n - base < PROWS ? n - base : PROWS);  // loaded rows
+        __syncthreads();  // the previous tile's LDS is free; its total is complete
+        if (t == 0) {
+            if (prev >= 0) {
+                const uint64_t tot = s_tot;
+                tile_tot[prev] = tot;
+                atomicAdd(reinterpret_cast<unsigned long long *>(&sup_tot[prev / SUP]),
+                          static_cast<unsigned long long>(tot));
+            }
+            s_tot = 0;
+            s_ovf = 0;
+        }
         {
             const int tot = tl * WT;
+            const bool full = FULLW && tl == PROWS;
 #pragma unroll
             for (int u = 0; u < NE; ++u) {
                 const int e = t + u * PT;
-                const bool ok = e < tot && (e % WT) < words;
-                if (e < PROWS * WT) rows[(e / WT) * LW + (e % WT)] = ok ? pre[u] : T(0);
+                if (e < PROWS * WT) {
+                    // e / WT = t / WT + u * RPU and e % WT = t % WT
+                    T *dst = rows + (t / WT + u * RPU) * LW + (t % WT);
+                    *dst = (full || (e < tot && (e % WT) < words)) ? pre[u] : T(0);
+                }
             }
         }
         const uint32_t cs = base + t < n ? pre_cs : 0u;
         mask[t] = 0;
-        if (t == 0) s_nres = 0;
+        if (lane == 0) s_nres[wv] = 0;
         __syncthreads();
         for (int r = t; r < tl; r += PT) {
             const T *me = rows + r * LW;
             uint32_t pc = 0;
 #pragma unroll
             for (int w = 0; w < WT; ++w) pc += popc<T>(me[w]);
-            // popcount, bit 31: row r starts a prefix group
             const bool hd = r == 0 || !same_prefix_t<T, WT>(me - LW, me, s);
-            pcs[r] = pc | (hd ? 0x80000000u : 0u);
+            pcs[r] = pc | (hd ? HEADF : 0u);
         }
-        if (t == 0) pcs[tl] = 0x80000000u;  // read only as "past the loaded rows"
+        for (int r = tl + t; r < PCS; r += PT) pcs[r] = PASTF;
         __syncthreads();
         if (tile + G8 < r1) prefetch(tile + G8);
         const int64_t i = base + t;
+        const bool more = base + tl < n;  // cells exist past the loaded rows
 
-        // entry: cell (8 bits) | offset (8 bits, 1..64) | position (16 bits)
-        auto found = [&](int t0, int d0, int k) {
-            atomicOr(&mask[t0], 1ull << (d0 - 1));
-            const uint32_t r = atomicAdd(&s_nres, 1u);
-            if (r < static_cast<uint32_t>(P_STASH))
-                res[r] = (static_cast<uint32_t>(t0) << 24) | (static_cast<uint32_t>(d0) << 16) |
-                         static_cast<uint32_t>(k);
+        // verify `cnt` ring entries from `from` (one per lane); hits to the
+        // mask and the wave's result list (one LDS counter update per wave)
+        auto verify = [&](uint32_t from, uint32_t cnt) {
+            const bool act = static_cast<uint32_t>(lane) < cnt;
+            const uint32_t e = act ? q[(from + lane) & (CQ - 1)] : 0u;
+            const int t0 = static_cast<int>(e >> 16), j0 = static_cast<int>(e & 0xffffu);
+            int pos;
+            const bool hit = act && dist_lds<T, WT>(rows + t0 * LW, rows + j0 * LW, &pos) == 1;
+            if (hit) atomicOr(&mask[t0], 1ull << (j0 - t0 - 1));
+            const uint64_t hm = ballot64(hit);
+            if (hm) {
+                uint32_t rb = 0;
+                if (lane == 0) rb = atomicAdd(&s_nres[wv], static_cast<uint32_t>(__popcll(hm)));
+                rb = __shfl(rb, 0, 64);
+                if (hit) {
+                    const uint32_t r = rb + static_cast<uint32_t>(__popcll(hm & lanemask_lt()));
+                    if (r < static_cast<uint32_t>(WST))
+                        wres[r] = (static_cast<uint32_t>(t0) << 24) | (static_cast<uint32_t>(j0 - t0) << 16) |
+                                  static_cast<uint32_t>(pos);
+                }
+            }
         };
 
-        // Lock-step over the offset d = j - i: a lane stays alive while row
-        // t + d is in its group; pairs whose popcounts differ by one set bit
-        // d - 1 of the lane's candidate mask.
-        const bool more = base + tl < n;  // cells exist past the loaded rows
+        // lock-step scan over d: alive while row t + d is in the cell's group
         bool alive = t < tr;
         bool big = false, spill = false;  // spill: the group runs past the loaded rows
-        const uint32_t pc = pcs[t < tl ? t : tl] & 0x7fffffffu;
-        unsigned long long cm = 0;
-        // four offsets per step: their four LDS reads are in flight together
-        for (int d0 = 1; d0 <= gm && ballot64(alive) != 0; d0 += 4) {
-            uint32_t x[4];
-#pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4) {
-                const int jj = t + d0 + q4;
-                x[q4] = pcs[jj < tl ? jj : tl];
-            }
-#pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4) {
-                const int d = d0 + q4;
-                const bool inr = d <= gm;  // the same for every lane
-                const bool past = t + d >= tl;
-                spill = spill || (inr && alive && past && more);
-                alive = alive && (!inr || (!past && (x[q4] >> 31) == 0));
-                const uint32_t po = x[q4] & 0x7fffffffu;
-                const bool cand = inr && alive && (po == pc + 1 || po + 1 == pc);
-                cm |= cand ? (1ull << (d - 1)) : 0ull;
-            }
-        }
-        if (alive) {  // still inside the group after gm rows: one more member means look-ups
-            const int jj = t + gm + 1;
-            if (jj < tl) big = (pcs[jj] >> 31) == 0;
-            else spill = spill || more;
-        }
-        // candidates to the wave's queue, checked 64 at a time on dense lanes
-        {
-            const uint32_t nc = static_cast<uint32_t>(__popcll(cm));
-            const uint32_t inc = wave_incl_scan_u32(nc);
-            const uint32_t tot = __shfl(inc, 63, 64);
-            const uint32_t off = inc - nc;
-            for (uint32_t done = 0; done < tot; done += CQ) {
-                unsigned long long m = cm;
-                uint32_t gi = off;
-                while (m) {
-                    const int d0 = __ffsll(m);  // offset d0 (bit d0 - 1)
-                    m &= m - 1;
-                    if (gi >= done && gi < done + CQ)
-                        q[gi - done] = (static_cast<uint32_t>(t) << 16) | static_cast<uint32_t>(t + d0);
-                    ++gi;
+        const uint32_t pcm1 = (pcs[t] & 0x3fffffffu) - 1u;
+        uint32_t qh = 0, qt = 0;  // ring head and tail (wave-uniform)
+        const uint32_t *pp = pcs + t;
+        uint32_t xn = pp[1];  // the next offset's entry is read one step ahead
+#pragma unroll 1
+        for (int d = 1; d <= gm; ++d) {
+            if ((d & 3) == 1 && ballot64(alive) == 0) break;
+            const uint32_t x = xn;
+            xn = pp[d + 1];
+            spill = spill || (alive && x >= PASTF && more);
+            alive = alive && x < HEADF;
+            const bool cand = alive && ((x - pcm1) & ~2u) == 0u;
+            const uint64_t m = ballot64(cand);
+            if (m) {
+                if (cand) q[(qt + static_cast<uint32_t>(__popcll(m & lanemask_lt()))) & (CQ - 1)] =
+                    (static_cast<uint32_t>(t) << 16) | static_cast<uint32_t>(t + d);
+                qt += static_cast<uint32_t>(__popcll(m));
+                if (qt - qh >= 64u) {
+                    __builtin_amdgcn_wave_barrier();
+                    verify(qh, 64u);
+                    qh += 64u;
                 }
-                __builtin_amdgcn_wave_barrier();
-                const uint32_t cnt = tot - done < static_cast<uint32_t>(CQ) ? tot - done : static_cast<uint32_t>(CQ);
-                for (uint32_t e0 = 0; e0 < cnt; e0 += 64) {
-                    // every lane runs the test (idle lanes compare row 0 with itself)
-                    const bool act = e0 + lane < cnt;
-                    const uint32_t e = act ? q[e0 + lane] : 0u;
-                    const int t0 = static_cast<int>(e >> 16), j0 = static_cast<int>(e & 0xffffu);
-                    int pos;
-                    const bool hit = dist_t4<T, WT>(rows + t0 * LW, rows + j0 * LW, &pos) == 1;
-                    if (hit) atomicOr(&mask[t0], 1ull << (j0 - t0 - 1));
-                    const uint64_t hm = ballot64(hit);  // one counter update per wave
-                    uint32_t rb = 0;
-                    if (lane == 0 && hm) rb = atomicAdd(&s_nres, static_cast<uint32_t>(__popcll(hm)));
-                    rb = __shfl(rb, 0, 64);
-                    if (hit) {
-                        const uint32_t r = rb + static_cast<uint32_t>(__popcll(hm & lanemask_lt()));
-                        if (r < static_cast<uint32_t>(P_STASH))
-                            res[r] = (static_cast<uint32_t>(t0) << 24) | (static_cast<uint32_t>(j0 - t0) << 16) |
-                                     static_cast<uint32_t>(pos);
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
             }
         }
-        if (spill) {
+        if (alive) {  // still inside the group after gm rows (xn = entry gm + 1): one more member means look-ups
+            if (xn < HEADF) big = true;
+            else spill = spill || (xn >= PASTF && more);
+        }
+        if (qt != qh) {
+            __builtin_amdgcn_wave_barrier();
+            verify(qh, qt - qh);
+        }
+        if (spill && !big) {
             // the group goes on past the loaded rows: finish it in global memory
             const T *me = rows + t * LW;
             for (int64_t j = base + tl; j < n; ++j) {
@@ -844,44 +882,64 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
                 if (!same_prefix<T>(me, o, s)) break;
                 if (j - i > gm) { big = true; break; }
                 int pos;
-                if (dist_full<T>(me, o, words, &pos) == 1) found(t, static_cast<int>(j - i), pos);
+                if (dist_full<T>(me, o, words, &pos) == 1) {
+                    const int d0 = static_cast<int>(j - i);
+                    atomicOr(&mask[t], 1ull << (d0 - 1));
+                    const uint32_t r = atomicAdd(&s_nres[wv], 1u);
+                    if (r < static_cast<uint32_t>(WST))
+                        wres[r] = (static_cast<uint32_t>(t) << 24) | (static_cast<uint32_t>(d0) << 16) |
+                                  static_cast<uint32_t>(pos);
+                }
             }
         }
         // cells of long groups: counted by k_big_lookup, which also adds them to the tile total
         wave_append<uint32_t>(big_list, big_n, n, big && t < tr, static_cast<uint32_t>(i));
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
         uint32_t cp = 0;
         if (t < tr) {
             cp = big ? BIG : static_cast<uint32_t>(__popcll(mask[t]));
             cntP[i] = cp;
         }
-        const uint32_t csv = t < tr ? cs : 0u;
         const uint32_t stashed = (cp & BIG) ? 0u : cp;
-        uint64_t tot_stash, tot_all;
-        const uint64_t ex = block256_excl_scan_u64(stashed, tmp, &tot_stash);
-        block256_excl_scan_u64(static_cast<uint64_t>(cp & ~BIG) + csv, tmp, &tot_all);
-        sbase[t] = (cp & BIG) ? 0xffffffffu : static_cast<uint32_t>(ex);
-        const uint32_t nres = s_nres;
-        if (t == 0) {
-            tile_tot[tile] = tot_all;
-            atomicAdd(reinterpret_cast<unsigned long long *>(&sup_tot[tile / SUP]),
-                      static_cast<unsigned long long>(tot_all));
-            const uint64_t m = nres > tot_stash ? nres : tot_stash;
-            stash_n[tile] = static_cast<uint32_t>(m > 0xffffffffull ? 0xffffffffull : m);
+        const uint32_t inc = wave_incl_scan_u32(stashed);
+        const uint32_t tot_stash = __shfl(inc, 63, 64);
+        const uint32_t all = wave_incl_scan_u32((cp & ~BIG) + (t < tr ? cs : 0u));
+        sbase[t] = (cp & BIG) ? 0xffffffffu : inc - stashed;
+        const uint32_t wall = __shfl(all, 63, 64);
+        const uint32_t nres = s_nres[wv];
+        const uint32_t m = nres > tot_stash ? nres : tot_stash;
+        if (lane == 0) {
+            stash_n[tile * PWAVES + wv] = m;
+            atomicAdd(reinterpret_cast<unsigned long long *>(&s_tot), static_cast<unsigned long long>(wall));
         }
-        __syncthreads();
-        if (nres <= static_cast<uint32_t>(P_STASH)) {  // else k_p_fix recomputes this tile
-            uint32_t *out = stash + tile * P_STASH;
-            for (uint32_t r = t; r < nres; r += PT) {
-                const uint32_t e = res[r];
+        __builtin_amdgcn_wave_barrier();
+        if (m <= static_cast<uint32_t>(WST)) {
+            uint32_t *out = stash + tile * P_STASH + wv * WST;
+            for (uint32_t r = lane; r < nres; r += 64) {
+                const uint32_t e = wres[r];
                 const int t0 = static_cast<int>(e >> 24);
                 const int d0 = static_cast<int>((e >> 16) & 0xffu);
-                if (sbase[t0] == 0xffffffffu) continue;  // found by look-up at placement instead
+                const uint32_t sb = sbase[t0];
+                if (sb == 0xffffffffu) continue;  // found by look-up at placement instead
                 const uint32_t rank = static_cast<uint32_t>(__popcll(mask[t0] & ((1ull << (d0 - 1)) - 1ull)));
-                out[sbase[t0] + rank] = (static_cast<uint32_t>(d0) << 16) | (e & 0xffffu);
+                out[sb + rank] = (static_cast<uint32_t>(d0) << 16) | (e & 0xffffu);
+            }
+        } else if (lane == 0) {
+            // this wave's stash overflowed: k_p_fix rescans the tile (listed
+            // once, by the first wave to overflow; the flag is cleared after
+            // the next tile's first barrier)
+            if (atomicOr(&s_ovf, 1u) == 0u) {
+                const unsigned long long k = atomicAdd(fix_n, 1ull);
+                if (static_cast<int64_t>(k) < ntiles) fix_list[k] = static_cast<uint32_t>(tile);
             }
         }
-        __syncthreads();  // LDS is refilled for the next tile
+        prev = tile;
+    }
+    __syncthreads();
+    if (t == 0 && prev >= 0) {
+        const uint64_t tot = s_tot;
+        tile_tot[prev] = tot;
+        atomicAdd(reinterpret_cast<unsigned long long *>(&sup_tot[prev / SUP]), static_cast<unsigned long long>(tot));
     }
 }
 
@@ -917,12 +975,15 @@ __global__ void __launch_bounds__(PT) k_p_place(const int64_t *d_n, int64_t ncap
         cs = cntS[i];
     }
     const uint64_t t_off = tile_offset(tile, tile_tot, sup_tot, tmp);
-    const uint32_t sn = stash_n[tile];
+    // each wave's 64 cells own one region of WST stash entries (k_p_find)
+    bool ovf = false;
+#pragma unroll
+    for (int w = 0; w < PWAVES; ++w) ovf = ovf || stash_n[tile * PWAVES + w] > static_cast<uint32_t>(WST);
     const uint32_t c = cp & ~BIG;
     const uint32_t stashed = (cp & BIG) ? 0u : cp;
-    uint64_t tot_all, tot_stash;
+    uint64_t tot_all;
     const uint64_t exa = block256_excl_scan_u64(static_cast<uint64_t>(c) + cs, tmp, &tot_all);
-    const uint64_t exs = block256_excl_scan_u64(stashed, tmp, &tot_stash);
+    const uint32_t exs = (t >> 6) * WST + wave_incl_scan_u32(stashed) - stashed;
     const int64_t out0 = static_cast<int64_t>(t_off + exa);
     if (t == 0 && base + tr == n) {  // the last tile: |E|, offsets[n], status
         const int64_t tot = static_cast<int64_t>(t_off + tot_all);
@@ -935,10 +996,10 @@ __global__ void __launch_bounds__(PT) k_p_place(const int64_t *d_n, int64_t ncap
         else if (cs || (cp & BIG)) offnext[i] = out0 + c + cs;
     }
     sx[t] = static_cast<uint32_t>(exa);
-    ssb[t] = static_cast<uint32_t>(exs);
+    ssb[t] = exs;
     scp[t] = t < tr ? cp : 0u;
     __syncthreads();
-    if (sn > static_cast<uint32_t>(P_STASH)) return;  // k_p_fix writes this tile's scanned P edges
+    if (ovf) return;  // k_p_fix writes this tile's scanned P edges
     const uint32_t *src = stash + tile * P_STASH;
     for (uint32_t r = t; r < static_cast<uint32_t>(tot_all); r += PT) {
         int lo = 0, hi = tr;  // last cell with sx <= r
@@ -956,12 +1017,14 @@ __global__ void __launch_bounds__(PT) k_p_place(const int64_t *d_n, int64_t ncap
     }
 }
 
-// Tiles whose P stash overflowed: reload and write their scanned P edges.
+// Tiles whose P stash overflowed (listed by k_p_find): reload and write their
+// scanned P edges.
 template <typename T, int WT>
 __global__ void __launch_bounds__(PT) k_p_fix(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
                                               int words, int s, int gmax, const uint32_t *__restrict__ cntS,
                                               const uint32_t *__restrict__ cntP,
-                                              const uint32_t *__restrict__ stash_n,
+                                              const uint32_t *__restrict__ fix_list,
+                                              const unsigned long long *__restrict__ fix_n,
                                               const uint64_t *__restrict__ tile_tot,
                                               const uint64_t *__restrict__ sup_tot, uint32_t *__restrict__ uv,
                                               uint16_t *__restrict__ bit, int64_t cap) {
@@ -970,15 +1033,16 @@ __global__ void __launch_bounds__(PT) k_p_fix(const T *__restrict__ cells, const
     __shared__ int s_th;
     const int64_t n = load_n(d_n, ncap);
     const int64_t ntiles = (n + PT - 1) / PT;
+    int64_t nfix = static_cast<int64_t>(*fix_n);
+    if (nfix > ntiles) nfix = ntiles;
     using L = PTile<T, WT>;
     T *rows = reinterpret_cast<T *>(smem);
     uint32_t *pcs = reinterpret_cast<uint32_t *>(smem + L::rows_bytes);
     uint32_t *nbl = pcs + PROWS;
     uint8_t *heads = reinterpret_cast<uint8_t *>(nbl + PT * NB);
     const int t = threadIdx.x;
-    // a few blocks walk the tiles; only overflowed ones have work
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        if (stash_n[tile] <= static_cast<uint32_t>(P_STASH)) continue;  // uniform over the block
+    for (int64_t k = blockIdx.x; k < nfix; k += gridDim.x) {
+        const int64_t tile = fix_list[k];
         const int64_t base = tile * PT;
         int th;
         const int tr = load_ptile<T, WT>(rows, pcs, heads, &s_th, cells, words, s, base, n, &th);
@@ -1014,7 +1078,8 @@ struct EdgesWs {
     uint4 *s_stash;              // S edges per block of the suffix order
     uint32_t *s_stash_n;
     uint32_t *s_big, *p_big;     // cells left to k_big_lookup
-    unsigned long long *big_n;   // [0]: S list length, [1]: P list length
+    uint32_t *p_fix;             // tiles whose P stash overflowed
+    unsigned long long *big_n;   // [0]: S list length, [1]: P list length, [2]: overflowed tiles
 };
 
 // Padded row width (power of two) for the P tiles, or 0 when rows are too
@@ -1041,13 +1106,14 @@ EdgesWs carve_edges(void *base, int64_t ncap, size_t *bytes) {
     w.nsup = (tiles + SUP - 1) / SUP;
     w.sup_tot = c.take<uint64_t>(w.nsup);
     w.p_stash = c.take<uint32_t>(tiles * P_STASH);
-    w.p_stash_n = c.take<uint32_t>(tiles);
+    w.p_stash_n = c.take<uint32_t>(tiles * PWAVES);
     const int64_t sblocks = (n + SC - 1) / SC;
     w.s_stash = c.take<uint4>(sblocks * S_STASH);
     w.s_stash_n = c.take<uint32_t>(sblocks);
     w.s_big = c.take<uint32_t>(n);
     w.p_big = c.take<uint32_t>(n);
-    w.big_n = c.take<unsigned long long>(2);
+    w.p_fix = c.take<uint32_t>(tiles);
+    w.big_n = c.take<unsigned long long>(3);
     *bytes = c.bytes();
     return w;
 }
@@ -1091,10 +1157,19 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
                            w.s_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, no_off, no_off, uv, bit, cap);
         CG_LAUNCHED("edges_s_big_count");
     }
-    const unsigned pblocks = persistent_blocks(reinterpret_cast<const void *>(&k_p_find<T, WT>), lds_find, ntiles);
-    hipLaunchKernelGGL((k_p_find<T, WT>), dim3(pblocks), dim3(PT), lds_find, s, cells, d.d_ncells, ncap, words, ell,
-                       sp, gmax, w.cntS, w.cntP, w.p_stash, w.p_stash_n, w.tile_tot, w.sup_tot, w.p_big,
-                       w.big_n + 1);
+    if (words == WT) {
+        const unsigned pblocks =
+            persistent_blocks(reinterpret_cast<const void *>(&k_p_find<T, WT, true>), lds_find, ntiles);
+        hipLaunchKernelGGL((k_p_find<T, WT, true>), dim3(pblocks), dim3(PT), lds_find, s, cells, d.d_ncells, ncap,
+                           words, ell, sp, gmax, w.cntS, w.cntP, w.p_stash, w.p_stash_n, w.tile_tot, w.sup_tot,
+                           w.p_big, w.big_n + 1, w.p_fix, w.big_n + 2);
+    } else {
+        const unsigned pblocks =
+            persistent_blocks(reinterpret_cast<const void *>(&k_p_find<T, WT, false>), lds_find, ntiles);
+        hipLaunchKernelGGL((k_p_find<T, WT, false>), dim3(pblocks), dim3(PT), lds_find, s, cells, d.d_ncells, ncap,
+                           words, ell, sp, gmax, w.cntS, w.cntP, w.p_stash, w.p_stash_n, w.tile_tot, w.sup_tot,
+                           w.p_big, w.big_n + 1, w.p_fix, w.big_n + 2);
+    }
     CG_LAUNCHED("edges_p_find");
     hipLaunchKernelGGL((k_big_lookup<T, BIG_P_COUNT>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
                        w.p_big, w.big_n + 1, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, no_off, no_off, uv, bit, cap);
@@ -1108,9 +1183,8 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
                        w.p_big, w.big_n + 1, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, d_offsets, offnext, uv, bit, cap);
     CG_LAUNCHED("edges_p_big_write");
     const int gm = gmax < PSCAN ? gmax : PSCAN;  // same scan limit as k_p_find
-    hipLaunchKernelGGL((k_p_fix<T, WT>), dim3(blocks_for(ntiles, 1, 512)), dim3(PT), lds, s, cells, d.d_ncells, ncap,
-                       words, sp, gm, w.cntS,
-                       w.cntP, w.p_stash_n, w.tile_tot, w.sup_tot, uv, bit, cap);
+    hipLaunchKernelGGL((k_p_fix<T, WT>), dim3(blocks_for(ntiles, 1, 64)), dim3(PT), lds, s, cells, d.d_ncells, ncap,
+                       words, sp, gm, w.cntS, w.cntP, w.p_fix, w.big_n + 2, w.tile_tot, w.sup_tot, uv, bit, cap);
     CG_LAUNCHED("edges_p_fix");
     if (sp > 0) {
         hipLaunchKernelGGL((k_s_scan<T, true>), sgrid, dim3(PT), 0, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
