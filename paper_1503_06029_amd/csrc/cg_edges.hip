@@ -205,16 +205,18 @@ __global__ void k_edges_init(uint32_t *cntS, int64_t ncap, int64_t *d_nedges, in
 // Each starter pairs with the later members of its run (at most rmax; ids
 // ascend along a run, so partners come in ascending v); the (starter,
 // partner) pairs of the block are numbered by a scan and checked by groups
-// of 16 lanes, each lane taking every 16th word of both rows, so a row is
-// read as whole 128-byte lines rather than one word per lane.  A found edge
+// of four lanes, each lane taking every fourth word of both rows (so a row's
+// words are read in 32-byte runs and 64 pairs are in flight per pass over
+// the block; a block takes 1,024 positions so that one round trip of loads
+// covers more of the order).  A found edge
 // sets bit j - 1 of its starter's mask (j = partner's offset in the run), so
 // a starter's rank of an edge is the popcount of its mask below j.  A starter
 // followed by more than rmax members looks up u xor e_k for every k < s
 // instead.  The count pass writes cntS[u]; the write pass redoes the checks
 // and emits at next(u) - cntS[u] + rank.
-constexpr int SC = PT;      // suffix-order positions per block
+constexpr int SC = 4 * PT;  // suffix-order positions per block (four per thread)
 constexpr int SRMAX = 64;   // most later run members scanned; more use look-ups
-constexpr int SG = 16;      // most lanes per pair check (fewer for short rows)
+constexpr int SG = 4;       // lanes per pair check (two for rows of up to two words)
 constexpr int S_STASH = 256;  // S edges kept per block of the suffix order
 
 template <typename T, bool WRITE>
@@ -333,9 +335,9 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
     if (t == 0) pofs[nst] = npairs;
     __syncthreads();
 
-    // pair checks: group g of sg lanes takes pairs g, g + PT / sg, ... where sg
-    // is the smallest power of two >= words, at most SG (the same for every lane)
-    const int sg = words <= 2 ? 2 : (words <= 4 ? 4 : (words <= 8 ? 8 : SG));
+    // pair checks: group g of sg lanes takes pairs g, g + PT / sg, ... (sg the
+    // same for every lane: two lanes for rows of up to two words, else SG)
+    const int sg = words <= 2 ? 2 : SG;
     const int lg = t % sg, g = t / sg, ng = PT / sg;
     auto check_pair = [&](uint32_t pidx, int *li_out, int *j_out, uint32_t *u_out, uint32_t *v_out, int *pos_out) {
         int lo = 0, hi = nst;  // last starter with pofs <= pidx
@@ -735,14 +737,30 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
     uint32_t *wres = res + wv * WST;
     const int gm = gmax < PSCAN ? gmax : PSCAN;
 
-    T pre[NE];
+    // FULLW with rows a whole number of 16-byte chunks: the tile moves as
+    // 16-byte pieces (half the load instructions of word loads)
+    constexpr bool V16 = FULLW && (WT * sizeof(T)) % 16 == 0;
+    constexpr int PW = 16 / static_cast<int>(sizeof(T));                // words per piece
+    constexpr int NC = (PROWS * WT / PW + PT - 1) / PT;                 // pieces per thread
+    constexpr int NPRE = V16 ? NC * PW : NE;
+    T pre[NPRE];
     uint32_t pre_cs = 0;
     auto prefetch = [&](int64_t tile) {
         const int64_t base = tile * PT;
         const int64_t av = n - base;
         const int avail = static_cast<int>(av < PROWS ? av : PROWS);
         const T *src = cells + base * words;
-        if (FULLW && avail == PROWS) {  // the tile and its halo are all there: plain loads
+        if (V16 && avail == PROWS) {  // the tile and its halo are all there: plain 16-byte loads
+            const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+#pragma unroll
+            for (int u = 0; u < NC; ++u) {
+                const int c = t + u * PT;
+                const uint4 v = c < PROWS * WT / PW ? s4[c] : make_uint4(0u, 0u, 0u, 0u);
+                const T *pv = reinterpret_cast<const T *>(&v);
+#pragma unroll
+                for (int k = 0; k < PW; ++k) pre[u * PW + k] = pv[k];
+            }
+        } else if (FULLW && avail == PROWS) {  // plain word loads
 #pragma unroll
             for (int u = 0; u < NE; ++u) {
                 const int e = t + u * PT;
@@ -785,7 +803,18 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
             s_tot = 0;
             s_ovf = 0;
         }
-        {
+        if (V16 && tl == PROWS) {
+            // piece c holds words c * PW .. c * PW + PW - 1 of the tile, all in one row
+#pragma unroll
+            for (int u = 0; u < NC; ++u) {
+                const int c = t + u * PT;
+                if (c < PROWS * WT / PW) {
+                    T *dst = rows + ((c * PW) / WT) * LW + ((c * PW) % WT);
+#pragma unroll
+                    for (int k = 0; k < PW; ++k) dst[k] = pre[u * PW + k];
+                }
+            }
+        } else {
             const int tot = tl * WT;
             const bool full = FULLW && tl == PROWS;
 #pragma unroll
@@ -799,6 +828,9 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
             }
         }
         const uint32_t cs = base + t < n ? pre_cs : 0u;
+        // the registers are free once stored: the next tile's loads go out now,
+        // before the barriers, so they are in flight during all of this tile
+        if (tile + G8 < r1) prefetch(tile + G8);
         mask[t] = 0;
         if (lane == 0) s_nres[wv] = 0;
         __syncthreads();
@@ -812,7 +844,6 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
         }
         for (int r = tl + t; r < PCS; r += PT) pcs[r] = PASTF;
         __syncthreads();
-        if (tile + G8 < r1) prefetch(tile + G8);
         const int64_t i = base + t;
         const bool more = base + tl < n;  // cells exist past the loaded rows
 
@@ -902,10 +933,10 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
         }
         const uint32_t stashed = (cp & BIG) ? 0u : cp;
         const uint32_t inc = wave_incl_scan_u32(stashed);
-        const uint32_t tot_stash = __shfl(inc, 63, 64);
+        const uint32_t tot_stash = lane63_u32(inc);
         const uint32_t all = wave_incl_scan_u32((cp & ~BIG) + (t < tr ? cs : 0u));
         sbase[t] = (cp & BIG) ? 0xffffffffu : inc - stashed;
-        const uint32_t wall = __shfl(all, 63, 64);
+        const uint32_t wall = lane63_u32(all);
         const uint32_t nres = s_nres[wv];
         const uint32_t m = nres > tot_stash ? nres : tot_stash;
         if (lane == 0) {

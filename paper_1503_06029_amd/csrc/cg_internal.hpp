@@ -77,24 +77,42 @@ __device__ __forceinline__ uint64_t shfl_u64_xor(uint64_t x, int m) {
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
-// Inclusive prefix sum across the 64 lanes of a wave.
-__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
-    int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint64_t y = shfl_up_u64(x, d);
-        if (l >= d) x += y;
-    }
+// Inclusive prefix sum across the 64 lanes of a wave, by data-parallel
+// primitives (DPP): shifts by 1, 2, 4, 8 lanes inside each 16-lane row, then
+// row 0's and row 2's last lanes broadcast into rows 1 and 3, and lane 31
+// into rows 2 and 3.  Lanes whose source is out of range, or whose row is
+// masked off, add 0.  Six dependent ALU steps, no LDS round trips.
+#define CG_DPP(x, ctrl, rmask) \
+    static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), (ctrl), (rmask), 0xf, true))
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+    x += CG_DPP(x, 0x111, 0xf);  // row_shr:1
+    x += CG_DPP(x, 0x112, 0xf);  // row_shr:2
+    x += CG_DPP(x, 0x114, 0xf);  // row_shr:4
+    x += CG_DPP(x, 0x118, 0xf);  // row_shr:8
+    x += CG_DPP(x, 0x142, 0xa);  // row_bcast:15 into rows 1 and 3
+    x += CG_DPP(x, 0x143, 0xc);  // row_bcast:31 into rows 2 and 3
     return x;
 }
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
-    int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t y = shfl_up_u32(x, d);
-        if (l >= d) x += y;
-    }
-    return x;
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
+    uint32_t lo = static_cast<uint32_t>(x), hi = static_cast<uint32_t>(x >> 32);
+    auto step = [&](uint32_t ylo, uint32_t yhi) {
+        const uint64_t r = ((static_cast<uint64_t>(hi) << 32) | lo) + ((static_cast<uint64_t>(yhi) << 32) | ylo);
+        lo = static_cast<uint32_t>(r);
+        hi = static_cast<uint32_t>(r >> 32);
+    };
+    step(CG_DPP(lo, 0x111, 0xf), CG_DPP(hi, 0x111, 0xf));
+    step(CG_DPP(lo, 0x112, 0xf), CG_DPP(hi, 0x112, 0xf));
+    step(CG_DPP(lo, 0x114, 0xf), CG_DPP(hi, 0x114, 0xf));
+    step(CG_DPP(lo, 0x118, 0xf), CG_DPP(hi, 0x118, 0xf));
+    step(CG_DPP(lo, 0x142, 0xa), CG_DPP(hi, 0x142, 0xa));
+    step(CG_DPP(lo, 0x143, 0xc), CG_DPP(hi, 0x143, 0xc));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+#undef CG_DPP
+// The value of lane 63 (a wave's total after an inclusive scan), as a
+// wave-uniform scalar.
+__device__ __forceinline__ uint32_t lane63_u32(uint32_t x) {
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 63));
 }
 
 // Exclusive prefix sum over a 256-thread block (4 waves); returns the
