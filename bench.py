@@ -148,7 +148,7 @@ def main():
     ap.add_argument("--cpu-dedup-rows", type=int, default=400_000)
     ap.add_argument("--cpu-search-cells", type=int, default=131072)
     ap.add_argument("--no-small-configs", action="store_true")
-    ap.add_argument("--workload", choices=("long", "batched", "served", "search", "sample", "queries"),
+    ap.add_argument("--workload", choices=("long", "batched", "served", "search", "sample", "queries", "paths"),
                     default="long",
                     help="long: 1024-bit vectors (the headline); batched: 512 plane scenes in one graph; "
                          "served: Poisson stream of those scenes")
@@ -169,6 +169,8 @@ def main():
         return bench_sample(args)
     if args.workload == "queries":
         return bench_queries(args)
+    if args.workload == "paths":
+        return bench_paths(args)
     if args.workload == "served":
         return bench_served(args)
 
@@ -664,6 +666,73 @@ def bench_queries(args):
         "correct": bool(ok),
     }
     print(json.dumps(out), flush=True)
+
+
+# integer lane-op peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit op per lane per cycle
+INT_LANE_OPS_PEAK = 256 * 64 * 2.4e9
+
+
+def bench_paths(args):
+    """The three edge paths on one dictionary (the plane arrangement: 10^6
+    points, 128 planes -> 85,032 cells): flip-and-look-up, the (*)-pruned
+    all-pairs scan of Section 3.1 (h = 0 and 4 references) and the O(n l)
+    additive-hash probes.  The all-pairs scan is bound by the integer ALUs:
+    its line counts pair tests per second and the filter's lane operations
+    (3 per reference per pair: subtract, compare, and) against the integer
+    lane-op peak; the exact test of the few surviving pairs is not counted."""
+    import torch
+    from paper_1503_06029_amd import binding as B, inputs, pipeline
+    log("generating the plane-arrangement scene")
+    R = inputs.plane_arrangement()
+    ell = R.shape[1]
+    bits = torch.from_numpy(np.ascontiguousarray(R)).cuda()
+    out = {}
+    ref = None
+    for name, kw in (("lookup", dict()), ("allpairs_h0", dict(path=B.CG_PATH_ALLPAIRS, n_refs=0)),
+                     ("allpairs_h4", dict(path=B.CG_PATH_ALLPAIRS, n_refs=4)), ("hash", dict(path=B.CG_PATH_HASH))):
+        g = pipeline.CellGraph(R.shape[0], ell, 32, params=B.cg_dict_params_default(**kw), edge_cap=1_100_000)
+        g.pack(bits)
+        g.run_checked()
+        nc, E = int(g.ncells.item()), int(g.nedges.item())
+        uv = g.uv[:E].cpu().numpy()
+        same = ref is None or np.array_equal(uv, ref)
+        ref = uv if ref is None else ref
+        steps = max(3, args.steps // (20 if name.startswith("allpairs") else 1))
+        for _ in range(2):
+            g.edges()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record()
+        for k in range(steps):
+            g.edges()
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        ms = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
+        rec = {"edges_ms": ms, "cells": nc, "edges": E, "same_bytes_as_lookup": bool(same)}
+        if name.startswith("allpairs"):
+            h = kw["n_refs"]
+            pairs = nc * (nc - 1) / 2
+            rec["pair_tests_per_s"] = pairs / (ms / 1e3)
+            if h:
+                ops = 3 * h * pairs / (ms / 1e3)
+                rec["filter_lane_ops_per_s"] = ops
+                rec["roofline"] = {"bound": "alu", "achieved": ops / 1e12, "peak": INT_LANE_OPS_PEAK / 1e12,
+                                   "unit": "Tops/s", "frac": ops / INT_LANE_OPS_PEAK}
+        if name == "hash":
+            rec["probes_per_s"] = nc * ell / 2 / (ms / 1e3)
+        out[name] = rec
+        log(f"{name}: {ms:.3f} ms, {E} edges, same bytes {same}")
+        del g
+        torch.cuda.empty_cache()
+    line = {"metric": "edge paths on one dictionary: lookup, (*)-pruned all-pairs, O(n l) hash probes",
+            "value": out["allpairs_h4"]["pair_tests_per_s"], "unit": "pair tests/s (all-pairs, h = 4)",
+            "n_gpus": 1, "steps": args.steps, "warmup": 2, "ms_per_step": out["allpairs_h4"]["edges_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "plane arrangement: 10^6 points, 128 planes in [-1, 1]^3",
+                       "cells": out["lookup"]["cells"], "edges": out["lookup"]["edges"]},
+            "roofline": out["allpairs_h4"].get("roofline"), "paths": out,
+            "correct": all(v["same_bytes_as_lookup"] for v in out.values())}
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -127,12 +127,16 @@ cg_status cg_dedup(const void *d_packed, int64_t n, cg_layout lay, void *d_cells
 #define CG_DICT_SORTED 0        /* sorted keys + prefix directory + suffix order */
 #define CG_PATH_LOOKUP 0        /* edges by flip-and-look-up over the two orders */
 #define CG_PATH_ALLPAIRS 1      /* edges by the (*)-filtered all-pairs scan       */
+#define CG_PATH_HASH 2          /* edges in O(n l) probes of an additive-hash table
+                                   (Section 6: the O(n l) construction); each flip
+                                   updates the key in O(1), hits are checked row by
+                                   row, so the output is the same                  */
 
 typedef struct cg_dict_params {
     int32_t kind;       /* CG_DICT_SORTED                                         */
     int32_t dir_bits;   /* p, 0..24; -1 = automatic (about log2 of the capacity)  */
     int32_t split_bit;  /* s, 0..l; -1 = automatic                                */
-    int32_t path;       /* CG_PATH_LOOKUP or CG_PATH_ALLPAIRS (used by cg_edges)  */
+    int32_t path;       /* CG_PATH_LOOKUP, _ALLPAIRS or _HASH (used by cg_edges)  */
     int32_t n_refs;     /* h, 0..8: reference vectors of the all-pairs path       */
     int32_t group_max;  /* groups larger than this are searched, not scanned;
                            1..1024, -1 = automatic                                */
@@ -209,8 +213,9 @@ cg_status cg_neighbors_d1(const cg_dict *dict, const void *d_queries, int64_t nq
  *              which case nothing is written at or past index cap, the
  *              contents below cap are unspecified, and the caller re-calls
  *              with cap >= *d_nedges and the same dictionary.
- * The dictionary's path parameter picks the method (flip-and-look-up or the
- * (*)-filtered all-pairs scan of Section 3.1); the output bytes are the same.
+ * The dictionary's path parameter picks the method (flip-and-look-up, the
+ * (*)-filtered all-pairs scan of Section 3.1, or the O(n l) hash probes of
+ * Section 6); the output bytes are the same.
  * Workspace: cg_edges_workspace(dict, cap) bytes.
  * Errors: CG_EINVAL, CG_EWORKSPACE.                                         */
 cg_status cg_edges_workspace(const cg_dict *dict, int64_t cap, size_t *bytes);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcellgraph.so")
 
 CG_OK, CG_EINVAL, CG_EWORKSPACE, CG_ECAPACITY, CG_EHIP, CG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 CG_DICT_SORTED = 0
-CG_PATH_LOOKUP, CG_PATH_ALLPAIRS = 0, 1
+CG_PATH_LOOKUP, CG_PATH_ALLPAIRS, CG_PATH_HASH = 0, 1, 2
 
 c_i32, c_i64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
 

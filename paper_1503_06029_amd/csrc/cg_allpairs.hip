@@ -9,10 +9,11 @@
 // Pairs involving a reference are scanned like all others.
 //
 // Tiling: one 256-thread block per pair of 256-cell tiles (I <= J); the
-// reference distances of tile J sit in LDS, each thread owns one cell of
-// tile I.  Found edges set bit k of a per-cell upward-neighbour mask and are
-// appended to a list; ranks within a cell (descending k = ascending v) come
-// from the mask, so the final placement matches the other path byte for byte.
+// reference distances and rows of tile J sit in LDS, each thread owns one
+// cell of tile I.  Found edges set bit k of a per-cell upward-neighbour mask
+// and are appended to a list; ranks within a cell (descending k = ascending
+// v) come from the mask, so the final placement matches the other paths byte
+// for byte.
 #include "cg_internal.hpp"
 
 #include <cmath>
@@ -41,13 +42,29 @@ __global__ void __launch_bounds__(256) k_ref_dists(const T *__restrict__ cells, 
     }
 }
 
-template <typename T>
+// One block per tile pair (I, J), I <= J.  Tile J's reference distances and
+// (WT > 0) its rows, zero-padded to WT words, sit in LDS; thread t owns cell
+// i0 + t of tile I with its own distances and row in registers.  All threads
+// walk the 256 cells of tile J together, so every LDS read is a broadcast.
+// Found edges go to a block stash in LDS and reach the global list with one
+// reservation per block (per-edge global atomics would serialise on the
+// cursor); a stash that fills up sends the rest one wave-reservation at a
+// time.  WT = 0: rows too wide for LDS, read from global memory.
+constexpr int AP_STASH = 1024;
+
+template <typename T, int WT>
 __global__ void __launch_bounds__(AP_TILE) k_allpairs(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
                                                       int words, int h, const uint16_t *__restrict__ D,
                                                       T *__restrict__ mask, uint4 *__restrict__ list,
                                                       unsigned long long *__restrict__ cursor, int64_t list_cap) {
     constexpr int B = Bits<T>::B;
+    constexpr int LW = WT + 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *rj = reinterpret_cast<T *>(smem);  // WT > 0: AP_TILE rows of LW words
     __shared__ uint16_t dj[AP_MAX_REFS][AP_TILE];
+    __shared__ uint4 stash[AP_STASH];
+    __shared__ uint32_t s_n;
+    __shared__ unsigned long long s_base;
     const int64_t n = load_n(d_n, ncap);
     // block -> (I, J), I <= J, from the triangular index b = J (J + 1) / 2 + I
     const int64_t b = blockIdx.x;
@@ -56,38 +73,90 @@ __global__ void __launch_bounds__(AP_TILE) k_allpairs(const T *__restrict__ cell
     while ((J + 1) * (J + 2) / 2 <= b) ++J;
     const int64_t I = b - J * (J + 1) / 2;
     const int64_t i0 = I * AP_TILE, j0 = J * AP_TILE;
-    if (j0 >= n) return;
-    const int t = threadIdx.x;
-    for (int d = 0; d < h; ++d) dj[d][t] = (j0 + t < n) ? D[static_cast<int64_t>(d) * ncap + j0 + t] : 0;
+    if (j0 >= n) return;  // the same for the whole block
+    const int t = threadIdx.x, lane = t & 63;
+    const int jn = static_cast<int>(n - j0 < AP_TILE ? n - j0 : AP_TILE);
+    for (int d = 0; d < h; ++d) dj[d][t] = t < jn ? D[static_cast<int64_t>(d) * ncap + j0 + t] : 0;
+    if (WT > 0) {
+        for (int e = t; e < AP_TILE * WT; e += AP_TILE) {
+            const int r = e / WT, w = e % WT;
+            rj[r * LW + w] = (r < jn && w < words) ? cells[(j0 + r) * words + w] : T(0);
+        }
+    }
+    if (t == 0) s_n = 0;
     __syncthreads();
     const int64_t i = i0 + t;
-    if (i >= n) return;
+    const bool own = i < n;
     uint16_t di[AP_MAX_REFS];
-    for (int d = 0; d < h; ++d) di[d] = D[static_cast<int64_t>(d) * ncap + i];
-    const T *xi = cells + i * words;
-    const int jn = static_cast<int>(n - j0 < AP_TILE ? n - j0 : AP_TILE);
+    for (int d = 0; d < AP_MAX_REFS; ++d) di[d] = (own && d < h) ? D[static_cast<int64_t>(d) * ncap + i] : 0;
+    T xi[WT > 0 ? WT : 1];
+    if (WT > 0) {
+#pragma unroll
+        for (int w = 0; w < (WT > 0 ? WT : 1); ++w) xi[w] = (own && w < words) ? cells[i * words + w] : T(0);
+    }
+    const T *xg = cells + (own ? i : 0) * words;
+    // j > i: in the diagonal tile only cells after i; lanes past the end idle
+    const int jstart = (I == J) ? t + 1 : 0;
     for (int jj = 0; jj < jn; ++jj) {
-        const int64_t j = j0 + jj;
-        if (j <= i) continue;
-        bool ok = true;
-        for (int d = 0; d < h && ok; ++d) {
+        bool ok = own && jj >= jstart;
+        for (int d = 0; d < h; ++d) {
             const int a = di[d], c = dj[d][jj];
-            ok = (a - c == 1) || (c - a == 1);
+            ok = ok && ((a - c == 1) || (c - a == 1));
         }
-        if (!ok) continue;
-        int pos;
-        if (dist_upto2<T>(xi, cells + j * words, words, &pos) == 1) {
-            // set bit pos of the cell's mask with a word-sized atomic
+        int pos = 0;
+        bool hit = false;
+        if (ok) {
+            if (WT > 0) {
+                int dd = 0, first = -1;
+#pragma unroll
+                for (int w = 0; w < (WT > 0 ? WT : 1); ++w) {
+                    const T x = xi[w] ^ rj[jj * LW + w];
+                    dd += popc<T>(x);
+                    first = (x && first < 0) ? w * B + clz_t<T>(x) : first;
+                }
+                hit = dd == 1;
+                pos = first;
+            } else {
+                hit = dist_upto2<T>(xg, cells + (j0 + jj) * words, words, &pos) == 1;
+            }
+        }
+        if (hit) {
             if (B == 64)
                 atomicOr(reinterpret_cast<unsigned long long *>(mask + i * words + pos / B),
                          static_cast<unsigned long long>(bitmask_of<T>(pos)));
             else
                 atomicOr(reinterpret_cast<unsigned int *>(mask + i * words + pos / B),
                          static_cast<unsigned int>(bitmask_of<T>(pos)));
-            const unsigned long long slot = atomicAdd(cursor, 1ull);
-            if (static_cast<int64_t>(slot) < list_cap)
-                list[slot] = make_uint4(static_cast<uint32_t>(i), static_cast<uint32_t>(j), static_cast<uint32_t>(pos), 0u);
         }
+        const uint64_t hm = ballot64(hit);
+        if (hm) {  // one LDS counter update per wave; past the stash, one global reservation per wave
+            uint32_t rb = 0;
+            if (lane == 0) rb = atomicAdd(&s_n, static_cast<uint32_t>(__popcll(hm)));
+            rb = __shfl(rb, 0, 64);
+            const uint32_t r = rb + static_cast<uint32_t>(__popcll(hm & lanemask_lt()));
+            const uint4 e = make_uint4(static_cast<uint32_t>(i), static_cast<uint32_t>(j0 + jj),
+                                       static_cast<uint32_t>(pos), 0u);
+            const bool in_stash = r < static_cast<uint32_t>(AP_STASH);
+            const uint64_t om = ballot64(hit && !in_stash);
+            if (hit && in_stash) stash[r] = e;
+            if (om) {
+                unsigned long long g = 0;
+                if (lane == 0) g = atomicAdd(cursor, static_cast<unsigned long long>(__popcll(om)));
+                g = shfl_u64(g, 0);
+                if (hit && !in_stash) {
+                    const unsigned long long k = g + static_cast<unsigned long long>(__popcll(om & lanemask_lt()));
+                    if (static_cast<int64_t>(k) < list_cap) list[k] = e;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t m = s_n < static_cast<uint32_t>(AP_STASH) ? s_n : static_cast<uint32_t>(AP_STASH);
+    if (t == 0) s_base = m ? atomicAdd(cursor, static_cast<unsigned long long>(m)) : 0ull;
+    __syncthreads();
+    for (uint32_t r = t; r < m; r += AP_TILE) {
+        const unsigned long long k = s_base + r;
+        if (static_cast<int64_t>(k) < list_cap) list[k] = stash[r];
     }
 }
 
@@ -169,8 +238,27 @@ cg_status ap_impl(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap, in
         const int64_t tiles = (ncap + AP_TILE - 1) / AP_TILE;
         const int64_t pairs = tiles * (tiles + 1) / 2;
         if (pairs > 0x7fffffffLL) return set_error(CG_EUNSUPPORTED, "all-pairs path: %lld cells is too many", (long long)ncap);
-        hipLaunchKernelGGL((k_allpairs<T>), dim3(static_cast<unsigned>(pairs)), dim3(AP_TILE), 0, s, cells,
-                           d.d_ncells, ncap, words, h, w.D, static_cast<T *>(w.mask), w.list, w.cursor, cap);
+        int wt = 1;
+        while (wt < words) wt <<= 1;
+        const int wcap = sizeof(T) == 8 ? 16 : 32;  // rows of up to 1024 bits are staged in LDS
+        const dim3 grid(static_cast<unsigned>(pairs));
+        T *mk = static_cast<T *>(w.mask);
+#define CG_AP(WTV)                                                                                                 \
+    hipLaunchKernelGGL((k_allpairs<T, WTV>), grid, dim3(AP_TILE), static_cast<size_t>(AP_TILE) * ((WTV) + 1) * sizeof(T), s, \
+                       cells, d.d_ncells, ncap, words, h, w.D, mk, w.list, w.cursor, cap)
+        if (wt > wcap) {
+            CG_AP(0);
+        } else {
+            switch (wt) {
+            case 1: CG_AP(1); break;
+            case 2: CG_AP(2); break;
+            case 4: CG_AP(4); break;
+            case 8: CG_AP(8); break;
+            case 16: CG_AP(16); break;
+            default: CG_AP(32); break;
+            }
+        }
+#undef CG_AP
         CG_LAUNCHED("allpairs_pairs");
     }
     CG_TRY(scan_rowpop_to_i64(w.mask, d.lay.word_bits, words, offsets, ncap, d.d_ncells, w.tile_sums, d_nedges, s));

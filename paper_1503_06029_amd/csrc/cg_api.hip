@@ -139,7 +139,8 @@ static cg_status check_params(const cg_dict_params *p, const cg_layout &lay) {
     if (p->dir_bits < -1 || p->dir_bits > 24) return set_error(CG_EINVAL, "dir_bits=%d out of range -1..24", p->dir_bits);
     if (p->split_bit < -1 || p->split_bit > lay.ell)
         return set_error(CG_EINVAL, "split_bit=%d out of range -1..ell", p->split_bit);
-    if (p->path != CG_PATH_LOOKUP && p->path != CG_PATH_ALLPAIRS) return set_error(CG_EINVAL, "path=%d", p->path);
+    if (p->path != CG_PATH_LOOKUP && p->path != CG_PATH_ALLPAIRS && p->path != CG_PATH_HASH)
+        return set_error(CG_EINVAL, "path=%d", p->path);
     if (p->n_refs < 0 || p->n_refs > 8) return set_error(CG_EINVAL, "n_refs=%d out of range 0..8", p->n_refs);
     if (p->group_max != -1 && (p->group_max < 1 || p->group_max > 1024))
         return set_error(CG_EINVAL, "group_max=%d out of range 1..1024", p->group_max);
@@ -195,8 +196,11 @@ cg_status cg_edges_workspace(const cg_dict *dict, int64_t cap, size_t *bytes) {
     CG_TRY(check_dict(dict));
     if (cap < 0) return set_error(CG_EINVAL, "cg_edges_workspace: cap < 0");
     if (!bytes) return set_error(CG_EINVAL, "cg_edges_workspace: bytes is NULL");
-    *bytes = dict->params.path == CG_PATH_ALLPAIRS ? allpairs_workspace_bytes(*dict, cap)
-                                                    : edges_workspace_bytes(*dict, cap);
+    switch (dict->params.path) {
+    case CG_PATH_ALLPAIRS: *bytes = allpairs_workspace_bytes(*dict, cap); break;
+    case CG_PATH_HASH: *bytes = hash_workspace_bytes(*dict, cap); break;
+    default: *bytes = edges_workspace_bytes(*dict, cap); break;
+    }
     return CG_OK;
 }
 
@@ -229,6 +233,8 @@ cg_status cg_edges(const cg_dict *dict, uint32_t *d_uv, uint16_t *d_bit, int64_t
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (dict->params.path == CG_PATH_ALLPAIRS)
         return run_edges_allpairs(*dict, d_uv, d_bit, cap, d_nedges, d_offsets, d_ws, ws_bytes, d_status, s);
+    if (dict->params.path == CG_PATH_HASH)
+        return run_edges_hash(*dict, d_uv, d_bit, cap, d_nedges, d_offsets, d_ws, d_status, s);
     return run_edges(*dict, d_uv, d_bit, cap, d_nedges, d_offsets, d_ws, ws_bytes, d_status, s);
 }
 

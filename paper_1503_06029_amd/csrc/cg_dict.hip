@@ -184,6 +184,108 @@ __global__ void __launch_bounds__(256) k_d1_query(const T *__restrict__ cells, c
     }
 }
 
+// Queries by the query's own directory bucket.  A flip at k >= p keeps the
+// top p bits, so q xor e_k can only be a cell of q's own bucket, and it is
+// one exactly when that cell is at distance 1 from q, differing at k.  So
+// instead of one search per flip, the wave reads the bucket's cells once
+// (one lane per cell) and sets mask bit k for each cell at distance 1 (the
+// cell at distance 0 is q itself); only the p flips inside the directory
+// bits are searched, each in its own bucket.  Buckets larger than DB_MAX
+// cells fall back to per-flip searches for k >= p too.  MW: most words per
+// row (the wave's mask is accumulated in LDS).
+constexpr int DB_MAX = 256;
+constexpr int D1_MW = 64;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_d1_bucket(const T *__restrict__ cells, int words, int ell,
+                                                   const uint32_t *__restrict__ dir, int p,
+                                                   const T *__restrict__ queries, int64_t nq,
+                                                   uint32_t *__restrict__ count, uint32_t *__restrict__ self,
+                                                   T *__restrict__ mask) {
+    constexpr int B = Bits<T>::B;
+    __shared__ T smask[4][D1_MW];
+    __shared__ uint32_t sself[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wid = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    T *sm = smask[wv];
+    for (int64_t qi = wid; qi < nq; qi += nw) {
+        const T *q = queries + qi * words;
+        const uint64_t qh = head64<T>(q, words);
+        const int64_t g = p ? static_cast<int64_t>(qh >> (64 - p)) : 0;
+        const uint32_t lo = dir[g], hi = dir[g + 1];
+        for (int w = lane; w < words; w += 64) sm[w] = T(0);
+        if (lane == 0) sself[wv] = 0xFFFFFFFFu;
+        __builtin_amdgcn_wave_barrier();
+        if (hi - lo <= static_cast<uint32_t>(DB_MAX)) {
+            // the bucket's cells, one lane each: distance 1 at k sets bit k
+            for (uint32_t c = lo + lane; c < hi; c += 64) {
+                const T *x = cells + static_cast<int64_t>(c) * words;
+                int d = 0, first = -1;
+                for (int w = 0; w < words && d < 2; ++w) {
+                    const T y = x[w] ^ q[w];
+                    if (y) {
+                        d += popc<T>(y);
+                        if (first < 0) first = w * B + clz_t<T>(y);
+                    }
+                }
+                if (d == 0) sself[wv] = c;
+                if (d == 1) {
+                    if (B == 64)
+                        atomicOr(reinterpret_cast<unsigned long long *>(&sm[first / B]),
+                                 static_cast<unsigned long long>(bitmask_of<T>(first)));
+                    else
+                        atomicOr(reinterpret_cast<unsigned int *>(&sm[first / B]),
+                                 static_cast<unsigned int>(bitmask_of<T>(first)));
+                }
+            }
+        } else {
+            // a long bucket: search it once per flip at k >= p
+            for (int k0 = p; k0 < ell; k0 += 64) {
+                const int k = k0 + lane;
+                const bool found = k < ell && find_row<T>(cells, words, lo, hi, q, k) >= 0;
+                if (found) {
+                    if (B == 64)
+                        atomicOr(reinterpret_cast<unsigned long long *>(&sm[k / B]),
+                                 static_cast<unsigned long long>(bitmask_of<T>(k)));
+                    else
+                        atomicOr(reinterpret_cast<unsigned int *>(&sm[k / B]), static_cast<unsigned int>(bitmask_of<T>(k)));
+                }
+            }
+            if (lane == 0) {
+                const int64_t id = find_row<T>(cells, words, lo, hi, q, -1);
+                if (id >= 0) sself[wv] = static_cast<uint32_t>(id);
+            }
+        }
+        // flips inside the directory bits: each in the bucket of its own top p bits
+        if (lane < p && lane < ell) {
+            const int k = lane;
+            const uint64_t th = qh ^ (1ull << (63 - k));
+            const int64_t g2 = static_cast<int64_t>(th >> (64 - p));
+            if (find_row<T>(cells, words, dir[g2], dir[g2 + 1], q, k) >= 0) {
+                if (B == 64)
+                    atomicOr(reinterpret_cast<unsigned long long *>(&sm[k / B]),
+                             static_cast<unsigned long long>(bitmask_of<T>(k)));
+                else
+                    atomicOr(reinterpret_cast<unsigned int *>(&sm[k / B]), static_cast<unsigned int>(bitmask_of<T>(k)));
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        uint32_t c = 0;
+        for (int w = lane; w < words; w += 64) {
+            const T m = sm[w];
+            c += static_cast<uint32_t>(popc<T>(m));
+            if (mask) mask[qi * words + w] = m;
+        }
+        const uint32_t tot = lane63_u32(wave_incl_scan_u32(c));
+        if (lane == 0) {
+            if (count) count[qi] = tot;
+            if (self) self[qi] = sself[wv];
+        }
+        __builtin_amdgcn_wave_barrier();  // the wave's LDS is cleared for its next query
+    }
+}
+
 struct DictMem {
     uint32_t *dir;
     uint4 *gaps;
@@ -357,6 +459,13 @@ template <typename T>
 static cg_status d1_impl(const cg_dict &d, const void *q, int64_t nq, uint32_t *count, uint32_t *self, void *mask,
                          hipStream_t s) {
     if (nq == 0) return CG_OK;
+    if (d.lay.words <= D1_MW) {
+        hipLaunchKernelGGL((k_d1_bucket<T>), dim3(blocks_for(nq, 4, 65536)), dim3(256), 0, s,
+                           static_cast<const T *>(d.cells), d.lay.words, d.lay.ell, d.dir, d.params.dir_bits,
+                           static_cast<const T *>(q), nq, count, self, static_cast<T *>(mask));
+        CG_LAUNCHED("d1_bucket");
+        return CG_OK;
+    }
     hipLaunchKernelGGL((k_d1_query<T>), dim3(blocks_for(nq, 4, 65536)), dim3(256), 0, s,
                        static_cast<const T *>(d.cells), d.d_ncells, d.ncells_cap, d.lay.words, d.lay.ell, d.dir,
                        d.params.dir_bits, static_cast<const T *>(q), nq, count, self, static_cast<T *>(mask));

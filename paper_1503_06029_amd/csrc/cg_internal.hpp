@@ -444,6 +444,9 @@ cg_status scan_u8_to_u32(const uint8_t *in, uint32_t *out, int64_t n_cap, const 
 // out[i] = sum_{j<i} (a[j] + b[j]) as int64; out[n] and *total = the sum.
 cg_status scan_pair_to_i64(const uint32_t *a, const uint32_t *b, int64_t *out, int64_t n_cap,
                            const int64_t *d_n, uint64_t *tile_sums, int64_t *total, hipStream_t s);
+// out[i] = sum_{j<i} a[j] as int64; out[n] and *total = the sum.
+cg_status scan_u32_to_i64(const uint32_t *a, int64_t *out, int64_t n_cap, const int64_t *d_n, uint64_t *tile_sums,
+                          int64_t *total, hipStream_t s);
 // Same for popcounts of `words` words per row (T-sized words).
 cg_status scan_rowpop_to_i64(const void *rows, int word_bits, int words, int64_t *out, int64_t n_cap,
                              const int64_t *d_n, uint64_t *tile_sums, int64_t *total, hipStream_t s);
@@ -499,6 +502,10 @@ size_t allpairs_workspace_bytes(const cg_dict &d, int64_t cap);
 cg_status run_edges_allpairs(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap,
                              int64_t *d_nedges, int64_t *d_offsets, void *ws, size_t ws_bytes,
                              int32_t *d_status, hipStream_t s);
+
+size_t hash_workspace_bytes(const cg_dict &d, int64_t cap);
+cg_status run_edges_hash(const cg_dict &d, uint32_t *uv, uint16_t *bit, int64_t cap, int64_t *d_nedges,
+                         int64_t *d_offsets, void *ws, int32_t *d_status, hipStream_t s);
 
 cg_status batch_layout(int32_t ell_max, cg_layout *lay);
 cg_status run_batch_pack(const uint8_t *bits, const int64_t *bits_off, const int32_t *scene_ell,

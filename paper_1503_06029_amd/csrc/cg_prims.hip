@@ -350,6 +350,11 @@ cg_status scan_pair_to_i64(const uint32_t *a, const uint32_t *b, int64_t *out, i
     return scan_generic(PairSum{a, b}, out, n_cap, d_n, tile_sums, out, total, nullptr, s);
 }
 
+cg_status scan_u32_to_i64(const uint32_t *a, int64_t *out, int64_t n_cap, const int64_t *d_n, uint64_t *tile_sums,
+                          int64_t *total, hipStream_t s) {
+    return scan_generic(U32Arr{a}, out, n_cap, d_n, tile_sums, out, total, nullptr, s);
+}
+
 cg_status scan_rowpop_to_i64(const void *rows, int word_bits, int words, int64_t *out, int64_t n_cap,
                              const int64_t *d_n, uint64_t *tile_sums, int64_t *total, hipStream_t s) {
     if (word_bits == 64)

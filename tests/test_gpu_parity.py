@@ -161,6 +161,7 @@ PARAMS = [
     dict(path=1, n_refs=1),
     dict(path=1, n_refs=4),
     dict(path=1, n_refs=8),
+    dict(path=2),
 ]
 
 
@@ -191,7 +192,7 @@ def test_split_at_full_length(gpu):
 
 # ------------------------------------------------------- capacity overflow
 
-@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("path", [0, 1, 2])
 def test_capacity_overflow(gpu, path):
     torch, B, P = gpu
     say("capacity", path)
@@ -224,7 +225,8 @@ def test_capacity_overflow(gpu, path):
 
 # ----------------------------------------------------- distance-1 queries
 
-@pytest.mark.parametrize("ell,wb", [(3, 32), (33, 32), (64, 64), (150, 64), (150, 32), (1024, 64)])
+@pytest.mark.parametrize("ell,wb", [(3, 32), (33, 32), (64, 64), (150, 64), (150, 32), (1024, 64), (4000, 64),
+                                    (4000, 32)])
 def test_neighbors_d1_parity(gpu, ell, wb):
     torch, B, P = gpu
     say("d1 queries", ell, wb)
@@ -280,6 +282,8 @@ def test_line_arrangement(gpu):
     ref = oracle_graph(R, 32, 32)
     assert_same(P.cell_graph(R, 32, 32), ref)
     assert_same(P.cell_graph(R, 32, 64), oracle_graph(R, 32, 64))
+    for h in (0, 3, 8):
+        assert_same(P.cell_graph(R, 32, 32, params=B.cg_dict_params_default(path=B.CG_PATH_ALLPAIRS, n_refs=h)), ref)
 
 
 @pytest.mark.timeout(600)
@@ -293,6 +297,11 @@ def test_plane_arrangement(gpu):
     res = P.cell_graph(R, 128, 32)
     assert_same(res, ref)
     assert res["nedges"] <= 1_040_512
+    say("plane arrangement: gpu, O(n l) hash path")
+    assert_same(P.cell_graph(R, 128, 32, params=B.cg_dict_params_default(path=B.CG_PATH_HASH)), ref)
+    for h in (0, 4):
+        say("plane arrangement: gpu, (*)-pruned all-pairs, h =", h)
+        assert_same(P.cell_graph(R, 128, 32, params=B.cg_dict_params_default(path=B.CG_PATH_ALLPAIRS, n_refs=h)), ref)
 
 
 def _sha(a):
