@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # table is in profiles/cg_edges_long_vectors_traffic.md.  It describes the
 # kernels as measured: set it to None when the cg_edges kernels change and
 # re-measure.
-EDGES_TRAFFIC_BYTES = 900308003
+EDGES_TRAFFIC_BYTES = 907363488
 
 
 def log(*a):
@@ -622,6 +622,17 @@ def bench_queries(args):
         ev[k + 1].record()
     torch.cuda.synchronize()
     ms = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]))
+    # probe bytes of the timed batch: per query its row, its own bucket's
+    # directory entries and every cell row of that bucket, and the directory
+    # entries of the p flips inside the directory bits; per query out: mask,
+    # id and count
+    pbits = int(svc.dict.params.dir_bits)
+    dir_h = svc.dict_mem[:4 * ((1 << pbits) + 1)].cpu().numpy().view(np.uint32)
+    heads = q[:, 0].cpu().numpy().view(np.uint64)
+    g = (heads >> np.uint64(64 - pbits)).astype(np.int64) if pbits else np.zeros(m, np.int64)
+    bucket = (dir_h[g + 1].astype(np.int64) - dir_h[g].astype(np.int64))
+    probe_bytes = int(m * (8 * W + 8 + 8 * pbits) + 8 * W * bucket.sum())
+    out_bytes = m * (8 * W + 8)
     # check a sample against the oracle
     import oracle
     hs = 2000
@@ -646,7 +657,7 @@ def bench_queries(args):
     t0 = time.perf_counter()
     svc.insert(new)
     ins_s = time.perf_counter() - t0
-    alg = m * (2 * 8 * W + 8)
+    alg = probe_bytes + out_bytes
     out = {
         "metric": "resident-dictionary queries/s (membership + all one-position flips per query)",
         "value": m / (ms / 1e3), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -658,9 +669,11 @@ def bench_queries(args):
         "served": {"requests_per_s": len(arr) / wall, "offered_per_s": rate, "queries_per_request": k_req,
                    "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)},
         "insert_rebuild_s": ins_s, "inserted_rows": int(n // 100), "cells_after_insert": svc.n,
-        "roofline": {"bound": "hbm", "kernel": "k_d1_query", "achieved": alg / (ms / 1e3) / 1e9, "peak": 8000.0,
+        "roofline": {"bound": "hbm", "kernel": "k_d1_bucket", "achieved": alg / (ms / 1e3) / 1e9, "peak": 8000.0,
                      "unit": "GB/s", "frac": alg / (ms / 1e3) / 8e12, "traffic": None, "alg_bytes": alg,
-                     "note": "query rows in + masks, ids and counts out; dictionary probes not counted"},
+                     "mean_bucket_cells": float(bucket.mean()),
+                     "note": "query rows, directory entries (own bucket and the p prefix flips) and every cell "
+                             "row of the query's bucket read; masks, ids and counts written"},
         "cpu_baseline": {"value": hs / cpu_s, "unit": "queries/s", "cores": int(oracle.threads()),
                          "kind": "oracle", "sample": f"{hs} queries by full scan of the cells ({cpu_s:.2f} s)"},
         "correct": bool(ok),

@@ -120,7 +120,8 @@ cg_status cg_dedup(const void *d_packed, int64_t n, cg_layout lay, void *d_cells
  *     bits are >= g, for g = 0 .. 2^p (the top levels of a 2^p-ary tree of
  *     Section 3.2, held as ranges);
  *   - a suffix-grouped order: the cell ids sorted by a 32-bit hash of bits
- *     s .. l-1, so cells that agree on all bits past s sit together.
+ *     s .. l-1, so cells that agree on all bits past s sit together (built
+ *     only for the flip-and-look-up edge path with s > 0, the one reader).
  * A distance-1 pair that differs at bit k >= s shares its first s bits and
  * is adjacent in the sorted order; one that differs at k < s shares bits
  * s .. l-1 and is adjacent in the suffix-grouped order.                     */
@@ -145,6 +146,23 @@ typedef struct cg_dict_params {
 
 /* The automatic parameters (all -1, kind/path 0, n_refs 4). */
 cg_status cg_dict_params_default(cg_dict_params *p);
+
+/* One entry of an autotuner table: the parameters measured fastest for
+ * rows of `words` words and about 2^log2_rows rows. */
+typedef struct cg_tune_entry {
+    int32_t words;
+    int32_t log2_rows;
+    cg_dict_params params;
+} cg_tune_entry;
+
+/* Parameters from an autotuner table (read only; the caller owns it): the
+ * entry with lay.words words whose log2_rows is nearest to log2(ncells_cap)
+ * (ties: the smaller), or the automatic parameters when no entry has these
+ * words.  Every choice gives the same output bytes; the table only decides
+ * speed.  Errors: CG_EINVAL (NULL out, NULL table with n_entries > 0,
+ * n_entries < 0, an entry whose parameters cg_dict_size would reject). */
+cg_status cg_dict_params_tuned(const cg_tune_entry *table, int32_t n_entries, int64_t ncells_cap, cg_layout lay,
+                               cg_dict_params *out);
 
 /* Host-side handle of device pointers.  It BORROWS d_cells, d_ncells and
  * d_mem, which must outlive it; it needs no destroy call.  Fields are

@@ -67,6 +67,7 @@ _sig("cg_dedup_workspace", [c_i64, Layout, ctypes.POINTER(c_sz)])
 _sig("cg_dedup", [c_vp, c_i64, Layout, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
 _sig("cg_dict_params_default", [ctypes.POINTER(DictParams)])
 _sig("cg_dict_size", [c_i64, Layout, ctypes.POINTER(DictParams), ctypes.POINTER(c_sz)])
+_sig("cg_dict_params_tuned", [c_vp, c_i32, c_i64, Layout, ctypes.POINTER(DictParams)])
 _sig("cg_dict_build", [c_vp, c_vp, c_i64, Layout, ctypes.POINTER(DictParams), c_vp, c_sz,
                        ctypes.POINTER(Dict), c_vp])
 _sig("cg_dedup_dict_workspace", [c_i64, Layout, ctypes.POINTER(c_sz)])
@@ -96,7 +97,8 @@ EXPORTS = ("cg_version", "cg_status_string", "cg_last_error", "cg_make_layout", 
            "cg_dict_build", "cg_neighbors_d1", "cg_edges_workspace", "cg_edges_workspace_size", "cg_edges",
            "cg_batch_layout", "cg_batch_pack", "cg_batch_split", "cg_graph_csr_workspace", "cg_graph_csr",
            "cg_bfs_workspace", "cg_bfs", "cg_bfs_path", "cg_sample_pack",
-           "cg_batch_sample_pack", "cg_dedup_dict_workspace", "cg_dedup_dict", "cg_edges_noalloc")
+           "cg_batch_sample_pack", "cg_dedup_dict_workspace", "cg_dedup_dict", "cg_edges_noalloc",
+           "cg_dict_params_tuned")
 
 
 def lib():
@@ -164,6 +166,21 @@ def cg_dict_params_default(**overrides) -> DictParams:
     for k, v in overrides.items():
         setattr(p, k, v)
     return p
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("words", c_i32), ("log2_rows", c_i32), ("params", DictParams)]
+
+
+def cg_dict_params_tuned(entries, ncells_cap: int, lay: Layout) -> DictParams:
+    """entries: [(words, log2_rows, DictParams)]."""
+    arr = (TuneEntry * max(len(entries), 1))()
+    for i, (w, lg, prm) in enumerate(entries):
+        arr[i].words, arr[i].log2_rows, arr[i].params = w, lg, prm
+    out = DictParams()
+    _check(_lib.cg_dict_params_tuned(ctypes.cast(arr, c_vp) if entries else None, len(entries), ncells_cap, lay,
+                                     ctypes.byref(out)))
+    return out
 
 
 def cg_dict_size(ncells_cap: int, lay: Layout, params: DictParams | None = None) -> int:

@@ -148,6 +148,28 @@ static cg_status check_params(const cg_dict_params *p, const cg_layout &lay) {
     return CG_OK;
 }
 
+cg_status cg_dict_params_tuned(const cg_tune_entry *table, int32_t n_entries, int64_t ncells_cap, cg_layout lay,
+                               cg_dict_params *out) {
+    if (!out) return set_error(CG_EINVAL, "cg_dict_params_tuned: out is NULL");
+    if (n_entries < 0 || (n_entries > 0 && !table)) return set_error(CG_EINVAL, "cg_dict_params_tuned: bad table");
+    CG_TRY(check_layout(lay));
+    int lg = 0;
+    while (lg < 62 && (int64_t(2) << lg) <= ncells_cap) ++lg;  // floor(log2(ncells_cap)), 0 for < 2
+    int best = -1, best_d = 0;
+    for (int32_t i = 0; i < n_entries; ++i) {
+        if (table[i].words != lay.words) continue;
+        const int dd = table[i].log2_rows > lg ? table[i].log2_rows - lg : lg - table[i].log2_rows;
+        if (best < 0 || dd < best_d || (dd == best_d && table[i].log2_rows < table[best].log2_rows)) {
+            best = i;
+            best_d = dd;
+        }
+    }
+    if (best < 0) return cg_dict_params_default(out);
+    CG_TRY(check_params(&table[best].params, lay));
+    *out = table[best].params;
+    return CG_OK;
+}
+
 cg_status cg_dict_size(int64_t ncells_cap, cg_layout lay, const cg_dict_params *p, size_t *bytes) {
     CG_TRY(check_layout(lay));
     CG_TRY(check_params(p, lay));

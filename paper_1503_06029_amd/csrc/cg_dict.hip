@@ -397,6 +397,10 @@ __global__ void __launch_bounds__(DT) k_dir_from_keys(const uint64_t *__restrict
     }
 }
 
+// The suffix-grouped order serves only the lookup path's S side (flips at
+// k < s); other paths and s = 0 skip its sort.
+static bool suffix_order_needed(const cg_dict_params &p) { return p.path == CG_PATH_LOOKUP && p.split_bit > 0; }
+
 template <typename T> static cg_status dict_build_impl(cg_dict &d, hipStream_t s) {
     size_t b;
     DictMem m = carve_dict(d.mem, d.ncells_cap, d.params, &b);
@@ -413,7 +417,7 @@ template <typename T> static cg_status dict_build_impl(cg_dict &d, hipStream_t s
     hipLaunchKernelGGL(k_dir_gaps, dim3(256), dim3(256), 0, s, m.dir, m.gaps, m.gap_n, m.gap_cap, m.huge, m.huge_cap);
     CG_LAUNCHED("dict_gaps");
     int which = 0;
-    if (ncap > 0)
+    if (ncap > 0 && suffix_order_needed(d.params))
         CG_TRY(radix_sort_u64(m.sfx, nullptr, ncap, d.d_ncells, 32, 64, m.hist, m.tile_sums, &which, s));
     d.dir = m.dir;
     d.sfx = m.sfx[which];
@@ -438,14 +442,16 @@ cg_status run_dedup_dict(const void *rows, int64_t n, cg_layout lay, void *cells
         return fill_u32(m.dir, 0u, G + 1, s);
     }
     DedupView v{};
-    CG_TRY(run_dedup_fused(rows, n, lay, cells, row_to_cell, d_ncells, ws, d.params.split_bit, m.sfx[0], &v, s));
+    const bool sfx = suffix_order_needed(d.params);
+    CG_TRY(run_dedup_fused(rows, n, lay, cells, row_to_cell, d_ncells, ws, sfx ? d.params.split_bit : -1,
+                           sfx ? m.sfx[0] : nullptr, &v, s));
     hipLaunchKernelGGL(k_dir_from_keys, dim3(blocks_for(n, DT)), dim3(DT), 0, s, v.keys, v.uniq, v.cidx, n, d_ncells,
                        d.params.dir_bits, m.dir, m.gaps, m.gap_n, m.gap_cap, m.huge, m.huge_cap);
     CG_LAUNCHED("dir_from_keys");
     hipLaunchKernelGGL(k_dir_gaps, dim3(256), dim3(256), 0, s, m.dir, m.gaps, m.gap_n, m.gap_cap, m.huge, m.huge_cap);
     CG_LAUNCHED("dict_gaps");
     int which = 0;
-    CG_TRY(radix_sort_u64(m.sfx, nullptr, d.ncells_cap, d_ncells, 32, 64, m.hist, m.tile_sums, &which, s));
+    if (sfx) CG_TRY(radix_sort_u64(m.sfx, nullptr, d.ncells_cap, d_ncells, 32, 64, m.hist, m.tile_sums, &which, s));
     d.sfx = m.sfx[which];
     return CG_OK;
 }

@@ -1,11 +1,14 @@
 """Autotuner for the dictionary / edge parameters of a batch class.
 
-Every parameter choice gives the same output bytes (the split bit s, the
-directory width p and the group limit only decide which cells are found by
-streaming and which by look-up), so the tuner may pick freely by speed.  It
-times each candidate with HIP events on the class's real data, checks that
-the edge count does not change, and keeps the fastest, keyed by (words per
-row, log2 of the row count); the table persists as JSON.
+Every parameter choice gives the same output bytes (the edge path -- flip
+and look-up or the O(n l) hash probes --, the split bit s, the directory
+width p and the group limit only decide how each edge is found), so the
+tuner may pick freely by speed.  It times each candidate with HIP events on
+the class's real data (the whole class run: pack, dedup, dictionary, edges,
+split), checks that the edge count does not change, and keeps the fastest,
+keyed by (words per row, log2 of the row count); the table persists as
+JSON.  Parameters are read back through the library's
+cg_dict_params_tuned, which picks the nearest entry for a size.
 """
 from __future__ import annotations
 
@@ -30,11 +33,17 @@ def candidates(ell: int, n_rows: int, tag_bits: int = 0):
     for s in sorted(v for v in splits if tag_bits < v < ell):
         for gmax in (32, 64):
             out.append(dict(split_bit=s, dir_bits=min(lg, 22, ell), group_max=gmax))
+    # the O(n l) hash probes need no suffix order (split 0)
+    out.append(dict(path=B.CG_PATH_HASH, split_bit=0, dir_bits=min(lg, 22, ell)))
     return out
 
 
+def log2_rows(n_rows: int) -> int:
+    return max(0, int(math.log2(max(n_rows, 1))))
+
+
 def key_of(words: int, n_rows: int) -> str:
-    return f"w{words}_n{max(0, int(math.log2(max(n_rows, 1))))}"
+    return f"w{words}_n{log2_rows(n_rows)}"
 
 
 class Tuner:
@@ -54,9 +63,22 @@ class Tuner:
             json.dump(self.table, f, indent=1, sort_keys=True)
         os.replace(tmp, self.path)
 
+    def entries(self):
+        """The table as (words, log2 rows, DictParams) entries."""
+        out = []
+        for k, e in sorted(self.table.items()):
+            w, n = k[1:].split("_n")
+            out.append((int(w), int(n), B.cg_dict_params_default(**e)))
+        return out
+
     def params_for(self, words: int, n_rows: int) -> B.DictParams | None:
-        e = self.table.get(key_of(words, n_rows))
-        return B.cg_dict_params_default(**e) if e else None
+        """The library's pick from the table for this class (the entry with
+        these words and the nearest size), or None without such an entry."""
+        ents = self.entries()
+        if not any(w == words for w, _, _ in ents):
+            return None
+        lay = B.cg_batch_layout(32 * (words - 1))
+        return B.cg_dict_params_tuned(ents, n_rows, lay)
 
     def tune_class(self, sb, reps: int = 2, tag_bits: int = 32):
         """Time candidate parameters on SceneBatch `sb` (already uploaded).

@@ -93,3 +93,40 @@ def test_product_has_no_cpu_fallback():
         if f.endswith(".py"):
             src = open(os.path.join(pkg, f)).read()
             assert "import oracle" not in src and "from oracle" not in src, f
+
+
+def test_tuned_params_pick_nearest_entry():
+    """cg_dict_params_tuned: the entry with the layout's words and the
+    nearest log2 size (ties to the smaller), defaults without such words."""
+    from paper_1503_06029_amd import binding as B
+    lay = B.cg_batch_layout(224)  # 8 words
+    mk = lambda s: B.cg_dict_params_default(split_bit=s)
+    table = [(8, 10, mk(40)), (8, 14, mk(48)), (8, 20, mk(64)), (16, 14, mk(96))]
+    assert B.cg_dict_params_tuned(table, 1 << 14, lay).split_bit == 48
+    assert B.cg_dict_params_tuned(table, 1 << 12, lay).split_bit == 40   # 12: 2 from 10 and 14 -> the smaller
+    assert B.cg_dict_params_tuned(table, (1 << 18) + 5, lay).split_bit == 64
+    assert B.cg_dict_params_tuned(table, 1, lay).split_bit == 40
+    other = B.cg_batch_layout(480)  # 16 words
+    assert B.cg_dict_params_tuned(table, 1 << 3, other).split_bit == 96
+    d = B.cg_dict_params_tuned(table, 1 << 14, B.cg_batch_layout(32))  # 2 words: none -> defaults
+    assert (d.split_bit, d.dir_bits, d.path) == (-1, -1, 0)
+    assert B.cg_dict_params_tuned([], 100, lay).split_bit == -1
+    with pytest.raises(B.CellGraphError) as e:
+        B.cg_dict_params_tuned([(8, 10, B.cg_dict_params_default(path=7))], 1 << 10, lay)
+    assert e.value.status == B.CG_EINVAL
+
+
+def test_tuner_table_round_trip(tmp_path):
+    """The tuner's JSON table comes back through the library's pick."""
+    from paper_1503_06029_amd import binding as B, tuner
+    p = tmp_path / "t.json"
+    tn = tuner.Tuner(str(p))
+    tn.table[tuner.key_of(4, 5000)] = dict(split_bit=48, dir_bits=12, group_max=32)
+    tn.table[tuner.key_of(4, 300000)] = dict(path=B.CG_PATH_HASH, split_bit=0, dir_bits=18)
+    tn.save()
+    tn2 = tuner.Tuner(str(p))
+    a = tn2.params_for(4, 6000)
+    assert (a.split_bit, a.dir_bits, a.group_max, a.path) == (48, 12, 32, 0)
+    b = tn2.params_for(4, 250000)
+    assert (b.path, b.split_bit) == (B.CG_PATH_HASH, 0)
+    assert tn2.params_for(8, 5000) is None

@@ -38,6 +38,7 @@ def dict_arrays(torch, g):
 
 
 def both(torch, P, rows, ell, wb, params=None, edge_cap=None):
+    from paper_1503_06029_amd import binding as B
     dev = P.to_device_words(rows)
     out = []
     for fused in (False, True):
@@ -51,6 +52,8 @@ def both(torch, P, rows, ell, wb, params=None, edge_cap=None):
         torch.cuda.synchronize()
         res = g.fetch()
         res["dir"], res["sfx"] = dict_arrays(torch, g)
+        if g.dict.params.split_bit <= 0 or g.dict.params.path != B.CG_PATH_LOOKUP:
+            res["sfx"] = np.zeros(0, np.uint64)  # no suffix order is built (no reader needs it)
         out.append(res)
     return out
 
