@@ -148,7 +148,7 @@ def main():
     ap.add_argument("--cpu-dedup-rows", type=int, default=400_000)
     ap.add_argument("--cpu-search-cells", type=int, default=131072)
     ap.add_argument("--no-small-configs", action="store_true")
-    ap.add_argument("--workload", choices=("long", "batched", "served", "search", "sample", "queries", "paths"),
+    ap.add_argument("--workload", choices=("long", "batched", "served", "search", "sample", "queries", "paths", "copy"),
                     default="long",
                     help="long: 1024-bit vectors (the headline); batched: 512 plane scenes in one graph; "
                          "served: Poisson stream of those scenes")
@@ -173,6 +173,8 @@ def main():
         return bench_paths(args)
     if args.workload == "served":
         return bench_served(args)
+    if args.workload == "copy":
+        return bench_copy(args)
 
     import torch
     from paper_1503_06029_amd import binding as B, inputs, pipeline
@@ -274,6 +276,27 @@ def main():
 def scene_pool(k):
     from paper_1503_06029_amd import inputs
     return [inputs.batch_scene(i) for i in range(k)]
+
+
+def bench_copy(args):
+    """A plain 512 MiB device-to-device copy (three of them): the kernel
+    whose FETCH_SIZE / WRITE_SIZE counter readings scale those of the
+    cell-graph kernels to bytes moved, and a measured HBM copy rate."""
+    import torch
+    a = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    print(json.dumps({"metric": "plain device copy (512 MiB read + 512 MiB written)", "value": 2 * (1 << 29) / ms / 1e6,
+                      "unit": "GB/s", "n_gpus": 1, "steps": 3, "warmup": 0, "ms_per_step": ms,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+                      "data": "synthetic", "config": {"workload": "copy of 536870912 bytes"}}), flush=True)
 
 
 def bench_batched(args):
