@@ -154,6 +154,8 @@ def main():
                          "served: Poisson stream of those scenes")
     ap.add_argument("--scenes", type=int, default=512)
     ap.add_argument("--no-tune", action="store_true", help="batched: skip the autotuner")
+    ap.add_argument("--key-bits", type=int, default=None, choices=(0, 32, 64),
+                    help="long: sort-key width of the fused build (default: timed choice among 0, 32, 64)")
     ap.add_argument("--seconds", type=float, default=5.0, help="served: trace length")
     ap.add_argument("--sampled", action="store_true",
                     help="served: scenes as descriptions sampled on the GPU (no sign bytes over PCIe)")
@@ -187,6 +189,27 @@ def main():
     g = pipeline.CellGraph(n, 1024, 64, edge_cap=want_E + 1024, with_bits=True)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+
+    # the sort-key width of the fused build (cg_dict_params.key_bits): every
+    # width gives the same bytes; pick the fastest on this input, as the
+    # autotuner does for batch classes
+    key_ms = {}
+    if args.key_bits is None:
+        for kb in (0, 32, 64):
+            g.params = B.cg_dict_params_default(key_bits=kb)
+            g.dedup_dict(dev_rows)
+            t = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            t[0].record(stream)
+            for j in range(3):
+                g.dedup_dict(dev_rows)
+                t[j + 1].record(stream)
+            torch.cuda.synchronize()
+            key_ms[kb] = min(t[j].elapsed_time(t[j + 1]) for j in range(3))
+        key_bits = min(key_ms, key=key_ms.get)
+        log(f"key width: {key_ms} ms -> {key_bits}")
+    else:
+        key_bits = args.key_bits
+    g.params = B.cg_dict_params_default(key_bits=key_bits)
 
     # a step: the fused dedup + dictionary build (cg_dedup_dict: the same
     # cells and dictionary as cg_dedup then cg_dict_build), then cg_edges
@@ -244,6 +267,8 @@ def main():
             "cells": nc,
             "edges": E,
             "path": "cg_dedup_dict (dedup + dictionary build, fused) then cg_edges",
+            "key_bits": key_bits,
+            "key_bits_ms": {str(k): v for k, v in key_ms.items()},
         },
         "cells_per_s": nc / (ms / 1e3),
         "p50_ms": float(np.percentile(step_ms, 50)),

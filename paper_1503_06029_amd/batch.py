@@ -54,7 +54,7 @@ def class_footprint(rows: int, scenes: int, nbytes: int, words: int, edge_cap: i
     tot += 8 * (scenes + 1) + 8 * scenes * 3 + 4 * scenes + 16 * scenes  # scene tables
     tot += max(nbytes, 16)                                            # sign bytes
     tot += 2 * 4 * m * words + 4 * m                                  # packed rows, cells, row_to_cell
-    tot += B.cg_dedup_workspace(rows, lay) + B.cg_dict_size(rows, lay, params)
+    tot += max(B.cg_dedup_workspace(rows, lay), B.cg_dedup_dict_workspace(rows, lay)) + B.cg_dict_size(rows, lay, params)
     tot += ecap * (8 + 2) + 8 * (m + 1)                               # uv, bit, offsets
     tot += B.cg_edges_workspace_for(rows, lay, params, ecap)
     tot += 16 * (scenes + 1)                                          # cell and edge offsets
@@ -93,7 +93,9 @@ class SceneBatch:
         self.cells = torch.empty((m, words), dtype=torch.int32, device=dev)
         self.r2c = torch.empty(m, dtype=torch.int32, device=dev)
         self.ncells = torch.zeros(1, dtype=torch.int64, device=dev)
-        self.ws_dedup_bytes = B.cg_dedup_workspace(self.cap_rows, self.lay)
+        # the fused build (taken with a chosen key width) needs a little more
+        self.ws_dedup_bytes = max(B.cg_dedup_workspace(self.cap_rows, self.lay),
+                                  B.cg_dedup_dict_workspace(self.cap_rows, self.lay))
         self.ws_dedup = torch.empty(self.ws_dedup_bytes, dtype=torch.uint8, device=dev)
         self.params = params if params is not None else default_params(words)
         self.dict_bytes = B.cg_dict_size(self.cap_rows, self.lay, self.params)
@@ -180,10 +182,16 @@ class SceneBatch:
         self._run_path(stream)
 
     def _run_path(self, stream=None):
-        B.cg_dedup(self.packed, self.n_rows, self.lay, self.cells, self.r2c, self.ncells, self.ws_dedup,
-                   self.ws_dedup_bytes, stream)
-        self.dict = B.cg_dict_build(self.cells, self.ncells, self.n_rows, self.lay, self.params, self.dict_mem,
-                                    self.dict_bytes, stream)
+        if self.params.key_bits:
+            # a chosen sort-key width: the fused dedup + dictionary build
+            self.dict = B.cg_dedup_dict(self.packed, self.n_rows, self.lay, self.cells, self.r2c, self.ncells,
+                                        self.ws_dedup, self.ws_dedup_bytes, self.params, self.dict_mem,
+                                        self.dict_bytes, stream)
+        else:
+            B.cg_dedup(self.packed, self.n_rows, self.lay, self.cells, self.r2c, self.ncells, self.ws_dedup,
+                       self.ws_dedup_bytes, stream)
+            self.dict = B.cg_dict_build(self.cells, self.ncells, self.n_rows, self.lay, self.params, self.dict_mem,
+                                        self.dict_bytes, stream)
         self._edges_ws()  # allocates only when a larger batch needs more
         B.cg_edges(self.dict, self.uv, self.bit, self.edge_cap, self.nedges, self.offsets, self.ws_edges,
                    self.ws_edges_bytes, self.status, stream)

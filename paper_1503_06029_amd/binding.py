@@ -29,7 +29,7 @@ class Layout(ctypes.Structure):
 
 class DictParams(ctypes.Structure):
     _fields_ = [("kind", c_i32), ("dir_bits", c_i32), ("split_bit", c_i32), ("path", c_i32),
-                ("n_refs", c_i32), ("group_max", c_i32), ("reserved", c_i32 * 2)]
+                ("n_refs", c_i32), ("group_max", c_i32), ("key_bits", c_i32), ("reserved", c_i32)]
 
 
 class Dict(ctypes.Structure):

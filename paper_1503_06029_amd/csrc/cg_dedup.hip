@@ -24,6 +24,17 @@ namespace {
 constexpr uint32_t SENT = 0xFFFFFFFFu;
 constexpr int64_t TILE_LDS = 53248;  // three blocks per CU
 constexpr int LMAX = 8192;          // longest segment sorted in one block's LDS (96 KB of it)
+// The sort key lives in two 32-bit planes: hi = the row's first 32 bits,
+// lo = the next 32 (absent when the key is 32 bits wide).  Read as one
+// 64-bit value with the low half zero when lo is absent.
+struct KeyPlanes {
+    const uint32_t *hi;
+    const uint32_t *lo;
+    __device__ __forceinline__ uint64_t operator[](int64_t i) const {
+        return (static_cast<uint64_t>(hi[i]) << 32) | (lo ? lo[i] : 0u);
+    }
+};
+
 // Rows longer than 64 bits are sorted on their first 64 bits, or on their
 // first 32 when a sample shows those already separate the rows (then the
 // four low radix passes are skipped); equal-key segments are finished by
@@ -63,14 +74,27 @@ __global__ void __launch_bounds__(1024) k_key_probe(const T *__restrict__ rows, 
     if (t == 0) counters[2] = ties <= PROBE_TIES ? 1ull : 0ull;
 }
 
+// The dedup's device counters (long-segment list lengths, the key-width
+// flag set to key32) and, for the fused build, the dictionary's gap-list
+// counters, in one launch.
+__global__ void k_dedup_init(unsigned long long *counters, unsigned long long key32, unsigned long long *extra,
+                             int n_extra) {
+    const int t = threadIdx.x;
+    if (t < 4) counters[t] = t == 2 ? key32 : 0ull;
+    if (extra && t < n_extra) extra[t] = 0ull;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_extract(const T *__restrict__ rows, int64_t n, int words,
                                                  const unsigned long long *__restrict__ key32,
-                                                 uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
-    const uint64_t kmask = (key32 && *key32) ? 0xFFFFFFFF00000000ull : ~0ull;
+                                                 uint32_t *__restrict__ khi, uint32_t *__restrict__ klo,
+                                                 uint32_t *__restrict__ vals) {
+    const bool lo = klo && !(key32 && *key32);  // the low plane only for 64-bit keys
     for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
          j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        keys[j] = head64<T>(rows + j * words, words) & kmask;
+        const uint64_t h = head64<T>(rows + j * words, words);
+        khi[j] = static_cast<uint32_t>(h >> 32);
+        if (lo) klo[j] = static_cast<uint32_t>(h);
         vals[j] = static_cast<uint32_t>(j);
     }
 }
@@ -90,8 +114,9 @@ __global__ void __launch_bounds__(256) k_hash_rows(const T *__restrict__ rows, i
 template <typename T>
 __global__ void __launch_bounds__(256) k_extract_hash(const T *__restrict__ rows, int64_t n, int words,
                                                       const unsigned long long *__restrict__ key32,
-                                                      uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                      int hash_s, uint32_t *__restrict__ rhash) {
+                                                      uint32_t *__restrict__ khi, uint32_t *__restrict__ klo,
+                                                      uint32_t *__restrict__ vals, int hash_s,
+                                                      uint32_t *__restrict__ rhash) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *lrows = reinterpret_cast<T *>(smem);
     const int LW = words | 1;
@@ -102,16 +127,18 @@ __global__ void __launch_bounds__(256) k_extract_hash(const T *__restrict__ rows
     __syncthreads();
     const int t = threadIdx.x;
     if (t >= tr) return;
-    const uint64_t kmask = (key32 && *key32) ? 0xFFFFFFFF00000000ull : ~0ull;
+    const bool lo = klo && !(key32 && *key32);
     const T *row = lrows + t * LW;
-    keys[base + t] = head64<T>(row, words) & kmask;
+    const uint64_t h = head64<T>(row, words);
+    khi[base + t] = static_cast<uint32_t>(h >> 32);
+    if (lo) klo[base + t] = static_cast<uint32_t>(h);
     vals[base + t] = static_cast<uint32_t>(base + t);
     rhash[base + t] = suffix_hash32<T>(row, words, hash_s);
 }
 
 // End of the run of keys equal to keys[j] (keys sorted ascending): the first
 // index e > j with keys[e] != keys[j], or n.
-__device__ __forceinline__ int64_t run_end(const uint64_t *keys, int64_t j, int64_t n) {
+__device__ __forceinline__ int64_t run_end(KeyPlanes keys, int64_t j, int64_t n) {
     const uint64_t k = keys[j];
     int64_t good = j, bad = j + 1, step = 1;
     while (bad < n && keys[bad] == k) {
@@ -130,8 +157,7 @@ __device__ __forceinline__ int64_t run_end(const uint64_t *keys, int64_t j, int6
 
 // l <= 64: the key is the whole row, so a row is a new cell iff its key
 // differs from its predecessor's.
-__global__ void __launch_bounds__(256) k_heads(const uint64_t *__restrict__ keys, int64_t n,
-                                               uint8_t *__restrict__ uniq) {
+__global__ void __launch_bounds__(256) k_heads(KeyPlanes keys, int64_t n, uint8_t *__restrict__ uniq) {
     const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (j < n) uniq[j] = ((j == 0) || keys[j] != keys[j - 1]) ? 1 : 0;
 }
@@ -148,12 +174,14 @@ __global__ void __launch_bounds__(256) k_heads(const uint64_t *__restrict__ keys
 constexpr int TT = 256;
 
 template <typename T>
-__global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, const uint64_t *__restrict__ keys,
-                                                    int64_t n, int words, int from64, int smax,
+__global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, const uint32_t *__restrict__ khi,
+                                                    const uint32_t *__restrict__ klo, int64_t n, int words, int from64,
+                                                    int smax,
                                                     uint32_t *__restrict__ vals, uint8_t *__restrict__ uniq,
                                                     uint2 *__restrict__ large_list,
                                                     unsigned long long *__restrict__ counters) {
     const int from = counters[2] ? from64 / 2 : from64;  // words covered by the sort key
+    const KeyPlanes keys{khi, counters[2] ? nullptr : klo};
     extern __shared__ __align__(16) unsigned char smem[];
     const int LW = words + ((words & 1) ? 0 : 1);
     const int slots = TT + smax;
@@ -285,8 +313,9 @@ constexpr int WSMAX = 128;           // longest segment sorted here
 constexpr int WSLOTS = TT + WSMAX;   // window: the tile and the longest segment reaching past it
 
 template <typename T, int WT, int KB, int HB = 8>
-__global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, const uint64_t *__restrict__ keys,
-                                                 int64_t n, int words, uint32_t *__restrict__ vals,
+__global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, const uint32_t *__restrict__ khi,
+                                                 const uint32_t *__restrict__ klo, int64_t n, int words,
+                                                 uint32_t *__restrict__ vals,
                                                  uint8_t *__restrict__ uniq, uint2 *__restrict__ large_list,
                                                  unsigned long long *__restrict__ counters) {
     constexpr int FROM = KB / Bits<T>::B;  // words covered by the sort key
@@ -305,6 +334,7 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
     __shared__ unsigned long long smask[NCH];
     __shared__ int tail_end;                // one past the last row past the tile sorted here
     if ((counters[2] != 0) != (KB == 32)) return;
+    const KeyPlanes keys{khi, KB == 64 ? klo : nullptr};
     const int64_t b0 = static_cast<int64_t>(blockIdx.x) * TT;
     const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
     const int64_t wend = (b0 + WSLOTS < n) ? b0 + WSLOTS : n;
@@ -506,14 +536,17 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
 }
 
 template <typename T, int WT>
-cg_status tiefix_w_launch(const T *rows, const uint64_t *keys, int64_t n, int words, uint32_t *vals, uint8_t *uniq,
-                          uint2 *large_list, unsigned long long *counters, bool probed, hipStream_t s) {
-    hipLaunchKernelGGL((k_tiefix_w<T, WT, 64>), dim3(blocks_for(n, TT)), dim3(TT), 0, s, rows, keys, n, words, vals,
-                       uniq, large_list, counters);
-    CG_LAUNCHED("dedup_tiefix_w");
-    if (probed) {  // the probe may have chosen 32-bit keys
-        hipLaunchKernelGGL((k_tiefix_w<T, WT, 32>), dim3(blocks_for(n, TT)), dim3(TT), 0, s, rows, keys, n, words,
+cg_status tiefix_w_launch(const T *rows, const uint32_t *khi, const uint32_t *klo, int64_t n, int words,
+                          uint32_t *vals, uint8_t *uniq, uint2 *large_list, unsigned long long *counters, bool may64,
+                          bool may32, hipStream_t s) {
+    if (may64) {
+        hipLaunchKernelGGL((k_tiefix_w<T, WT, 64>), dim3(blocks_for(n, TT)), dim3(TT), 0, s, rows, khi, klo, n, words,
                            vals, uniq, large_list, counters);
+        CG_LAUNCHED("dedup_tiefix_w");
+    }
+    if (may32) {  // 32-bit keys chosen by the caller or possibly by the probe
+        hipLaunchKernelGGL((k_tiefix_w<T, WT, 32>), dim3(blocks_for(n, TT)), dim3(TT), 0, s, rows, khi, klo, n,
+                           words, vals, uniq, large_list, counters);
         CG_LAUNCHED("dedup_tiefix_w32");
     }
     return CG_OK;
@@ -743,7 +776,8 @@ __global__ void __launch_bounds__(256) k_gather(const V *__restrict__ rows, int6
 }
 
 struct DedupWs {
-    uint64_t *keys[2];
+    uint32_t *khi[2];
+    uint32_t *klo[2];
     uint32_t *vals[2];
     uint32_t *hist;
     uint64_t *tile_sums;
@@ -759,8 +793,10 @@ DedupWs carve_dedup(void *base, int64_t n, cg_layout lay, size_t *bytes, bool wi
     Carver c(base);
     DedupWs w{};
     const int64_t m = n > 0 ? n : 1;
-    w.keys[0] = c.take<uint64_t>(m);
-    w.keys[1] = c.take<uint64_t>(m);
+    w.khi[0] = c.take<uint32_t>(m);
+    w.khi[1] = c.take<uint32_t>(m);
+    w.klo[0] = c.take<uint32_t>(m);
+    w.klo[1] = c.take<uint32_t>(m);
     w.vals[0] = c.take<uint32_t>(m);
     w.vals[1] = c.take<uint32_t>(m);
     w.hist = c.take<uint32_t>(radix_hist_entries(m));
@@ -785,7 +821,8 @@ DedupWs carve_dedup(void *base, int64_t n, cg_layout lay, size_t *bytes, bool wi
 // new-cell flags and the cell numbering for the directory.
 template <typename T>
 cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t *row_to_cell, int64_t *d_ncells,
-                     void *ws, hipStream_t s, int hash_s = -1, uint64_t *sfx = nullptr, DedupView *view = nullptr) {
+                     void *ws, hipStream_t s, int hash_s = -1, uint64_t *sfx = nullptr, DedupView *view = nullptr,
+                     int key_bits = 0, unsigned long long *extra_zero = nullptr, int n_extra = 0) {
     size_t bytes;
     DedupWs w = carve_dedup(ws, n, lay, &bytes, hash_s >= 0);
     // the gather hashes a row from its pieces when they are a power of two
@@ -799,19 +836,31 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
     if (n == 0) return fill_i64(d_ncells, 0, 1, s);
 
     const bool tiefix = lay.ell > 64;
-    const bool probe = tiefix && n >= PROBE_MIN_N;
-    CG_TRY(fill_i64(reinterpret_cast<int64_t *>(w.counters), 0, 4, s));
+    // key width for l > 64: the caller's 32 or 64, or (0) a sample decides
+    // on the device for long inputs, else 64
+    const bool k32 = tiefix && key_bits == 32;
+    const bool probe = tiefix && key_bits == 0 && n >= PROBE_MIN_N;
+    hipLaunchKernelGGL(k_dedup_init, dim3(1), dim3(64), 0, s, w.counters, k32 ? 1ull : 0ull, extra_zero, n_extra);
+    CG_LAUNCHED("dedup_init");
     if (probe) {
         hipLaunchKernelGGL((k_key_probe<T>), dim3(1), dim3(1024), 0, s, rows, n, words, w.counters);
         CG_LAUNCHED("dedup_key_probe");
     }
+    // key bits that can be nonzero: [64 - sig, 64); the low plane (key bits
+    // 0..31) exists only when they reach below bit 32, and with 32-bit keys
+    // chosen on the device its four passes are skipped there
+    const int sig = tiefix ? (k32 ? 32 : 64) : lay.ell;
+    const int lo = ((64 - sig) / 8) * 8;
+    const bool lo_plane = sig > 32;
+    uint32_t *klo0 = lo_plane ? w.klo[0] : nullptr;
+    const unsigned long long *key32 = probe ? w.counters + 2 : nullptr;
     const size_t xlds = static_cast<size_t>(256) * (words | 1) * sizeof(T);
     if (rhash && xlds <= 65536) {
-        hipLaunchKernelGGL((k_extract_hash<T>), dim3(blocks_for(n, 256)), dim3(256), xlds, s, rows, n, words,
-                           probe ? w.counters + 2 : nullptr, w.keys[0], w.vals[0], hash_s, rhash);
+        hipLaunchKernelGGL((k_extract_hash<T>), dim3(blocks_for(n, 256)), dim3(256), xlds, s, rows, n, words, key32,
+                           w.khi[0], klo0, w.vals[0], hash_s, rhash);
     } else {
-        hipLaunchKernelGGL((k_extract<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words,
-                           probe ? w.counters + 2 : nullptr, w.keys[0], w.vals[0]);
+        hipLaunchKernelGGL((k_extract<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words, key32,
+                           w.khi[0], klo0, w.vals[0]);
         if (rhash) {  // rows too wide to stage: hash them in place
             hipLaunchKernelGGL((k_hash_rows<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words,
                                hash_s, rhash);
@@ -820,20 +869,16 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
     }
     CG_LAUNCHED("dedup_extract");
 
-    // key bits that can be nonzero: [64 - sig, 64); with 32-bit keys the four
-    // passes below bit 32 find every digit zero and are skipped on the device
-    const int sig = tiefix ? 64 : lay.ell;
-    const int lo = ((64 - sig) / 8) * 8;
     int which = 0;
-    CG_TRY(radix_sort_u64(w.keys, w.vals, n, nullptr, lo, 64, w.hist, w.tile_sums, &which, s,
-                          probe ? w.counters + 2 : nullptr, 32));
-    uint64_t *keys = w.keys[which];
+    CG_TRY(radix_sort_k32(w.khi, w.klo, w.vals, n, nullptr, lo, w.hist, &which, s, lo_plane, key32));
+    uint32_t *khi = w.khi[which];
+    uint32_t *klo = lo_plane ? w.klo[which] : nullptr;
     uint32_t *vals = w.vals[which];
 
     const int B = static_cast<int>(sizeof(T) * 8);
     const int from = 64 / B;  // words covered by a 64-bit sort key (the mid pass halves it for 32)
     if (!tiefix) {
-        hipLaunchKernelGGL(k_heads, dim3(blocks_for(n, 256)), dim3(256), 0, s, keys, n, w.uniq);
+        hipLaunchKernelGGL(k_heads, dim3(blocks_for(n, 256)), dim3(256), 0, s, KeyPlanes{khi, klo}, n, w.uniq);
         CG_LAUNCHED("dedup_heads");
     } else {
         const int LW = words + ((words % 2 == 0) ? 1 : 0);
@@ -849,15 +894,15 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
         while (wt < words) wt <<= 1;
         if (wt <= 32) {  // head rows of up to 32 words fit the summary kernel's LDS
             switch (wt) {
-            case 2: CG_TRY((tiefix_w_launch<T, 2>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
-            case 4: CG_TRY((tiefix_w_launch<T, 4>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
-            case 8: CG_TRY((tiefix_w_launch<T, 8>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
-            case 16: CG_TRY((tiefix_w_launch<T, 16>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
-            default: CG_TRY((tiefix_w_launch<T, 32>(rows, keys, n, words, vals, w.uniq, w.large_list, w.counters, probe, s))); break;
+            case 2: CG_TRY((tiefix_w_launch<T, 2>(rows, khi, klo, n, words, vals, w.uniq, w.large_list, w.counters, !k32, probe || k32, s))); break;
+            case 4: CG_TRY((tiefix_w_launch<T, 4>(rows, khi, klo, n, words, vals, w.uniq, w.large_list, w.counters, !k32, probe || k32, s))); break;
+            case 8: CG_TRY((tiefix_w_launch<T, 8>(rows, khi, klo, n, words, vals, w.uniq, w.large_list, w.counters, !k32, probe || k32, s))); break;
+            case 16: CG_TRY((tiefix_w_launch<T, 16>(rows, khi, klo, n, words, vals, w.uniq, w.large_list, w.counters, !k32, probe || k32, s))); break;
+            default: CG_TRY((tiefix_w_launch<T, 32>(rows, khi, klo, n, words, vals, w.uniq, w.large_list, w.counters, !k32, probe || k32, s))); break;
             }
         } else {
-            hipLaunchKernelGGL((k_tiefix_tile<T>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, keys, n, words,
-                               from, static_cast<int>(smax), vals, w.uniq, w.large_list, w.counters);
+            hipLaunchKernelGGL((k_tiefix_tile<T>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, khi, klo, n,
+                               words, from, static_cast<int>(smax), vals, w.uniq, w.large_list, w.counters);
             CG_LAUNCHED("dedup_tiefix_tile");
         }
         constexpr int MID_S = 2048;  // segments up to this many rows: 256-thread blocks, 24 KB of LDS each
@@ -907,7 +952,7 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
     }
     CG_LAUNCHED("dedup_gather");
     if (view) {
-        view->keys = keys;
+        view->khi = khi;
         view->uniq = w.uniq;
         view->cidx = w.cidx;
     }
@@ -929,12 +974,13 @@ size_t dedup_fused_workspace_bytes(int64_t n, cg_layout lay) {
 }
 
 cg_status run_dedup_fused(const void *rows, int64_t n, cg_layout lay, void *cells, uint32_t *row_to_cell,
-                          int64_t *d_ncells, void *ws, int hash_s, uint64_t *sfx, DedupView *view, hipStream_t s) {
+                          int64_t *d_ncells, void *ws, int hash_s, uint64_t *sfx, DedupView *view, int key_bits,
+                          unsigned long long *extra_zero, int n_extra, hipStream_t s) {
     if (lay.word_bits == 64)
         return dedup_impl<uint64_t>(static_cast<const uint64_t *>(rows), n, lay, static_cast<uint64_t *>(cells),
-                                    row_to_cell, d_ncells, ws, s, hash_s, sfx, view);
+                                    row_to_cell, d_ncells, ws, s, hash_s, sfx, view, key_bits, extra_zero, n_extra);
     return dedup_impl<uint32_t>(static_cast<const uint32_t *>(rows), n, lay, static_cast<uint32_t *>(cells),
-                                row_to_cell, d_ncells, ws, s, hash_s, sfx, view);
+                                row_to_cell, d_ncells, ws, s, hash_s, sfx, view, key_bits, extra_zero, n_extra);
 }
 
 cg_status run_dedup(const void *rows, int64_t n, cg_layout lay, void *cells, uint32_t *row_to_cell,

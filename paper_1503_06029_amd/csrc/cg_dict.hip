@@ -352,7 +352,7 @@ size_t dict_mem_bytes(int64_t ncap, cg_layout, const cg_dict_params &p) {
 // the cells.  The previous position holds the previous cell or a copy of it
 // (equal rows have equal keys), and the sort key always keeps the top 32
 // bits, so no cell row is read.
-__global__ void __launch_bounds__(DT) k_dir_from_keys(const uint64_t *__restrict__ keys,
+__global__ void __launch_bounds__(DT) k_dir_from_keys(const uint32_t *__restrict__ keys,
                                                       const uint8_t *__restrict__ uniq,
                                                       const uint32_t *__restrict__ cidx, int64_t n,
                                                       const int64_t *d_ncells, int p, uint32_t *__restrict__ dir,
@@ -363,7 +363,7 @@ __global__ void __launch_bounds__(DT) k_dir_from_keys(const uint64_t *__restrict
     // all loads issued together (in range), used only by positions that start a cell
     const int64_t ii = i < n ? i : n - 1;
     const uint8_t un = uniq[ii];
-    const uint64_t k = keys[ii], kp = keys[ii > 0 ? ii - 1 : 0];
+    const uint32_t k = keys[ii], kp = keys[ii > 0 ? ii - 1 : 0];
     const uint32_t ci = cidx[ii];
     const bool act = i < n && un != 0;
     int64_t gi = 0, gp = 0;
@@ -371,8 +371,8 @@ __global__ void __launch_bounds__(DT) k_dir_from_keys(const uint64_t *__restrict
     bool long_gap = false, huge_gap = false;
     if (act) {
         c = ci;
-        gi = p ? static_cast<int64_t>(k >> (64 - p)) : 0;
-        gp = i == 0 ? -1 : (p ? static_cast<int64_t>(kp >> (64 - p)) : 0);
+        gi = p ? static_cast<int64_t>(k >> (32 - p)) : 0;
+        gp = i == 0 ? -1 : (p ? static_cast<int64_t>(kp >> (32 - p)) : 0);
         long_gap = gi - gp > GAPMIN;
         huge_gap = gi - gp > GAPHUGE;
         if (long_gap) {
@@ -434,7 +434,6 @@ cg_status run_dedup_dict(const void *rows, int64_t n, cg_layout lay, void *cells
     size_t b;
     DictMem m = carve_dict(d.mem, d.ncells_cap, d.params, &b);
     const int64_t G = int64_t(1) << d.params.dir_bits;
-    CG_TRY(fill_i64(reinterpret_cast<int64_t *>(m.gap_n), 0, 2, s));
     d.dir = m.dir;
     d.sfx = m.sfx[0];
     if (n == 0) {
@@ -443,9 +442,10 @@ cg_status run_dedup_dict(const void *rows, int64_t n, cg_layout lay, void *cells
     }
     DedupView v{};
     const bool sfx = suffix_order_needed(d.params);
+    // the dedup's init launch also clears the gap-list counters
     CG_TRY(run_dedup_fused(rows, n, lay, cells, row_to_cell, d_ncells, ws, sfx ? d.params.split_bit : -1,
-                           sfx ? m.sfx[0] : nullptr, &v, s));
-    hipLaunchKernelGGL(k_dir_from_keys, dim3(blocks_for(n, DT)), dim3(DT), 0, s, v.keys, v.uniq, v.cidx, n, d_ncells,
+                           sfx ? m.sfx[0] : nullptr, &v, d.params.key_bits, m.gap_n, 2, s));
+    hipLaunchKernelGGL(k_dir_from_keys, dim3(blocks_for(n, DT)), dim3(DT), 0, s, v.khi, v.uniq, v.cidx, n, d_ncells,
                        d.params.dir_bits, m.dir, m.gaps, m.gap_n, m.gap_cap, m.huge, m.huge_cap);
     CG_LAUNCHED("dir_from_keys");
     hipLaunchKernelGGL(k_dir_gaps, dim3(256), dim3(256), 0, s, m.dir, m.gaps, m.gap_n, m.gap_cap, m.huge, m.huge_cap);

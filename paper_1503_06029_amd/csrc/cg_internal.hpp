@@ -177,6 +177,16 @@ template <> __device__ __forceinline__ uint64_t head64<uint32_t>(const uint32_t 
     return (hi << 32) | lo;
 }
 
+// Tile of block b when a grid's tiles are dealt out per XCD: workgroups go
+// round-robin over the 8 XCDs (b mod 8), so XCD x is given one contiguous run
+// of tiles and neighbouring tiles share that XCD's L2 (their partial lines
+// of output are merged there before they reach HBM).  A bijection of
+// [0, g) for any grid size g.
+__device__ __forceinline__ int xcd_tile(int b, int g) {
+    const int x = b & 7, i = b >> 3, q = g >> 3, r = g & 7;
+    return x * q + (x < r ? x : r) + i;
+}
+
 template <typename T> __device__ __forceinline__ int popc(T x);
 template <> __device__ __forceinline__ int popc<uint32_t>(uint32_t x) { return __popc(x); }
 template <> __device__ __forceinline__ int popc<uint64_t>(uint64_t x) { return __popcll(x); }
@@ -460,6 +470,17 @@ cg_status radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], int64_t n_cap, co
                          int bit_hi, uint32_t *hist, uint64_t *tile_sums, int *which, hipStream_t s,
                          const unsigned long long *skip = nullptr, int skip_below = 0);
 
+// LSD radix sort of a 64-bit key held as two 32-bit planes (khi = key bits
+// 32..63, klo = bits 0..31) with 32-bit values, by key bits [bit_lo, 64), 8
+// bits per pass, stable.  lo_plane: klo is still wanted after the sort (it is
+// carried through the high-plane passes; with key32 set on the device it is
+// dropped).  key32 (device flag, may be null): when nonzero the low-plane
+// passes do nothing (the key is its high plane), an even number of them, so
+// *which stays right.  The sorted planes and values end in [*which].
+cg_status radix_sort_k32(uint32_t *khi[2], uint32_t *klo[2], uint32_t *vals[2], int64_t n_cap, const int64_t *d_n,
+                         int bit_lo, uint32_t *hist, int *which, hipStream_t s, bool lo_plane,
+                         const unsigned long long *key32);
+
 // Fill kernel (graph-capture safe replacement for hipMemsetAsync).
 cg_status fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 cg_status fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
@@ -475,13 +496,14 @@ size_t dedup_workspace_bytes(int64_t n, cg_layout lay);
 // sfx, and in *view the sorted keys, new-cell flags and exclusive cell
 // numbering (device arrays in the workspace, n entries) for the directory.
 struct DedupView {
-    const uint64_t *keys;
+    const uint32_t *khi;  // sorted keys' first 32 bits (the rows' first 32 bits)
     const uint8_t *uniq;
     const uint32_t *cidx;
 };
 size_t dedup_fused_workspace_bytes(int64_t n, cg_layout lay);
 cg_status run_dedup_fused(const void *rows, int64_t n, cg_layout lay, void *cells, uint32_t *row_to_cell,
-                          int64_t *d_ncells, void *ws, int hash_s, uint64_t *sfx, DedupView *view, hipStream_t s);
+                          int64_t *d_ncells, void *ws, int hash_s, uint64_t *sfx, DedupView *view, int key_bits,
+                          unsigned long long *extra_zero, int n_extra, hipStream_t s);
 cg_status run_dedup(const void *rows, int64_t n, cg_layout lay, void *cells, uint32_t *row_to_cell,
                     int64_t *d_ncells, void *ws, size_t ws_bytes, hipStream_t s);
 

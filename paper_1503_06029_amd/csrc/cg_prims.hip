@@ -149,7 +149,8 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint64_t *keys,
     h[t] = 0;
     __syncthreads();
     const int64_t n = load_n(d_n, n_cap);
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * RS_TILE;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t base = static_cast<int64_t>(tile) * RS_TILE;
     if (base < n) {
         // the tile's loads are issued together, then counted
         uint64_t k[RS_ITEMS];
@@ -163,7 +164,7 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_hist(const uint64_t *keys,
             if (base + j * RS_THREADS + t < n) atomicAdd(&h[(k[j] >> shift) & (RADIX - 1)], 1u);
     }
     __syncthreads();
-    hist[static_cast<int64_t>(t) * num_tiles + blockIdx.x] = h[t];
+    hist[static_cast<int64_t>(t) * num_tiles + tile] = h[t];
 }
 
 // Column scan of the digit-major tile histograms hist[d * num_tiles + tile],
@@ -236,7 +237,8 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *ki
     __shared__ uint64_t tmp[4];
 
     const int64_t n = load_n(d_n, n_cap);
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * RS_TILE;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t base = static_cast<int64_t>(tile) * RS_TILE;
     if (base >= n) return;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int tile_n = static_cast<int>(n - base < RS_TILE ? n - base : RS_TILE);
@@ -295,7 +297,7 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *ki
         // first output position of digit t: the totals of the smaller digits
         // plus this digit's count in the tiles before this one
         const uint64_t dbase = block256_excl_scan_u64(dtot[t], tmp, &tot);
-        gbase[t] = static_cast<uint32_t>(dbase) + hist_off[static_cast<int64_t>(t) * num_tiles + blockIdx.x];
+        gbase[t] = static_cast<uint32_t>(dbase) + hist_off[static_cast<int64_t>(t) * num_tiles + tile];
     }
     __syncthreads();
 #pragma unroll
@@ -315,6 +317,134 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix_scatter(const uint64_t *ki
         int64_t g = static_cast<int64_t>(gbase[d]) + (i - static_cast<int>(tile_start[d]));
         kout[g] = k;
         if (HAS_VALS) vout[g] = sv[i];
+    }
+}
+
+// The same passes over 32-bit keys with one or two 32-bit payloads (the
+// dedup's sort key kept as two planes, so a pass over the high plane moves 8
+// bytes per row when the low plane is no longer needed).  A pass returns at
+// once when *skip is set; the second payload moves only when v1in is given
+// and *drop_v1 (if given) is clear.
+__global__ void __launch_bounds__(RS_THREADS) k_radix32_hist(const uint32_t *keys, int64_t n_cap, const int64_t *d_n,
+                                                             int shift, uint32_t *hist, int num_tiles,
+                                                             const unsigned long long *skip) {
+    if (skip && *skip) return;
+    __shared__ uint32_t h[RADIX];
+    const int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const int64_t n = load_n(d_n, n_cap);
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t base = static_cast<int64_t>(tile) * RS_TILE;
+    if (base < n) {
+        uint32_t k[RS_ITEMS];
+#pragma unroll
+        for (int j = 0; j < RS_ITEMS; ++j) {
+            const int64_t i = base + j * RS_THREADS + t;
+            k[j] = i < n ? keys[i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < RS_ITEMS; ++j)
+            if (base + j * RS_THREADS + t < n) atomicAdd(&h[(k[j] >> shift) & (RADIX - 1)], 1u);
+    }
+    __syncthreads();
+    hist[static_cast<int64_t>(t) * num_tiles + tile] = h[t];
+}
+
+__global__ void __launch_bounds__(RS_THREADS) k_radix32_scatter(const uint32_t *kin, const uint32_t *v0in,
+                                                                const uint32_t *v1in, uint32_t *kout, uint32_t *v0out,
+                                                                uint32_t *v1out, int64_t n_cap, const int64_t *d_n,
+                                                                int shift, const uint32_t *hist_off,
+                                                                const uint32_t *dtot, int num_tiles,
+                                                                const unsigned long long *skip,
+                                                                const unsigned long long *drop_v1) {
+    if (skip && *skip) return;
+    __shared__ uint32_t wcnt[RS_WAVES][RADIX];
+    __shared__ uint32_t tile_start[RADIX];
+    __shared__ uint32_t gbase[RADIX];
+    __shared__ uint32_t sk[RS_TILE];
+    __shared__ uint32_t sv0[RS_TILE];
+    __shared__ uint32_t sv1[RS_TILE];
+    __shared__ uint64_t tmp[4];
+
+    const int64_t n = load_n(d_n, n_cap);
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t base = static_cast<int64_t>(tile) * RS_TILE;
+    if (base >= n) return;
+    const bool two = v1in != nullptr && !(drop_v1 && *drop_v1);
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int tile_n = static_cast<int>(n - base < RS_TILE ? n - base : RS_TILE);
+
+    for (int i = t; i < RS_WAVES * RADIX; i += RS_THREADS) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+
+    uint32_t key[RS_ITEMS], v0[RS_ITEMS], v1[RS_ITEMS], rank[RS_ITEMS];
+    const uint64_t lt = lanemask_lt();
+    // wave w owns the contiguous sub-tile [w * 64 * ITEMS, (w + 1) * 64 * ITEMS);
+    // every load is issued before the ranking starts
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int li = (w * RS_ITEMS + j) * 64 + lane;
+        const bool valid = li < tile_n;
+        key[j] = valid ? kin[base + li] : 0u;
+        v0[j] = valid ? v0in[base + li] : 0u;
+        v1[j] = (valid && two) ? v1in[base + li] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int li = (w * RS_ITEMS + j) * 64 + lane;
+        const bool valid = li < tile_n;
+        const int d = static_cast<int>((key[j] >> shift) & (RADIX - 1));
+        uint64_t m = ballot64(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bb = ballot64((d >> b) & 1);
+            m &= ((d >> b) & 1) ? bb : ~bb;
+        }
+        uint32_t before = 0;
+        if (valid) before = wcnt[w][d];
+        __builtin_amdgcn_wave_barrier();
+        if (valid) {
+            rank[j] = before + static_cast<uint32_t>(__popcll(m & lt));
+            if ((m & lt) == 0) wcnt[w][d] = before + static_cast<uint32_t>(__popcll(m));
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+        uint32_t c[RS_WAVES], run = 0;
+#pragma unroll
+        for (int i = 0; i < RS_WAVES; ++i) {
+            c[i] = wcnt[i][t];
+            wcnt[i][t] = run;
+            run += c[i];
+        }
+        uint64_t tot;
+        const uint64_t ex = block256_excl_scan_u64(run, tmp, &tot);
+        tile_start[t] = static_cast<uint32_t>(ex);
+        const uint64_t dbase = block256_excl_scan_u64(dtot[t], tmp, &tot);
+        gbase[t] = static_cast<uint32_t>(dbase) + hist_off[static_cast<int64_t>(t) * num_tiles + tile];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const int li = (w * RS_ITEMS + j) * 64 + lane;
+        if (li < tile_n) {
+            const int d = static_cast<int>((key[j] >> shift) & (RADIX - 1));
+            const uint32_t p = tile_start[d] + wcnt[w][d] + rank[j];
+            sk[p] = key[j];
+            sv0[p] = v0[j];
+            if (two) sv1[p] = v1[j];
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < tile_n; i += RS_THREADS) {
+        const uint32_t k = sk[i];
+        const int d = static_cast<int>((k >> shift) & (RADIX - 1));
+        const int64_t g = static_cast<int64_t>(gbase[d]) + (i - static_cast<int>(tile_start[d]));
+        kout[g] = k;
+        v0out[g] = sv0[i];
+        if (two) v1out[g] = sv1[i];
     }
 }
 
@@ -393,6 +523,37 @@ cg_status radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], int64_t n_cap, co
                                n_cap, d_n, shift, hist, dtot, num_tiles, sk);
         }
         CG_LAUNCHED("radix_scatter");
+        cur ^= 1;
+    }
+    *which = cur;
+    return CG_OK;
+}
+
+cg_status radix_sort_k32(uint32_t *khi[2], uint32_t *klo[2], uint32_t *vals[2], int64_t n_cap, const int64_t *d_n,
+                         int bit_lo, uint32_t *hist, int *which, hipStream_t s, bool lo_plane,
+                         const unsigned long long *key32) {
+    const int num_tiles = static_cast<int>(blocks_for(n_cap, RS_TILE));
+    uint32_t *dtot = hist + static_cast<int64_t>(RADIX) * num_tiles;  // digit totals after the rows
+    int cur = 0;
+    for (int bit = bit_lo; bit < 64; bit += 8) {
+        const bool hi = bit >= 32;
+        // low-plane passes: key klo, payloads vals and khi; skipped when the
+        // device chose 32-bit keys.  High-plane passes: key khi, payloads
+        // vals and (while the low plane is still needed) klo.
+        const unsigned long long *sk = hi ? nullptr : key32;
+        uint32_t *const *kp = hi ? khi : klo;
+        uint32_t *const *pp = hi ? klo : khi;
+        const bool carry = hi ? lo_plane : true;
+        hipLaunchKernelGGL(k_radix32_hist, dim3(num_tiles), dim3(RS_THREADS), 0, s, kp[cur], n_cap, d_n, bit & 31,
+                           hist, num_tiles, sk);
+        CG_LAUNCHED("radix32_hist");
+        hipLaunchKernelGGL(k_radix_dscan, dim3(RADIX), dim3(RS_THREADS), 0, s, hist, num_tiles, dtot, sk);
+        CG_LAUNCHED("radix32_dscan");
+        hipLaunchKernelGGL(k_radix32_scatter, dim3(num_tiles), dim3(RS_THREADS), 0, s, kp[cur], vals[cur],
+                           carry ? pp[cur] : static_cast<uint32_t *>(nullptr), kp[cur ^ 1], vals[cur ^ 1],
+                           carry ? pp[cur ^ 1] : static_cast<uint32_t *>(nullptr), n_cap, d_n, bit & 31, hist, dtot,
+                           num_tiles, sk, hi ? key32 : static_cast<const unsigned long long *>(nullptr));
+        CG_LAUNCHED("radix32_scatter");
         cur ^= 1;
     }
     *which = cur;

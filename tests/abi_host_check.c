@@ -61,8 +61,13 @@ int main(void) {
     p.kind = 9;
     CHECK(cg_dict_size(1000, lay, &p, &bytes) != CG_OK);
     cg_dict_params_default(&p);
-    p.reserved[1] = 3;
+    p.reserved = 3;
     CHECK(cg_dict_size(1000, lay, &p, &bytes) == CG_EINVAL);
+    cg_dict_params_default(&p);
+    p.key_bits = 40;
+    CHECK(cg_dict_size(1000, lay, &p, &bytes) == CG_EINVAL);
+    p.key_bits = 32;
+    CHECK(cg_dict_size(1000, lay, &p, &bytes) == CG_OK);
     cg_dict_params_default(&p);
     CHECK(cg_edges_workspace_size(100000, lay, &p, 1000, &bytes) == CG_OK && bytes > 0);
     CHECK(cg_edges_workspace_size(100000, lay, NULL, -1, &bytes) == CG_EINVAL);

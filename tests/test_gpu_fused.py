@@ -128,3 +128,57 @@ def test_fused_long_vectors_full_size(gpu):
     a, b = both(torch, P, rows, 1024, 64, edge_cap=want_E + 1024)
     assert b["ncells"] == want_cells and b["nedges"] == want_E
     assert_same_build(a, b)
+
+
+def _shared_head(rng, n, ell, head_bits):
+    """n random rows of ell bits whose first head_bits bits are all equal, so
+    32-bit sort keys leave one segment of every row."""
+    R = rng.integers(0, 2, size=(n, ell), dtype=np.uint8)
+    R[:, :head_bits] = rng.integers(0, 2, size=head_bits, dtype=np.uint8)
+    R[n // 2:] = R[:n - n // 2]  # duplicates
+    return R
+
+
+@pytest.mark.parametrize("key_bits", [32, 64])
+def test_fused_key_bits(gpu, key_bits):
+    """A caller-chosen sort-key width changes no byte: clustered sets, rows
+    sharing their first 40 bits (one segment of 3,000 / 20,000 rows under
+    32-bit keys: the LDS and global-memory tie-fixes), batch-tagged rows,
+    against the unfused build (automatic width) and the oracle."""
+    torch, B, P = gpu
+    rng = np.random.default_rng(11 + key_bits)
+    sets = [(inputs.clustered_multiset(rng, 300, 130, 10, 300), 64),
+            (inputs.clustered_multiset(rng, 300, 300, 12, 200), 32),
+            (_shared_head(rng, 3000, 200, 40), 64),
+            (_shared_head(rng, 20000, 96, 40), 32)]
+    for R, wb in sets:
+        rows = oracle.pack(R, wb)
+        ell = R.shape[1]
+        say("key_bits", key_bits, ell, wb, rows.shape)
+        a, b = both(torch, P, rows, ell, wb, params=B.cg_dict_params_default(key_bits=key_bits))
+        assert_same_build(a, b)
+        cells, r2c = oracle.dedup(rows, ell, wb)
+        assert np.array_equal(b["cells"], cells) and np.array_equal(b["row_to_cell"], r2c)
+
+
+@pytest.mark.parametrize("key_bits", [32, 64])
+def test_fused_long_vectors_key_bits(gpu, key_bits):
+    """The long-vector workload with either key width: same bytes as the
+    automatic build (which takes 32 bits here)."""
+    torch, B, P = gpu
+    rows = inputs.long_vectors()
+    want_cells, want_E = inputs.long_vectors_expected()
+    say("long vectors, key_bits", key_bits)
+    dev = P.to_device_words(rows)
+    res = []
+    for kb in (0, key_bits):
+        g = P.CellGraph(rows.shape[0], 1024, 64, B.cg_dict_params_default(key_bits=kb), edge_cap=want_E + 1024)
+        g.dedup_dict(dev)
+        g.edges()
+        torch.cuda.synchronize()
+        r = g.fetch()
+        r["dir"], r["sfx"] = dict_arrays(torch, g)
+        res.append(r)
+        del g
+    assert res[1]["ncells"] == want_cells and res[1]["nedges"] == want_E
+    assert_same_build(res[0], res[1])
