@@ -154,6 +154,7 @@ def main():
                          "served: Poisson stream of those scenes")
     ap.add_argument("--scenes", type=int, default=512)
     ap.add_argument("--no-tune", action="store_true", help="batched: skip the autotuner")
+    ap.add_argument("--no-baseline", action="store_true", help="batched: skip the per-scene launch chains")
     ap.add_argument("--key-bits", type=int, default=None, choices=(0, 32, 64),
                     help="long: sort-key width of the fused build (default: timed choice among 0, 32, 64)")
     ap.add_argument("--seconds", type=float, default=5.0, help="served: trace length")
@@ -359,6 +360,30 @@ def bench_batched(args):
     torch.cuda.synchronize()
     step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
     cells, edges = runner.totals()
+    base_ms, base_edges = None, edges
+    if not args.no_baseline:
+        base_ms, base_edges = per_scene_baseline(scenes)
+    ms = float(step_ms.mean())
+    out = {
+        "metric": "batched scenes: cell-graph edges/s, one captured graph vs per-scene launches",
+        "value": edges / (ms / 1e3), "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(scenes)} scenes, l uniform 16..512 planes in R^3, log-uniform 1e3..2e5 "
+                               f"points ({rows} rows)", "cells": cells, "edges": edges,
+                   "tuned": tuned, "tune_s": round(t_tune, 2)},
+        "rows_per_s": rows / (ms / 1e3),
+        "p50_ms": float(np.percentile(step_ms, 50)), "p99_ms": float(np.percentile(step_ms, 99)),
+        "per_scene_ms": base_ms, "speedup_vs_per_scene": None if base_ms is None else base_ms / ms,
+        "correct": base_edges == edges,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def per_scene_baseline(scenes):
+    """The same scenes as plain per-scene launch chains: (ms, edges)."""
+    import torch
+    from paper_1503_06029_amd import pipeline
     log("per-scene baseline")
     graphs = []
     for R in scenes:
@@ -377,22 +402,7 @@ def bench_batched(args):
         g.run()
     torch.cuda.synchronize()
     base_ms = (time.perf_counter() - t0) * 1e3
-    base_edges = sum(int(g.nedges.item()) for g, _ in graphs)
-    ms = float(step_ms.mean())
-    out = {
-        "metric": "batched scenes: cell-graph edges/s, one captured graph vs per-scene launches",
-        "value": edges / (ms / 1e3), "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": f"{len(scenes)} scenes, l uniform 16..512 planes in R^3, log-uniform 1e3..2e5 "
-                               f"points ({rows} rows)", "cells": cells, "edges": edges,
-                   "tuned": tuned, "tune_s": round(t_tune, 2)},
-        "rows_per_s": rows / (ms / 1e3),
-        "p50_ms": float(np.percentile(step_ms, 50)), "p99_ms": float(np.percentile(step_ms, 99)),
-        "per_scene_ms": base_ms, "speedup_vs_per_scene": base_ms / ms,
-        "correct": base_edges == edges,
-    }
-    print(json.dumps(out), flush=True)
+    return base_ms, sum(int(g.nedges.item()) for g, _ in graphs)
 
 
 def bench_served_sampled(args):

@@ -35,25 +35,30 @@ __device__ __forceinline__ uint32_t nibble_of(uint32_t x) {
 // >= 1 packs columns 32 (w - 1) .. 32 w - 1 of the scene's row, MSB first.
 // The 32 bytes are read as aligned 4-byte words (those lying wholly inside
 // the scene's bytes; the others byte by byte) and aligned with alignbyte.
+// A block takes one contiguous chunk of (row, word) elements: one binary
+// search for the scene of its first row, after which each thread steps its
+// own scene index forward as its rows advance (a chunk spans a few scene
+// boundaries at most), so no load chain precedes each step's work.
 __global__ void __launch_bounds__(256) k_batch_pack(const uint8_t *__restrict__ bits,
                                                     const int64_t *__restrict__ bits_off,
                                                     const int32_t *__restrict__ scene_ell,
                                                     const int64_t *__restrict__ scene_rows, int n_scenes,
-                                                    int64_t n_rows, int words, uint32_t *__restrict__ out) {
+                                                    int64_t n_rows, int words, int64_t chunk,
+                                                    uint32_t *__restrict__ out) {
     __shared__ int s_j0;
     const int64_t total = n_rows * words;
     const bool aligned = (reinterpret_cast<uintptr_t>(bits) & 3) == 0;
-    for (int64_t g0 = static_cast<int64_t>(blockIdx.x) * blockDim.x; g0 < total;
-         g0 += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        // one binary search per block (its first row); each thread walks on from there
-        __syncthreads();
-        if (threadIdx.x == 0) s_j0 = scene_of(scene_rows, n_scenes, g0 / words);
-        __syncthreads();
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * chunk;
+    const int64_t c1 = c0 + chunk < total ? c0 + chunk : total;
+    if (c0 >= total) return;
+    if (threadIdx.x == 0) s_j0 = scene_of(scene_rows, n_scenes, c0 / words);
+    __syncthreads();
+    int j = s_j0;
+    for (int64_t g0 = c0; g0 < c1; g0 += blockDim.x) {
         const int64_t g = g0 + threadIdx.x;
-        if (g >= total) continue;
+        if (g >= c1) break;
         const int64_t r = g / words;
         const int w = static_cast<int>(g - r * words);
-        int j = s_j0;
         while (j + 1 < n_scenes && scene_rows[j + 1] <= r) ++j;
         uint32_t v;
         if (w == 0) {
@@ -166,8 +171,11 @@ cg_status run_batch_pack(const uint8_t *bits, const int64_t *bits_off, const int
         return set_error(CG_EINVAL, "cg_batch_pack: n_scenes=%d out of 0..%d", n_scenes, MAX_SCENES);
     if (n_rows == 0) return CG_OK;
     const int64_t total = n_rows * lay.words;
-    hipLaunchKernelGGL(k_batch_pack, dim3(blocks_for(total, 256, 1 << 20)), dim3(256), 0, s, bits, bits_off,
-                       scene_ell, scene_rows, n_scenes, n_rows, lay.words, static_cast<uint32_t *>(out));
+    // chunks of whole 256-element steps, at most 8,192 blocks
+    const int64_t nb = blocks_for(total, 256, 8192);
+    const int64_t chunk = ((total + nb - 1) / nb + 255) / 256 * 256;
+    hipLaunchKernelGGL(k_batch_pack, dim3(blocks_for(total, chunk)), dim3(256), 0, s, bits, bits_off, scene_ell,
+                       scene_rows, n_scenes, n_rows, lay.words, chunk, static_cast<uint32_t *>(out));
     CG_LAUNCHED("batch_pack");
     return CG_OK;
 }

@@ -474,8 +474,30 @@ __global__ void __launch_bounds__(256) k_big_lookup(const T *__restrict__ cells,
          it += nw) {
         const uint32_t u = list[it];
         const T *q = cells + static_cast<int64_t>(u) * words;
+        // a P-neighbour (k >= s) follows u inside u's prefix group: search
+        // [u + 1, end of the group) only (the end found once per cell by a
+        // galloping search over the first s bits; dir's last entry is the
+        // cell count)
+        int64_t lo_b = 0, hi_b = INT64_MAX;
+        if (!S_SIDE) {
+            const int64_t n = dir[static_cast<int64_t>(1) << p];
+            int64_t good = u, bad = static_cast<int64_t>(u) + 1, step = 1;
+            while (bad < n && same_prefix<T>(cells + bad * words, q, s)) {
+                good = bad;
+                step <<= 1;
+                bad = static_cast<int64_t>(u) + step;
+            }
+            if (bad > n) bad = n;
+            while (bad - good > 1) {
+                const int64_t mid = good + ((bad - good) >> 1);
+                if (same_prefix<T>(cells + mid * words, q, s)) good = mid; else bad = mid;
+            }
+            lo_b = static_cast<int64_t>(u) + 1;
+            hi_b = bad;
+        }
         if (MODE == BIG_S_COUNT || MODE == BIG_P_COUNT) {
-            const uint32_t c = wave_flip_lookups<T>(cells, words, dir, p, q, khi, klo, [](uint32_t, int, uint32_t) {});
+            const uint32_t c = wave_flip_lookups<T>(cells, words, dir, p, q, khi, klo, [](uint32_t, int, uint32_t) {},
+                                                    lo_b, hi_b);
             if (lane == 0) {
                 if (MODE == BIG_S_COUNT) {
                     cntS[u] = c;
@@ -498,7 +520,7 @@ __global__ void __launch_bounds__(256) k_big_lookup(const T *__restrict__ cells,
             }
             wave_flip_lookups<T>(cells, words, dir, p, q, khi, klo, [&](uint32_t v, int k, uint32_t r) {
                 emit(uv, bit, cap, base + r, u, v, k);
-            });
+            }, lo_b, hi_b);
         }
     }
 }

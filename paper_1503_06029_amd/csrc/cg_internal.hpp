@@ -355,31 +355,37 @@ __device__ __forceinline__ int64_t find_row(const T *cells, int words, int64_t l
 }
 
 // find_row for q xor e_k, searching only the directory bucket of the flipped
-// vector's top p bits (dir[g] = first cell whose top p bits are >= g).
+// vector's top p bits (dir[g] = first cell whose top p bits are >= g),
+// narrowed to [lo_b, hi_b) when the caller knows the target lies there.
 template <typename T>
 __device__ __forceinline__ int64_t find_flip_dir(const T *cells, int words, const uint32_t *dir, int p, const T *q,
-                                                 int k) {
+                                                 int k, int64_t lo_b = 0, int64_t hi_b = INT64_MAX) {
     uint64_t h = head64<T>(q, words);
     if (k < 64) h ^= 1ull << (63 - k);
     const int64_t g = p ? static_cast<int64_t>(h >> (64 - p)) : 0;
-    return find_row<T>(cells, words, dir[g], dir[g + 1], q, k);
+    int64_t lo = dir[g], hi = dir[g + 1];
+    if (lo < lo_b) lo = lo_b;
+    if (hi > hi_b) hi = hi_b;
+    return lo < hi ? find_row<T>(cells, words, lo, hi, q, k) : -1;
 }
 
 // Wave-cooperative look-ups of q xor e_k for k = khi, khi - 1, ..., klo
-// where q has a 0 at k (so the target is larger than q): each round the
+// where q has a 0 at k (so the target is larger than q; targets are searched
+// in [lo_b, hi_b) of the sorted cells only): each round the
 // lanes take 64 consecutive k, descending.  f(v, k, rank) runs on the lane
 // that found cell v; rank counts the targets found at larger k (that is,
 // smaller v).  Every lane of the wave calls it with the same q; returns the
 // number found.
 template <typename T, class F>
 __device__ __forceinline__ uint32_t wave_flip_lookups(const T *cells, int words, const uint32_t *dir, int p,
-                                                      const T *q, int khi, int klo, F f) {
+                                                      const T *q, int khi, int klo, F f, int64_t lo_b = 0,
+                                                      int64_t hi_b = INT64_MAX) {
     const int lane = __lane_id();
     uint32_t c = 0;
     for (int k0 = khi; k0 >= klo; k0 -= 64) {
         const int k = k0 - lane;
         int64_t v = -1;
-        if (k >= klo && !get_bit<T>(q, k)) v = find_flip_dir<T>(cells, words, dir, p, q, k);
+        if (k >= klo && !get_bit<T>(q, k)) v = find_flip_dir<T>(cells, words, dir, p, q, k, lo_b, hi_b);
         const uint64_t m = __ballot(v >= 0);
         if (v >= 0) {
             const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));

@@ -140,6 +140,42 @@ def _shared_head(rng, n, ell, head_bits):
 
 
 @pytest.mark.parametrize("key_bits", [32, 64])
+def _grouped_tails(rng, groups, per, ell, head_bits, tail_from):
+    """groups x per rows: all share their first head_bits bits; a group's rows
+    share bits up to tail_from and differ only after it (plus duplicates), so
+    rows tie on every 64-bit value a sort takes before tail_from."""
+    R = rng.integers(0, 2, size=(groups * per, ell), dtype=np.uint8)
+    R[:, :head_bits] = rng.integers(0, 2, size=head_bits, dtype=np.uint8)
+    for g in range(groups):
+        R[g * per:(g + 1) * per, head_bits:tail_from] = rng.integers(0, 2, size=tail_from - head_bits,
+                                                                      dtype=np.uint8)
+    R = np.concatenate([R, R[rng.integers(0, len(R), len(R) // 5)]])  # duplicate rows
+    return R[rng.permutation(len(R))]
+
+
+@pytest.mark.parametrize("key_bits", [0, 32, 64])
+def test_tie_runs_in_long_segments(gpu, key_bits):
+    """Segments of 129..8,192 rows (one block each) whose rows tie on the
+    next 64 bits too: short tie runs (one thread sorts each), long ones (the
+    block sorts them), runs of equal rows; against the oracle."""
+    torch, B, P = gpu
+    rng = np.random.default_rng(71 + key_bits)
+    sets = [(_grouped_tails(rng, 60, 25, 300, 40, 140), 32),    # runs of ~25: thread-sorted
+            (_grouped_tails(rng, 3, 700, 300, 40, 160), 64),    # runs of ~700: block-sorted
+            (_grouped_tails(rng, 1, 3000, 200, 20, 150), 32),   # one segment of 3,000, one run
+            (_grouped_tails(rng, 8, 150, 130, 50, 128), 64)]    # rows differing in the last bits only
+    for R, wb in sets:
+        rows = oracle.pack(R, wb)
+        ell = R.shape[1]
+        say("tie runs", key_bits, ell, wb, rows.shape)
+        a, b = both(torch, P, rows, ell, wb, params=B.cg_dict_params_default(key_bits=key_bits))
+        assert_same_build(a, b)
+        cells, r2c = oracle.dedup(rows, ell, wb)
+        assert np.array_equal(b["cells"], cells) and np.array_equal(b["row_to_cell"], r2c)
+        assert np.array_equal(a["cells"], cells) and np.array_equal(a["row_to_cell"], r2c)
+
+
+@pytest.mark.parametrize("key_bits", [32, 64])
 def test_fused_key_bits(gpu, key_bits):
     """A caller-chosen sort-key width changes no byte: clustered sets, rows
     sharing their first 40 bits (one segment of 3,000 / 20,000 rows under
