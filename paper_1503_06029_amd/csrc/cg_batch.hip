@@ -31,79 +31,141 @@ __device__ __forceinline__ uint32_t nibble_of(uint32_t x) {
     return (y * 0x80402010u) >> 28;  // byte b's flag lands on bit 31 - b, nothing carries into 28..31
 }
 
-// One thread per (virtual row, 32-bit word): word 0 is the scene tag, word w
-// >= 1 packs columns 32 (w - 1) .. 32 w - 1 of the scene's row, MSB first.
-// The 32 bytes are read as aligned 4-byte words (those lying wholly inside
-// the scene's bytes; the others byte by byte) and aligned with alignbyte.
-// A block takes one contiguous chunk of (row, word) elements: one binary
-// search for the scene of its first row, after which each thread steps its
-// own scene index forward as its rows advance (a chunk spans a few scene
-// boundaries at most), so no load chain precedes each step's work.
+// Sign bytes of one 32-byte column group at LDS byte address A (any
+// alignment; lim <= 32 valid bytes) -> the packed word, MSB first.
+__device__ __forceinline__ uint32_t pack32_lds(const uint8_t *lds, int A, int lim) {
+    const int A4 = A & ~3, off = A & 3;
+    uint32_t wd[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) wd[k] = *reinterpret_cast<const uint32_t *>(lds + A4 + 4 * k);
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t x = __builtin_amdgcn_alignbyte(wd[k + 1], wd[k], static_cast<uint32_t>(off));
+        v |= nibble_of(x) << (28 - 4 * k);
+    }
+    return lim < 32 ? v & (~0u << (32 - lim)) : v;
+}
+
+// A block packs PR consecutive virtual rows.  Their scenes' sign bytes are
+// contiguous per scene (row r of scene j at bits_off[j] + r l_j), so the
+// block first copies each scene's share of its rows into LDS with aligned
+// 16-byte loads (only the first and last piece of a share, where it may
+// reach outside the scene's bytes, go byte by byte), then packs: one thread
+// per (row, word), word 0 the scene tag, word w >= 1 columns 32 (w - 1) ..
+// 32 w - 1 read from LDS.  Global reads are whole 16-byte pieces of one
+// contiguous stream; the scene search is done once per block.  A scene with
+// l beyond the layout's RB = 32 (words - 1) bytes (refused by the host
+// check) has only its first RB bytes per row copied, byte by byte.
 __global__ void __launch_bounds__(256) k_batch_pack(const uint8_t *__restrict__ bits,
                                                     const int64_t *__restrict__ bits_off,
                                                     const int32_t *__restrict__ scene_ell,
                                                     const int64_t *__restrict__ scene_rows, int n_scenes,
-                                                    int64_t n_rows, int words, int64_t chunk,
-                                                    uint32_t *__restrict__ out) {
-    __shared__ int s_j0;
-    const int64_t total = n_rows * words;
-    const bool aligned = (reinterpret_cast<uintptr_t>(bits) & 3) == 0;
-    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * chunk;
-    const int64_t c1 = c0 + chunk < total ? c0 + chunk : total;
-    if (c0 >= total) return;
-    if (threadIdx.x == 0) s_j0 = scene_of(scene_rows, n_scenes, c0 / words);
+                                                    int64_t n_rows, int words, int PR, uint32_t *__restrict__ out) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    // per segment (one scene's share of the block's rows): first row, l, LDS
+    // byte offset of its first row, scene; per row: its segment
+    int *seg_row0 = reinterpret_cast<int *>(smem);
+    int *seg_ell = seg_row0 + PR;
+    int *seg_off = seg_ell + PR;
+    int *seg_j = seg_off + PR;
+    uint16_t *row_seg = reinterpret_cast<uint16_t *>(seg_j + PR);
+    uint8_t *lb = reinterpret_cast<uint8_t *>(smem) + ((16 * PR + 2 * PR + 15) & ~15);
+    __shared__ int s_nseg;
+    const int RB = 32 * (words - 1);
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * PR;
+    const int nr = static_cast<int>(n_rows - r0 < PR ? n_rows - r0 : PR);
+    const int t = threadIdx.x;
+    if (t == 0) {
+        int j = scene_of(scene_rows, n_scenes, r0);
+        int ns = 0, off = 0;
+        for (; j < n_scenes && scene_rows[j] < r0 + nr; ++j) {
+            const int64_t a = scene_rows[j] > r0 ? scene_rows[j] : r0;
+            const int64_t b = scene_rows[j + 1] < r0 + nr ? scene_rows[j + 1] : r0 + nr;
+            if (b <= a) continue;  // an empty scene
+            const int ell = scene_ell[j];
+            const int rb = ell < RB ? ell : RB;
+            seg_row0[ns] = static_cast<int>(a - r0);
+            seg_ell[ns] = ell;
+            // keep the global stream's address alignment mod 16 in LDS
+            const int64_t g = bits_off[j] + (a - scene_rows[j]) * ell;
+            seg_off[ns] = off + static_cast<int>(ell <= RB ? ((reinterpret_cast<uintptr_t>(bits) + g) & 15) : 0);
+            seg_j[ns] = j;
+            for (int64_t r = a; r < b; ++r) row_seg[r - r0] = static_cast<uint16_t>(ns);
+            off += ((static_cast<int>(b - a) * rb + 16 + 15) & ~15) + 16;
+            ++ns;
+        }
+        s_nseg = ns;
+    }
     __syncthreads();
-    int j = s_j0;
-    for (int64_t g0 = c0; g0 < c1; g0 += blockDim.x) {
-        const int64_t g = g0 + threadIdx.x;
-        if (g >= c1) break;
-        const int64_t r = g / words;
-        const int w = static_cast<int>(g - r * words);
-        while (j + 1 < n_scenes && scene_rows[j + 1] <= r) ++j;
+    const int nseg = s_nseg;
+    for (int q = 0; q < nseg; ++q) {
+        const int j = seg_j[q], ell = seg_ell[q];
+        const int rs = seg_row0[q];
+        const int re = q + 1 < nseg ? seg_row0[q + 1] : nr;
+        const int64_t s0 = bits_off[j];
+        const int64_t s1 = s0 + (scene_rows[j + 1] - scene_rows[j]) * ell;  // end of the scene's bytes
+        const int64_t g0 = s0 + (r0 + rs - scene_rows[j]) * ell;
+        uint8_t *dst = lb + seg_off[q];
+        if (ell <= RB) {
+            const int64_t nb = static_cast<int64_t>(re - rs) * ell;
+            const int64_t a16 = g0 - static_cast<int64_t>((reinterpret_cast<uintptr_t>(bits) + g0) & 15);
+            const int64_t nchunks = (g0 + nb - a16 + 15) >> 4;
+            uint8_t *d16 = dst - (g0 - a16);  // LDS address of the aligned piece start
+            for (int64_t c = t; c < nchunks; c += blockDim.x) {
+                const int64_t p = a16 + 16 * c;
+                if (p >= s0 && p + 16 <= s1) {
+                    *reinterpret_cast<uint4 *>(d16 + 16 * c) = *reinterpret_cast<const uint4 *>(bits + p);
+                } else {
+                    for (int b = 0; b < 16; ++b)
+                        if (p + b >= g0 && p + b < g0 + nb) d16[16 * c + b] = bits[p + b];
+                }
+            }
+        } else {
+            const int cnt = (re - rs) * RB;
+            for (int e = t; e < cnt; e += blockDim.x) {
+                const int rr = e / RB, col = e - rr * RB;
+                dst[e] = bits[g0 + static_cast<int64_t>(rr) * ell + col];
+            }
+        }
+    }
+    __syncthreads();
+    const int tot = nr * words;
+    for (int e = t; e < tot; e += blockDim.x) {
+        const int rr = e / words, w = e - rr * words;
+        const int q = row_seg[rr];
+        const int j = seg_j[q];
         uint32_t v;
         if (w == 0) {
             v = (static_cast<uint32_t>(j) << 16) | static_cast<uint32_t>(j);
         } else {
-            const int ell = scene_ell[j];
+            const int ell = seg_ell[q];
+            const int rb = ell < RB ? ell : RB;
             const int col0 = (w - 1) * 32;
             v = 0;
-            if (col0 < ell) {
-                const int64_t s0 = bits_off[j];
-                const int64_t s1 = s0 + (scene_rows[j + 1] - scene_rows[j]) * ell;  // end of the scene's bytes
-                const int64_t A = s0 + (r - scene_rows[j]) * ell + col0;
-                const int lim = ell - col0 < 32 ? ell - col0 : 32;
-                if (aligned) {
-                    const int64_t A4 = A & ~int64_t(3);
-                    const int off = static_cast<int>(A - A4);
-                    uint32_t wd[9];
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) {
-                        const int64_t p = A4 + 4 * k;
-                        if (p >= A + lim) {
-                            wd[k] = 0;
-                        } else if (p >= s0 && p + 4 <= s1) {
-                            wd[k] = *reinterpret_cast<const uint32_t *>(bits + p);
-                        } else {
-                            uint32_t x = 0;
-                            for (int b = 0; b < 4; ++b)
-                                if (p + b >= s0 && p + b < s1) x |= static_cast<uint32_t>(bits[p + b]) << (8 * b);
-                            wd[k] = x;
-                        }
-                    }
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const uint32_t x = __builtin_amdgcn_alignbyte(wd[k + 1], wd[k], static_cast<uint32_t>(off));
-                        v |= nibble_of(x) << (28 - 4 * k);
-                    }
-                    if (lim < 32) v &= ~0u << (32 - lim);
-                } else {
-                    const uint8_t *src = bits + A;
-                    for (int c = 0; c < lim; ++c) v |= static_cast<uint32_t>(src[c] != 0) << (31 - c);
-                }
+            if (col0 < rb) {
+                const int lim = rb - col0 < 32 ? rb - col0 : 32;
+                v = pack32_lds(lb, seg_off[q] + (rr - seg_row0[q]) * rb + col0, lim);
             }
         }
-        out[g] = v;
+        out[(r0 + rr) * words + w] = v;
     }
+}
+
+// Rows per block of the batch pack and its LDS bytes: about 32 KB of sign
+// bytes per block.
+static int batch_pack_rows(int words) {
+    const int RB = 32 * (words - 1);
+    int pr = 32768 / (RB > 0 ? RB : 32);
+    if (pr > 256) pr = 256;
+    if (pr < 16) pr = 16;
+    return pr;
+}
+static size_t batch_pack_lds(int words, int pr) {
+    const size_t RB = 32 * static_cast<size_t>(words - 1);
+    // per-segment tables, then per segment its rows, alignment slack, 16
+    // bytes of padding read past its end (at most pr segments)
+    return ((16 * static_cast<size_t>(pr) + 2 * pr + 15) & ~size_t(15)) + pr * RB + pr * 48 + 64;
 }
 
 // cell_off[j] = first cell whose tag word is >= tag(j); edge_off[j] = its
@@ -170,12 +232,11 @@ cg_status run_batch_pack(const uint8_t *bits, const int64_t *bits_off, const int
     if (n_scenes < 0 || n_scenes > MAX_SCENES)
         return set_error(CG_EINVAL, "cg_batch_pack: n_scenes=%d out of 0..%d", n_scenes, MAX_SCENES);
     if (n_rows == 0) return CG_OK;
-    const int64_t total = n_rows * lay.words;
-    // chunks of whole 256-element steps, at most 8,192 blocks
-    const int64_t nb = blocks_for(total, 256, 8192);
-    const int64_t chunk = ((total + nb - 1) / nb + 255) / 256 * 256;
-    hipLaunchKernelGGL(k_batch_pack, dim3(blocks_for(total, chunk)), dim3(256), 0, s, bits, bits_off, scene_ell,
-                       scene_rows, n_scenes, n_rows, lay.words, chunk, static_cast<uint32_t *>(out));
+    const int pr = batch_pack_rows(lay.words);
+    const size_t lds = batch_pack_lds(lay.words, pr);
+    CG_TRY(allow_lds(reinterpret_cast<const void *>(&k_batch_pack), lds));
+    hipLaunchKernelGGL(k_batch_pack, dim3(blocks_for(n_rows, pr)), dim3(256), lds, s, bits, bits_off, scene_ell,
+                       scene_rows, n_scenes, n_rows, lay.words, pr, static_cast<uint32_t *>(out));
     CG_LAUNCHED("batch_pack");
     return CG_OK;
 }

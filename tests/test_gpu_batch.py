@@ -136,3 +136,45 @@ def test_directory_over_sparse_tags(gpu):
     B.cg_neighbors_d1(sb.dict, q, nc, None, self_id, None)
     torch.cuda.synchronize()
     assert np.array_equal(self_id.cpu().numpy(), np.arange(nc, dtype=np.int32))
+
+
+@pytest.mark.parametrize("shift", [0, 1, 6, 13])
+def test_batch_pack_layouts(gpu, shift):
+    """cg_batch_pack against the oracle's packing, word for word: the sign
+    bytes' base address is `shift` bytes past an aligned one, scenes are
+    laid out with gaps between them, and many are tiny or empty (several
+    scenes share one block of rows), for every class width."""
+    torch, B, batch = gpu
+    rng = np.random.default_rng(40 + shift)
+    for ell_max in (30, 96, 480, 992):
+        ells = [int(rng.integers(1, ell_max + 1)) for _ in range(60)]
+        ns = [int(rng.choice([0, 1, 2, 3, 50, 700])) for _ in range(60)]
+        ells[0], ns[0] = ell_max, 300
+        scenes = [(rng.random((n, l)) < 0.5).astype(np.uint8) for n, l in zip(ns, ells)]
+        lay = B.cg_batch_layout(ell_max)
+        W = lay.words
+        offs, pos = [], 0
+        for R in scenes:
+            offs.append(pos)
+            pos += R.size + int(rng.integers(0, 40))  # gaps between scenes
+        host = rng.integers(0, 256, size=shift + pos + 64, dtype=np.uint8)  # garbage around the scenes
+        for o, R in zip(offs, scenes):
+            host[shift + o:shift + o + R.size] = R.reshape(-1) * rng.integers(1, 256, size=R.size, dtype=np.uint8)
+        rows = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+        n_rows = int(rows[-1])
+        bits = torch.from_numpy(host).cuda()
+        packed = torch.empty((max(n_rows, 1), W), dtype=torch.int32, device="cuda")
+        say("batch pack", shift, ell_max, W, n_rows)
+        B.cg_batch_pack(bits.data_ptr() + shift, torch.tensor(offs, dtype=torch.int64).cuda(),
+                        torch.tensor(ells, dtype=torch.int32).cuda(), torch.from_numpy(rows).cuda(), len(scenes),
+                        n_rows, lay, packed)
+        torch.cuda.synchronize()
+        got = packed[:n_rows].cpu().numpy().view(np.uint32)
+        want = np.zeros((n_rows, W), np.uint32)
+        for j, R in enumerate(scenes):
+            if R.shape[0] == 0:
+                continue
+            want[rows[j]:rows[j + 1], 0] = (j << 16) | j
+            p = oracle.pack(R, 32)
+            want[rows[j]:rows[j + 1], 1:1 + p.shape[1]] = p
+        assert np.array_equal(got, want), (shift, ell_max)
