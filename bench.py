@@ -155,8 +155,8 @@ def main():
     ap.add_argument("--scenes", type=int, default=512)
     ap.add_argument("--no-tune", action="store_true", help="batched: skip the autotuner")
     ap.add_argument("--no-baseline", action="store_true", help="batched: skip the per-scene launch chains")
-    ap.add_argument("--key-bits", type=int, default=None, choices=(0, 32, 64),
-                    help="long: sort-key width of the fused build (default: timed choice among 0, 32, 64)")
+    ap.add_argument("--key-bits", type=int, default=None, choices=(0, 32, 64, 96),
+                    help="long: sort-key width of the fused build (default: timed choice among 0, 32, 64, 96)")
     ap.add_argument("--seconds", type=float, default=5.0, help="served: trace length")
     ap.add_argument("--sampled", action="store_true",
                     help="served: scenes as descriptions sampled on the GPU (no sign bytes over PCIe)")
@@ -196,7 +196,7 @@ def main():
     # autotuner does for batch classes
     key_ms = {}
     if args.key_bits is None:
-        for kb in (0, 32, 64):
+        for kb in (0, 32, 64, 96):
             g.params = B.cg_dict_params_default(key_bits=kb)
             g.dedup_dict(dev_rows)
             t = [torch.cuda.Event(enable_timing=True) for _ in range(4)]

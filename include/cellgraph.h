@@ -141,11 +141,12 @@ typedef struct cg_dict_params {
     int32_t n_refs;     /* h, 0..8: reference vectors of the all-pairs path       */
     int32_t group_max;  /* groups larger than this are searched, not scanned;
                            1..1024, -1 = automatic                                */
-    int32_t key_bits;   /* sort-key width of cg_dedup_dict when l > 64: 32 or 64
-                           bits of each row; 0 = automatic (for 2^20 rows or
-                           more a sample of rows decides on the device, else
-                           64).  Rows sharing the key are ordered by full-row
-                           comparison either way, so only speed changes     */
+    int32_t key_bits;   /* sort-key width of cg_dedup_dict when l > 64: 32, 64 or
+                           96 bits of each row; 0 = automatic (for 2^20 rows
+                           or more a sample of rows decides between 32 and 64
+                           on the device, else 64).  Rows sharing the key are
+                           ordered by full-row comparison either way, so only
+                           speed changes                                    */
     int32_t reserved;   /* must be 0                                              */
 } cg_dict_params;
 

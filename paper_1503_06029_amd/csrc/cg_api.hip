@@ -144,8 +144,8 @@ static cg_status check_params(const cg_dict_params *p, const cg_layout &lay) {
     if (p->n_refs < 0 || p->n_refs > 8) return set_error(CG_EINVAL, "n_refs=%d out of range 0..8", p->n_refs);
     if (p->group_max != -1 && (p->group_max < 1 || p->group_max > 1024))
         return set_error(CG_EINVAL, "group_max=%d out of range 1..1024", p->group_max);
-    if (p->key_bits != 0 && p->key_bits != 32 && p->key_bits != 64)
-        return set_error(CG_EINVAL, "key_bits=%d: 0, 32 or 64", p->key_bits);
+    if (p->key_bits != 0 && p->key_bits != 32 && p->key_bits != 64 && p->key_bits != 96)
+        return set_error(CG_EINVAL, "key_bits=%d: 0, 32, 64 or 96", p->key_bits);
     if (p->reserved) return set_error(CG_EINVAL, "reserved field must be 0");
     return CG_OK;
 }

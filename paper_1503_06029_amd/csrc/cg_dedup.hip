@@ -24,16 +24,43 @@ namespace {
 constexpr uint32_t SENT = 0xFFFFFFFFu;
 constexpr int64_t TILE_LDS = 53248;  // three blocks per CU
 constexpr int LMAX = 8192;          // longest segment sorted in one block's LDS (96 KB of it)
-// The sort key lives in two 32-bit planes: hi = the row's first 32 bits,
-// lo = the next 32 (absent when the key is 32 bits wide).  Read as one
-// 64-bit value with the low half zero when lo is absent.
+// The sort key lives in up to three 32-bit planes: p0 = the row's first 32
+// bits, p1 = the next 32, p2 = the 32 after those (absent planes are not
+// part of the key).  Read as (first 64 bits, next 32) with absent planes 0.
+struct Key96 {
+    uint64_t a;
+    uint32_t b;
+    __device__ __forceinline__ bool operator==(const Key96 &o) const { return a == o.a && b == o.b; }
+    __device__ __forceinline__ bool operator!=(const Key96 &o) const { return !(*this == o); }
+};
 struct KeyPlanes {
-    const uint32_t *hi;
-    const uint32_t *lo;
-    __device__ __forceinline__ uint64_t operator[](int64_t i) const {
-        return (static_cast<uint64_t>(hi[i]) << 32) | (lo ? lo[i] : 0u);
+    const uint32_t *p0;
+    const uint32_t *p1;
+    const uint32_t *p2;
+    __device__ __forceinline__ Key96 operator[](int64_t i) const {
+        return Key96{(static_cast<uint64_t>(p0[i]) << 32) | (p1 ? p1[i] : 0u), p2 ? p2[i] : 0u};
+    }
+    // the planes of a key of kbits bits
+    __device__ __forceinline__ KeyPlanes width(int kbits) const {
+        return KeyPlanes{p0, kbits > 32 ? p1 : nullptr, kbits > 64 ? p2 : nullptr};
     }
 };
+
+// Key width chosen for this call: 96 when the caller asked for it
+// (counters[3]), else 32 when chosen by the caller or the sample
+// (counters[2]), else 64.
+__device__ __forceinline__ int key_width(const unsigned long long *counters) {
+    return counters[3] ? 96 : (counters[2] ? 32 : 64);
+}
+
+// Bits 64 .. 95 of a row (0 past its end).
+template <typename T> __device__ __forceinline__ uint32_t head_third(const T *row, int words);
+template <> __device__ __forceinline__ uint32_t head_third<uint64_t>(const uint64_t *row, int words) {
+    return words > 1 ? static_cast<uint32_t>(row[1] >> 32) : 0u;
+}
+template <> __device__ __forceinline__ uint32_t head_third<uint32_t>(const uint32_t *row, int words) {
+    return words > 2 ? row[2] : 0u;
+}
 
 // Rows longer than 64 bits are sorted on their first 64 bits, or on their
 // first 32 when a sample shows those already separate the rows (then the
@@ -74,27 +101,29 @@ __global__ void __launch_bounds__(1024) k_key_probe(const T *__restrict__ rows, 
     if (t == 0) counters[2] = ties <= PROBE_TIES ? 1ull : 0ull;
 }
 
-// The dedup's device counters (long-segment list lengths, the key-width
-// flag set to key32) and, for the fused build, the dictionary's gap-list
-// counters, in one launch.
-__global__ void k_dedup_init(unsigned long long *counters, unsigned long long key32, unsigned long long *extra,
-                             int n_extra) {
+// The dedup's device counters (long-segment list length, the key-width
+// flags: [2] 32-bit keys, [3] 96-bit keys) and, for the fused build, the
+// dictionary's gap-list counters, in one launch.
+__global__ void k_dedup_init(unsigned long long *counters, unsigned long long key32, unsigned long long key96,
+                             unsigned long long *extra, int n_extra) {
     const int t = threadIdx.x;
-    if (t < 4) counters[t] = t == 2 ? key32 : 0ull;
+    if (t < 4) counters[t] = t == 2 ? key32 : (t == 3 ? key96 : 0ull);
     if (extra && t < n_extra) extra[t] = 0ull;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_extract(const T *__restrict__ rows, int64_t n, int words,
-                                                 const unsigned long long *__restrict__ key32,
-                                                 uint32_t *__restrict__ khi, uint32_t *__restrict__ klo,
+                                                 const unsigned long long *__restrict__ key32, uint32_t *__restrict__ k0,
+                                                 uint32_t *__restrict__ k1, uint32_t *__restrict__ k2,
                                                  uint32_t *__restrict__ vals) {
-    const bool lo = klo && !(key32 && *key32);  // the low plane only for 64-bit keys
+    const bool has1 = k1 && !(key32 && *key32);  // the second plane unless the sample chose 32 bits
     for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
          j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const uint64_t h = head64<T>(rows + j * words, words);
-        khi[j] = static_cast<uint32_t>(h >> 32);
-        if (lo) klo[j] = static_cast<uint32_t>(h);
+        const T *row = rows + j * words;
+        const uint64_t h = head64<T>(row, words);
+        k0[j] = static_cast<uint32_t>(h >> 32);
+        if (has1) k1[j] = static_cast<uint32_t>(h);
+        if (k2) k2[j] = head_third<T>(row, words);
         vals[j] = static_cast<uint32_t>(j);
     }
 }
@@ -114,9 +143,9 @@ __global__ void __launch_bounds__(256) k_hash_rows(const T *__restrict__ rows, i
 template <typename T>
 __global__ void __launch_bounds__(256) k_extract_hash(const T *__restrict__ rows, int64_t n, int words,
                                                       const unsigned long long *__restrict__ key32,
-                                                      uint32_t *__restrict__ khi, uint32_t *__restrict__ klo,
-                                                      uint32_t *__restrict__ vals, int hash_s,
-                                                      uint32_t *__restrict__ rhash) {
+                                                      uint32_t *__restrict__ k0, uint32_t *__restrict__ k1,
+                                                      uint32_t *__restrict__ k2, uint32_t *__restrict__ vals,
+                                                      int hash_s, uint32_t *__restrict__ rhash) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *lrows = reinterpret_cast<T *>(smem);
     const int LW = words | 1;
@@ -127,11 +156,12 @@ __global__ void __launch_bounds__(256) k_extract_hash(const T *__restrict__ rows
     __syncthreads();
     const int t = threadIdx.x;
     if (t >= tr) return;
-    const bool lo = klo && !(key32 && *key32);
+    const bool has1 = k1 && !(key32 && *key32);
     const T *row = lrows + t * LW;
     const uint64_t h = head64<T>(row, words);
-    khi[base + t] = static_cast<uint32_t>(h >> 32);
-    if (lo) klo[base + t] = static_cast<uint32_t>(h);
+    k0[base + t] = static_cast<uint32_t>(h >> 32);
+    if (has1) k1[base + t] = static_cast<uint32_t>(h);
+    if (k2) k2[base + t] = head_third<T>(row, words);
     vals[base + t] = static_cast<uint32_t>(base + t);
     rhash[base + t] = suffix_hash32<T>(row, words, hash_s);
 }
@@ -139,7 +169,7 @@ __global__ void __launch_bounds__(256) k_extract_hash(const T *__restrict__ rows
 // End of the run of keys equal to keys[j] (keys sorted ascending): the first
 // index e > j with keys[e] != keys[j], or n.
 __device__ __forceinline__ int64_t run_end(KeyPlanes keys, int64_t j, int64_t n) {
-    const uint64_t k = keys[j];
+    const Key96 k = keys[j];
     int64_t good = j, bad = j + 1, step = 1;
     while (bad < n && keys[bad] == k) {
         good = bad;
@@ -174,20 +204,21 @@ __global__ void __launch_bounds__(256) k_heads(KeyPlanes keys, int64_t n, uint8_
 constexpr int TT = 256;
 
 template <typename T>
-__global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, const uint32_t *__restrict__ khi,
-                                                    const uint32_t *__restrict__ klo, int64_t n, int words, int from64,
-                                                    int smax,
+__global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, KeyPlanes planes, int64_t n,
+                                                    int words, int smax,
                                                     uint32_t *__restrict__ vals, uint8_t *__restrict__ uniq,
                                                     uint2 *__restrict__ large_list,
                                                     unsigned long long *__restrict__ counters) {
-    const int from = counters[2] ? from64 / 2 : from64;  // words covered by the sort key
-    const KeyPlanes keys{khi, counters[2] ? nullptr : klo};
+    const int kbits = key_width(counters);
+    const int from = kbits / Bits<T>::B;  // whole words covered by the sort key
+    const KeyPlanes keys = planes.width(kbits);
     extern __shared__ __align__(16) unsigned char smem[];
     const int LW = words + ((words & 1) ? 0 : 1);
     const int slots = TT + smax;
     // keys of positions b0 - 1 .. b0 + slots - 1 (index = position - b0 + 1)
     uint64_t *skeys = reinterpret_cast<uint64_t *>(smem);
-    T *lrows = reinterpret_cast<T *>(skeys + slots + 1);
+    uint32_t *skx = reinterpret_cast<uint32_t *>(skeys + slots + 1);  // third planes
+    T *lrows = reinterpret_cast<T *>(skx + ((slots + 2) & ~1));
     // with smax == 1 no segment is small and the row area is not allocated
     int32_t *segof = reinterpret_cast<int32_t *>(lrows + (smax > 1 ? static_cast<size_t>(slots) * LW : 0));
     int32_t *seglen = segof + slots;
@@ -196,15 +227,18 @@ __global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, 
     const int t = threadIdx.x;
     const int64_t wend = (b0 + slots < n) ? b0 + slots : n;  // window end (exclusive)
     for (int e0 = t; e0 <= slots; e0 += TT * 4) {
-        uint64_t v[4];
+        Key96 v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t pos = b0 - 1 + e0 + u * TT;
-            v[u] = (e0 + u * TT <= slots && pos >= 0 && pos < wend) ? keys[pos] : 0;
+            v[u] = (e0 + u * TT <= slots && pos >= 0 && pos < wend) ? keys[pos] : Key96{0, 0};
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (e0 + u * TT <= slots) skeys[e0 + u * TT] = v[u];
+            if (e0 + u * TT <= slots) {
+                skeys[e0 + u * TT] = v[u].a;
+                skx[e0 + u * TT] = v[u].b;
+            }
     }
     for (int r = t; r < slots; r += TT) segof[r] = -1;
     __syncthreads();
@@ -213,10 +247,11 @@ __global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, 
     uint2 seg = make_uint2(0u, 0u);
     if (p < n) {
         const uint64_t k = skeys[t + 1];
-        const bool head = (p == 0) || k != skeys[t];
+        const uint32_t kx = skx[t + 1];
+        const bool head = (p == 0) || k != skeys[t] || kx != skx[t];
         if (head) {
             int64_t e = p + 1;
-            while (e < wend && skeys[e - b0 + 1] == k) ++e;
+            while (e < wend && skeys[e - b0 + 1] == k && skx[e - b0 + 1] == kx) ++e;
             if (e == wend && e < n) e = run_end(keys, p, n);  // reaches past the window: long segment
             const int64_t len = e - p;
             if (len == 1) {
@@ -313,8 +348,7 @@ constexpr int WSMAX = 128;           // longest segment sorted here
 constexpr int WSLOTS = TT + WSMAX;   // window: the tile and the longest segment reaching past it
 
 template <typename T, int WT, int KB, int HB = 8>
-__global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, const uint32_t *__restrict__ khi,
-                                                 const uint32_t *__restrict__ klo, int64_t n, int words,
+__global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, KeyPlanes planes, int64_t n, int words,
                                                  uint32_t *__restrict__ vals,
                                                  uint8_t *__restrict__ uniq, uint2 *__restrict__ large_list,
                                                  unsigned long long *__restrict__ counters) {
@@ -323,6 +357,7 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
     constexpr uint32_t GMASK = (WT >= 32) ? 0xFFFFFFFFu : ((1u << WT) - 1u);
     constexpr int RPS = TT / WT;           // rows per TT consecutive elements
     __shared__ uint64_t skeys[WSLOTS + 1];  // positions b0 - 1 .. b0 + WSLOTS - 1
+    __shared__ uint32_t skx[WSLOTS + 1];    // their third planes (96-bit keys)
     __shared__ uint32_t sval[WSLOTS];
     __shared__ int16_t segof[WSLOTS];       // slot of the row's head, -1 if not sorted here
     __shared__ int16_t seglen[WSLOTS];
@@ -333,8 +368,8 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
     __shared__ T sv[LV * WSLOTS];           // per row and level: the row's word there
     __shared__ unsigned long long smask[NCH];
     __shared__ int tail_end;                // one past the last row past the tile sorted here
-    if ((counters[2] != 0) != (KB == 32)) return;
-    const KeyPlanes keys{khi, KB == 64 ? klo : nullptr};
+    if (key_width(counters) != KB) return;
+    const KeyPlanes keys = planes.width(KB);
     const int64_t b0 = static_cast<int64_t>(blockIdx.x) * TT;
     const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
     const int64_t wend = (b0 + WSLOTS < n) ? b0 + WSLOTS : n;
@@ -342,19 +377,22 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
     if (t == 0) tail_end = TT;
     // keys of the window and the row indices of its positions, loaded together
     for (int e0 = t; e0 <= WSLOTS; e0 += TT * 4) {
-        uint64_t v[4];
+        Key96 v[4];
         uint32_t x[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t pos = b0 - 1 + e0 + u * TT;
             const bool in = e0 + u * TT <= WSLOTS && pos >= 0 && pos < wend;
-            v[u] = in ? keys[pos] : 0;
+            v[u] = in ? keys[pos] : Key96{0, 0};
             x[u] = (in && pos >= b0) ? vals[pos] : 0u;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = e0 + u * TT;
-            if (e <= WSLOTS) skeys[e] = v[u];
+            if (e <= WSLOTS) {
+                skeys[e] = v[u].a;
+                skx[e] = v[u].b;
+            }
             if (e >= 1 && e <= WSLOTS) sval[e - 1] = x[u];
         }
     }
@@ -363,7 +401,7 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int e = t + k * TT;
-        const bool st = e < nw && (b0 + e == 0 || skeys[e + 1] != skeys[e]);
+        const bool st = e < nw && (b0 + e == 0 || skeys[e + 1] != skeys[e] || skx[e + 1] != skx[e]);
         const unsigned long long m = ballot64(st);
         if (lane == 0) smask[wv + k * (TT / 64)] = m;
     }
@@ -536,18 +574,24 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, con
 }
 
 template <typename T, int WT>
-cg_status tiefix_w_launch(const T *rows, const uint32_t *khi, const uint32_t *klo, int64_t n, int words,
-                          uint32_t *vals, uint8_t *uniq, uint2 *large_list, unsigned long long *counters, bool may64,
-                          bool may32, hipStream_t s) {
+cg_status tiefix_w_launch(const T *rows, KeyPlanes planes, int64_t n, int words, uint32_t *vals, uint8_t *uniq,
+                          uint2 *large_list, unsigned long long *counters, bool may32, bool may64, bool may96,
+                          hipStream_t s) {
+    // one launch per width that may be the chosen one; the others return at once
     if (may64) {
-        hipLaunchKernelGGL((k_tiefix_w<T, WT, 64>), dim3(blocks_for(n, TT)), dim3(TT), 0, s, rows, khi, klo, n, words,
+        hipLaunchKernelGGL((k_tiefix_w<T, WT, 64>), dim3(blocks_for(n, TT)), dim3(TT), 0, s, rows, planes, n, words,
                            vals, uniq, large_list, counters);
         CG_LAUNCHED("dedup_tiefix_w");
     }
-    if (may32) {  // 32-bit keys chosen by the caller or possibly by the probe
-        hipLaunchKernelGGL((k_tiefix_w<T, WT, 32>), dim3(blocks_for(n, TT)), dim3(TT), 0, s, rows, khi, klo, n,
-                           words, vals, uniq, large_list, counters);
+    if (may32) {
+        hipLaunchKernelGGL((k_tiefix_w<T, WT, 32>), dim3(blocks_for(n, TT)), dim3(TT), 0, s, rows, planes, n, words,
+                           vals, uniq, large_list, counters);
         CG_LAUNCHED("dedup_tiefix_w32");
+    }
+    if (may96) {
+        hipLaunchKernelGGL((k_tiefix_w<T, WT, 96>), dim3(blocks_for(n, TT)), dim3(TT), 0, s, rows, planes, n, words,
+                           vals, uniq, large_list, counters);
+        CG_LAUNCHED("dedup_tiefix_w96");
     }
     return CG_OK;
 }
@@ -568,7 +612,8 @@ __global__ void __launch_bounds__(1024) k_tiefix_large(const T *__restrict__ row
                                                       const uint2 *__restrict__ list,
                                                       const unsigned long long *__restrict__ counters, uint32_t *vals,
                                                       uint8_t *uniq, uint32_t *scratch) {
-    const int from = counters[2] ? from64 / 2 : from64;  // words covered by the sort key
+    (void)from64;
+    const int from = key_width(counters) / Bits<T>::B;  // whole words covered by the sort key
     const uint32_t count = static_cast<uint32_t>(counters[1]);
     for (uint32_t s = blockIdx.x; s < count; s += gridDim.x) {
         const uint2 seg = list[s];
@@ -637,7 +682,8 @@ __global__ void __launch_bounds__(NT) k_tiefix_mid(const T *__restrict__ rows, i
                                                      const uint2 *__restrict__ list,
                                                      const unsigned long long *__restrict__ counters,
                                                      uint32_t *__restrict__ vals, uint8_t *__restrict__ uniq) {
-    const int from = counters[2] ? from64 / 2 : from64;  // words covered by the sort key
+    (void)from64;
+    const int from = key_width(counters) / Bits<T>::B;  // whole words covered by the sort key
     extern __shared__ __align__(16) unsigned char smem[];  // LM keys, then LM indices
     uint64_t *sk = reinterpret_cast<uint64_t *>(smem);
     uint32_t *si = reinterpret_cast<uint32_t *>(smem + LM * sizeof(uint64_t));
@@ -778,6 +824,7 @@ __global__ void __launch_bounds__(256) k_gather(const V *__restrict__ rows, int6
 struct DedupWs {
     uint32_t *khi[2];
     uint32_t *klo[2];
+    uint32_t *kx[2];  // third key plane (96-bit keys, rows longer than 64 bits)
     uint32_t *vals[2];
     uint32_t *hist;
     uint64_t *tile_sums;
@@ -797,6 +844,10 @@ DedupWs carve_dedup(void *base, int64_t n, cg_layout lay, size_t *bytes, bool wi
     w.khi[1] = c.take<uint32_t>(m);
     w.klo[0] = c.take<uint32_t>(m);
     w.klo[1] = c.take<uint32_t>(m);
+    if (lay.ell > 64) {
+        w.kx[0] = c.take<uint32_t>(m);
+        w.kx[1] = c.take<uint32_t>(m);
+    }
     w.vals[0] = c.take<uint32_t>(m);
     w.vals[1] = c.take<uint32_t>(m);
     w.hist = c.take<uint32_t>(radix_hist_entries(m));
@@ -836,31 +887,35 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
     if (n == 0) return fill_i64(d_ncells, 0, 1, s);
 
     const bool tiefix = lay.ell > 64;
-    // key width for l > 64: the caller's 32 or 64, or (0) a sample decides
-    // on the device for long inputs, else 64
+    // key width for l > 64: the caller's 32, 64 or 96, or (0) a sample
+    // decides between 32 and 64 on the device for long inputs, else 64
     const bool k32 = tiefix && key_bits == 32;
+    const bool k96 = tiefix && key_bits == 96;
     const bool probe = tiefix && key_bits == 0 && n >= PROBE_MIN_N;
-    hipLaunchKernelGGL(k_dedup_init, dim3(1), dim3(64), 0, s, w.counters, k32 ? 1ull : 0ull, extra_zero, n_extra);
+    hipLaunchKernelGGL(k_dedup_init, dim3(1), dim3(64), 0, s, w.counters, k32 ? 1ull : 0ull, k96 ? 1ull : 0ull,
+                       extra_zero, n_extra);
     CG_LAUNCHED("dedup_init");
     if (probe) {
         hipLaunchKernelGGL((k_key_probe<T>), dim3(1), dim3(1024), 0, s, rows, n, words, w.counters);
         CG_LAUNCHED("dedup_key_probe");
     }
-    // key bits that can be nonzero: [64 - sig, 64); the low plane (key bits
-    // 0..31) exists only when they reach below bit 32, and with 32-bit keys
-    // chosen on the device its four passes are skipped there
-    const int sig = tiefix ? (k32 ? 32 : 64) : lay.ell;
-    const int lo = ((64 - sig) / 8) * 8;
-    const bool lo_plane = sig > 32;
-    uint32_t *klo0 = lo_plane ? w.klo[0] : nullptr;
+    // key bits that can be nonzero, in 32-bit planes from the row's start:
+    // the sort runs over the last 32 nplanes - sig bits' complement; with
+    // 32-bit keys chosen on the device the second plane's passes are skipped
+    const int sig = tiefix ? (k32 ? 32 : (k96 ? 96 : 64)) : lay.ell;
+    const int nplanes = (sig + 31) / 32;
+    const int bit_lo = ((32 * nplanes - sig) / 8) * 8;
+    uint32_t *pl[3][2] = {{w.khi[0], w.khi[1]},
+                          {nplanes > 1 ? w.klo[0] : nullptr, nplanes > 1 ? w.klo[1] : nullptr},
+                          {nplanes > 2 ? w.kx[0] : nullptr, nplanes > 2 ? w.kx[1] : nullptr}};
     const unsigned long long *key32 = probe ? w.counters + 2 : nullptr;
     const size_t xlds = static_cast<size_t>(256) * (words | 1) * sizeof(T);
     if (rhash && xlds <= 65536) {
         hipLaunchKernelGGL((k_extract_hash<T>), dim3(blocks_for(n, 256)), dim3(256), xlds, s, rows, n, words, key32,
-                           w.khi[0], klo0, w.vals[0], hash_s, rhash);
+                           pl[0][0], pl[1][0], pl[2][0], w.vals[0], hash_s, rhash);
     } else {
         hipLaunchKernelGGL((k_extract<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words, key32,
-                           w.khi[0], klo0, w.vals[0]);
+                           pl[0][0], pl[1][0], pl[2][0], w.vals[0]);
         if (rhash) {  // rows too wide to stage: hash them in place
             hipLaunchKernelGGL((k_hash_rows<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words,
                                hash_s, rhash);
@@ -870,39 +925,40 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
     CG_LAUNCHED("dedup_extract");
 
     int which = 0;
-    CG_TRY(radix_sort_k32(w.khi, w.klo, w.vals, n, nullptr, lo, w.hist, &which, s, lo_plane, key32));
-    uint32_t *khi = w.khi[which];
-    uint32_t *klo = lo_plane ? w.klo[which] : nullptr;
+    CG_TRY(radix_sort_k32(pl, nplanes, w.vals, n, nullptr, bit_lo, w.hist, &which, s, nplanes > 1, key32));
+    const KeyPlanes planes{pl[0][which], pl[1][which], pl[2][which]};
+    uint32_t *khi = pl[0][which];
     uint32_t *vals = w.vals[which];
 
     const int B = static_cast<int>(sizeof(T) * 8);
-    const int from = 64 / B;  // words covered by a 64-bit sort key (the mid pass halves it for 32)
+    const int from = 64 / B;  // unused by the tie-fixes, which take the key width from the device counters
     if (!tiefix) {
-        hipLaunchKernelGGL(k_heads, dim3(blocks_for(n, 256)), dim3(256), 0, s, KeyPlanes{khi, klo}, n, w.uniq);
+        hipLaunchKernelGGL(k_heads, dim3(blocks_for(n, 256)), dim3(256), 0, s, planes, n, w.uniq);
         CG_LAUNCHED("dedup_heads");
     } else {
         const int LW = words + ((words % 2 == 0) ? 1 : 0);
-        const int64_t per_slot = static_cast<int64_t>(LW) * sizeof(T) + 20;
+        // per slot: its row, key (8 + 4 bytes), segment, length, row index
+        const int64_t per_slot = static_cast<int64_t>(LW) * sizeof(T) + 24;
         int64_t smax = TILE_LDS / per_slot - TT - 1;
         if (smax > 512) smax = 512;
-        size_t lds = static_cast<size_t>(TT + smax) * per_slot + 8;
+        size_t lds = static_cast<size_t>(TT + smax) * per_slot + 16;
         if (smax < 2) {  // rows too wide for LDS: every multi-row segment takes the large path
             smax = 1;
-            lds = static_cast<size_t>(TT + 1) * 20 + 8;
+            lds = static_cast<size_t>(TT + 1) * 24 + 16;
         }
         int wt = 1;
         while (wt < words) wt <<= 1;
         if (wt <= 32) {  // head rows of up to 32 words fit the summary kernel's LDS
             switch (wt) {
-            case 2: CG_TRY((tiefix_w_launch<T, 2>(rows, khi, klo, n, words, vals, w.uniq, w.large_list, w.counters, !k32, probe || k32, s))); break;
-            case 4: CG_TRY((tiefix_w_launch<T, 4>(rows, khi, klo, n, words, vals, w.uniq, w.large_list, w.counters, !k32, probe || k32, s))); break;
-            case 8: CG_TRY((tiefix_w_launch<T, 8>(rows, khi, klo, n, words, vals, w.uniq, w.large_list, w.counters, !k32, probe || k32, s))); break;
-            case 16: CG_TRY((tiefix_w_launch<T, 16>(rows, khi, klo, n, words, vals, w.uniq, w.large_list, w.counters, !k32, probe || k32, s))); break;
-            default: CG_TRY((tiefix_w_launch<T, 32>(rows, khi, klo, n, words, vals, w.uniq, w.large_list, w.counters, !k32, probe || k32, s))); break;
+            case 2: CG_TRY((tiefix_w_launch<T, 2>(rows, planes, n, words, vals, w.uniq, w.large_list, w.counters, probe || k32, !k32 && !k96, k96, s))); break;
+            case 4: CG_TRY((tiefix_w_launch<T, 4>(rows, planes, n, words, vals, w.uniq, w.large_list, w.counters, probe || k32, !k32 && !k96, k96, s))); break;
+            case 8: CG_TRY((tiefix_w_launch<T, 8>(rows, planes, n, words, vals, w.uniq, w.large_list, w.counters, probe || k32, !k32 && !k96, k96, s))); break;
+            case 16: CG_TRY((tiefix_w_launch<T, 16>(rows, planes, n, words, vals, w.uniq, w.large_list, w.counters, probe || k32, !k32 && !k96, k96, s))); break;
+            default: CG_TRY((tiefix_w_launch<T, 32>(rows, planes, n, words, vals, w.uniq, w.large_list, w.counters, probe || k32, !k32 && !k96, k96, s))); break;
             }
         } else {
-            hipLaunchKernelGGL((k_tiefix_tile<T>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, khi, klo, n,
-                               words, from, static_cast<int>(smax), vals, w.uniq, w.large_list, w.counters);
+            hipLaunchKernelGGL((k_tiefix_tile<T>), dim3(blocks_for(n, TT)), dim3(TT), lds, s, rows, planes, n, words,
+                               static_cast<int>(smax), vals, w.uniq, w.large_list, w.counters);
             CG_LAUNCHED("dedup_tiefix_tile");
         }
         constexpr int MID_S = 2048;  // segments up to this many rows: 256-thread blocks, 24 KB of LDS each

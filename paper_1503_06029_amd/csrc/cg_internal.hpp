@@ -476,15 +476,18 @@ cg_status radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], int64_t n_cap, co
                          int bit_hi, uint32_t *hist, uint64_t *tile_sums, int *which, hipStream_t s,
                          const unsigned long long *skip = nullptr, int skip_below = 0);
 
-// LSD radix sort of a 64-bit key held as two 32-bit planes (khi = key bits
-// 32..63, klo = bits 0..31) with 32-bit values, by key bits [bit_lo, 64), 8
-// bits per pass, stable.  lo_plane: klo is still wanted after the sort (it is
-// carried through the high-plane passes; with key32 set on the device it is
-// dropped).  key32 (device flag, may be null): when nonzero the low-plane
-// passes do nothing (the key is its high plane), an even number of them, so
-// *which stays right.  The sorted planes and values end in [*which].
-cg_status radix_sort_k32(uint32_t *khi[2], uint32_t *klo[2], uint32_t *vals[2], int64_t n_cap, const int64_t *d_n,
-                         int bit_lo, uint32_t *hist, int *which, hipStream_t s, bool lo_plane,
+// LSD radix sort of a key held as nplanes (1..3) 32-bit planes, planes[0]
+// the most significant (for a dedup key: the row's first 32 bits, then the
+// next 32, ...), with 32-bit values, by key bits [bit_lo, 32 nplanes)
+// counted from the least significant end, 8 bits per pass, stable.
+// lower_planes: the planes below the highest are still wanted after the
+// sort (they are carried through the passes of the planes above them).
+// key32 (two planes only; device flag, may be null): when nonzero the low
+// plane's passes do nothing (the key is its high plane, an even number of
+// skipped passes, so *which stays right) and the high plane's passes drop
+// it.  The sorted planes and values end in [*which].
+cg_status radix_sort_k32(uint32_t *planes[3][2], int nplanes, uint32_t *vals[2], int64_t n_cap, const int64_t *d_n,
+                         int bit_lo, uint32_t *hist, int *which, hipStream_t s, bool lower_planes,
                          const unsigned long long *key32);
 
 // Fill kernel (graph-capture safe replacement for hipMemsetAsync).

@@ -352,8 +352,9 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix32_hist(const uint32_t *key
 }
 
 __global__ void __launch_bounds__(RS_THREADS) k_radix32_scatter(const uint32_t *kin, const uint32_t *v0in,
-                                                                const uint32_t *v1in, uint32_t *kout, uint32_t *v0out,
-                                                                uint32_t *v1out, int64_t n_cap, const int64_t *d_n,
+                                                                const uint32_t *v1in, const uint32_t *v2in,
+                                                                uint32_t *kout, uint32_t *v0out, uint32_t *v1out,
+                                                                uint32_t *v2out, int64_t n_cap, const int64_t *d_n,
                                                                 int shift, const uint32_t *hist_off,
                                                                 const uint32_t *dtot, int num_tiles,
                                                                 const unsigned long long *skip,
@@ -365,20 +366,22 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix32_scatter(const uint32_t *
     __shared__ uint32_t sk[RS_TILE];
     __shared__ uint32_t sv0[RS_TILE];
     __shared__ uint32_t sv1[RS_TILE];
+    __shared__ uint32_t sv2[RS_TILE];
     __shared__ uint64_t tmp[4];
 
     const int64_t n = load_n(d_n, n_cap);
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t base = static_cast<int64_t>(tile) * RS_TILE;
     if (base >= n) return;
-    const bool two = v1in != nullptr && !(drop_v1 && *drop_v1);
+    const bool has1 = v1in != nullptr && !(drop_v1 && *drop_v1);
+    const bool has2 = v2in != nullptr;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int tile_n = static_cast<int>(n - base < RS_TILE ? n - base : RS_TILE);
 
     for (int i = t; i < RS_WAVES * RADIX; i += RS_THREADS) (&wcnt[0][0])[i] = 0;
     __syncthreads();
 
-    uint32_t key[RS_ITEMS], v0[RS_ITEMS], v1[RS_ITEMS], rank[RS_ITEMS];
+    uint32_t key[RS_ITEMS], v0[RS_ITEMS], v1[RS_ITEMS], v2[RS_ITEMS], rank[RS_ITEMS];
     const uint64_t lt = lanemask_lt();
     // wave w owns the contiguous sub-tile [w * 64 * ITEMS, (w + 1) * 64 * ITEMS);
     // every load is issued before the ranking starts
@@ -388,7 +391,8 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix32_scatter(const uint32_t *
         const bool valid = li < tile_n;
         key[j] = valid ? kin[base + li] : 0u;
         v0[j] = valid ? v0in[base + li] : 0u;
-        v1[j] = (valid && two) ? v1in[base + li] : 0u;
+        v1[j] = (valid && has1) ? v1in[base + li] : 0u;
+        v2[j] = (valid && has2) ? v2in[base + li] : 0u;
     }
 #pragma unroll
     for (int j = 0; j < RS_ITEMS; ++j) {
@@ -434,7 +438,8 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix32_scatter(const uint32_t *
             const uint32_t p = tile_start[d] + wcnt[w][d] + rank[j];
             sk[p] = key[j];
             sv0[p] = v0[j];
-            if (two) sv1[p] = v1[j];
+            if (has1) sv1[p] = v1[j];
+            if (has2) sv2[p] = v2[j];
         }
     }
     __syncthreads();
@@ -444,7 +449,8 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix32_scatter(const uint32_t *
         const int64_t g = static_cast<int64_t>(gbase[d]) + (i - static_cast<int>(tile_start[d]));
         kout[g] = k;
         v0out[g] = sv0[i];
-        if (two) v1out[g] = sv1[i];
+        if (has1) v1out[g] = sv1[i];
+        if (has2) v2out[g] = sv2[i];
     }
 }
 
@@ -529,30 +535,36 @@ cg_status radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], int64_t n_cap, co
     return CG_OK;
 }
 
-cg_status radix_sort_k32(uint32_t *khi[2], uint32_t *klo[2], uint32_t *vals[2], int64_t n_cap, const int64_t *d_n,
-                         int bit_lo, uint32_t *hist, int *which, hipStream_t s, bool lo_plane,
+cg_status radix_sort_k32(uint32_t *planes[3][2], int nplanes, uint32_t *vals[2], int64_t n_cap, const int64_t *d_n,
+                         int bit_lo, uint32_t *hist, int *which, hipStream_t s, bool lower_planes,
                          const unsigned long long *key32) {
     const int num_tiles = static_cast<int>(blocks_for(n_cap, RS_TILE));
     uint32_t *dtot = hist + static_cast<int64_t>(RADIX) * num_tiles;  // digit totals after the rows
+    uint32_t *none[2] = {nullptr, nullptr};
     int cur = 0;
-    for (int bit = bit_lo; bit < 64; bit += 8) {
-        const bool hi = bit >= 32;
-        // low-plane passes: key klo, payloads vals and khi; skipped when the
-        // device chose 32-bit keys.  High-plane passes: key khi, payloads
-        // vals and (while the low plane is still needed) klo.
-        const unsigned long long *sk = hi ? nullptr : key32;
-        uint32_t *const *kp = hi ? khi : klo;
-        uint32_t *const *pp = hi ? klo : khi;
-        const bool carry = hi ? lo_plane : true;
-        hipLaunchKernelGGL(k_radix32_hist, dim3(num_tiles), dim3(RS_THREADS), 0, s, kp[cur], n_cap, d_n, bit & 31,
-                           hist, num_tiles, sk);
+    for (int bit = bit_lo; bit < 32 * nplanes; bit += 8) {
+        // the pass's plane (planes[0] most significant) and the other planes,
+        // carried as payloads: planes above it always (their passes follow),
+        // planes below it while they are wanted after the sort
+        const int q = nplanes - 1 - bit / 32;
+        uint32_t *const *o1 = none, *const *o2 = none;
+        for (int r = 0; r < nplanes; ++r) {
+            if (r == q || (r > q && !lower_planes)) continue;
+            if (o1 == none) o1 = planes[r]; else o2 = planes[r];
+        }
+        // with two planes the device may have chosen 32-bit keys: the low
+        // plane's passes do nothing, and the high plane's drop it
+        const bool low2 = nplanes == 2 && q == 1;
+        const unsigned long long *sk = low2 ? key32 : nullptr;
+        const unsigned long long *drop = (nplanes == 2 && q == 0) ? key32 : nullptr;
+        hipLaunchKernelGGL(k_radix32_hist, dim3(num_tiles), dim3(RS_THREADS), 0, s, planes[q][cur], n_cap, d_n,
+                           bit & 31, hist, num_tiles, sk);
         CG_LAUNCHED("radix32_hist");
         hipLaunchKernelGGL(k_radix_dscan, dim3(RADIX), dim3(RS_THREADS), 0, s, hist, num_tiles, dtot, sk);
         CG_LAUNCHED("radix32_dscan");
-        hipLaunchKernelGGL(k_radix32_scatter, dim3(num_tiles), dim3(RS_THREADS), 0, s, kp[cur], vals[cur],
-                           carry ? pp[cur] : static_cast<uint32_t *>(nullptr), kp[cur ^ 1], vals[cur ^ 1],
-                           carry ? pp[cur ^ 1] : static_cast<uint32_t *>(nullptr), n_cap, d_n, bit & 31, hist, dtot,
-                           num_tiles, sk, hi ? key32 : static_cast<const unsigned long long *>(nullptr));
+        hipLaunchKernelGGL(k_radix32_scatter, dim3(num_tiles), dim3(RS_THREADS), 0, s, planes[q][cur], vals[cur],
+                           o1[cur], o2[cur], planes[q][cur ^ 1], vals[cur ^ 1], o1[cur ^ 1], o2[cur ^ 1], n_cap, d_n,
+                           bit & 31, hist, dtot, num_tiles, sk, drop);
         CG_LAUNCHED("radix32_scatter");
         cur ^= 1;
     }

@@ -116,7 +116,7 @@ class Tuner:
                 best, best_ms = cand, ms
         # then the sort-key width of the fused dedup + dictionary build, with
         # the best edge parameters (0: separate calls, automatic width)
-        for kb in (32, 64):
+        for kb in (32, 64, 96):
             cand = dict(best, key_bits=kb)
             sb.params = B.cg_dict_params_default(**cand)
             timed_run()

@@ -75,7 +75,7 @@ def test_argument_validation_without_gpu():
     p = B.cg_dict_params_default()
     assert (p.dir_bits, p.split_bit, p.group_max, p.path) == (-1, -1, -1, 0)
     assert B.cg_dict_size(1000, lay, p) > 0
-    for kb in (0, 32, 64):
+    for kb in (0, 32, 64, 96):
         assert B.cg_dict_size(1000, lay, B.cg_dict_params_default(key_bits=kb)) > 0
     for field, val in (("dir_bits", 30), ("split_bit", 101), ("n_refs", 9), ("group_max", 0), ("kind", 7),
                        ("key_bits", 48), ("key_bits", -1), ("reserved", 1)):

@@ -153,7 +153,7 @@ def _grouped_tails(rng, groups, per, ell, head_bits, tail_from):
     return R[rng.permutation(len(R))]
 
 
-@pytest.mark.parametrize("key_bits", [0, 32, 64])
+@pytest.mark.parametrize("key_bits", [0, 32, 64, 96])
 def test_tie_runs_in_long_segments(gpu, key_bits):
     """Segments of 129..8,192 rows (one block each) whose rows tie on the
     next 64 bits too: short tie runs (one thread sorts each), long ones (the
@@ -175,7 +175,7 @@ def test_tie_runs_in_long_segments(gpu, key_bits):
         assert np.array_equal(a["cells"], cells) and np.array_equal(a["row_to_cell"], r2c)
 
 
-@pytest.mark.parametrize("key_bits", [32, 64])
+@pytest.mark.parametrize("key_bits", [32, 64, 96])
 def test_fused_key_bits(gpu, key_bits):
     """A caller-chosen sort-key width changes no byte: clustered sets, rows
     sharing their first 40 bits (one segment of 3,000 / 20,000 rows under
@@ -197,7 +197,7 @@ def test_fused_key_bits(gpu, key_bits):
         assert np.array_equal(b["cells"], cells) and np.array_equal(b["row_to_cell"], r2c)
 
 
-@pytest.mark.parametrize("key_bits", [32, 64])
+@pytest.mark.parametrize("key_bits", [32, 64, 96])
 def test_fused_long_vectors_key_bits(gpu, key_bits):
     """The long-vector workload with either key width: same bytes as the
     automatic build (which takes 32 bits here)."""
