@@ -347,49 +347,75 @@ size_t dict_mem_bytes(int64_t ncap, cg_layout, const cg_dict_params &p) {
 }
 
 // Directory from the dedup's sorted keys (the fused dedup + dictionary
-// build): the position that starts cell c writes the entries from just past
-// the previous position's top p bits up to its own, as k_dict_scan does from
-// the cells.  The previous position holds the previous cell or a copy of it
-// (equal rows have equal keys), and the sort key always keeps the top 32
-// bits, so no cell row is read.
+// build): entry g is the first cell whose top p bits are >= g; the position
+// that starts that cell is the first position whose key's top p bits are
+// >= g (the previous position has smaller top bits, so it starts a cell).
+// The sort key always keeps the top 32 bits, so no cell row is read.  A
+// wave covers 64 positions and the entries from just past its first
+// position's predecessor up to its last position: with at most DW of them,
+// each lane takes entries 64 apart and finds its position by a binary
+// search over the wave's 64 top-bit values in LDS, so writes leave
+// coalesced; a wider stretch (sparse keys) is written as k_dict_scan does,
+// each cell's entries by its own lane and long gaps listed for k_dir_gaps.
+constexpr int DW = 4096;
 __global__ void __launch_bounds__(DT) k_dir_from_keys(const uint32_t *__restrict__ keys,
                                                       const uint8_t *__restrict__ uniq,
                                                       const uint32_t *__restrict__ cidx, int64_t n,
                                                       const int64_t *d_ncells, int p, uint32_t *__restrict__ dir,
                                                       uint4 *__restrict__ gaps, unsigned long long *gap_n,
                                                       int64_t gap_cap, uint4 *__restrict__ huge, int64_t huge_cap) {
+    __shared__ int64_t sg[DT];
+    __shared__ uint32_t sc[DT];
     const int64_t G = int64_t(1) << p;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * DT + threadIdx.x;
-    // all loads issued together (in range), used only by positions that start a cell
+    const int lane = threadIdx.x & 63, wb = threadIdx.x & ~63;
+    const int64_t i0 = i - lane;  // the wave's first position
+    if (i0 >= n) return;          // whole waves only: the shuffles below see every lane
     const int64_t ii = i < n ? i : n - 1;
+    const bool valid = i < n;
     const uint8_t un = uniq[ii];
     const uint32_t k = keys[ii], kp = keys[ii > 0 ? ii - 1 : 0];
-    const uint32_t ci = cidx[ii];
-    const bool act = i < n && un != 0;
-    int64_t gi = 0, gp = 0;
-    uint32_t c = 0;
-    bool long_gap = false, huge_gap = false;
-    if (act) {
-        c = ci;
-        gi = p ? static_cast<int64_t>(k >> (32 - p)) : 0;
-        gp = i == 0 ? -1 : (p ? static_cast<int64_t>(kp >> (32 - p)) : 0);
-        long_gap = gi - gp > GAPMIN;
-        huge_gap = gi - gp > GAPHUGE;
-        if (long_gap) {
-            dir[gi] = c;
-        } else {
-            for (int64_t g = gp + 1; g <= gi; ++g) dir[g] = c;
-        }
-    }
-    push_gap(gaps, gap_n, gap_cap, act && long_gap && !huge_gap, gp + 1, gi - 1, c);
-    push_gap(huge, gap_n + 1, huge_cap, act && huge_gap, gp + 1, gi - 1, c);
+    const uint32_t c = cidx[ii];
     const int64_t nc = *d_ncells;
+    const bool act = valid && un != 0;
+    const int64_t gi = p ? static_cast<int64_t>(k >> (32 - p)) : 0;
+    const int64_t gp = i == 0 ? -1 : (p ? static_cast<int64_t>(kp >> (32 - p)) : 0);
+    // the wave's stretch of entries: (lane 0's predecessor, last valid lane]
+    const int64_t lo = static_cast<int64_t>(shfl_u64(static_cast<uint64_t>(gp), 0)) + 1;
+    const int last = static_cast<int>((n - i0 < 64 ? n - i0 : 64) - 1);
+    const int64_t hi = static_cast<int64_t>(shfl_u64(static_cast<uint64_t>(gi), last));
+    if (hi - lo + 1 <= DW) {
+        sg[threadIdx.x] = valid ? gi : INT64_MAX;
+        sc[threadIdx.x] = c;
+        __builtin_amdgcn_wave_barrier();
+        for (int64_t g = lo + lane; g <= hi; g += 64) {
+            int a = 0, b = last;  // first lane whose top bits are >= g (lane last's are)
+            while (a < b) {
+                const int m = (a + b) >> 1;
+                if (sg[wb + m] < g) a = m + 1; else b = m;
+            }
+            dir[g] = sc[wb + a];
+        }
+    } else {
+        bool long_gap = false, huge_gap = false;
+        if (act) {
+            long_gap = gi - gp > GAPMIN;
+            huge_gap = gi - gp > GAPHUGE;
+            if (long_gap) {
+                dir[gi] = c;
+            } else {
+                for (int64_t g = gp + 1; g <= gi; ++g) dir[g] = c;
+            }
+        }
+        push_gap(gaps, gap_n, gap_cap, act && long_gap && !huge_gap, gp + 1, gi - 1, c);
+        push_gap(huge, gap_n + 1, huge_cap, act && huge_gap, gp + 1, gi - 1, c);
+    }
     if (act && static_cast<int64_t>(c) == nc - 1) {  // entries gi + 1 .. G point past the end
         if (G - gi > GAPMIN) {
             const bool hg = G - gi > GAPHUGE;
-            const unsigned long long k = atomicAdd(hg ? gap_n + 1 : gap_n, 1ull);
-            if (static_cast<int64_t>(k) < (hg ? huge_cap : gap_cap))
-                (hg ? huge : gaps)[k] = make_uint4(static_cast<uint32_t>(gi + 1), static_cast<uint32_t>(G),
+            const unsigned long long q = atomicAdd(hg ? gap_n + 1 : gap_n, 1ull);
+            if (static_cast<int64_t>(q) < (hg ? huge_cap : gap_cap))
+                (hg ? huge : gaps)[q] = make_uint4(static_cast<uint32_t>(gi + 1), static_cast<uint32_t>(G),
                                                    static_cast<uint32_t>(nc), 0u);
         } else {
             for (int64_t g = gi + 1; g <= G; ++g) dir[g] = static_cast<uint32_t>(nc);

@@ -455,6 +455,8 @@ inline unsigned blocks_for(int64_t items, int64_t per_block, int64_t max_blocks 
 int64_t scan_tiles(int64_t n_cap);
 cg_status scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n_cap, const int64_t *d_n,
                           uint64_t *tile_sums, uint32_t *total, hipStream_t s);
+// The byte form takes flags that are 0 or 1 (it counts a word's flags with
+// one multiply).
 cg_status scan_u8_to_u32(const uint8_t *in, uint32_t *out, int64_t n_cap, const int64_t *d_n,
                          uint64_t *tile_sums, int64_t *total, hipStream_t s);
 // out[i] = sum_{j<i} (a[j] + b[j]) as int64; out[n] and *total = the sum.

@@ -18,10 +18,6 @@ struct U32Arr {
     const uint32_t *p;
     __device__ uint32_t operator()(int64_t i) const { return p[i]; }
 };
-struct U8Arr {
-    const uint8_t *p;
-    __device__ uint32_t operator()(int64_t i) const { return p[i]; }
-};
 struct PairSum {
     const uint32_t *a, *b;
     __device__ uint32_t operator()(int64_t i) const { return a[i] + b[i]; }
@@ -114,6 +110,74 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(F f, TO *out, int64_
     for (int j = 0; j < SCAN_ITEMS; ++j) {
         int64_t i = base + j * SCAN_THREADS + t;
         if (i < n) out[i] = static_cast<TO>(vals[j * SCAN_THREADS + t]);
+    }
+}
+
+// Exclusive scan of 0/1 byte flags into u32: a thread takes 16 consecutive
+// flags with one 16-byte load (byte loads at the end of the input or when
+// it is not 16-byte aligned) and counts a word's flags by one multiply; the
+// down-sweep writes its 16 outputs as four 16-byte stores.
+__device__ __forceinline__ void load_flags16(const uint8_t *p, int64_t i, int64_t n, bool vec, uint32_t f[4]) {
+    if (vec && i + 16 <= n) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(p + i);
+        f[0] = v.x; f[1] = v.y; f[2] = v.z; f[3] = v.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            uint32_t x = 0;
+            for (int b = 0; b < 4; ++b) {
+                const int64_t q = i + 4 * k + b;
+                if (q < n) x |= static_cast<uint32_t>(p[q]) << (8 * b);
+            }
+            f[k] = x;
+        }
+    }
+}
+__device__ __forceinline__ uint32_t flags_in_word(uint32_t x) { return (x * 0x01010101u) >> 24; }
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan8_reduce(const uint8_t *flags, int64_t n_cap,
+                                                               const int64_t *d_n, uint64_t *tile_sums) {
+    __shared__ uint64_t tmp[4];
+    const int64_t n = load_n(d_n, n_cap);
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * SCAN_TILE + 16 * threadIdx.x;
+    const bool vec = (reinterpret_cast<uintptr_t>(flags) & 15) == 0;
+    uint64_t acc = 0;
+    if (i < n) {
+        uint32_t f[4];
+        load_flags16(flags, i, n, vec, f);
+        acc = flags_in_word(f[0]) + flags_in_word(f[1]) + flags_in_word(f[2]) + flags_in_word(f[3]);
+    }
+    uint64_t total;
+    block256_excl_scan_u64(acc, tmp, &total);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan8_down(const uint8_t *flags, uint32_t *out, int64_t n_cap,
+                                                             const int64_t *d_n, const uint64_t *tile_sums) {
+    __shared__ uint64_t tmp[4];
+    const int64_t n = load_n(d_n, n_cap);
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE;
+    if (base >= n) return;
+    const int64_t i = base + 16 * threadIdx.x;
+    const bool vec = (reinterpret_cast<uintptr_t>(flags) & 15) == 0;
+    uint32_t f[4] = {0u, 0u, 0u, 0u};
+    if (i < n) load_flags16(flags, i, n, vec, f);
+    const uint64_t sum = flags_in_word(f[0]) + flags_in_word(f[1]) + flags_in_word(f[2]) + flags_in_word(f[3]);
+    uint64_t tot;
+    uint32_t ex = static_cast<uint32_t>(block256_excl_scan_u64(sum, tmp, &tot) + tile_sums[blockIdx.x]);
+    if (i >= n) return;
+    uint32_t o[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        o[k] = ex;
+        ex += (f[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+    }
+    if (i + 16 <= n && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+        uint4 *o4 = reinterpret_cast<uint4 *>(out + i);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o4[k] = make_uint4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+    } else {
+        for (int k = 0; k < 16 && i + k < n; ++k) out[i + k] = o[k];
     }
 }
 
@@ -477,8 +541,15 @@ cg_status scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n_cap, cons
 
 cg_status scan_u8_to_u32(const uint8_t *in, uint32_t *out, int64_t n_cap, const int64_t *d_n,
                          uint64_t *tile_sums, int64_t *total, hipStream_t s) {
-    return scan_generic(U8Arr{in}, out, n_cap, d_n, tile_sums, static_cast<uint32_t *>(nullptr), total,
-                        nullptr, s);
+    const unsigned tiles = blocks_for(n_cap, SCAN_TILE);
+    hipLaunchKernelGGL(k_scan8_reduce, dim3(tiles), dim3(SCAN_THREADS), 0, s, in, n_cap, d_n, tile_sums);
+    CG_LAUNCHED("scan8_reduce");
+    hipLaunchKernelGGL((k_scan_tiles<uint32_t>), dim3(1), dim3(SCAN_THREADS), 0, s, tile_sums, n_cap, d_n,
+                       static_cast<uint32_t *>(nullptr), total, static_cast<uint32_t *>(nullptr));
+    CG_LAUNCHED("scan_tiles");
+    hipLaunchKernelGGL(k_scan8_down, dim3(tiles), dim3(SCAN_THREADS), 0, s, in, out, n_cap, d_n, tile_sums);
+    CG_LAUNCHED("scan8_down");
+    return CG_OK;
 }
 
 cg_status scan_pair_to_i64(const uint32_t *a, const uint32_t *b, int64_t *out, int64_t n_cap,
