@@ -103,19 +103,28 @@ __global__ void __launch_bounds__(1024) k_key_probe(const T *__restrict__ rows, 
 
 // The dedup's device counters (long-segment list length, the key-width
 // flags: [2] 32-bit keys, [3] 96-bit keys) and, for the fused build, the
-// dictionary's gap-list counters, in one launch.
-__global__ void k_dedup_init(unsigned long long *counters, unsigned long long key32, unsigned long long key96,
-                             unsigned long long *extra, int n_extra) {
-    const int t = threadIdx.x;
-    if (t < 4) counters[t] = t == 2 ? key32 : (t == 3 ? key96 : 0ull);
-    if (extra && t < n_extra) extra[t] = 0ull;
-}
+// dictionary's gap-list counters: set by block 0 of the key extraction, or
+// by a launch of their own before the sample (which sets [2]).
+struct DedupInit {
+    unsigned long long *counters;  // null: already set
+    unsigned long long key32, key96;
+    unsigned long long *extra;
+    int n_extra;
+    __device__ __forceinline__ void run() const {
+        const int t = threadIdx.x;
+        if (!counters || blockIdx.x != 0) return;
+        if (t < 4) counters[t] = t == 2 ? key32 : (t == 3 ? key96 : 0ull);
+        if (extra && t < n_extra) extra[t] = 0ull;
+    }
+};
+__global__ void k_dedup_init(DedupInit in) { in.run(); }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_extract(const T *__restrict__ rows, int64_t n, int words,
                                                  const unsigned long long *__restrict__ key32, uint32_t *__restrict__ k0,
                                                  uint32_t *__restrict__ k1, uint32_t *__restrict__ k2,
-                                                 uint32_t *__restrict__ vals) {
+                                                 uint32_t *__restrict__ vals, DedupInit init) {
+    init.run();
     const bool has1 = k1 && !(key32 && *key32);  // the second plane unless the sample chose 32 bits
     for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
          j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -145,7 +154,8 @@ __global__ void __launch_bounds__(256) k_extract_hash(const T *__restrict__ rows
                                                       const unsigned long long *__restrict__ key32,
                                                       uint32_t *__restrict__ k0, uint32_t *__restrict__ k1,
                                                       uint32_t *__restrict__ k2, uint32_t *__restrict__ vals,
-                                                      int hash_s, uint32_t *__restrict__ rhash) {
+                                                      int hash_s, uint32_t *__restrict__ rhash, DedupInit init) {
+    init.run();
     extern __shared__ __align__(16) unsigned char smem[];
     T *lrows = reinterpret_cast<T *>(smem);
     const int LW = words | 1;
@@ -607,52 +617,43 @@ __device__ __forceinline__ bool idx_less(const T *rows, int words, int from, uin
 
 // One block per long segment: bitonic network over its index array, kept in
 // global scratch at [2a, 2a + P), P = next power of two >= len.
+// A segment longer than LMAX rows, by the whole block: bitonic network on
+// its index array in global scratch at [2a, 2a + P), P = next power of two
+// >= len (slow, met only by heavy-duplicate inputs).
 template <typename T>
-__global__ void __launch_bounds__(1024) k_tiefix_large(const T *__restrict__ rows, int words, int from64,
-                                                      const uint2 *__restrict__ list,
-                                                      const unsigned long long *__restrict__ counters, uint32_t *vals,
-                                                      uint8_t *uniq, uint32_t *scratch) {
-    (void)from64;
-    const int from = key_width(counters) / Bits<T>::B;  // whole words covered by the sort key
-    const uint32_t count = static_cast<uint32_t>(counters[1]);
-    for (uint32_t s = blockIdx.x; s < count; s += gridDim.x) {
-        const uint2 seg = list[s];
-        const int64_t a = seg.x;
-        const int64_t len = seg.y;
-        if (len <= LMAX) continue;  // k_tiefix_mid took it
-        int64_t P = 1;
-        while (P < len) P <<= 1;
-        uint32_t *scr = scratch + 2 * a;
-        for (int64_t i = threadIdx.x; i < P; i += blockDim.x) scr[i] = i < len ? vals[a + i] : SENT;
-        __syncthreads();
-        for (int64_t k = 2; k <= P; k <<= 1) {
-            for (int64_t j = k >> 1; j > 0; j >>= 1) {
-                for (int64_t i = threadIdx.x; i < P; i += blockDim.x) {
-                    const int64_t p = i ^ j;
-                    if (p > i) {
-                        const uint32_t x = scr[i], y = scr[p];
-                        const bool asc = (i & k) == 0;
-                        const bool swap = asc ? idx_less<T>(rows, words, from, y, x)
-                                              : idx_less<T>(rows, words, from, x, y);
-                        if (swap) { scr[i] = y; scr[p] = x; }
-                    }
+__device__ void sort_large_segment(const T *__restrict__ rows, int words, int from, int64_t a, int64_t len,
+                                   uint32_t *vals, uint8_t *uniq, uint32_t *scratch) {
+    int64_t P = 1;
+    while (P < len) P <<= 1;
+    uint32_t *scr = scratch + 2 * a;
+    for (int64_t i = threadIdx.x; i < P; i += blockDim.x) scr[i] = i < len ? vals[a + i] : SENT;
+    __syncthreads();
+    for (int64_t k = 2; k <= P; k <<= 1) {
+        for (int64_t j = k >> 1; j > 0; j >>= 1) {
+            for (int64_t i = threadIdx.x; i < P; i += blockDim.x) {
+                const int64_t p = i ^ j;
+                if (p > i) {
+                    const uint32_t x = scr[i], y = scr[p];
+                    const bool asc = (i & k) == 0;
+                    const bool swap = asc ? idx_less<T>(rows, words, from, y, x) : idx_less<T>(rows, words, from, x, y);
+                    if (swap) { scr[i] = y; scr[p] = x; }
                 }
-                __syncthreads();
             }
+            __syncthreads();
         }
-        for (int64_t i = threadIdx.x; i < len; i += blockDim.x) {
-            const uint32_t x = scr[i];
-            vals[a + i] = x;
-            bool u = true;
-            if (i > 0) {
-                const uint32_t y = scr[i - 1];
-                u = row_cmp4<T>(rows + static_cast<int64_t>(x) * words, rows + static_cast<int64_t>(y) * words,
-                               words, from) != 0;
-            }
-            uniq[a + i] = u ? 1 : 0;
-        }
-        __syncthreads();
     }
+    for (int64_t i = threadIdx.x; i < len; i += blockDim.x) {
+        const uint32_t x = scr[i];
+        vals[a + i] = x;
+        bool u = true;
+        if (i > 0) {
+            const uint32_t y = scr[i - 1];
+            u = row_cmp4<T>(rows + static_cast<int64_t>(x) * words, rows + static_cast<int64_t>(y) * words, words,
+                           from) != 0;
+        }
+        uniq[a + i] = u ? 1 : 0;
+    }
+    __syncthreads();
 }
 
 // Segments longer than the tile kernel takes, up to LMAX rows: one block per
@@ -681,7 +682,8 @@ template <typename T, int NT, int LM, int LO>
 __global__ void __launch_bounds__(NT) k_tiefix_mid(const T *__restrict__ rows, int words, int from64,
                                                      const uint2 *__restrict__ list,
                                                      const unsigned long long *__restrict__ counters,
-                                                     uint32_t *__restrict__ vals, uint8_t *__restrict__ uniq) {
+                                                     uint32_t *__restrict__ vals, uint8_t *__restrict__ uniq,
+                                                     uint32_t *__restrict__ scratch) {
     (void)from64;
     const int from = key_width(counters) / Bits<T>::B;  // whole words covered by the sort key
     extern __shared__ __align__(16) unsigned char smem[];  // LM keys, then LM indices
@@ -693,8 +695,13 @@ __global__ void __launch_bounds__(NT) k_tiefix_mid(const T *__restrict__ rows, i
     for (uint32_t sgi = blockIdx.x; sgi < count; sgi += gridDim.x) {
         const uint2 seg = list[sgi];
         const int64_t a = seg.x;
-        const int len = static_cast<int>(seg.y);
-        if (len > LM || len <= LO) continue;  // another launch takes it
+        const int64_t len64 = seg.y;
+        if (len64 > LM) {  // the launch of the longest LDS segments also takes the longer ones
+            if (LM == LMAX) sort_large_segment<T>(rows, words, from, a, len64, vals, uniq, scratch);
+            continue;
+        }
+        const int len = static_cast<int>(len64);
+        if (len <= LO) continue;  // another launch takes it
         int P = 1;
         while (P < len) P <<= 1;
         for (int i = threadIdx.x; i < P; i += blockDim.x) {
@@ -892,16 +899,17 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
     const bool k32 = tiefix && key_bits == 32;
     const bool k96 = tiefix && key_bits == 96;
     const bool probe = tiefix && key_bits == 0 && n >= PROBE_MIN_N;
-    hipLaunchKernelGGL(k_dedup_init, dim3(1), dim3(64), 0, s, w.counters, k32 ? 1ull : 0ull, k96 ? 1ull : 0ull,
-                       extra_zero, n_extra);
-    CG_LAUNCHED("dedup_init");
-    if (probe) {
+    DedupInit init{w.counters, k32 ? 1ull : 0ull, k96 ? 1ull : 0ull, extra_zero, n_extra};
+    if (probe) {  // the counters are set before the sample; else by the extraction's block 0
+        hipLaunchKernelGGL(k_dedup_init, dim3(1), dim3(64), 0, s, init);
+        CG_LAUNCHED("dedup_init");
+        init.counters = nullptr;
         hipLaunchKernelGGL((k_key_probe<T>), dim3(1), dim3(1024), 0, s, rows, n, words, w.counters);
         CG_LAUNCHED("dedup_key_probe");
     }
-    // key bits that can be nonzero, in 32-bit planes from the row's start:
-    // the sort runs over the last 32 nplanes - sig bits' complement; with
-    // 32-bit keys chosen on the device the second plane's passes are skipped
+    // the sort key: the row's first sig bits in 32-bit planes, sorted by
+    // its bits that can be nonzero; with 32-bit keys chosen on the device
+    // the second plane's passes are skipped
     const int sig = tiefix ? (k32 ? 32 : (k96 ? 96 : 64)) : lay.ell;
     const int nplanes = (sig + 31) / 32;
     const int bit_lo = ((32 * nplanes - sig) / 8) * 8;
@@ -912,10 +920,10 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
     const size_t xlds = static_cast<size_t>(256) * (words | 1) * sizeof(T);
     if (rhash && xlds <= 65536) {
         hipLaunchKernelGGL((k_extract_hash<T>), dim3(blocks_for(n, 256)), dim3(256), xlds, s, rows, n, words, key32,
-                           pl[0][0], pl[1][0], pl[2][0], w.vals[0], hash_s, rhash);
+                           pl[0][0], pl[1][0], pl[2][0], w.vals[0], hash_s, rhash, init);
     } else {
         hipLaunchKernelGGL((k_extract<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words, key32,
-                           pl[0][0], pl[1][0], pl[2][0], w.vals[0]);
+                           pl[0][0], pl[1][0], pl[2][0], w.vals[0], init);
         if (rhash) {  // rows too wide to stage: hash them in place
             hipLaunchKernelGGL((k_hash_rows<T>), dim3(blocks_for(n, 256, 16384)), dim3(256), 0, s, rows, n, words,
                                hash_s, rhash);
@@ -964,16 +972,13 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
         constexpr int MID_S = 2048;  // segments up to this many rows: 256-thread blocks, 24 KB of LDS each
         const size_t mid_lds_s = static_cast<size_t>(MID_S) * (sizeof(uint64_t) + sizeof(uint32_t));
         hipLaunchKernelGGL((k_tiefix_mid<T, 256, MID_S, 0>), dim3(2048), dim3(256), mid_lds_s, s, rows, words, from,
-                           w.large_list, w.counters, vals, w.uniq);
+                           w.large_list, w.counters, vals, w.uniq, w.scratch);
         CG_LAUNCHED("dedup_tiefix_mid_s");
         const size_t mid_lds = static_cast<size_t>(LMAX) * (sizeof(uint64_t) + sizeof(uint32_t));
         CG_TRY(allow_lds(reinterpret_cast<const void *>(&k_tiefix_mid<T, 1024, LMAX, MID_S>), mid_lds));
         hipLaunchKernelGGL((k_tiefix_mid<T, 1024, LMAX, MID_S>), dim3(1024), dim3(1024), mid_lds, s, rows, words, from,
-                           w.large_list, w.counters, vals, w.uniq);
+                           w.large_list, w.counters, vals, w.uniq, w.scratch);
         CG_LAUNCHED("dedup_tiefix_mid");
-        hipLaunchKernelGGL((k_tiefix_large<T>), dim3(256), dim3(1024), 0, s, rows, words, from, w.large_list,
-                           w.counters, vals, w.uniq, w.scratch);
-        CG_LAUNCHED("dedup_tiefix_large");
     }
     CG_TRY(scan_u8_to_u32(w.uniq, w.cidx, n, nullptr, w.tile_sums, d_ncells, s));
     if (rowbytes % 16 == 0) {

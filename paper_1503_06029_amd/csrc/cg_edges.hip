@@ -156,9 +156,12 @@ __global__ void k_status(const int64_t *total, int64_t cap, int32_t *status) {
 //   E2 P-find    persistent, per cell tile, rows in LDS: cntP[u], P edges
 //                (v - u, k) to the tile's P stash, tile and super-tile totals
 //                of cntP + cntS; cells of long groups to a list (flag BIG)
-//   E3 look-ups  listed cells, one wave each: their counts (and totals)
-//   E4 P-place   per cell tile: offsets, |E| and status (last tile), P edges
-//                from the stash slot by slot; listed cells' P edges after it
+//   E3 look-ups  listed cells of both sides (long S runs, long P groups),
+//                one wave each: their counts, added to their tile totals
+//   E4 P-place   per cell tile: offsets (the super-tile prefix summed in the
+//                block when there are few super-tiles), |E| and status (last
+//                tile), P edges from the stash slot by slot; then the listed
+//                cells' S and P edges by look-up
 //   E5 P-fix     tiles whose P stash overflowed: rescan and write
 //   E6 S-place   stashed S edges to next(u) - cntS[u] + rank (blocks whose
 //                stash overflowed run the S pass again in write mode)
@@ -169,16 +172,27 @@ constexpr uint32_t BIG = 0x80000000u;
 constexpr int SUP = 64;              // tiles per super-tile
 
 // Output offset of a cell tile: the exclusive prefix of the super-tile
-// totals (k_sup_scan) at its super-tile plus the totals of the tiles before
-// it in that super-tile.  Block-wide over 256 threads, contains barriers.
+// totals at its super-tile plus the totals of the tiles before it in that
+// super-tile.  With raw_sup the super-tile totals are not scanned (at most
+// SUP_INLINE of them) and the block sums those before its own; else they
+// hold their exclusive prefix (k_sup_scan).  Block-wide over 256 threads,
+// contains barriers.
+constexpr int SUP_INLINE = 1024;
 __device__ __forceinline__ uint64_t tile_offset(int64_t tile, const uint64_t *__restrict__ tile_tot,
-                                                const uint64_t *__restrict__ sup_pre, uint64_t *tmp) {
+                                                const uint64_t *__restrict__ sup, bool raw_sup, uint64_t *tmp) {
     const int64_t sidx = tile / SUP;
     const int64_t k2 = sidx * SUP + threadIdx.x;
-    const uint64_t part = (static_cast<int>(threadIdx.x) < SUP && k2 < tile) ? tile_tot[k2] : 0;
+    uint64_t part = (static_cast<int>(threadIdx.x) < SUP && k2 < tile) ? tile_tot[k2] : 0;
+    if (raw_sup) {  // the super-tiles before this one join the same block sum
+#pragma unroll
+        for (int k = 0; k < SUP_INLINE / 256; ++k) {
+            const int64_t j = threadIdx.x + 256 * k;
+            if (j < sidx) part += sup[j];
+        }
+    }
     uint64_t tot;
     block256_excl_scan_u64(part, tmp, &tot);
-    return sup_pre[sidx] + tot;
+    return (raw_sup ? 0 : sup[sidx]) + tot;
 }
 
 
@@ -434,11 +448,8 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
 }
 
 // Cells whose group (P) or run (S) is too long to scan are listed by the
-// scanning kernels and handled here, one wave per cell, lanes over the bits
-// (wave_flip_lookups): MODE 0 counts S-neighbours (k < s) into cntS, MODE 1
-// counts P-neighbours (k >= s) into cntP (flagged BIG) and the cell's tile
-// total, MODE 2 and 3 write the S and P edges at their slots.
-enum { BIG_S_COUNT = 0, BIG_P_COUNT = 1, BIG_S_WRITE = 2, BIG_P_WRITE = 3 };
+// scanning kernels and handled by k_big_lookup, one wave per cell, lanes
+// over the bits (wave_flip_lookups).
 
 // One block: exclusive prefix of the super-tile totals, in place.
 __global__ void __launch_bounds__(256) k_sup_scan(uint64_t *sup_tot, int64_t nsup) {
@@ -454,32 +465,39 @@ __global__ void __launch_bounds__(256) k_sup_scan(uint64_t *sup_tot, int64_t nsu
     }
 }
 
-template <typename T, int MODE>
+// Listed cells of both sides in one launch: items [0, nS) are S-listed
+// cells (k < s), then the P-listed ones (k >= s), one wave each.  Count
+// (WRITE = false): cntS[u] or cntP[u] (flagged BIG), and the count is added
+// to the cell's tile and super-tile totals (k_p_find has already written
+// those, counting these cells as 0).  Write: the edges at their slots.
+template <typename T, bool WRITE>
 __global__ void __launch_bounds__(256) k_big_lookup(const T *__restrict__ cells, const uint32_t *__restrict__ dir,
                                                     int p, int words, int ell, int s,
-                                                    const uint32_t *__restrict__ list,
-                                                    const unsigned long long *__restrict__ list_n, int64_t list_cap,
+                                                    const uint32_t *__restrict__ s_list,
+                                                    const uint32_t *__restrict__ p_list,
+                                                    const unsigned long long *__restrict__ big_n, int64_t list_cap,
                                                     uint32_t *__restrict__ cntS, uint32_t *__restrict__ cntP,
                                                     uint64_t *__restrict__ tile_tot, uint64_t *__restrict__ sup_tot,
                                                     const int64_t *__restrict__ offsets,
                                                     const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
                                                     uint16_t *__restrict__ bit, int64_t cap) {
-    int64_t cnt = static_cast<int64_t>(*list_n);
-    if (cnt > list_cap) cnt = list_cap;
+    int64_t ns = static_cast<int64_t>(big_n[0]), np = static_cast<int64_t>(big_n[1]);
+    if (ns > list_cap) ns = list_cap;
+    if (np > list_cap) np = list_cap;
     const int lane = threadIdx.x & 63;
     const int64_t nw = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
-    constexpr bool S_SIDE = MODE == BIG_S_COUNT || MODE == BIG_S_WRITE;
-    const int khi = S_SIDE ? s - 1 : ell - 1, klo = S_SIDE ? 0 : s;
-    for (int64_t it = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); it < cnt;
+    for (int64_t it = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); it < ns + np;
          it += nw) {
-        const uint32_t u = list[it];
+        const bool sside = it < ns;  // the same for the whole wave
+        const uint32_t u = sside ? s_list[it] : p_list[it - ns];
         const T *q = cells + static_cast<int64_t>(u) * words;
+        const int khi = sside ? s - 1 : ell - 1, klo = sside ? 0 : s;
         // a P-neighbour (k >= s) follows u inside u's prefix group: search
         // [u + 1, end of the group) only (the end found once per cell by a
         // galloping search over the first s bits; dir's last entry is the
         // cell count)
         int64_t lo_b = 0, hi_b = INT64_MAX;
-        if (!S_SIDE) {
+        if (!sside) {
             const int64_t n = dir[static_cast<int64_t>(1) << p];
             int64_t good = u, bad = static_cast<int64_t>(u) + 1, step = 1;
             while (bad < n && same_prefix<T>(cells + bad * words, q, s)) {
@@ -495,23 +513,18 @@ __global__ void __launch_bounds__(256) k_big_lookup(const T *__restrict__ cells,
             lo_b = static_cast<int64_t>(u) + 1;
             hi_b = bad;
         }
-        if (MODE == BIG_S_COUNT || MODE == BIG_P_COUNT) {
+        if (!WRITE) {
             const uint32_t c = wave_flip_lookups<T>(cells, words, dir, p, q, khi, klo, [](uint32_t, int, uint32_t) {},
                                                     lo_b, hi_b);
             if (lane == 0) {
-                if (MODE == BIG_S_COUNT) {
-                    cntS[u] = c;
-                } else {
-                    cntP[u] = BIG | c;
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&tile_tot[u / PT]),
-                              static_cast<unsigned long long>(c));
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&sup_tot[(u / PT) / SUP]),
-                              static_cast<unsigned long long>(c));
-                }
+                if (sside) cntS[u] = c; else cntP[u] = BIG | c;
+                atomicAdd(reinterpret_cast<unsigned long long *>(&tile_tot[u / PT]), static_cast<unsigned long long>(c));
+                atomicAdd(reinterpret_cast<unsigned long long *>(&sup_tot[(u / PT) / SUP]),
+                          static_cast<unsigned long long>(c));
             }
         } else {
             int64_t base;
-            if (MODE == BIG_S_WRITE) {
+            if (sside) {
                 const uint32_t ct = cntS[u];
                 base = (offsets ? offsets[static_cast<int64_t>(u) + 1] : offnext[u]) - ct;
             } else {
@@ -1007,10 +1020,10 @@ __global__ void __launch_bounds__(PT) k_p_place(const int64_t *d_n, int64_t ncap
                                                 const uint32_t *__restrict__ stash,
                                                 const uint32_t *__restrict__ stash_n,
                                                 const uint64_t *__restrict__ tile_tot,
-                                                const uint64_t *__restrict__ sup_tot, int64_t *__restrict__ offsets,
-                                                int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
-                                                uint16_t *__restrict__ bit, int64_t cap, int64_t *__restrict__ d_nedges,
-                                                int32_t *__restrict__ status) {
+                                                const uint64_t *__restrict__ sup_tot, bool raw_sup,
+                                                int64_t *__restrict__ offsets, int64_t *__restrict__ offnext,
+                                                uint32_t *__restrict__ uv, uint16_t *__restrict__ bit, int64_t cap,
+                                                int64_t *__restrict__ d_nedges, int32_t *__restrict__ status) {
     __shared__ uint64_t tmp[4];
     __shared__ uint32_t sx[PT];   // tile-relative first slot of each cell
     __shared__ uint32_t ssb[PT];  // first stash entry of each cell
@@ -1027,7 +1040,7 @@ __global__ void __launch_bounds__(PT) k_p_place(const int64_t *d_n, int64_t ncap
         cp = cntP[i];
         cs = cntS[i];
     }
-    const uint64_t t_off = tile_offset(tile, tile_tot, sup_tot, tmp);
+    const uint64_t t_off = tile_offset(tile, tile_tot, sup_tot, raw_sup, tmp);
     // each wave's 64 cells own one region of WST stash entries (k_p_find)
     bool ovf = false;
 #pragma unroll
@@ -1079,8 +1092,8 @@ __global__ void __launch_bounds__(PT) k_p_fix(const T *__restrict__ cells, const
                                               const uint32_t *__restrict__ fix_list,
                                               const unsigned long long *__restrict__ fix_n,
                                               const uint64_t *__restrict__ tile_tot,
-                                              const uint64_t *__restrict__ sup_tot, uint32_t *__restrict__ uv,
-                                              uint16_t *__restrict__ bit, int64_t cap) {
+                                              const uint64_t *__restrict__ sup_tot, bool raw_sup,
+                                              uint32_t *__restrict__ uv, uint16_t *__restrict__ bit, int64_t cap) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint64_t tmp[4];
     __shared__ int s_th;
@@ -1107,7 +1120,7 @@ __global__ void __launch_bounds__(PT) k_p_fix(const T *__restrict__ cells, const
         }
         uint64_t tot;
         const uint64_t exa = block256_excl_scan_u64(static_cast<uint64_t>(cp & ~BIG) + cs, tmp, &tot);
-        const uint64_t t_off = tile_offset(tile, tile_tot, sup_tot, tmp);
+        const uint64_t t_off = tile_offset(tile, tile_tot, sup_tot, raw_sup, tmp);
         if (t < tr && !(cp & BIG) && cp != 0) {
             const int64_t out0 = static_cast<int64_t>(t_off + exa);
             p_scan_t<T, WT>(rows, pcs, heads, tr + th, t, i, base, n, cells, words, s, gmax,
@@ -1206,9 +1219,6 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
         hipLaunchKernelGGL((k_s_scan<T, false>), sgrid, dim3(PT), 0, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
                            rmax, w.cntS, no_off, no_off, uv, bit, cap, w.s_big, w.big_n, w.s_stash, w.s_stash_n);
         CG_LAUNCHED("edges_s_count");
-        hipLaunchKernelGGL((k_big_lookup<T, BIG_S_COUNT>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
-                           w.s_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, no_off, no_off, uv, bit, cap);
-        CG_LAUNCHED("edges_s_big_count");
     }
     if (words == WT) {
         const unsigned pblocks =
@@ -1224,28 +1234,34 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
                            w.p_big, w.big_n + 1, w.p_fix, w.big_n + 2);
     }
     CG_LAUNCHED("edges_p_find");
-    hipLaunchKernelGGL((k_big_lookup<T, BIG_P_COUNT>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
-                       w.p_big, w.big_n + 1, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, no_off, no_off, uv, bit, cap);
-    hipLaunchKernelGGL(k_sup_scan, dim3(1), dim3(256), 0, s, w.sup_tot, w.nsup);
-    CG_LAUNCHED("edges_sup_scan");
-    CG_LAUNCHED("edges_p_big_count");
+    // listed cells of both sides: their counts, added to their tile totals
+    hipLaunchKernelGGL((k_big_lookup<T, false>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp, w.s_big,
+                       w.p_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, no_off, no_off, uv, bit, cap);
+    CG_LAUNCHED("edges_big_count");
+    // up to SUP_INLINE super-tiles each placement block sums those before
+    // its own; more are scanned first
+    const bool raw_sup = w.nsup <= SUP_INLINE;
+    if (!raw_sup) {
+        hipLaunchKernelGGL(k_sup_scan, dim3(1), dim3(256), 0, s, w.sup_tot, w.nsup);
+        CG_LAUNCHED("edges_sup_scan");
+    }
     hipLaunchKernelGGL((k_p_place<T>), grid, dim3(PT), 0, s, d.d_ncells, ncap, w.cntS, w.cntP, w.p_stash,
-                       w.p_stash_n, w.tile_tot, w.sup_tot, d_offsets, offnext, uv, bit, cap, d_nedges, d_status);
+                       w.p_stash_n, w.tile_tot, w.sup_tot, raw_sup, d_offsets, offnext, uv, bit, cap, d_nedges,
+                       d_status);
     CG_LAUNCHED("edges_p_place");
-    hipLaunchKernelGGL((k_big_lookup<T, BIG_P_WRITE>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
-                       w.p_big, w.big_n + 1, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, d_offsets, offnext, uv, bit, cap);
-    CG_LAUNCHED("edges_p_big_write");
+    hipLaunchKernelGGL((k_big_lookup<T, true>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp, w.s_big,
+                       w.p_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, d_offsets, offnext, uv, bit,
+                       cap);
+    CG_LAUNCHED("edges_big_write");
     const int gm = gmax < PSCAN ? gmax : PSCAN;  // same scan limit as k_p_find
     hipLaunchKernelGGL((k_p_fix<T, WT>), dim3(blocks_for(ntiles, 1, 64)), dim3(PT), lds, s, cells, d.d_ncells, ncap,
-                       words, sp, gm, w.cntS, w.cntP, w.p_fix, w.big_n + 2, w.tile_tot, w.sup_tot, uv, bit, cap);
+                       words, sp, gm, w.cntS, w.cntP, w.p_fix, w.big_n + 2, w.tile_tot, w.sup_tot, raw_sup, uv, bit,
+                       cap);
     CG_LAUNCHED("edges_p_fix");
     if (sp > 0) {
         hipLaunchKernelGGL((k_s_scan<T, true>), sgrid, dim3(PT), 0, s, cells, d.sfx, d.d_ncells, ncap, words, sp,
                            rmax, w.cntS, d_offsets, offnext, uv, bit, cap, w.s_big, w.big_n, w.s_stash, w.s_stash_n);
         CG_LAUNCHED("edges_s_write_place");
-        hipLaunchKernelGGL((k_big_lookup<T, BIG_S_WRITE>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp,
-                           w.s_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, d_offsets, offnext, uv, bit, cap);
-        CG_LAUNCHED("edges_s_big_write");
     }
     return CG_OK;
 }
