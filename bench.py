@@ -472,9 +472,12 @@ def bench_served(args):
         "config": {"workload": f"Poisson 2000/s for {args.seconds} s over {len(pool)} scenes "
                                "(l 16..512, 1e3..2e5 points)", "requests": int(len(t)), "rows": int(rows)},
         "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        # past the first second: every scene has been seen (resident dictionaries built)
+        "p99_after_1s_ms": float(np.percentile(lat[t >= 1.0], 99) * 1e3),
         "resident": pool_stats,
         "no_resident": {"requests_per_s": len(t) / wall0, "p50_ms": float(np.percentile(lat0, 50) * 1e3),
-                        "p99_ms": float(np.percentile(lat0, 99) * 1e3)},
+                        "p99_ms": float(np.percentile(lat0, 99) * 1e3),
+                        "p99_after_1s_ms": float(np.percentile(lat0[t >= 1.0], 99) * 1e3)},
         "baseline": {"requests_per_s": len(t) / bwall, "p50_ms": float(np.percentile(blat, 50) * 1e3),
                      "p99_ms": float(np.percentile(blat, 99) * 1e3)},
     }
