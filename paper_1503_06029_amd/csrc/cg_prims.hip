@@ -415,6 +415,9 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix32_hist(const uint32_t *key
     hist[static_cast<int64_t>(t) * num_tiles + tile] = h[t];
 }
 
+// NP: how many payload planes besides the values the launch may carry (the
+// LDS staging is sized for them).
+template <int NP>
 __global__ void __launch_bounds__(RS_THREADS) k_radix32_scatter(const uint32_t *kin, const uint32_t *v0in,
                                                                 const uint32_t *v1in, const uint32_t *v2in,
                                                                 uint32_t *kout, uint32_t *v0out, uint32_t *v1out,
@@ -429,16 +432,16 @@ __global__ void __launch_bounds__(RS_THREADS) k_radix32_scatter(const uint32_t *
     __shared__ uint32_t gbase[RADIX];
     __shared__ uint32_t sk[RS_TILE];
     __shared__ uint32_t sv0[RS_TILE];
-    __shared__ uint32_t sv1[RS_TILE];
-    __shared__ uint32_t sv2[RS_TILE];
+    __shared__ uint32_t sv1[NP >= 1 ? RS_TILE : 1];
+    __shared__ uint32_t sv2[NP >= 2 ? RS_TILE : 1];
     __shared__ uint64_t tmp[4];
 
     const int64_t n = load_n(d_n, n_cap);
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t base = static_cast<int64_t>(tile) * RS_TILE;
     if (base >= n) return;
-    const bool has1 = v1in != nullptr && !(drop_v1 && *drop_v1);
-    const bool has2 = v2in != nullptr;
+    const bool has1 = NP >= 1 && v1in != nullptr && !(drop_v1 && *drop_v1);
+    const bool has2 = NP >= 2 && v2in != nullptr;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int tile_n = static_cast<int>(n - base < RS_TILE ? n - base : RS_TILE);
 
@@ -633,9 +636,15 @@ cg_status radix_sort_k32(uint32_t *planes[3][2], int nplanes, uint32_t *vals[2],
         CG_LAUNCHED("radix32_hist");
         hipLaunchKernelGGL(k_radix_dscan, dim3(RADIX), dim3(RS_THREADS), 0, s, hist, num_tiles, dtot, sk);
         CG_LAUNCHED("radix32_dscan");
-        hipLaunchKernelGGL(k_radix32_scatter, dim3(num_tiles), dim3(RS_THREADS), 0, s, planes[q][cur], vals[cur],
-                           o1[cur], o2[cur], planes[q][cur ^ 1], vals[cur ^ 1], o1[cur ^ 1], o2[cur ^ 1], n_cap, d_n,
-                           bit & 31, hist, dtot, num_tiles, sk, drop);
+        const int np = o2 != none ? 2 : (o1 != none ? 1 : 0);
+#define CG_SCATTER32(NPV)                                                                                          \
+    hipLaunchKernelGGL((k_radix32_scatter<NPV>), dim3(num_tiles), dim3(RS_THREADS), 0, s, planes[q][cur], vals[cur], \
+                       o1[cur], o2[cur], planes[q][cur ^ 1], vals[cur ^ 1], o1[cur ^ 1], o2[cur ^ 1], n_cap, d_n,    \
+                       bit & 31, hist, dtot, num_tiles, sk, drop)
+        if (np == 2) CG_SCATTER32(2);
+        else if (np == 1) CG_SCATTER32(1);
+        else CG_SCATTER32(0);
+#undef CG_SCATTER32
         CG_LAUNCHED("radix32_scatter");
         cur ^= 1;
     }

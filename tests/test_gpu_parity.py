@@ -403,6 +403,33 @@ def test_stash_overflow_past_first_supertile(gpu):
         assert_same(res, oracle_graph(R, ell, wb))
 
 
+def test_many_super_tiles(gpu):
+    """More than 1,024 super-tiles of capacity (over 16.7M rows): the
+    super-tile totals are scanned by their own launch instead of inside each
+    placement block.  2^12 cells, each row repeated 4,200 times, packed as
+    words: cells are 0 .. 4095 and the edges those of the 12-cube."""
+    torch, B, P = gpu
+    ell, reps = 12, 4200
+    n = (2 ** ell) * reps
+    words = np.tile(np.arange(2 ** ell, dtype=np.uint32) << np.uint32(32 - ell), reps)
+    words = words[np.random.default_rng(12).permutation(n)].reshape(n, 1)
+    say("many super-tiles", n)
+    res = P.cell_graph(words, ell, 32, packed=True)
+    assert res["ncells"] == 2 ** ell
+    cells = (res["cells"][:, 0] >> np.uint32(32 - ell)).astype(np.int64)
+    assert np.array_equal(cells, np.arange(2 ** ell))
+    assert np.array_equal(res["row_to_cell"], (words[:, 0] >> np.uint32(32 - ell)).astype(np.uint32))
+    uv = res["uv"].astype(np.int64)
+    assert res["nedges"] == ell * 2 ** (ell - 1)
+    x = uv[:, 0] ^ uv[:, 1]
+    assert np.all(uv[:, 0] < uv[:, 1]) and np.all((x & (x - 1)) == 0)
+    assert np.all(res["bit"] == ell - 1 - np.log2(x).astype(np.int64))
+    order = np.lexsort((uv[:, 1], uv[:, 0]))
+    assert np.array_equal(order, np.arange(len(uv)))
+    deg = np.bincount(uv[:, 0], minlength=2 ** ell)
+    assert np.array_equal(res["offsets"], np.concatenate([[0], np.cumsum(deg)]))
+
+
 def _tie_segments(rng, ell, lens, dup_frac=0.1):
     """Rows in segments that share their first 64 bits.  The first row of
     each segment (placed before the rest, so a stable key sort keeps it
