@@ -139,7 +139,6 @@ def _shared_head(rng, n, ell, head_bits):
     return R
 
 
-@pytest.mark.parametrize("key_bits", [32, 64])
 def _grouped_tails(rng, groups, per, ell, head_bits, tail_from):
     """groups x per rows: all share their first head_bits bits; a group's rows
     share bits up to tail_from and differ only after it (plus duplicates), so
