@@ -354,6 +354,19 @@ __global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, 
 // compared (both differ from the head in more than LV words and agree on the
 // first LV of them).  A row's rank in its segment (ties broken by position)
 // is its sorted position; it is a duplicate iff an equal row precedes it.
+// Bits [at, at + nb) of a 192-bit string held most significant first in
+// k[0..2] take the nb low bits of v (v < 2^nb; nb <= 64).
+__device__ __forceinline__ void put_bits(uint64_t (&k)[3], int at, uint64_t v, int nb) {
+    const int w = at >> 6, room = 64 - (at & 63);  // bits left in word w
+    if (nb <= room) {
+        k[w] |= v << (room - nb);
+    } else {
+        const int rest = nb - room;  // bits that spill into word w + 1
+        k[w] |= v >> rest;
+        k[w + 1] |= v << (64 - rest);
+    }
+}
+
 constexpr int WSMAX = 128;           // longest segment sorted here
 constexpr int WSLOTS = TT + WSMAX;   // window: the tile and the longest segment reaching past it
 
@@ -366,16 +379,29 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, Key
     constexpr int NCH = 2 * TT / 64;       // 64-slot chunks of start flags
     constexpr uint32_t GMASK = (WT >= 32) ? 0xFFFFFFFFu : ((1u << WT) - 1u);
     constexpr int RPS = TT / WT;           // rows per TT consecutive elements
-    __shared__ uint64_t skeys[WSLOTS + 1];  // positions b0 - 1 .. b0 + WSLOTS - 1
-    __shared__ uint32_t skx[WSLOTS + 1];    // their third planes (96-bit keys)
     __shared__ uint32_t sval[WSLOTS];
     __shared__ int16_t segof[WSLOTS];       // slot of the row's head, -1 if not sorted here
     __shared__ int16_t seglen[WSLOTS];
     // summary levels per row: 32-bit words keep four for the LDS two 64-bit
     // words take (rows of 32-bit words tend to share more leading words)
     constexpr int LV = sizeof(T) == 4 ? 4 : 2;
-    __shared__ uint8_t scode[LV * WSLOTS];  // per row and level: code (| flag on the last level)
-    __shared__ T sv[LV * WSLOTS];           // per row and level: the row's word there
+    // One pool, used twice: first the window's keys (positions b0 - 1 ..
+    // b0 + WSLOTS - 1, with their third planes for 96-bit keys) and the
+    // summary levels (per row and level: the code, | flag on the last level,
+    // and the row's word there); then each row's summary packed into three
+    // 64-bit words for the ranking.
+    constexpr size_t P_KEYS = (WSLOTS + 1) * sizeof(uint64_t);
+    constexpr size_t P_SV = P_KEYS;
+    constexpr size_t P_SKX = P_SV + LV * WSLOTS * sizeof(T);
+    constexpr size_t P_SCODE = P_SKX + (WSLOTS + 1) * sizeof(uint32_t);
+    constexpr size_t P_END = P_SCODE + LV * WSLOTS;
+    constexpr size_t P_PACKED = 3 * WSLOTS * sizeof(uint64_t);
+    __shared__ __align__(16) unsigned char pool[P_END > P_PACKED ? P_END : P_PACKED];
+    uint64_t *skeys = reinterpret_cast<uint64_t *>(pool);
+    T *sv = reinterpret_cast<T *>(pool + P_SV);
+    uint32_t *skx = reinterpret_cast<uint32_t *>(pool + P_SKX);
+    uint8_t *scode = pool + P_SCODE;
+    uint64_t *pk = reinterpret_cast<uint64_t *>(pool);  // pk[3 r .. 3 r + 2]: row r's packed summary
     __shared__ unsigned long long smask[NCH];
     __shared__ int tail_end;                // one past the last row past the tile sorted here
     if (key_width(counters) != KB) return;
@@ -527,52 +553,70 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, Key
         }
     }
     __syncthreads();
-    for (int r = t; r < WSLOTS; r += TT) {
-        const int a = segof[r];
-        if (a < 0) continue;
-        const int len = seglen[r];
-        int cm[LV];
-        T vm[LV];
+    // Each row's summary as one 192-bit string, most significant first: per
+    // level the 7-bit code then the word (so strings order as the summaries
+    // do), the flag in the last bit.  Written over the pool once every row's
+    // levels are read.
+    uint64_t kp[2][3];
 #pragma unroll
-        for (int c = 0; c < LV; ++c) {
-            cm[c] = scode[LV * r + c] & 0x7f;
-            vm[c] = sv[LV * r + c];
-        }
-        const bool fm = (scode[LV * r + LV - 1] & 0x80) != 0;
-        // lexicographic over the levels: (code, word) pairs
-        auto cmp_levels = [&](int j, bool &lt, bool &eq, bool &fj) {
-            lt = false;
-            eq = true;
+    for (int h = 0; h < 2; ++h) {
+        const int r = t + h * TT;
+        kp[h][0] = kp[h][1] = kp[h][2] = 0;
+        if (r < WSLOTS && segof[r] >= 0) {
 #pragma unroll
             for (int c = 0; c < LV; ++c) {
-                const int cf = scode[LV * j + c];
-                const int cj = cf & 0x7f;
-                const T vj = sv[LV * j + c];
-                const bool e = (cj == cm[c]) & (vj == vm[c]);
-                lt = lt | (eq & ((cj < cm[c]) | ((cj == cm[c]) & (vj < vm[c]))));
-                eq = eq & e;
-                if (c == LV - 1) fj = (cf & 0x80) != 0;
+                constexpr int B = Bits<T>::B;
+                put_bits(kp[h], c * (7 + B), scode[LV * r + c] & 0x7f, 7);
+                put_bits(kp[h], c * (7 + B) + 7, static_cast<uint64_t>(sv[LV * r + c]), B);
             }
-        };
+            kp[h][2] |= (scode[LV * r + LV - 1] & 0x80) ? 1ull : 0ull;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = t + h * TT;
+        if (r < WSLOTS && segof[r] >= 0) {
+            pk[3 * r] = kp[h][0];
+            pk[3 * r + 1] = kp[h][1];
+            pk[3 * r + 2] = kp[h][2];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = t + h * TT;
+        const int a = r < WSLOTS ? segof[r] : -1;
+        if (a < 0) continue;
+        const int len = seglen[r];
+        const uint64_t m0 = kp[h][0], m1 = kp[h][1], m2 = kp[h][2] | 1ull;
+        const uint64_t fm = kp[h][2] & 1ull;
         int rank = 0;
         bool dup = false, anytie = false;
+        // the flag bit is set on both sides, so it takes no part in the
+        // order; j's string is below r's iff the 192-bit subtraction borrows
 #pragma unroll 2
         for (int j = a; j < a + len; ++j) {
-            bool lt, eq, fj;
-            cmp_levels(j, lt, eq, fj);
-            const bool same = eq & fm & fj;
-            const bool before = j < r;
-            rank += (lt | (same & before)) ? 1 : 0;
-            dup = dup | (same & before);
+            const uint64_t j0 = pk[3 * j], j1 = pk[3 * j + 1], j2r = pk[3 * j + 2];
+            const uint64_t j2 = j2r | 1ull;
+            unsigned long long bw;
+            (void)__builtin_subcll(j2, m2, 0ull, &bw);
+            (void)__builtin_subcll(j1, m1, bw, &bw);
+            (void)__builtin_subcll(j0, m0, bw, &bw);
+            const bool eq = ((j0 ^ m0) | (j1 ^ m1) | (j2 ^ m2)) == 0;
+            const bool same = eq & ((j2r & fm) != 0);
+            const bool sb = same & (j < r);
+            rank += static_cast<int>(bw) + (sb ? 1 : 0);
+            dup = dup | sb;
             anytie = anytie | (eq & !same & (j != r));
         }
         if (anytie) {
             // rows with equal summaries that may differ: compare them in full
             const T *me = rows + static_cast<int64_t>(sval[r]) * words;
             for (int j = a; j < a + len; ++j) {
-                bool lt, eq, fj;
-                cmp_levels(j, lt, eq, fj);
-                if (!eq || j == r || (fm && fj)) continue;
+                const uint64_t j2r = pk[3 * j + 2];
+                const bool eq = pk[3 * j] == m0 && pk[3 * j + 1] == m1 && (j2r | 1ull) == m2;
+                if (!eq || j == r || (j2r & fm)) continue;
                 const int c = row_cmp4<T>(rows + static_cast<int64_t>(sval[j]) * words, me, words, FROM);
                 rank += (c < 0 || (c == 0 && j < r)) ? 1 : 0;
                 dup = dup || (c == 0 && j < r);
