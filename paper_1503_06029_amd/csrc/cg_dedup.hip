@@ -862,7 +862,11 @@ __global__ void __launch_bounds__(256) k_gather(const V *__restrict__ rows, int6
             if (sfx) {
                 if (hash_lanes > 0) {
                     uint64_t t = uu[q] ? piece_terms<T, V>(v[q], wp[q], hash_s) : 0ull;
-                    for (int d = 1; d < hash_lanes; d <<= 1) t += shfl_u64_xor(t, d);
+                    if constexpr (PL >= 0) {
+                        t = group_sum_u64<(1 << (PL >= 0 ? PL : 0))>(t);  // hash_lanes == 1 << PL
+                    } else {
+                        for (int d = 1; d < hash_lanes; d <<= 1) t += shfl_u64_xor(t, d);
+                    }
                     if (uu[q] && wp[q] == 0) sfx[cid[q]] = (static_cast<uint64_t>(suffix_finish(t)) << 32) | cid[q];
                 } else if (uu[q] && wp[q] == 0) {
                     sfx[cid[q]] = (static_cast<uint64_t>(rhash[src[q]]) << 32) | cid[q];

@@ -93,6 +93,28 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
     x += CG_DPP(x, 0x143, 0xc);  // row_bcast:31 into rows 2 and 3
     return x;
 }
+// Sum over each aligned group of G lanes (G a power of two up to 64), in
+// every lane of the group: quad permutes for pairs and quads, the
+// half-row and row mirrors for 8 and 16 lanes (after the smaller sums a
+// lane's mirror holds the other half's sum), lane shuffles beyond.
+template <int G>
+__device__ __forceinline__ uint64_t group_sum_u64(uint64_t x) {
+    static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "group of a power of two lanes");
+    uint32_t lo = static_cast<uint32_t>(x), hi = static_cast<uint32_t>(x >> 32);
+    auto add = [&](uint32_t ylo, uint32_t yhi) {
+        const uint64_t r = ((static_cast<uint64_t>(hi) << 32) | lo) + ((static_cast<uint64_t>(yhi) << 32) | ylo);
+        lo = static_cast<uint32_t>(r);
+        hi = static_cast<uint32_t>(r >> 32);
+    };
+    if constexpr (G >= 2) add(CG_DPP(lo, 0xB1, 0xf), CG_DPP(hi, 0xB1, 0xf));    // quad_perm 1,0,3,2
+    if constexpr (G >= 4) add(CG_DPP(lo, 0x4E, 0xf), CG_DPP(hi, 0x4E, 0xf));    // quad_perm 2,3,0,1
+    if constexpr (G >= 8) add(CG_DPP(lo, 0x141, 0xf), CG_DPP(hi, 0x141, 0xf));  // row_half_mirror
+    if constexpr (G >= 16) add(CG_DPP(lo, 0x140, 0xf), CG_DPP(hi, 0x140, 0xf)); // row_mirror
+    uint64_t r = (static_cast<uint64_t>(hi) << 32) | lo;
+    if constexpr (G >= 32) r += shfl_u64_xor(r, 16);
+    if constexpr (G >= 64) r += shfl_u64_xor(r, 32);
+    return r;
+}
 __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
     uint32_t lo = static_cast<uint32_t>(x), hi = static_cast<uint32_t>(x >> 32);
     auto step = [&](uint32_t ylo, uint32_t yhi) {
