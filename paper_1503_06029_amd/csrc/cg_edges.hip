@@ -371,9 +371,15 @@ __global__ void __launch_bounds__(PT) k_s_scan(const T *__restrict__ cells, cons
             d += popc<T>(x);
             first = (x && first == 0x7fffffff) ? w * B + clz_t<T>(x) : first;
         }
-        for (int m = sg / 2; m > 0; m >>= 1) {
-            d += __shfl_xor(d, m, 64);
-            const int o = __shfl_xor(first, m, 64);
+        // the sg lanes of a pair are one aligned pair or quad: quad permutes
+        if (sg == 4) {
+            d += static_cast<int>(quad_xor2(static_cast<uint32_t>(d)));
+            const int o = static_cast<int>(quad_xor2(static_cast<uint32_t>(first)));
+            first = o < first ? o : first;
+        }
+        {
+            d += static_cast<int>(quad_xor1(static_cast<uint32_t>(d)));
+            const int o = static_cast<int>(quad_xor1(static_cast<uint32_t>(first)));
             first = o < first ? o : first;
         }
         *li_out = lo;
@@ -711,16 +717,12 @@ template <typename T, int WT> struct PFind {
 template <typename T, int WT>
 __device__ __forceinline__ int dist_lds(const T *a, const T *b, int *pos) {
     constexpr int B = Bits<T>::B;
-    constexpr int C = WT < 4 ? WT : 4;  // words per step: few registers live at once
     int d = 0, wi = 0;
-#pragma unroll 1
-    for (int w0 = 0; w0 < WT; w0 += C) {
 #pragma unroll
-        for (int u = 0; u < C; ++u) {
-            const T x = a[w0 + u] ^ b[w0 + u];
-            d += popc<T>(x);
-            wi = x ? w0 + u : wi;
-        }
+    for (int w = 0; w < WT; ++w) {  // unrolled: the LDS loads issue together
+        const T x = a[w] ^ b[w];
+        d += popc<T>(x);
+        wi = x ? w : wi;
     }
     const T x = a[wi] ^ b[wi];
     *pos = wi * B + clz_t<T>(x | T(1));

@@ -93,6 +93,11 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
     x += CG_DPP(x, 0x143, 0xc);  // row_bcast:31 into rows 2 and 3
     return x;
 }
+// The value of the lane one (xor 1) or two (xor 2) places away within the
+// lane's quad of four.
+__device__ __forceinline__ uint32_t quad_xor1(uint32_t x) { return CG_DPP(x, 0xB1, 0xf); }  // quad_perm 1,0,3,2
+__device__ __forceinline__ uint32_t quad_xor2(uint32_t x) { return CG_DPP(x, 0x4E, 0xf); }  // quad_perm 2,3,0,1
+
 // Sum over each aligned group of G lanes (G a power of two up to 64), in
 // every lane of the group: quad permutes for pairs and quads, the
 // half-row and row mirrors for 8 and 16 lanes (after the smaller sums a
@@ -106,8 +111,8 @@ __device__ __forceinline__ uint64_t group_sum_u64(uint64_t x) {
         lo = static_cast<uint32_t>(r);
         hi = static_cast<uint32_t>(r >> 32);
     };
-    if constexpr (G >= 2) add(CG_DPP(lo, 0xB1, 0xf), CG_DPP(hi, 0xB1, 0xf));    // quad_perm 1,0,3,2
-    if constexpr (G >= 4) add(CG_DPP(lo, 0x4E, 0xf), CG_DPP(hi, 0x4E, 0xf));    // quad_perm 2,3,0,1
+    if constexpr (G >= 2) add(quad_xor1(lo), quad_xor1(hi));
+    if constexpr (G >= 4) add(quad_xor2(lo), quad_xor2(hi));
     if constexpr (G >= 8) add(CG_DPP(lo, 0x141, 0xf), CG_DPP(hi, 0x141, 0xf));  // row_half_mirror
     if constexpr (G >= 16) add(CG_DPP(lo, 0x140, 0xf), CG_DPP(hi, 0x140, 0xf)); // row_mirror
     uint64_t r = (static_cast<uint64_t>(hi) << 32) | lo;
