@@ -67,7 +67,11 @@ def assert_same_build(a, b):
 
 CASES = [("l20", 20, 200, 4, 100, 32), ("l40", 40, 300, 6, 100, 32), ("l64", 64, 300, 6, 100, 64),
          ("l65", 65, 300, 6, 100, 64), ("l130", 130, 700, 10, 700, 64), ("l300", 300, 400, 12, 300, 32),
-         ("l1024", 1024, 300, 15, 500, 64)]
+         ("l1024", 1024, 300, 15, 500, 64),
+         # rows of 4, 16, 32 and 64 16-byte pieces: the gather adds a row's
+         # suffix-hash terms over that many lanes
+         ("l512", 512, 300, 10, 200, 64), ("l2048", 2048, 200, 12, 100, 64),
+         ("l4096", 4096, 100, 8, 60, 64), ("l8192", 8192, 60, 6, 40, 64)]
 
 
 @pytest.mark.parametrize("name,ell,nb,fam,dups,wb", CASES)
