@@ -907,21 +907,51 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
             }
         };
 
-        // lock-step scan over d: alive while row t + d is in the cell's group
-        bool alive = t < tr;
-        bool big = false, spill = false;  // spill: the group runs past the loaded rows
+        // Each cell's run: the loaded rows after it up to the next group head
+        // or the end of the loaded rows (every flag is in a 64-row mask; the
+        // wave's three masks cover rows t + 1 .. t + gm + 1).  A run longer
+        // than gm rows means look-ups (big); a run that stops at the end of
+        // the loaded rows while cells remain is finished in global memory
+        // (spill).  Then a lock-step scan over d up to the longest run.
         const uint32_t pcm1 = (pcs[t] & 0x3fffffffu) - 1u;
+        int run = 0;
+        bool big = false, spill = false;
+        {
+            unsigned long long hm[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int r = (wv + k) * 64 + lane;
+                hm[k] = ballot64(r < PCS && pcs[r] >= HEADF);
+            }
+            const int r1 = lane + 1;  // row t + 1, counted from the wave's first row
+            const unsigned long long a0 = r1 < 64 ? hm[0] & (~0ull << r1) : 0ull;
+            const unsigned long long a1 = r1 < 64 ? hm[1] : hm[1] & (~0ull << (r1 - 64));
+            const int e = a0 ? __ffsll(a0) - 1 : (a1 ? 64 + __ffsll(a1) - 1 : (hm[2] ? 128 + __ffsll(hm[2]) - 1 : 192));
+            const int de = e - lane;  // offset of the first flagged row after t
+            if (t < tr) {
+                if (de <= gm + 1) {
+                    run = de - 1 < gm ? de - 1 : gm;
+                    spill = pcs[t + de] >= PASTF && more;
+                } else {
+                    run = gm;
+                    big = true;
+                }
+            }
+        }
+        int rmax = run;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int v = __shfl_xor(rmax, o, 64);
+            rmax = v > rmax ? v : rmax;
+        }
         uint32_t qh = 0, qt = 0;  // ring head and tail (wave-uniform)
         const uint32_t *pp = pcs + t;
         uint32_t xn = pp[1];  // the next offset's entry is read one step ahead
 #pragma unroll 1
-        for (int d = 1; d <= gm; ++d) {
-            if ((d & 3) == 1 && ballot64(alive) == 0) break;
+        for (int d = 1; d <= rmax; ++d) {
             const uint32_t x = xn;
             xn = pp[d + 1];
-            spill = spill || (alive && x >= PASTF && more);
-            alive = alive && x < HEADF;
-            const bool cand = alive && ((x - pcm1) & ~2u) == 0u;
+            const bool cand = d <= run && ((x - pcm1) & ~2u) == 0u;
             const uint64_t m = ballot64(cand);
             if (m) {
                 if (cand) q[(qt + static_cast<uint32_t>(__popcll(m & lanemask_lt()))) & (CQ - 1)] =
@@ -933,10 +963,6 @@ __global__ void __launch_bounds__(PT, (p_find_blocks<T, WT>())) k_p_find(const T
                     qh += 64u;
                 }
             }
-        }
-        if (alive) {  // still inside the group after gm rows (xn = entry gm + 1): one more member means look-ups
-            if (xn < HEADF) big = true;
-            else spill = spill || (xn >= PASTF && more);
         }
         if (qt != qh) {
             __builtin_amdgcn_wave_barrier();
