@@ -1030,7 +1030,8 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
     }
     CG_TRY(scan_u8_to_u32(w.uniq, w.cidx, n, nullptr, w.tile_sums, d_ncells, s));
     if (rowbytes % 16 == 0) {
-        const dim3 g(blocks_for(n * pieces, 256, 65536));
+        // GU pieces per thread, all in flight: the grid covers every piece in one step
+        const dim3 g(blocks_for(n * pieces, 256 * 4, 65536));
         const uint4 *r4 = reinterpret_cast<const uint4 *>(rows);
         uint4 *c4 = reinterpret_cast<uint4 *>(cells);
 #define CG_GATHER4(PLV)                                                                                            \
@@ -1048,7 +1049,7 @@ cg_status dedup_impl(const T *rows, int64_t n, cg_layout lay, T *cells, uint32_t
         }
 #undef CG_GATHER4
     } else {
-        const dim3 g(blocks_for(n * words, 256, 65536));
+        const dim3 g(blocks_for(n * words, 256 * 4, 65536));
 #define CG_GATHER1(PLV)                                                                                            \
     hipLaunchKernelGGL((k_gather<T, T, PLV>), g, dim3(256), 0, s, rows, n, words, vals, w.uniq, w.cidx, cells,     \
                        row_to_cell, rhash, sfx, hash_lanes, hash_s)
