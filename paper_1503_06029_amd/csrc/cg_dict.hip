@@ -358,6 +358,7 @@ size_t dict_mem_bytes(int64_t ncap, cg_layout, const cg_dict_params &p) {
 // coalesced; a wider stretch (sparse keys) is written as k_dict_scan does,
 // each cell's entries by its own lane and long gaps listed for k_dir_gaps.
 constexpr int DW = 4096;
+constexpr int DK = 4;  // position chunks per block of the directory from sorted keys
 __global__ void __launch_bounds__(DT) k_dir_from_keys(const uint32_t *__restrict__ keys,
                                                       const uint8_t *__restrict__ uniq,
                                                       const uint32_t *__restrict__ cidx, int64_t n,
@@ -367,58 +368,72 @@ __global__ void __launch_bounds__(DT) k_dir_from_keys(const uint32_t *__restrict
     __shared__ int64_t sg[DT];
     __shared__ uint32_t sc[DT];
     const int64_t G = int64_t(1) << p;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * DT + threadIdx.x;
     const int lane = threadIdx.x & 63, wb = threadIdx.x & ~63;
-    const int64_t i0 = i - lane;  // the wave's first position
-    if (i0 >= n) return;          // whole waves only: the shuffles below see every lane
-    const int64_t ii = i < n ? i : n - 1;
-    const bool valid = i < n;
-    const uint8_t un = uniq[ii];
-    const uint32_t k = keys[ii], kp = keys[ii > 0 ? ii - 1 : 0];
-    const uint32_t c = cidx[ii];
     const int64_t nc = *d_ncells;
-    const bool act = valid && un != 0;
-    const int64_t gi = p ? static_cast<int64_t>(k >> (32 - p)) : 0;
-    const int64_t gp = i == 0 ? -1 : (p ? static_cast<int64_t>(kp >> (32 - p)) : 0);
-    // the wave's stretch of entries: (lane 0's predecessor, last valid lane]
-    const int64_t lo = static_cast<int64_t>(shfl_u64(static_cast<uint64_t>(gp), 0)) + 1;
-    const int last = static_cast<int>((n - i0 < 64 ? n - i0 : 64) - 1);
-    const int64_t hi = static_cast<int64_t>(shfl_u64(static_cast<uint64_t>(gi), last));
-    if (hi - lo + 1 <= DW) {
-        sg[threadIdx.x] = valid ? gi : INT64_MAX;
-        sc[threadIdx.x] = c;
-        __builtin_amdgcn_wave_barrier();
-        for (int64_t g = lo + lane; g <= hi; g += 64) {
-            int a = 0, b = last;  // first lane whose top bits are >= g (lane last's are)
-            while (a < b) {
-                const int m = (a + b) >> 1;
-                if (sg[wb + m] < g) a = m + 1; else b = m;
-            }
-            dir[g] = sc[wb + a];
-        }
-    } else {
-        bool long_gap = false, huge_gap = false;
-        if (act) {
-            long_gap = gi - gp > GAPMIN;
-            huge_gap = gi - gp > GAPHUGE;
-            if (long_gap) {
-                dir[gi] = c;
-            } else {
-                for (int64_t g = gp + 1; g <= gi; ++g) dir[g] = c;
-            }
-        }
-        push_gap(gaps, gap_n, gap_cap, act && long_gap && !huge_gap, gp + 1, gi - 1, c);
-        push_gap(huge, gap_n + 1, huge_cap, act && huge_gap, gp + 1, gi - 1, c);
+    // DK chunks of DT positions per block, their loads issued together; each
+    // wave then handles its 64 positions of each chunk in turn
+    uint8_t un[DK];
+    uint32_t kk[DK], kq[DK], cc[DK];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+        const int64_t i = (static_cast<int64_t>(blockIdx.x) * DK + k) * DT + threadIdx.x;
+        const int64_t ii = i < n ? i : (n > 0 ? n - 1 : 0);
+        un[k] = uniq[ii];
+        kk[k] = keys[ii];
+        kq[k] = keys[ii > 0 ? ii - 1 : 0];
+        cc[k] = cidx[ii];
     }
-    if (act && static_cast<int64_t>(c) == nc - 1) {  // entries gi + 1 .. G point past the end
-        if (G - gi > GAPMIN) {
-            const bool hg = G - gi > GAPHUGE;
-            const unsigned long long q = atomicAdd(hg ? gap_n + 1 : gap_n, 1ull);
-            if (static_cast<int64_t>(q) < (hg ? huge_cap : gap_cap))
-                (hg ? huge : gaps)[q] = make_uint4(static_cast<uint32_t>(gi + 1), static_cast<uint32_t>(G),
-                                                   static_cast<uint32_t>(nc), 0u);
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+        const int64_t i = (static_cast<int64_t>(blockIdx.x) * DK + k) * DT + threadIdx.x;
+        const int64_t i0 = i - lane;  // the wave's first position
+        if (i0 >= n) break;           // whole waves only: the shuffles below see every lane
+        const bool valid = i < n;
+        const uint32_t k0 = kk[k], c = cc[k];
+        const bool act = valid && un[k] != 0;
+        const int64_t gi = p ? static_cast<int64_t>(k0 >> (32 - p)) : 0;
+        const int64_t gp = i == 0 ? -1 : (p ? static_cast<int64_t>(kq[k] >> (32 - p)) : 0);
+        // the wave's stretch of entries: (lane 0's predecessor, last valid lane]
+        const int64_t lo = static_cast<int64_t>(shfl_u64(static_cast<uint64_t>(gp), 0)) + 1;
+        const int last = static_cast<int>((n - i0 < 64 ? n - i0 : 64) - 1);
+        const int64_t hi = static_cast<int64_t>(shfl_u64(static_cast<uint64_t>(gi), last));
+        if (hi - lo + 1 <= DW) {
+            __builtin_amdgcn_wave_barrier();  // the previous chunk's searches are done with sg, sc
+            sg[threadIdx.x] = valid ? gi : INT64_MAX;
+            sc[threadIdx.x] = c;
+            __builtin_amdgcn_wave_barrier();
+            for (int64_t g = lo + lane; g <= hi; g += 64) {
+                int a = 0, b = last;  // first lane whose top bits are >= g (lane last's are)
+                while (a < b) {
+                    const int m = (a + b) >> 1;
+                    if (sg[wb + m] < g) a = m + 1; else b = m;
+                }
+                dir[g] = sc[wb + a];
+            }
         } else {
-            for (int64_t g = gi + 1; g <= G; ++g) dir[g] = static_cast<uint32_t>(nc);
+            bool long_gap = false, huge_gap = false;
+            if (act) {
+                long_gap = gi - gp > GAPMIN;
+                huge_gap = gi - gp > GAPHUGE;
+                if (long_gap) {
+                    dir[gi] = c;
+                } else {
+                    for (int64_t g = gp + 1; g <= gi; ++g) dir[g] = c;
+                }
+            }
+            push_gap(gaps, gap_n, gap_cap, act && long_gap && !huge_gap, gp + 1, gi - 1, c);
+            push_gap(huge, gap_n + 1, huge_cap, act && huge_gap, gp + 1, gi - 1, c);
+        }
+        if (act && static_cast<int64_t>(c) == nc - 1) {  // entries gi + 1 .. G point past the end
+            if (G - gi > GAPMIN) {
+                const bool hg = G - gi > GAPHUGE;
+                const unsigned long long q = atomicAdd(hg ? gap_n + 1 : gap_n, 1ull);
+                if (static_cast<int64_t>(q) < (hg ? huge_cap : gap_cap))
+                    (hg ? huge : gaps)[q] = make_uint4(static_cast<uint32_t>(gi + 1), static_cast<uint32_t>(G),
+                                                       static_cast<uint32_t>(nc), 0u);
+            } else {
+                for (int64_t g = gi + 1; g <= G; ++g) dir[g] = static_cast<uint32_t>(nc);
+            }
         }
     }
 }
@@ -471,7 +486,7 @@ cg_status run_dedup_dict(const void *rows, int64_t n, cg_layout lay, void *cells
     // the dedup's init launch also clears the gap-list counters
     CG_TRY(run_dedup_fused(rows, n, lay, cells, row_to_cell, d_ncells, ws, sfx ? d.params.split_bit : -1,
                            sfx ? m.sfx[0] : nullptr, &v, d.params.key_bits, m.gap_n, 2, s));
-    hipLaunchKernelGGL(k_dir_from_keys, dim3(blocks_for(n, DT)), dim3(DT), 0, s, v.khi, v.uniq, v.cidx, n, d_ncells,
+    hipLaunchKernelGGL(k_dir_from_keys, dim3(blocks_for(n, DT * DK)), dim3(DT), 0, s, v.khi, v.uniq, v.cidx, n, d_ncells,
                        d.params.dir_bits, m.dir, m.gaps, m.gap_n, m.gap_cap, m.huge, m.huge_cap);
     CG_LAUNCHED("dir_from_keys");
     hipLaunchKernelGGL(k_dir_gaps, dim3(256), dim3(256), 0, s, m.dir, m.gaps, m.gap_n, m.gap_cap, m.huge, m.huge_cap);
