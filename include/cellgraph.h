@@ -126,6 +126,12 @@ cg_status cg_dedup(const void *d_packed, int64_t n, cg_layout lay, void *d_cells
  * is adjacent in the sorted order; one that differs at k < s shares bits
  * s .. l-1 and is adjacent in the suffix-grouped order.                     */
 #define CG_DICT_SORTED 0        /* sorted keys + prefix directory + suffix order */
+#define CG_DICT_TREE 1          /* the same, plus Section 3.2's leaf-valued 2^r-ary
+                                   tree held as index ranges (Algorithm 3: level h
+                                   has one node per distinct h-digit prefix of r-bit
+                                   digits); distance-1 queries descend it digit by
+                                   digit (Algorithm 4); edges use the directory,
+                                   whose ranges are the tree's top levels           */
 #define CG_PATH_LOOKUP 0        /* edges by flip-and-look-up over the two orders */
 #define CG_PATH_ALLPAIRS 1      /* edges by the (*)-filtered all-pairs scan       */
 #define CG_PATH_HASH 2          /* edges in O(n l) probes of an additive-hash table
@@ -134,7 +140,7 @@ cg_status cg_dedup(const void *d_packed, int64_t n, cg_layout lay, void *d_cells
                                    row, so the output is the same                  */
 
 typedef struct cg_dict_params {
-    int32_t kind;       /* CG_DICT_SORTED                                         */
+    int32_t kind;       /* CG_DICT_SORTED or CG_DICT_TREE                         */
     int32_t dir_bits;   /* p, 0..24; -1 = automatic (about log2 of the capacity)  */
     int32_t split_bit;  /* s, 0..l; -1 = automatic                                */
     int32_t path;       /* CG_PATH_LOOKUP, _ALLPAIRS or _HASH (used by cg_edges)  */
@@ -147,7 +153,9 @@ typedef struct cg_dict_params {
                            on the device, else 64).  Rows sharing the key are
                            ordered by full-row comparison either way, so only
                            speed changes                                    */
-    int32_t reserved;   /* must be 0                                              */
+    int32_t fanout_bits; /* r, bits per digit of the CG_DICT_TREE tree (fan-out
+                           2^r): 1..8, 0 = 2 (the paper's Figure 2); must be 0
+                           for CG_DICT_SORTED                               */
 } cg_dict_params;
 
 /* The automatic parameters (all -1, kind/path 0, n_refs 4). */
@@ -185,6 +193,13 @@ typedef struct cg_dict {
     uint64_t *sfx;              /* ncells_cap entries: (hash << 32) | id      */
     void *mem;
     size_t mem_bytes;
+    /* CG_DICT_TREE only (else NULL), depth = ceil(l / r) levels below the root: */
+    uint16_t *tree_depth;       /* ncells_cap entries: for cell i >= 1, the deepest
+                                   level whose node holds both cell i - 1 and cell
+                                   i (their common leading bits / r); cell i starts
+                                   a node at every level below it                */
+    uint32_t *tree_levels;      /* depth + 1 entries: nodes per level, level 0 the
+                                   root (Algorithm 3's level sizes)              */
 } cg_dict;
 
 /* Bytes of dictionary memory for up to ncells_cap cells. */

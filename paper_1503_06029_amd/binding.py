@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcellgraph.so")
 
 CG_OK, CG_EINVAL, CG_EWORKSPACE, CG_ECAPACITY, CG_EHIP, CG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 CG_DICT_SORTED = 0
+CG_DICT_TREE = 1
 CG_PATH_LOOKUP, CG_PATH_ALLPAIRS, CG_PATH_HASH = 0, 1, 2
 
 c_i32, c_i64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
@@ -29,13 +30,14 @@ class Layout(ctypes.Structure):
 
 class DictParams(ctypes.Structure):
     _fields_ = [("kind", c_i32), ("dir_bits", c_i32), ("split_bit", c_i32), ("path", c_i32),
-                ("n_refs", c_i32), ("group_max", c_i32), ("key_bits", c_i32), ("reserved", c_i32)]
+                ("n_refs", c_i32), ("group_max", c_i32), ("key_bits", c_i32), ("fanout_bits", c_i32)]
 
 
 class Dict(ctypes.Structure):
     _fields_ = [("magic", ctypes.c_uint32), ("lay", Layout), ("params", DictParams),
                 ("ncells_cap", c_i64), ("cells", c_vp), ("d_ncells", c_vp), ("dir", c_vp),
-                ("sfx", c_vp), ("mem", c_vp), ("mem_bytes", c_sz)]
+                ("sfx", c_vp), ("mem", c_vp), ("mem_bytes", c_sz), ("tree_depth", c_vp),
+                ("tree_levels", c_vp)]
 
 
 class CellGraphError(RuntimeError):

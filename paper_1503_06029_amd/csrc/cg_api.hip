@@ -135,7 +135,8 @@ cg_status cg_dict_params_default(cg_dict_params *p) {
 
 static cg_status check_params(const cg_dict_params *p, const cg_layout &lay) {
     if (!p) return CG_OK;
-    if (p->kind != CG_DICT_SORTED) return set_error(CG_EUNSUPPORTED, "dictionary kind %d not supported", p->kind);
+    if (p->kind != CG_DICT_SORTED && p->kind != CG_DICT_TREE)
+        return set_error(CG_EUNSUPPORTED, "dictionary kind %d not supported", p->kind);
     if (p->dir_bits < -1 || p->dir_bits > 24) return set_error(CG_EINVAL, "dir_bits=%d out of range -1..24", p->dir_bits);
     if (p->split_bit < -1 || p->split_bit > lay.ell)
         return set_error(CG_EINVAL, "split_bit=%d out of range -1..ell", p->split_bit);
@@ -146,7 +147,10 @@ static cg_status check_params(const cg_dict_params *p, const cg_layout &lay) {
         return set_error(CG_EINVAL, "group_max=%d out of range 1..1024", p->group_max);
     if (p->key_bits != 0 && p->key_bits != 32 && p->key_bits != 64 && p->key_bits != 96)
         return set_error(CG_EINVAL, "key_bits=%d: 0, 32, 64 or 96", p->key_bits);
-    if (p->reserved) return set_error(CG_EINVAL, "reserved field must be 0");
+    if (p->kind == CG_DICT_SORTED && p->fanout_bits)
+        return set_error(CG_EINVAL, "fanout_bits=%d: must be 0 for the sorted kind", p->fanout_bits);
+    if (p->fanout_bits < 0 || p->fanout_bits > 8)
+        return set_error(CG_EINVAL, "fanout_bits=%d out of range 0..8", p->fanout_bits);
     return CG_OK;
 }
 

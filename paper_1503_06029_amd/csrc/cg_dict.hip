@@ -296,9 +296,14 @@ struct DictMem {
     uint64_t *sfx[2];
     uint32_t *hist;
     uint64_t *tile_sums;
+    uint16_t *tdep;   // tree kind: per cell, the deepest level shared with its predecessor
+    uint32_t *tlev;   // tree kind: nodes per level (depth + 1)
+    uint32_t *thist;  // tree kind: cells per shared depth (depth entries)
 };
 
-DictMem carve_dict(void *base, int64_t ncap, const cg_dict_params &p, size_t *bytes) {
+int tree_depth_of(int ell, int r) { return (ell + r - 1) / r; }
+
+DictMem carve_dict(void *base, int64_t ncap, int ell, const cg_dict_params &p, size_t *bytes) {
     Carver c(base);
     DictMem m{};
     const int64_t n = ncap > 0 ? ncap : 1;
@@ -313,6 +318,12 @@ DictMem carve_dict(void *base, int64_t ncap, const cg_dict_params &p, size_t *by
     m.hist = c.take<uint32_t>(radix_hist_entries(n));
     int64_t ts = scan_tiles(n), ts2 = scan_tiles(radix_hist_entries(n));
     m.tile_sums = c.take<uint64_t>(std::max(ts, ts2));
+    if (p.kind == CG_DICT_TREE) {
+        const int depth = tree_depth_of(ell, p.fanout_bits);
+        m.tdep = c.take<uint16_t>(n);
+        m.tlev = c.take<uint32_t>(depth + 1);
+        m.thist = c.take<uint32_t>(depth);
+    }
     *bytes = c.bytes();
     return m;
 }
@@ -337,12 +348,13 @@ cg_dict_params resolve_params(int64_t ncap, cg_layout lay, const cg_dict_params 
         p.split_bit = std::min(s, lay.ell);
     }
     if (p.group_max < 0) p.group_max = 64;
+    if (p.kind == CG_DICT_TREE && p.fanout_bits == 0) p.fanout_bits = 2;
     return p;
 }
 
-size_t dict_mem_bytes(int64_t ncap, cg_layout, const cg_dict_params &p) {
+size_t dict_mem_bytes(int64_t ncap, cg_layout lay, const cg_dict_params &p) {
     size_t b;
-    carve_dict(nullptr, ncap, p, &b);
+    carve_dict(nullptr, ncap, lay.ell, p, &b);
     return b;
 }
 
@@ -438,13 +450,175 @@ __global__ void __launch_bounds__(DT) k_dir_from_keys(const uint32_t *__restrict
     }
 }
 
+// ------------------------------------------------------------ tree kind
+// Section 3.2's 2^r-ary tree over the sorted cells, held as index ranges:
+// level h has one node per distinct prefix of h digits (digit i = bits
+// i r .. i r + r - 1, most significant first, zero past l), a node's cells
+// are a contiguous range, and a leaf holds one cell, its id the value.
+// Algorithm 3 builds the levels one after another; here they follow from
+// each cell's shared depth with its predecessor: cell i >= 1 shares its
+// node with cell i - 1 down to level floor(lcp / r) (lcp = their common
+// leading bits) and starts a node at every deeper level, so level h holds
+// 1 + |{i >= 1 : depth_i < h}| nodes.
+constexpr int TREE_HB = 1024;  // shared depths counted in LDS below this, deeper ones in memory
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_tree_depth(const T *__restrict__ cells, const int64_t *d_ncells,
+                                                    int64_t ncap, int words, int r, int depth,
+                                                    uint16_t *__restrict__ tdep, uint32_t *__restrict__ thist) {
+    constexpr int B = Bits<T>::B;
+    __shared__ uint32_t h[TREE_HB];
+    for (int i = threadIdx.x; i < TREE_HB; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int64_t n = load_n(d_ncells, ncap);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) tdep[0] = 0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x + 1; i < n; i += stride) {
+        const T *a = cells + (i - 1) * words;
+        const T *b = cells + i * words;
+        int w = 0;
+        T x = a[0] ^ b[0];
+        while (x == T(0) && w + 1 < words) {
+            ++w;
+            x = a[w] ^ b[w];
+        }
+        const int lcp = x ? w * B + clz_t<T>(x) : words * B;
+        int dl = lcp / r;
+        if (dl > depth - 1) dl = depth - 1;  // equal rows (not sorted-distinct input): the deepest level
+        tdep[i] = static_cast<uint16_t>(dl);
+        if (dl < TREE_HB) atomicAdd(&h[dl], 1u);
+        else atomicAdd(&thist[dl], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < TREE_HB && i < depth; i += blockDim.x)
+        if (h[i]) atomicAdd(&thist[i], h[i]);
+}
+
+// Level sizes from the shared-depth counts: levels[0] = 1 (the root, when
+// there are cells), levels[h] = levels[0] + count of depths below h.
+__global__ void __launch_bounds__(256) k_tree_levels(const uint32_t *__restrict__ thist, int depth,
+                                                     const int64_t *d_ncells, int64_t ncap,
+                                                     uint32_t *__restrict__ tlev) {
+    __shared__ uint64_t tmp[4];
+    const int64_t n = load_n(d_ncells, ncap);
+    const uint64_t root = n > 0 ? 1u : 0u;
+    if (threadIdx.x == 0) tlev[0] = static_cast<uint32_t>(root);
+    uint64_t carry = root;
+    for (int c0 = 0; c0 < depth; c0 += 256) {
+        const int v = c0 + static_cast<int>(threadIdx.x);
+        const uint64_t x = v < depth ? thist[v] : 0u;
+        uint64_t tot;
+        const uint64_t ex = block256_excl_scan_u64(x, tmp, &tot);
+        if (v < depth) tlev[v + 1] = static_cast<uint32_t>(carry + ex + x);
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+// Digit h of a row (r bits from bit h r, most significant first).
+template <typename T>
+__device__ __forceinline__ uint32_t digit_at(const T *row, int words, int r, int h) {
+    constexpr int B = Bits<T>::B;
+    const int p = h * r, w = p / B, o = p % B;
+    if (o + r <= B) return static_cast<uint32_t>((row[w] >> (B - o - r)) & static_cast<T>((1u << r) - 1u));
+    const int lo_bits = o + r - B;  // bits taken from the next word
+    uint32_t d = static_cast<uint32_t>((row[w] & (static_cast<T>(~T(0)) >> o)) << lo_bits);
+    if (w + 1 < words) d |= static_cast<uint32_t>(row[w + 1] >> (B - lo_bits));
+    return d;
+}
+
+// Algorithm 4's search for q xor e_k (k < 0: q itself) down the tree: at
+// level h the node's range narrows to the cells whose digit h is the
+// query's (two binary searches over the range, which is sorted on that
+// digit); a range of one cell is compared in full.
+template <typename T>
+__device__ int64_t find_tree(const T *cells, int words, int r, int depth, int64_t n, const T *q, int k) {
+    int64_t lo = 0, hi = n;
+    for (int h = 0; h < depth && hi - lo > 1; ++h) {
+        uint32_t d = digit_at<T>(q, words, r, h);
+        if (k >= h * r && k < h * r + r) d ^= 1u << (r - 1 - (k - h * r));
+        int64_t a = lo, b = hi;
+        while (a < b) {
+            const int64_t m = a + ((b - a) >> 1);
+            if (digit_at<T>(cells + m * words, words, r, h) < d) a = m + 1; else b = m;
+        }
+        int64_t c = a, e = hi;
+        while (c < e) {
+            const int64_t m = c + ((e - c) >> 1);
+            if (digit_at<T>(cells + m * words, words, r, h) <= d) c = m + 1; else e = m;
+        }
+        lo = a;
+        hi = c;
+    }
+    return hi > lo ? find_row<T>(cells, words, lo, hi, q, k) : -1;
+}
+
+// Distance-1 queries through the tree: one wave per query, a lane per
+// flipped bit (the output is that of k_d1_query).
+template <typename T>
+__global__ void __launch_bounds__(256) k_d1_tree(const T *__restrict__ cells, const int64_t *d_n, int64_t ncap,
+                                                 int words, int ell, int r, int depth,
+                                                 const T *__restrict__ queries, int64_t nq,
+                                                 uint32_t *__restrict__ count, uint32_t *__restrict__ self,
+                                                 T *__restrict__ mask) {
+    constexpr int B = Bits<T>::B;
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    const int64_t n = load_n(d_n, ncap);
+    for (int64_t qi = wid; qi < nq; qi += nw) {
+        const T *q = queries + qi * words;
+        uint32_t total = 0;
+        for (int k0 = 0; k0 < ell; k0 += 64) {
+            const int k = k0 + lane;
+            const bool found = k < ell && find_tree<T>(cells, words, r, depth, n, q, k) >= 0;
+            const uint64_t m = ballot64(found);
+            total += static_cast<uint32_t>(__popcll(m));
+            if (mask) {
+                T *mrow = mask + qi * words;
+                if (B == 64) {
+                    if (lane == 0) mrow[k0 / 64] = static_cast<T>(__brevll(m));
+                } else {
+                    const int w = k0 / 32;
+                    if (lane == 0) mrow[w] = static_cast<T>(__brev(static_cast<uint32_t>(m)));
+                    if (lane == 1 && w + 1 < words) mrow[w + 1] = static_cast<T>(__brev(static_cast<uint32_t>(m >> 32)));
+                }
+            }
+        }
+        if (lane == 0) {
+            if (count) count[qi] = total;
+            if (self) {
+                const int64_t id = find_tree<T>(cells, words, r, depth, n, q, -1);
+                self[qi] = id >= 0 ? static_cast<uint32_t>(id) : 0xFFFFFFFFu;
+            }
+        }
+    }
+}
+
+// The tree's arrays over d's cells (written by then in stream order).
+template <typename T>
+static cg_status tree_build(cg_dict &d, const DictMem &m, hipStream_t s) {
+    const int r = d.params.fanout_bits;
+    const int depth = tree_depth_of(d.lay.ell, r);
+    CG_TRY(fill_u32(m.thist, 0u, depth, s));
+    hipLaunchKernelGGL((k_tree_depth<T>), dim3(blocks_for(d.ncells_cap, 256, 4096)), dim3(256), 0, s,
+                       static_cast<const T *>(d.cells), d.d_ncells, d.ncells_cap, d.lay.words, r, depth, m.tdep,
+                       m.thist);
+    CG_LAUNCHED("tree_depth");
+    hipLaunchKernelGGL(k_tree_levels, dim3(1), dim3(256), 0, s, m.thist, depth, d.d_ncells, d.ncells_cap, m.tlev);
+    CG_LAUNCHED("tree_levels");
+    d.tree_depth = m.tdep;
+    d.tree_levels = m.tlev;
+    return CG_OK;
+}
+
 // The suffix-grouped order serves only the lookup path's S side (flips at
 // k < s); other paths and s = 0 skip its sort.
 static bool suffix_order_needed(const cg_dict_params &p) { return p.path == CG_PATH_LOOKUP && p.split_bit > 0; }
 
 template <typename T> static cg_status dict_build_impl(cg_dict &d, hipStream_t s) {
     size_t b;
-    DictMem m = carve_dict(d.mem, d.ncells_cap, d.params, &b);
+    DictMem m = carve_dict(d.mem, d.ncells_cap, d.lay.ell, d.params, &b);
     const int64_t ncap = d.ncells_cap;
     const int64_t G = int64_t(1) << d.params.dir_bits;
     const int64_t items = std::max<int64_t>(ncap, G + 1);
@@ -462,6 +636,7 @@ template <typename T> static cg_status dict_build_impl(cg_dict &d, hipStream_t s
         CG_TRY(radix_sort_u64(m.sfx, nullptr, ncap, d.d_ncells, 32, 64, m.hist, m.tile_sums, &which, s));
     d.dir = m.dir;
     d.sfx = m.sfx[which];
+    if (d.params.kind == CG_DICT_TREE) CG_TRY(tree_build<T>(d, m, s));
     return CG_OK;
 }
 
@@ -473,12 +648,17 @@ template <typename T> static cg_status dict_build_impl(cg_dict &d, hipStream_t s
 cg_status run_dedup_dict(const void *rows, int64_t n, cg_layout lay, void *cells, uint32_t *row_to_cell,
                          int64_t *d_ncells, void *ws, cg_dict &d, hipStream_t s) {
     size_t b;
-    DictMem m = carve_dict(d.mem, d.ncells_cap, d.params, &b);
+    DictMem m = carve_dict(d.mem, d.ncells_cap, d.lay.ell, d.params, &b);
     const int64_t G = int64_t(1) << d.params.dir_bits;
     d.dir = m.dir;
     d.sfx = m.sfx[0];
     if (n == 0) {
         CG_TRY(fill_i64(d_ncells, 0, 1, s));
+        if (d.params.kind == CG_DICT_TREE) {
+            CG_TRY(fill_u32(m.tlev, 0u, tree_depth_of(lay.ell, d.params.fanout_bits) + 1, s));
+            d.tree_depth = m.tdep;
+            d.tree_levels = m.tlev;
+        }
         return fill_u32(m.dir, 0u, G + 1, s);
     }
     DedupView v{};
@@ -494,6 +674,10 @@ cg_status run_dedup_dict(const void *rows, int64_t n, cg_layout lay, void *cells
     int which = 0;
     if (sfx) CG_TRY(radix_sort_u64(m.sfx, nullptr, d.ncells_cap, d_ncells, 32, 64, m.hist, m.tile_sums, &which, s));
     d.sfx = m.sfx[which];
+    if (d.params.kind == CG_DICT_TREE) {
+        if (lay.word_bits == 64) CG_TRY(tree_build<uint64_t>(d, m, s));
+        else CG_TRY(tree_build<uint32_t>(d, m, s));
+    }
     return CG_OK;
 }
 
@@ -506,6 +690,14 @@ template <typename T>
 static cg_status d1_impl(const cg_dict &d, const void *q, int64_t nq, uint32_t *count, uint32_t *self, void *mask,
                          hipStream_t s) {
     if (nq == 0) return CG_OK;
+    if (d.params.kind == CG_DICT_TREE) {
+        hipLaunchKernelGGL((k_d1_tree<T>), dim3(blocks_for(nq, 4, 65536)), dim3(256), 0, s,
+                           static_cast<const T *>(d.cells), d.d_ncells, d.ncells_cap, d.lay.words, d.lay.ell,
+                           d.params.fanout_bits, tree_depth_of(d.lay.ell, d.params.fanout_bits),
+                           static_cast<const T *>(q), nq, count, self, static_cast<T *>(mask));
+        CG_LAUNCHED("d1_tree");
+        return CG_OK;
+    }
     if (d.lay.words <= D1_MW) {
         hipLaunchKernelGGL((k_d1_bucket<T>), dim3(blocks_for(nq, 4, 65536)), dim3(256), 0, s,
                            static_cast<const T *>(d.cells), d.lay.words, d.lay.ell, d.dir, d.params.dir_bits,

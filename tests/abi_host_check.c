@@ -61,7 +61,11 @@ int main(void) {
     p.kind = 9;
     CHECK(cg_dict_size(1000, lay, &p, &bytes) != CG_OK);
     cg_dict_params_default(&p);
-    p.reserved = 3;
+    p.fanout_bits = 3;  /* the sorted kind has no tree */
+    CHECK(cg_dict_size(1000, lay, &p, &bytes) == CG_EINVAL);
+    p.kind = CG_DICT_TREE;
+    CHECK(cg_dict_size(1000, lay, &p, &bytes) == CG_OK);
+    p.fanout_bits = 9;
     CHECK(cg_dict_size(1000, lay, &p, &bytes) == CG_EINVAL);
     cg_dict_params_default(&p);
     p.key_bits = 40;

@@ -77,8 +77,15 @@ def test_argument_validation_without_gpu():
     assert B.cg_dict_size(1000, lay, p) > 0
     for kb in (0, 32, 64, 96):
         assert B.cg_dict_size(1000, lay, B.cg_dict_params_default(key_bits=kb)) > 0
+    # the tree kind: fan-out bits 0 (automatic: 2) to 8; its arrays add to the size
+    sorted_bytes = B.cg_dict_size(1000, lay, B.cg_dict_params_default())
+    for r in range(0, 9):
+        assert B.cg_dict_size(1000, lay, B.cg_dict_params_default(kind=B.CG_DICT_TREE, fanout_bits=r)) > sorted_bytes
+    for r in (-1, 9):
+        with pytest.raises(B.CellGraphError):
+            B.cg_dict_size(1000, lay, B.cg_dict_params_default(kind=B.CG_DICT_TREE, fanout_bits=r))
     for field, val in (("dir_bits", 30), ("split_bit", 101), ("n_refs", 9), ("group_max", 0), ("kind", 7),
-                       ("key_bits", 48), ("key_bits", -1), ("reserved", 1)):
+                       ("key_bits", 48), ("key_bits", -1), ("fanout_bits", 1)):
         q = B.cg_dict_params_default(**{field: val})
         with pytest.raises(B.CellGraphError) as e:
             B.cg_dict_size(1000, lay, q)
