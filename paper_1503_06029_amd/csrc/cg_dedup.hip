@@ -336,8 +336,8 @@ __global__ void __launch_bounds__(TT) k_tiefix_tile(const T *__restrict__ rows, 
 // returns at once; HB: rows in flight per thread).  Rows stream in with WT
 // lanes per row, each lane loading one word of the row and the same word of
 // the segment's first row, its head (loaded by every row of the segment, so
-// mostly served from cache; no LDS copy of the heads keeps the block at 13 KB
-// of LDS), and a ballot over the lanes gives the words where the row and the
+// mostly served from cache; no LDS copy of the heads keeps the block near
+// 15 KB of LDS), and a ballot over the lanes gives the words where the row and the
 // head differ.  Each row keeps an LV-level
 // summary against its head (LV = 2 for 64-bit words, 4 for 32-bit words):
 //   level c: the (c+1)-th word past the sort key where they differ, as an
@@ -812,8 +812,9 @@ __device__ __forceinline__ uint64_t piece_terms(const V &v, int piece, int s) {
 // sfx (when not null): each cell's suffix-order key (hash << 32 | id).  With
 // hash_lanes > 0 (a row's pieces a power of two, at most 64, so a row's
 // lanes are adjacent within one wave) the lanes of a row add their pieces'
-// hash terms; otherwise the hash comes from rhash[row].  All lanes of a wave
-// stay in the loop together so the shuffles see every lane.
+// hash terms (DPP permutes within the row's lane group); otherwise the hash
+// comes from rhash[row].  All lanes of a wave stay in the loop together so
+// the permutes see every lane.
 //
 // PL >= 0: pieces == 1 << PL, so a piece's row and position are a shift and
 // a mask (the general form divides a 64-bit index, dozens of instructions).
@@ -825,7 +826,8 @@ __global__ void __launch_bounds__(256) k_gather(const V *__restrict__ rows, int6
                                                 uint64_t *__restrict__ sfx, int hash_lanes, int hash_s) {
     // GU pieces per thread per step, each step's pieces a whole number of
     // waves apart, so their loads are in flight together and a row's lanes
-    // stay adjacent for the hash shuffles
+    // stay adjacent for the hash sums; the grid is sized so that one step
+    // covers every piece
     constexpr int GU = 4;
     const int64_t total = n * pieces;
     const int64_t span = static_cast<int64_t>(gridDim.x) * blockDim.x;
