@@ -207,6 +207,7 @@ __global__ void k_edges_init(uint32_t *cntS, int64_t ncap, int64_t *d_nedges, in
         big_n[0] = 0;
         big_n[1] = 0;
         big_n[2] = 0;
+        big_n[3] = 0;
         *d_nedges = 0;
         if (offsets) offsets[0] = 0;
         *status = CG_OK;
@@ -476,6 +477,9 @@ __global__ void __launch_bounds__(256) k_sup_scan(uint64_t *sup_tot, int64_t nsu
 // (WRITE = false): cntS[u] or cntP[u] (flagged BIG), and the count is added
 // to the cell's tile and super-tile totals (k_p_find has already written
 // those, counting these cells as 0).  Write: the edges at their slots.
+constexpr int BQ = 128;                 // listed-cell neighbours a wave keeps in LDS
+constexpr uint32_t BST_NONE = 0xFFFFFFFFu;
+
 template <typename T, bool WRITE>
 __global__ void __launch_bounds__(256) k_big_lookup(const T *__restrict__ cells, const uint32_t *__restrict__ dir,
                                                     int p, int words, int ell, int s,
@@ -486,7 +490,15 @@ __global__ void __launch_bounds__(256) k_big_lookup(const T *__restrict__ cells,
                                                     uint64_t *__restrict__ tile_tot, uint64_t *__restrict__ sup_tot,
                                                     const int64_t *__restrict__ offsets,
                                                     const int64_t *__restrict__ offnext, uint32_t *__restrict__ uv,
-                                                    uint16_t *__restrict__ bit, int64_t cap) {
+                                                    uint16_t *__restrict__ bit, int64_t cap,
+                                                    uint2 *__restrict__ bst, unsigned long long *__restrict__ bst_n,
+                                                    int64_t bst_cap, uint32_t *__restrict__ bstart) {
+    // the count pass keeps each listed cell's neighbours (v, k) in found order
+    // (a wave's first BQ in LDS, then a share of bst reserved for them), so
+    // the write pass copies them instead of searching again; a cell with more,
+    // or past bst's capacity, is searched again (bstart = BST_NONE)
+    __shared__ uint2 bq[4][BQ];
+    const int wv = threadIdx.x >> 6;
     int64_t ns = static_cast<int64_t>(big_n[0]), np = static_cast<int64_t>(big_n[1]);
     if (ns > list_cap) ns = list_cap;
     if (np > list_cap) np = list_cap;
@@ -520,9 +532,23 @@ __global__ void __launch_bounds__(256) k_big_lookup(const T *__restrict__ cells,
             hi_b = bad;
         }
         if (!WRITE) {
-            const uint32_t c = wave_flip_lookups<T>(cells, words, dir, p, q, khi, klo, [](uint32_t, int, uint32_t) {},
-                                                    lo_b, hi_b);
+            const uint32_t c = wave_flip_lookups<T>(cells, words, dir, p, q, khi, klo, [&](uint32_t v, int k, uint32_t r) {
+                if (r < static_cast<uint32_t>(BQ)) bq[wv][r] = make_uint2(v, static_cast<uint32_t>(k));
+            }, lo_b, hi_b);
+            __builtin_amdgcn_wave_barrier();
+            uint32_t st = c == 0 ? 0u : BST_NONE;
+            if (c > 0 && c <= static_cast<uint32_t>(BQ)) {
+                unsigned long long b0 = 0;
+                if (lane == 0) b0 = atomicAdd(bst_n, static_cast<unsigned long long>(c));
+                b0 = shfl_u64(b0, 0);
+                if (static_cast<int64_t>(b0 + c) <= bst_cap) {
+                    st = static_cast<uint32_t>(b0);
+                    for (uint32_t r = lane; r < c; r += 64) bst[b0 + r] = bq[wv][r];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();  // bq is free for the wave's next cell
             if (lane == 0) {
+                bstart[it] = st;
                 if (sside) cntS[u] = c; else cntP[u] = BIG | c;
                 atomicAdd(reinterpret_cast<unsigned long long *>(&tile_tot[u / PT]), static_cast<unsigned long long>(c));
                 atomicAdd(reinterpret_cast<unsigned long long *>(&sup_tot[(u / PT) / SUP]),
@@ -537,9 +563,18 @@ __global__ void __launch_bounds__(256) k_big_lookup(const T *__restrict__ cells,
                 base = offsets ? offsets[u]
                                : offnext[u] - static_cast<int64_t>(cntP[u] & ~BIG) - static_cast<int64_t>(cntS[u]);
             }
-            wave_flip_lookups<T>(cells, words, dir, p, q, khi, klo, [&](uint32_t v, int k, uint32_t r) {
-                emit(uv, bit, cap, base + r, u, v, k);
-            }, lo_b, hi_b);
+            const uint32_t st = bstart[it];
+            if (st != BST_NONE) {
+                const uint32_t c = sside ? cntS[u] : (cntP[u] & ~BIG);
+                for (uint32_t r = lane; r < c; r += 64) {
+                    const uint2 e = bst[static_cast<int64_t>(st) + r];
+                    emit(uv, bit, cap, base + r, u, e.x, static_cast<int>(e.y));
+                }
+            } else {
+                wave_flip_lookups<T>(cells, words, dir, p, q, khi, klo, [&](uint32_t v, int k, uint32_t r) {
+                    emit(uv, bit, cap, base + r, u, v, k);
+                }, lo_b, hi_b);
+            }
         }
     }
 }
@@ -1173,7 +1208,11 @@ struct EdgesWs {
     uint32_t *s_stash_n;
     uint32_t *s_big, *p_big;     // cells left to k_big_lookup
     uint32_t *p_fix;             // tiles whose P stash overflowed
-    unsigned long long *big_n;   // [0]: S list length, [1]: P list length, [2]: overflowed tiles
+    unsigned long long *big_n;   // [0]: S list length, [1]: P list length, [2]: overflowed tiles,
+                                 // [3]: entries of bst taken
+    uint2 *bst;                  // listed cells' neighbours (v, k), count pass to write pass
+    int64_t bst_cap;
+    uint32_t *bstart;            // per listed cell: its first bst entry, or BST_NONE
 };
 
 // Padded row width (power of two) for the P tiles, or 0 when rows are too
@@ -1207,7 +1246,10 @@ EdgesWs carve_edges(void *base, int64_t ncap, size_t *bytes) {
     w.s_big = c.take<uint32_t>(n);
     w.p_big = c.take<uint32_t>(n);
     w.p_fix = c.take<uint32_t>(tiles);
-    w.big_n = c.take<unsigned long long>(3);
+    w.big_n = c.take<unsigned long long>(4);
+    w.bst_cap = n;
+    w.bst = c.take<uint2>(w.bst_cap);
+    w.bstart = c.take<uint32_t>(2 * n);
     *bytes = c.bytes();
     return w;
 }
@@ -1264,7 +1306,8 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
     CG_LAUNCHED("edges_p_find");
     // listed cells of both sides: their counts, added to their tile totals
     hipLaunchKernelGGL((k_big_lookup<T, false>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp, w.s_big,
-                       w.p_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, no_off, no_off, uv, bit, cap);
+                       w.p_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, no_off, no_off, uv, bit, cap,
+                       w.bst, w.big_n + 3, w.bst_cap, w.bstart);
     CG_LAUNCHED("edges_big_count");
     // up to SUP_INLINE super-tiles each placement block sums those before
     // its own; more are scanned first
@@ -1279,7 +1322,7 @@ cg_status p_pass_launch(const cg_dict &d, const EdgesWs &w, int64_t cap, int64_t
     CG_LAUNCHED("edges_p_place");
     hipLaunchKernelGGL((k_big_lookup<T, true>), bgrid, dim3(256), 0, s, cells, d.dir, pb, words, ell, sp, w.s_big,
                        w.p_big, w.big_n, ncap, w.cntS, w.cntP, w.tile_tot, w.sup_tot, d_offsets, offnext, uv, bit,
-                       cap);
+                       cap, w.bst, w.big_n + 3, w.bst_cap, w.bstart);
     CG_LAUNCHED("edges_big_write");
     const int gm = gmax < PSCAN ? gmax : PSCAN;  // same scan limit as k_p_find
     hipLaunchKernelGGL((k_p_fix<T, WT>), dim3(blocks_for(ntiles, 1, 64)), dim3(PT), lds, s, cells, d.d_ncells, ncap,
