@@ -382,6 +382,8 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, Key
     __shared__ uint32_t sval[WSLOTS];
     __shared__ int16_t segof[WSLOTS];       // slot of the row's head, -1 if not sorted here
     __shared__ int16_t seglen[WSLOTS];
+    __shared__ int16_t sord[WSLOTS];        // slot of the segment row at each sorted position
+    __shared__ uint8_t sfull[WSLOTS];       // per segment head: equal summaries to look at again
     // summary levels per row: 32-bit words keep four for the LDS two 64-bit
     // words take (rows of 32-bit words tend to share more leading words)
     constexpr int LV = sizeof(T) == 4 ? 4 : 2;
@@ -488,6 +490,7 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, Key
         if (e < WSLOTS) {
             segof[e] = so;
             seglen[e] = sl;
+            sfull[e] = 0;
             if (so >= 0) {
 #pragma unroll
                 for (int c = 0; c < LV; ++c) {
@@ -555,8 +558,12 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, Key
     __syncthreads();
     // Each row's summary as one 192-bit string, most significant first: per
     // level the 7-bit code then the word (so strings order as the summaries
-    // do), the flag in the last bit.  Written over the pool once every row's
-    // levels are read.
+    // do); under them the row's slot (bits 1 .. 9 of the last word), which
+    // makes a segment's strings distinct and orders equal summaries by
+    // position; the flag in the last bit.  Written over the pool once every
+    // row's levels are read.
+    static_assert(LV * (7 + Bits<T>::B) <= 182 && WSLOTS <= 512, "summary, slot and flag fit 192 bits");
+    constexpr uint64_t SLOTM = 0x3FEull;
     uint64_t kp[2][3];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -569,7 +576,7 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, Key
                 put_bits(kp[h], c * (7 + B), scode[LV * r + c] & 0x7f, 7);
                 put_bits(kp[h], c * (7 + B) + 7, static_cast<uint64_t>(sv[LV * r + c]), B);
             }
-            kp[h][2] |= (scode[LV * r + LV - 1] & 0x80) ? 1ull : 0ull;
+            kp[h][2] |= (static_cast<uint64_t>(r) << 1) | ((scode[LV * r + LV - 1] & 0x80) ? 1ull : 0ull);
         }
     }
     __syncthreads();
@@ -583,43 +590,121 @@ __global__ void __launch_bounds__(TT) k_tiefix_w(const T *__restrict__ rows, Key
         }
     }
     __syncthreads();
+    // A row's rank: how many strings of its segment lie below its own (j's
+    // string is below r's iff the 192-bit subtraction borrows; the slots
+    // differ, so the flag never decides).  The sorted order goes to sord.
+    int rk[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = t + h * TT;
+        const int a = r < WSLOTS ? segof[r] : -1;
+        rk[h] = 0;
+        if (a < 0) continue;
+        const int len = seglen[r];
+        const uint64_t m0 = kp[h][0], m1 = kp[h][1], m2 = kp[h][2];
+        int rank = 0;
+#pragma unroll 2
+        for (int j = a; j < a + len; ++j) {
+            unsigned long long bw;
+            (void)__builtin_subcll(pk[3 * j + 2], m2, 0ull, &bw);
+            (void)__builtin_subcll(pk[3 * j + 1], m1, bw, &bw);
+            (void)__builtin_subcll(pk[3 * j], m0, bw, &bw);
+            rank += static_cast<int>(bw);
+        }
+        rk[h] = rank;
+        sord[a + rank] = static_cast<int16_t>(r);
+    }
+    __syncthreads();
+    // Equal summaries are neighbours in that order, sorted by slot.  A row
+    // whose predecessor there has its summary: with both flags set the rows
+    // are equal and it is a duplicate; otherwise they may differ past the
+    // summary, and the segment is marked for a second look.
+    bool dupf[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = t + h * TT;
+        const int a = r < WSLOTS ? segof[r] : -1;
+        dupf[h] = false;
+        if (a < 0 || rk[h] == 0) continue;
+        const int j = sord[a + rk[h] - 1];
+        const uint64_t j2 = pk[3 * j + 2];
+        if (pk[3 * j] == kp[h][0] && pk[3 * j + 1] == kp[h][1] && ((j2 ^ kp[h][2]) & ~(SLOTM | 1ull)) == 0) {
+            if (j2 & kp[h][2] & 1ull) dupf[h] = true;
+            else sfull[a] = 1;
+        }
+    }
+    __syncthreads();
+    // In a marked segment each row is ranked again.  32-bit words: the row
+    // walks the run of summaries equal to its own on both sides, and for a
+    // pair without both flags the rank counted by slot is replaced by a
+    // comparison of the rows in full.  64-bit words (equal summaries without
+    // flags are rarer there): the whole segment is compared again with the
+    // slots left out, such pairs compared in full.
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int r = t + h * TT;
         const int a = r < WSLOTS ? segof[r] : -1;
         if (a < 0) continue;
-        const int len = seglen[r];
-        const uint64_t m0 = kp[h][0], m1 = kp[h][1], m2 = kp[h][2] | 1ull;
-        const uint64_t fm = kp[h][2] & 1ull;
-        int rank = 0;
-        bool dup = false, anytie = false;
-        // the flag bit is set on both sides, so it takes no part in the
-        // order; j's string is below r's iff the 192-bit subtraction borrows
-#pragma unroll 2
-        for (int j = a; j < a + len; ++j) {
-            const uint64_t j0 = pk[3 * j], j1 = pk[3 * j + 1], j2r = pk[3 * j + 2];
-            const uint64_t j2 = j2r | 1ull;
-            unsigned long long bw;
-            (void)__builtin_subcll(j2, m2, 0ull, &bw);
-            (void)__builtin_subcll(j1, m1, bw, &bw);
-            (void)__builtin_subcll(j0, m0, bw, &bw);
-            const bool eq = ((j0 ^ m0) | (j1 ^ m1) | (j2 ^ m2)) == 0;
-            const bool same = eq & ((j2r & fm) != 0);
-            const bool sb = same & (j < r);
-            rank += static_cast<int>(bw) + (sb ? 1 : 0);
-            dup = dup | sb;
-            anytie = anytie | (eq & !same & (j != r));
-        }
-        if (anytie) {
-            // rows with equal summaries that may differ: compare them in full
-            const T *me = rows + static_cast<int64_t>(sval[r]) * words;
-            for (int j = a; j < a + len; ++j) {
-                const uint64_t j2r = pk[3 * j + 2];
-                const bool eq = pk[3 * j] == m0 && pk[3 * j + 1] == m1 && (j2r | 1ull) == m2;
-                if (!eq || j == r || (j2r & fm)) continue;
-                const int c = row_cmp4<T>(rows + static_cast<int64_t>(sval[j]) * words, me, words, FROM);
-                rank += (c < 0 || (c == 0 && j < r)) ? 1 : 0;
-                dup = dup || (c == 0 && j < r);
+        int rank = rk[h];
+        bool dup = dupf[h];
+        if (sfull[a]) {
+            const int len = seglen[r];
+            auto full_cmp = [&](int j) {
+                return row_cmp4<T>(rows + static_cast<int64_t>(sval[j]) * words,
+                                   rows + static_cast<int64_t>(sval[r]) * words, words, FROM);
+            };
+            dup = false;
+            if constexpr (sizeof(T) == 4) {
+                const int q = a + rank;
+                const uint64_t m0 = kp[h][0], m1 = kp[h][1], m2 = kp[h][2];
+                auto same_summary = [&](int j) {
+                    return pk[3 * j] == m0 && pk[3 * j + 1] == m1 && ((pk[3 * j + 2] ^ m2) & ~(SLOTM | 1ull)) == 0;
+                };
+                for (int p = q - 1; p >= a; --p) {  // slots below r
+                    const int j = sord[p];
+                    if (!same_summary(j)) break;
+                    if (pk[3 * j + 2] & m2 & 1ull) {
+                        dup = true;
+                    } else {
+                        const int c = full_cmp(j);
+                        rank -= c > 0 ? 1 : 0;
+                        dup = dup || c == 0;
+                    }
+                }
+                for (int p = q + 1; p < a + len; ++p) {  // slots above r
+                    const int j = sord[p];
+                    if (!same_summary(j)) break;
+                    if (!(pk[3 * j + 2] & m2 & 1ull)) rank += full_cmp(j) < 0 ? 1 : 0;
+                }
+            } else {
+                const uint64_t m0 = kp[h][0], m1 = kp[h][1], m2 = kp[h][2] | SLOTM | 1ull;
+                const uint64_t fm = kp[h][2] & 1ull;
+                bool anytie = false;
+                rank = 0;
+                for (int j = a; j < a + len; ++j) {
+                    const uint64_t j0 = pk[3 * j], j1 = pk[3 * j + 1], j2r = pk[3 * j + 2];
+                    const uint64_t j2 = j2r | SLOTM | 1ull;
+                    unsigned long long bw;
+                    (void)__builtin_subcll(j2, m2, 0ull, &bw);
+                    (void)__builtin_subcll(j1, m1, bw, &bw);
+                    (void)__builtin_subcll(j0, m0, bw, &bw);
+                    const bool eq = ((j0 ^ m0) | (j1 ^ m1) | (j2 ^ m2)) == 0;
+                    const bool same = eq & ((j2r & fm) != 0);
+                    const bool sb = same & (j < r);
+                    rank += static_cast<int>(bw) + (sb ? 1 : 0);
+                    dup = dup | sb;
+                    anytie = anytie | (eq & !same & (j != r));
+                }
+                if (anytie) {
+                    for (int j = a; j < a + len; ++j) {
+                        const uint64_t j2r = pk[3 * j + 2];
+                        const bool eq = pk[3 * j] == m0 && pk[3 * j + 1] == m1 && (j2r | SLOTM | 1ull) == m2;
+                        if (!eq || j == r || (j2r & fm)) continue;
+                        const int c = full_cmp(j);
+                        rank += (c < 0 || (c == 0 && j < r)) ? 1 : 0;
+                        dup = dup || (c == 0 && j < r);
+                    }
+                }
             }
         }
         vals[b0 + a + rank] = sval[r];
