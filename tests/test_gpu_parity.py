@@ -351,7 +351,7 @@ def test_batch_scenes(gpu, i):
     torch, B, P = gpu
     ell, n = inputs.batch_scene_params(i)
     if n > 60000:
-        pytest.skip("large scene: covered by the batched tests")
+        pytest.skip("large scene: compared with its oracle digest in test_gpu_full_configs (all 512 scenes)")
     say("batch scene", i, ell, n)
     R = inputs.batch_scene(i)
     wb = 32 if i % 2 else 64
